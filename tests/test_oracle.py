@@ -1,0 +1,493 @@
+"""Pins for the FP64 oracle: each check is fixed by the paper or by mathematics,
+not by re-typing the oracle's own formula.
+
+  * Lemma 1: the relaxation sandwiches ReLU on a dense grid; the paper's boundary
+    cases; a hand-computed unstable neuron.
+  * The layer operators against PyTorch's own conv2d / conv_transpose2d (float64)
+    and the adjoint identity <W x, y> = <x, W^T y>.
+  * Theorem 2: for a box the closed form is exact -> equals brute-force vertex
+    enumeration.
+  * Theorem 1 with no unstable neuron is exact -> equals the true minimum found by
+    enumerating the vertices of a 2-D box.
+  * eps = 0 gives lower = upper = C f(x0).
+  * Soundness on tiny 2-D-input nets: 1e5 uniform samples plus a 317x317 grid
+    (corners included) for random alpha, and for random beta >= 0 on the split-feasible
+    points.
+  * Linear programming (scipy HiGHS) on the triangle relaxation: any alpha gives a
+    bound <= the LP value <= the sampled minimum; for one hidden layer and one row the
+    optimised alpha (and beta with split constraints) reaches the LP value.
+  * The adjoint against central finite differences (h = 1e-6).
+  * Adam against torch.optim.Adam.
+  * CROWN with alpha = 0 is never looser than interval bounds on one hidden layer.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+from oracle import crown as O
+import workloads as W
+
+
+def tiny_mlp(dims, seed):
+    return W.mlp(dims, seed=seed)
+
+
+def sample_box(x_lo, x_hi, n, seed):
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(x_lo, np.float64)
+    hi = np.asarray(x_hi, np.float64)
+    return lo + (hi - lo) * rng.uniform(0, 1, size=(n, lo.size))
+
+
+def grid_2d(x_lo, x_hi, k=317):
+    a = np.linspace(float(x_lo[0]), float(x_hi[0]), k)
+    b = np.linspace(float(x_lo[1]), float(x_hi[1]), k)
+    A, B = np.meshgrid(a, b, indexing="ij")
+    return np.stack([A.ravel(), B.ravel()], axis=1)
+
+
+# ---------------------------------------------------------------------------- Lemma 1
+def test_relax_hand_example():
+    D_lo, D_up, b_lo, b_up, unst = O.relax(np.array([-1.0]), np.array([3.0]), np.array([0.3]))
+    assert unst[0]
+    assert D_up[0] == pytest.approx(0.75) and b_up[0] == pytest.approx(0.75)
+    assert D_lo[0] == pytest.approx(0.3) and b_lo[0] == 0.0
+
+
+def test_relax_cases():
+    l = np.array([0.0, 0.5, -1.0, -2.0, 0.0, -1.0])
+    u = np.array([0.0, 1.0, 0.0, -1.0, 2.0, 1.0])
+    D_lo, D_up, b_lo, b_up, unst = O.relax(l, u, np.full(6, 0.25))
+    # active (l >= 0), inactive (u <= 0), unstable (l < 0 < u)
+    assert list(unst) == [False, False, False, False, False, True]
+    assert list(D_lo[:5]) == [1, 1, 0, 0, 1] and list(D_up[:5]) == [1, 1, 0, 0, 1]
+    assert np.all(b_up[:5] == 0)
+
+
+def test_relax_sandwich_grid():
+    rng = np.random.default_rng(0)
+    for _ in range(200):
+        l = -rng.uniform(0.01, 3)
+        u = rng.uniform(0.01, 3)
+        a = rng.uniform(0, 1)
+        D_lo, D_up, b_lo, b_up, _ = O.relax(np.array([l]), np.array([u]), np.array([a]))
+        z = np.linspace(l, u, 1001)
+        r = np.maximum(z, 0)
+        assert np.all(D_lo[0] * z + b_lo[0] <= r + 1e-12)
+        assert np.all(r <= D_up[0] * z + b_up[0] + 1e-12)
+        # the upper line passes through (l, 0) and (u, u)
+        assert D_up[0] * l + b_up[0] == pytest.approx(0.0, abs=1e-12)
+        assert D_up[0] * u + b_up[0] == pytest.approx(u, abs=1e-12)
+
+
+# -------------------------------------------------------------------- layer operators
+@pytest.mark.parametrize("cin,cout,k,s,p,H", [(3, 4, 3, 1, 1, 7), (2, 5, 4, 2, 1, 8),
+                                              (4, 3, 3, 2, 0, 9), (1, 2, 4, 2, 1, 6)])
+def test_conv_operators_vs_torch(cin, cout, k, s, p, H):
+    rng = np.random.default_rng(1)
+    Wt = rng.normal(size=(cout, cin, k, k))
+    b = rng.normal(size=cout)
+    OH = (H + 2 * p - k) // s + 1
+    layer = {"kind": "conv", "W": Wt, "b": b, "in_shape": (cin, H, H),
+             "out_shape": (cout, OH, OH), "stride": s, "pad": p}
+    x = rng.normal(size=(3, cin * H * H))
+    ref = F.conv2d(torch.from_numpy(x.reshape(3, cin, H, H)), torch.from_numpy(Wt),
+                   torch.from_numpy(b), stride=s, padding=p).numpy().reshape(3, -1)
+    np.testing.assert_allclose(O.affine(layer, x), ref, rtol=1e-12, atol=1e-12)
+    lam = rng.normal(size=(4, cout * OH * OH))
+    opad = H - ((OH - 1) * s - 2 * p + k)
+    refT = F.conv_transpose2d(torch.from_numpy(lam.reshape(4, cout, OH, OH)),
+                              torch.from_numpy(Wt), stride=s, padding=p,
+                              output_padding=opad).numpy().reshape(4, -1)
+    np.testing.assert_allclose(O.linear_T(layer, lam), refT, rtol=1e-12, atol=1e-12)
+    # adjoint identity
+    lhs = np.sum(O.linear_fwd(layer, x[:1]) * lam[:1])
+    rhs = np.sum(x[:1] * O.linear_T(layer, lam[:1]))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_linear_operators_vs_numpy_definition():
+    rng = np.random.default_rng(2)
+    layer = W.mlp([5, 4])[0]
+    x = rng.normal(size=(3, 5))
+    ref = torch.nn.functional.linear(torch.from_numpy(x),
+                                     torch.from_numpy(layer["W"].astype(np.float64)),
+                                     torch.from_numpy(layer["b"].astype(np.float64))).numpy()
+    np.testing.assert_allclose(O.affine(layer, x), ref, rtol=1e-13)
+
+
+# -------------------------------------------------------------------------- Theorem 2
+def test_concretize_equals_vertex_enumeration():
+    rng = np.random.default_rng(3)
+    for d in (1, 3, 6, 9):
+        Wt = rng.normal(size=(5, d))
+        bt = rng.normal(size=5)
+        lo = rng.uniform(-1, 0, d)
+        hi = lo + rng.uniform(0, 2, d)
+        verts = np.array(list(itertools.product(*[(lo[j], hi[j]) for j in range(d)])))
+        brute = (verts @ Wt.T + bt).min(axis=0)
+        np.testing.assert_allclose(O.concretize(Wt, bt, lo, hi), brute, rtol=1e-12, atol=1e-12)
+
+
+def test_single_linear_layer_closed_form():
+    net = W.mlp([6, 4], seed=5)
+    x0 = W.uniform_inputs(1, 6, seed=6)[0]
+    eps = 0.1
+    lo, hi = W.linf_box(x0, eps)
+    C = np.eye(4)[[0, 1, 2]] - np.eye(4)[[3, 3, 3]]
+    got = O.spec_lower(net, 1, C, [], lo, hi, use_slack=False)
+    # lower_i = (C W c + C b)_i - sum_j |(CW)_ij| r_j, with the fp32 box (exact in fp64)
+    Wm = net[0]["W"].astype(np.float64)
+    c = (lo.astype(np.float64) + hi) / 2
+    r = (hi.astype(np.float64) - lo) / 2
+    verts = np.array(list(itertools.product(*[(lo[j], hi[j]) for j in range(6)])),
+                     dtype=np.float64)
+    vals = (verts @ Wm.T + net[0]["b"].astype(np.float64)) @ C.T
+    np.testing.assert_allclose(got, vals.min(axis=0), rtol=1e-12, atol=1e-12)
+    # with an eps-ball of radius exactly eps: minus eps * ||(CW)_i||_1
+    cw = C @ Wm
+    closed = C @ (Wm @ c + net[0]["b"]) - np.abs(cw) @ r
+    np.testing.assert_allclose(got, closed, rtol=1e-12)
+
+
+# -------------------------------------------------------------------------- Theorem 1
+def _planted_stable_net(seed, active_only):
+    net = W.mlp([2, 6, 5, 3], seed=seed)
+    for layer in net[:-1]:
+        if active_only:
+            layer["b"] = (np.abs(layer["b"]) + 20.0).astype(np.float32)
+        else:
+            sgn = np.where(np.arange(len(layer["b"])) % 2 == 0, 1.0, -1.0)
+            layer["b"] = (sgn * 20.0).astype(np.float32)
+    return net
+
+
+@pytest.mark.parametrize("active_only", [True, False])
+def test_no_unstable_neuron_is_exact(active_only):
+    net = _planted_stable_net(7, active_only)
+    lo = np.array([-0.5, 0.25], np.float32)
+    hi = np.array([0.5, 0.75], np.float32)
+    C = np.array([[1.0, -1.0, 0.0], [0.0, 1.0, -1.0], [1.0, 0.0, 0.0]])
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    for (l, u) in bounds:
+        assert np.all((l >= 0) | (u <= 0))
+    low = O.spec_lower(net, 3, C, bounds, lo, hi, use_slack=False)
+    up = -O.spec_lower(net, 3, -C, bounds, lo, hi, use_slack=False)
+    verts = np.array(list(itertools.product((lo[0], hi[0]), (lo[1], hi[1]))), np.float64)
+    f = O.forward(net, verts)[-1] @ C.T
+    np.testing.assert_allclose(low, f.min(axis=0), rtol=1e-12, atol=1e-10)
+    np.testing.assert_allclose(up, f.max(axis=0), rtol=1e-12, atol=1e-10)
+
+
+def test_eps_zero():
+    net = W.mlp([4, 7, 6, 3], seed=8)
+    x0 = W.uniform_inputs(1, 4, seed=9)[0]
+    C = np.array([[1.0, -1.0, 0.0], [1.0, 0.0, -1.0]])
+    bounds, low, up = O.crown(net, C, x0, x0, use_slack=False)
+    f = O.forward(net, x0[None])[-1][0] @ C.T
+    np.testing.assert_allclose(low, f, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(up, f, rtol=1e-12, atol=1e-12)
+
+
+# --------------------------------------------------------------------------- soundness
+SOUND_NETS = [([2, 8, 8, 3], 11), ([2, 16, 16, 16, 2], 12), ([2, 12, 3], 13)]
+
+
+@pytest.mark.parametrize("dims,seed", SOUND_NETS)
+def test_soundness_random_alpha(dims, seed):
+    net = tiny_mlp(dims, seed)
+    lo = np.array([-1.0, -0.5], np.float32)
+    hi = np.array([0.5, 1.0], np.float32)
+    pts = np.concatenate([sample_box(lo, hi, 100_000, seed), grid_2d(lo, hi)])
+    zs = O.forward(net, pts)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    for m, (l, u) in enumerate(bounds):
+        assert np.all(zs[m] >= l - 1e-9) and np.all(zs[m] <= u + 1e-9)
+    L = len(net)
+    C = np.eye(dims[-1])
+    C = np.concatenate([C, -C])
+    rng = np.random.default_rng(seed)
+    f = zs[-1] @ C.T
+    for trial in range(4):
+        alpha = [rng.uniform(0, 1, len(l)) for (l, _) in bounds]
+        low = O.spec_lower(net, L, C, bounds, lo, hi, alpha, use_slack=False)
+        assert np.all(f.min(axis=0) >= low - 1e-9)
+
+
+@pytest.mark.parametrize("dims,seed", SOUND_NETS)
+def test_soundness_beta_splits(dims, seed):
+    net = tiny_mlp(dims, seed)
+    lo = np.array([-1.0, -0.5], np.float32)
+    hi = np.array([0.5, 1.0], np.float32)
+    pts = np.concatenate([sample_box(lo, hi, 100_000, seed + 1), grid_2d(lo, hi)])
+    zs = O.forward(net, pts)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    unst = [(m + 1, j) for m, (l, u) in enumerate(bounds) for j in range(len(l))
+            if l[j] < 0 < u[j]]
+    assert len(unst) >= 3
+    rng = np.random.default_rng(seed)
+    L = len(net)
+    C = np.concatenate([np.eye(dims[-1]), -np.eye(dims[-1])])
+    checked = 0
+    for trial in range(12):
+        k = int(rng.integers(1, min(4, len(unst)) + 1))
+        pick = rng.choice(len(unst), size=k, replace=False)
+        splits = [(unst[i][0], unst[i][1], int(rng.choice([-1, 1]))) for i in pick]
+        feas = np.ones(len(pts), bool)
+        for (m, j, sg) in splits:
+            feas &= sg * zs[m - 1][:, j] >= 0
+        if feas.sum() < 10:
+            continue
+        beta = rng.uniform(0, 2, size=(len(splits), C.shape[0]))
+        alpha = [rng.uniform(0, 1, len(l)) for (l, _) in bounds]
+        low = O.spec_lower(net, L, C, bounds, lo, hi, alpha, splits, beta, use_slack=False)
+        f = zs[-1][feas] @ C.T
+        assert np.all(f.min(axis=0) >= low - 1e-9)
+        low0 = O.spec_lower(net, L, C, bounds, lo, hi, alpha, splits, None, use_slack=False)
+        assert np.all(f.min(axis=0) >= low0 - 1e-9)
+        checked += 1
+    assert checked >= 4
+
+
+def test_beta_zero_equals_clamped_plain_crown():
+    net = tiny_mlp([3, 10, 10, 4], 21)
+    lo = np.array([-1.0, -1.0, -1.0], np.float32)
+    hi = np.array([1.0, 1.0, 1.0], np.float32)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    unst = [(m + 1, j) for m, (l, u) in enumerate(bounds) for j in range(len(l))
+            if l[j] < 0 < u[j]]
+    splits = [(unst[0][0], unst[0][1], 1), (unst[-1][0], unst[-1][1], -1)]
+    C = np.eye(4)
+    a = O.spec_lower(net, 3, C, bounds, lo, hi, None, splits, np.zeros((2, 4)),
+                     use_slack=False)
+    # the same constraints written directly into the pre-activation box
+    manual = [(l.copy(), u.copy()) for (l, u) in bounds]
+    manual[unst[0][0] - 1][0][unst[0][1]] = 0.0
+    manual[unst[-1][0] - 1][1][unst[-1][1]] = 0.0
+    b = O.spec_lower(net, 3, C, manual, lo, hi, use_slack=False)
+    np.testing.assert_allclose(a, b, rtol=1e-13)
+
+
+def test_infeasible_split_gives_plus_inf():
+    net = tiny_mlp([2, 6, 2], 22)
+    lo = np.array([-1.0, -1.0], np.float32)
+    hi = np.array([1.0, 1.0], np.float32)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    l, u = bounds[0]
+    j = int(np.argmin(u))
+    bounds[0][1][j] = -abs(bounds[0][1][j]) - 1.0   # make it strictly inactive
+    bounds[0][0][j] = min(bounds[0][0][j], bounds[0][1][j] - 1.0)
+    low = O.spec_lower(net, 2, np.eye(2), bounds, lo, hi, None, [(1, j, 1)], None)
+    assert np.all(np.isinf(low)) and np.all(low > 0)
+
+
+# -------------------------------------------------------------------------------- LP
+def _lp_one_hidden(net, c_row, lo, hi, bounds, splits=()):
+    """min c^T (W2 h + b2) over the triangle relaxation of one hidden layer (HiGHS)."""
+    from scipy.optimize import linprog
+    W1 = net[0]["W"].astype(np.float64)
+    b1 = net[0]["b"].astype(np.float64)
+    W2 = net[1]["W"].astype(np.float64)
+    b2 = net[1]["b"].astype(np.float64)
+    d0, d1 = W1.shape[1], W1.shape[0]
+    l, u = [np.array(v, np.float64) for v in bounds[0]]
+    for (m, j, sg) in splits:
+        if sg > 0:
+            l[j] = max(l[j], 0.0)
+        else:
+            u[j] = min(u[j], 0.0)
+    nv = d0 + 2 * d1          # x, z, h
+    cost = np.zeros(nv)
+    cost[d0 + d1:] = c_row @ W2
+    A_eq, b_eq, A_ub, b_ub = [], [], [], []
+    for j in range(d1):      # z = W1 x + b1
+        row = np.zeros(nv)
+        row[:d0] = -W1[j]
+        row[d0 + j] = 1.0
+        A_eq.append(row)
+        b_eq.append(b1[j])
+    for j in range(d1):
+        zi, hi_ = d0 + j, d0 + d1 + j
+        if l[j] >= 0:
+            row = np.zeros(nv); row[hi_] = 1; row[zi] = -1
+            A_eq.append(row); b_eq.append(0.0)
+        elif u[j] <= 0:
+            row = np.zeros(nv); row[hi_] = 1
+            A_eq.append(row); b_eq.append(0.0)
+        else:
+            row = np.zeros(nv); row[hi_] = -1; row[zi] = 1          # z - h <= 0
+            A_ub.append(row); b_ub.append(0.0)
+            s = u[j] / (u[j] - l[j])                                 # h <= s (z - l)
+            row = np.zeros(nv); row[hi_] = 1; row[zi] = -s
+            A_ub.append(row); b_ub.append(-s * l[j])
+        for (m, jj, sg) in splits:                                   # sigma z >= 0
+            if jj == j:
+                row = np.zeros(nv); row[zi] = -sg
+                A_ub.append(row); b_ub.append(0.0)
+    bnds = [(float(lo[i]), float(hi[i])) for i in range(d0)] + \
+        [(float(l[j]), float(u[j])) for j in range(d1)] + [(0.0, None)] * d1
+    res = linprog(cost, A_ub=np.array(A_ub) if A_ub else None,
+                  b_ub=np.array(b_ub) if b_ub else None, A_eq=np.array(A_eq),
+                  b_eq=np.array(b_eq), bounds=bnds, method="highs")
+    assert res.status == 0
+    return res.fun + c_row @ b2
+
+
+def _maximise(net, C, bounds, lo, hi, splits, use_beta, steps=1500):
+    best, _, _ = O.optimize_alpha_beta(net, C, bounds, lo, hi, splits, steps=steps, lr=0.02,
+                                       alpha0=0.5, use_beta=use_beta)
+    return best
+
+
+@pytest.mark.parametrize("seed", [31, 32, 33])
+def test_lp_one_hidden_layer(seed):
+    net = tiny_mlp([3, 8, 2], seed)
+    lo = np.array([-1.0, -1.0, -1.0], np.float32)
+    hi = np.array([1.0, 1.0, 1.0], np.float32)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    C = np.array([[1.0, -1.0]])
+    lp = _lp_one_hidden(net, C[0], lo, hi, bounds)
+    pts = sample_box(lo, hi, 100_000, seed)
+    true_min = (O.forward(net, pts)[-1] @ C.T).min()
+    rng = np.random.default_rng(seed)
+    for _ in range(5):
+        alpha = [rng.uniform(0, 1, 8)]
+        assert O.spec_lower(net, 2, C, bounds, lo, hi, alpha, use_slack=False)[0] <= lp + 1e-9
+    assert lp <= true_min + 1e-9
+    best = _maximise(net, C, bounds, lo, hi, (), False)
+    assert best[0] <= lp + 1e-7
+    assert best[0] >= lp - 2e-3 * max(1.0, abs(lp))
+
+
+@pytest.mark.parametrize("seed", [41, 42])
+def test_lp_one_hidden_layer_with_splits(seed):
+    net = tiny_mlp([3, 8, 2], seed)
+    lo = np.array([-1.0, -1.0, -1.0], np.float32)
+    hi = np.array([1.0, 1.0, 1.0], np.float32)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    l, u = bounds[0]
+    unst = [j for j in range(8) if l[j] < 0 < u[j]]
+    splits = [(1, unst[0], 1), (1, unst[1], -1)]
+    C = np.array([[1.0, -1.0]])
+    lp = _lp_one_hidden(net, C[0], lo, hi, bounds, splits)
+    best = _maximise(net, C, bounds, lo, hi, splits, True)
+    assert best[0] <= lp + 1e-7
+    assert best[0] >= lp - 2e-3 * max(1.0, abs(lp))
+
+
+# ---------------------------------------------------------------------------- adjoint
+def _fd_check(net, C, bounds, lo, hi, splits, n_coord=32, seed=0):
+    rng = np.random.default_rng(seed)
+    L = len(net)
+    alpha = [rng.uniform(0.05, 0.95, len(l)) for (l, _) in bounds]
+    beta = rng.uniform(0.05, 1.0, size=(len(splits), C.shape[0])) if splits else None
+    gbar = rng.uniform(0.5, 1.5, C.shape[0])
+    _, ga, gb = O.spec_lower_grad(net, L, C, bounds, lo, hi, alpha, splits, beta, gbar)
+
+    def val(al, be):
+        return float(gbar @ O.spec_lower(net, L, C, bounds, lo, hi, al, splits, be,
+                                         use_slack=False))
+
+    coords = []
+    cb, _ = O.clamp_splits(bounds, splits)
+    for m, (l, u) in enumerate(cb):
+        for j in np.nonzero((l < 0) & (u > 0))[0]:
+            coords.append(("a", m, int(j)))
+    if splits:
+        for q in range(len(splits)):
+            for r in range(C.shape[0]):
+                coords.append(("b", q, r))
+    pick = rng.choice(len(coords), size=min(n_coord, len(coords)), replace=False)
+    h = 1e-6
+    n_alpha_nonzero = 0
+    for i in pick:
+        kind, a, b = coords[i]
+        if kind == "a":
+            ap = [x.copy() for x in alpha]; am = [x.copy() for x in alpha]
+            ap[a][b] += h; am[a][b] -= h
+            fd = (val(ap, beta) - val(am, beta)) / (2 * h)
+            an = ga[a][b]
+            n_alpha_nonzero += an != 0
+        else:
+            bp = beta.copy(); bm = beta.copy()
+            bp[a, b] += h; bm[a, b] -= h
+            fd = (val(alpha, bp) - val(alpha, bm)) / (2 * h)
+            an = gb[a, b]
+        assert an == pytest.approx(fd, rel=1e-5, abs=1e-6 * (1 + abs(fd))), (kind, a, b)
+    return n_alpha_nonzero
+
+
+def test_adjoint_fd_mlp():
+    net = tiny_mlp([5, 12, 12, 12, 4], 51)
+    lo, hi = W.linf_box(W.uniform_inputs(1, 5, 52)[0], 0.3)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    C = np.array([[1.0, -1.0, 0, 0], [1.0, 0, -1.0, 0], [1.0, 0, 0, -1.0]])
+    assert _fd_check(net, C, bounds, lo, hi, ()) > 0
+
+
+def test_adjoint_fd_mlp_splits():
+    net = tiny_mlp([5, 12, 12, 12, 4], 53)
+    lo, hi = W.linf_box(W.uniform_inputs(1, 5, 54)[0], 0.3)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    unst = [(m + 1, j) for m, (l, u) in enumerate(bounds) for j in range(len(l))
+            if l[j] < 0 < u[j]]
+    splits = [(unst[0][0], unst[0][1], 1), (unst[3][0], unst[3][1], -1),
+              (unst[-1][0], unst[-1][1], 1)]
+    C = np.array([[1.0, -1.0, 0, 0], [1.0, 0, -1.0, 0], [1.0, 0, 0, -1.0]])
+    _fd_check(net, C, bounds, lo, hi, splits, n_coord=32, seed=1)
+
+
+def test_adjoint_fd_cnn():
+    net = W.cnn(seed=55, in_shape=(2, 8, 8), spec=[(3, 3, 1), (4, 4, 2)], fc=(16, 3))
+    lo, hi = W.linf_box(W.uniform_inputs(1, 128, 56)[0], 0.1)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    unst = [(m + 1, j) for m, (l, u) in enumerate(bounds) for j in range(len(l))
+            if l[j] < 0 < u[j]]
+    splits = [(unst[1][0], unst[1][1], -1), (unst[-2][0], unst[-2][1], 1)]
+    C = np.array([[1.0, -1.0, 0], [0, 1.0, -1.0]])
+    assert _fd_check(net, C, bounds, lo, hi, splits, n_coord=32, seed=2) > 0
+
+
+# ------------------------------------------------------------------------------- Adam
+def test_adam_matches_torch():
+    rng = np.random.default_rng(61)
+    p0 = rng.uniform(0, 1, 20)
+    grads = [rng.normal(size=20) for _ in range(5)]
+    tp = torch.tensor(p0.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=0.1)
+    p, m, v = p0.copy(), np.zeros(20), np.zeros(20)
+    for t, g in enumerate(grads, start=1):
+        opt.zero_grad()
+        tp.grad = torch.tensor(g)
+        opt.step()
+        p, m, v = O.adam_step(p, g, m, v, t, 0.1)
+    np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+# ------------------------------------------------------------------------ IBP relation
+@pytest.mark.parametrize("seed", [71, 72, 73])
+def test_crown_alpha0_not_looser_than_ibp_one_hidden(seed):
+    net = tiny_mlp([6, 20, 5], seed)
+    lo, hi = W.linf_box(W.uniform_inputs(1, 6, seed)[0], 0.2)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    ib = O.ibp(net, lo, hi)
+    np.testing.assert_allclose(bounds[0][0], ib[0][0], rtol=1e-12, atol=1e-12)
+    alpha = [np.zeros(20)]
+    C = np.eye(5)
+    low = O.spec_lower(net, 2, C, bounds, lo, hi, alpha, use_slack=False)
+    up = -O.spec_lower(net, 2, -C, bounds, lo, hi, alpha, use_slack=False)
+    assert np.all(low >= ib[1][0] - 1e-12)
+    assert np.all(up <= ib[1][1] + 1e-12)
+
+
+def test_slack_is_outward_and_small():
+    net = tiny_mlp([4, 9, 9, 3], 81)
+    lo, hi = W.linf_box(W.uniform_inputs(1, 4, 82)[0], 0.1)
+    b_raw = O.crown_bounds(net, lo, hi, use_slack=False)
+    b_sl = O.crown_bounds(net, lo, hi, use_slack=True)
+    for (l0, u0), (l1, u1) in zip(b_raw, b_sl):
+        assert np.all(l1 <= l0) and np.all(u1 >= u0)
+        assert np.all(l0 - l1 <= 1e-4 * (1 + np.abs(l0)))
