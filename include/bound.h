@@ -1,0 +1,196 @@
+/*
+ * bound.h -- C ABI of the MI355X (gfx950) CROWN / alpha / beta bound-propagation library.
+ *
+ * The library computes the linear lower bound of Theorem 1 of the paper's Appendix B
+ * (CROWN backward propagation through Linear / Conv2d layers and the ReLU relaxation
+ * of Lemma 1), concretised over an input box by Theorem 2, for many instances
+ * (inputs or branch-and-bound subdomains) at once.  It also evaluates the gradient of
+ * that bound with respect to the free lower slopes alpha (Lemma 1) and the Lagrange
+ * multipliers beta of ReLU split constraints, and performs the projected Adam step
+ * that optimises them.
+ *
+ * Network: z_m = W_m h_{m-1} + b_m, h_m = ReLU(z_m) for m < L, h_0 = x (the
+ * verification problem of Appendix B).  Neuron order inside a layer is C-major
+ * (channel, row, column), as PyTorch flattens NCHW tensors.
+ *
+ * Conventions for every call:
+ *  - All tensors are float32 (split indices int32, split signs int8), contiguous and
+ *    row-major, and live in device memory unless a parameter says "host".
+ *  - The caller owns every pointer it passes.  The library keeps none of them past the
+ *    call, except the layer weights and biases handed to bound_init, which must stay
+ *    valid until bound_destroy.
+ *  - Work is enqueued asynchronously on the HIP stream passed in (NULL = the default
+ *    stream).  Argument and shape errors are returned synchronously; a device-side
+ *    failure is reported as BOUND_E_HIP by the call that observes it.
+ *  - bound_last_error() returns a message for the last non-OK status of the calling
+ *    thread.
+ */
+#ifndef BOUND_H
+#define BOUND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BOUND_OK = 0,
+    BOUND_E_ARG = -1,    /* null / inconsistent argument */
+    BOUND_E_SHAPE = -2,  /* layer chain or tensor shapes do not fit together */
+    BOUND_E_NOMEM = -3,  /* request exceeds the workspace sized at bound_init */
+    BOUND_E_HIP = -4,    /* a HIP runtime call failed */
+    BOUND_E_STATE = -5   /* call order violated (e.g. bound_grad with no saved pass) */
+} bound_status;
+
+enum { BOUND_LINEAR = 0, BOUND_CONV2D = 1 };
+
+/* Pass flags. */
+enum {
+    BOUND_SAVE_FOR_GRAD = 1, /* keep the pre-relaxation coefficients for bound_grad */
+    BOUND_NO_SLACK = 2,      /* report the raw bound without the FP32 rounding allowance */
+    BOUND_BOTH_SIDES = 4     /* also upper bounds: rows [spec; -spec], upper = -lower(-spec) */
+};
+
+typedef struct bound_net bound_net; /* opaque, owned by the library */
+
+/* One layer z = W h + b.  A ReLU follows every layer except the last.
+ * Linear : weight [out_c, in_c] (in_c = in_c*in_h*in_w of a conv-shaped input,
+ *          C-major), bias [out_c]; in_h = in_w = out_h = out_w = 1 unless the
+ *          input is the flattened output of a conv layer (then in_c/in_h/in_w give
+ *          that shape and the weight has in_c*in_h*in_w columns).
+ * Conv2d : weight [out_c, in_c, kh, kw], bias [out_c]; square kernel (kh == kw),
+ *          symmetric zero padding `pad`, stride `stride`;
+ *          out_h = (in_h + 2 pad - kh) / stride + 1 (likewise out_w). */
+typedef struct {
+    int32_t kind;
+    int32_t in_c, in_h, in_w;
+    int32_t out_c, out_h, out_w;
+    int32_t kh, kw, stride, pad;
+    const float *weight;
+    const float *bias;
+} bound_layer;
+
+/* One bound pass: lower bounds of spec rows applied to z_target, for n_inst instances.
+ * Let d_m = width of z_m, n_relu = d_1 + ... + d_{L-1}, relu_off(m) = d_1+...+d_{m-1}.
+ *
+ * spec      [n_inst, rows, d_target] coefficient rows (Theorem 1's A(L), generalised
+ *           from I to a specification matrix), or NULL for the identity: rows must
+ *           equal d_target and row r bounds neuron r of z_target (intermediate bounds).
+ * lo, hi    [n_bounds, n_relu] pre-activation bounds (l, u of Lemma 1) of the ReLU
+ *           layers; only layers 1 .. target-1 are read.
+ * bound_of  [n_inst] row of lo/hi used by each instance (subdomains of one root share
+ *           it), or NULL: instance i uses row i.  Rows outside [0, n_bounds) are
+ *           clamped into it (the caller's arrays are never read out of range).
+ * alpha     [n_inst, n_relu] lower relaxation slopes in [0, 1] (read at unstable
+ *           neurons only), or NULL for the rule alpha = 1 if u >= -l else 0.
+ * split_off [n_inst + 1], split_idx [nnz], split_sign [nnz]: CSR list of split
+ *           constraints sign * z_j >= 0 (j a global ReLU index: relu_off(m) + neuron);
+ *           each neuron at most once per instance.  A split clamps l or u to 0; an
+ *           instance whose clamped box is empty gets lower = +inf (upper = -inf).
+ *           All three NULL and nnz = 0 when there are no splits.
+ * beta      [nnz, rows] Lagrange multipliers (>= 0) of the splits, or NULL (= 0):
+ *           each adds -beta * sign to the coefficient of its split neuron.
+ * x_lo,x_hi [n_inst, d_0] the input box.  NULL: do not concretise; the pass then
+ *           writes the coefficient form (bound_out.coeff / offset / offset_mag).
+ * flags     BOUND_SAVE_FOR_GRAD (requires an explicit spec, no BOTH_SIDES, and
+ *           n_inst*rows <= max_save_rows), BOUND_NO_SLACK, BOUND_BOTH_SIDES (not
+ *           with beta). */
+typedef struct {
+    int32_t n_inst;
+    int32_t rows;
+    int32_t target;
+    int32_t n_bounds;
+    const float *spec;
+    const float *lo;
+    const float *hi;
+    const int32_t *bound_of;
+    const float *alpha;
+    const int32_t *split_off;
+    const int32_t *split_idx;
+    const int8_t *split_sign;
+    int32_t nnz;
+    const float *beta;
+    const float *x_lo;
+    const float *x_hi;
+    int32_t flags;
+} bound_pass;
+
+/* Outputs of a pass.
+ * lower  [n_inst, ld] lower bound of spec row r at lower[i*ld + r];
+ * upper  same layout (BOTH_SIDES only, else may be NULL);
+ * ld     row stride of lower/upper in elements (0 = rows);
+ * coeff  [n_inst*rows(*2 with BOTH_SIDES), d_0] coefficients W~(1) on x (Theorem 1),
+ * offset [n_inst*rows(*2)] the offsets b~(1), offset_mag [...] the sum of |terms| of
+ *        b~(1) (for the rounding allowance) -- written only when x_lo == NULL;
+ * best   [n_inst, ld] or NULL: updated to max(best, lower) (every alpha in [0, 1] and
+ *        beta >= 0 gives a valid bound, so the best over optimisation steps is kept). */
+typedef struct {
+    float *lower;
+    float *upper;
+    int64_t ld;
+    float *coeff;
+    float *offset;
+    float *offset_mag;
+    float *best;
+} bound_out;
+
+/* Create a network handle.  Validates the layer chain, packs the weights for the
+ * gfx950 kernels and allocates the workspace:
+ *  max_inst      most instances in one pass;
+ *  max_rows      most coefficient rows (instances x rows, x2 with BOTH_SIDES) held at
+ *                once; larger passes without SAVE_FOR_GRAD are processed in chunks;
+ *  max_save_rows most rows of a SAVE_FOR_GRAD pass (0 = no gradient support).
+ * stream is used for the packing kernels; the call returns after they finish. */
+bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max_inst,
+                        int64_t max_rows, int64_t max_save_rows, void *stream,
+                        bound_net **out);
+
+/* Widths d_0 .. d_L into d (host, n_layers + 1 entries) and n_relu into *n_relu. */
+bound_status bound_dims(const bound_net *net, int32_t *n_layers, int32_t *d, int32_t *n_relu);
+
+/* Backward bound pass (Theorem 1 with Lemma 1's relaxation, the split multipliers,
+ * and Theorem 2's concretisation fused into the last layer).  With
+ * BOUND_SAVE_FOR_GRAD the state needed by bound_grad is kept in the workspace until
+ * the next bound_backward call on the same handle (any pass invalidates it). */
+bound_status bound_backward(bound_net *net, const bound_pass *pass, const bound_out *out,
+                            void *stream);
+
+/* Standalone concretisation (Theorem 2 for a box) of coefficient rows:
+ * lower[i*rows + r] = coeff[i,r,:] . c - |coeff[i,r,:]| . rad + offset[i,r]
+ *                     - (unless BOUND_NO_SLACK) 64 * 2^-24 * (|coeff| . (|c| + rad)
+ *                                                           + offset_mag[i,r])
+ * with c = (x_lo + x_hi) / 2, rad = (x_hi - x_lo) / 2 per instance i.
+ * coeff [n_inst, rows, d0]; offset, offset_mag [n_inst, rows] (offset_mag may be
+ * NULL = 0); x_lo, x_hi [n_inst, d0]; lower [n_inst, rows]. */
+bound_status bound_concretize(int32_t n_inst, int32_t rows, int32_t d0, const float *coeff,
+                              const float *offset, const float *offset_mag,
+                              const float *x_lo, const float *x_hi, int32_t flags,
+                              float *lower, void *stream);
+
+/* Gradient of sum_{i,r} grad_lower[i,r] * lower_raw[i,r] of the last SAVE_FOR_GRAD
+ * pass (the raw bound, i.e. without the rounding allowance; intermediate bounds held
+ * fixed) with respect to alpha and beta:
+ * grad_alpha [n_inst, n_relu] (overwritten; zero outside unstable, unsplit neurons of
+ * layers 1 .. target-1), grad_beta [nnz, rows] (overwritten; may be NULL).
+ * Infeasible instances get zero gradients. */
+bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alpha,
+                        float *grad_beta, void *stream);
+
+/* One Adam step (PyTorch's bias-corrected form) on n parameters, minimising a loss
+ * whose gradient is grad_scale * grad, then clipping to [clip_lo, clip_hi]:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps);  p = clip(p).
+ * step is 1-based.  Used to maximise the bound (grad_scale = -1) over alpha in [0,1]
+ * and beta in [0, inf). */
+bound_status bound_adam(int64_t n, float *param, const float *grad, float *m, float *v,
+                        int32_t step, float lr, float b1, float b2, float eps,
+                        float grad_scale, float clip_lo, float clip_hi, void *stream);
+
+void bound_destroy(bound_net *net);
+const char *bound_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BOUND_H */

@@ -1,0 +1,166 @@
+"""ctypes binding of include/bound.h: the same entry points, argument marshalling only.
+
+Every function takes torch tensors (device memory from PyTorch) and hands their data
+pointers and the current HIP stream to libbound.so; all arithmetic runs in the
+library's gfx950 kernels.  The library must be built in-tree (``build.py``); there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbound.so")
+
+BOUND_OK, BOUND_E_ARG, BOUND_E_SHAPE, BOUND_E_NOMEM, BOUND_E_HIP, BOUND_E_STATE = 0, -1, -2, -3, -4, -5
+BOUND_LINEAR, BOUND_CONV2D = 0, 1
+BOUND_SAVE_FOR_GRAD, BOUND_NO_SLACK, BOUND_BOTH_SIDES = 1, 2, 4
+
+EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "bound_grad",
+            "bound_adam", "bound_destroy", "bound_last_error")
+
+_p = ctypes.c_void_p
+
+
+class BoundLayer(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("in_c", ctypes.c_int32), ("in_h", ctypes.c_int32),
+                ("in_w", ctypes.c_int32), ("out_c", ctypes.c_int32), ("out_h", ctypes.c_int32),
+                ("out_w", ctypes.c_int32), ("kh", ctypes.c_int32), ("kw", ctypes.c_int32),
+                ("stride", ctypes.c_int32), ("pad", ctypes.c_int32), ("weight", _p), ("bias", _p)]
+
+
+class BoundPass(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int32), ("rows", ctypes.c_int32), ("target", ctypes.c_int32),
+                ("n_bounds", ctypes.c_int32), ("spec", _p), ("lo", _p), ("hi", _p),
+                ("bound_of", _p), ("alpha", _p), ("split_off", _p), ("split_idx", _p),
+                ("split_sign", _p), ("nnz", ctypes.c_int32), ("beta", _p), ("x_lo", _p),
+                ("x_hi", _p), ("flags", ctypes.c_int32)]
+
+
+class BoundOut(ctypes.Structure):
+    _fields_ = [("lower", _p), ("upper", _p), ("ld", ctypes.c_int64), ("coeff", _p),
+                ("offset", _p), ("offset_mag", _p), ("best", _p)]
+
+
+class BoundError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_LIB = None
+
+
+def lib():
+    """Load libbound.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.bound_init.argtypes = [ctypes.POINTER(BoundLayer), ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int64, ctypes.c_int64, _p, ctypes.POINTER(_p)]
+        L.bound_dims.argtypes = [_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_int32)]
+        L.bound_backward.argtypes = [_p, ctypes.POINTER(BoundPass), ctypes.POINTER(BoundOut), _p]
+        L.bound_concretize.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _p, _p, _p,
+                                       _p, _p, ctypes.c_int32, _p, _p]
+        L.bound_grad.argtypes = [_p, _p, _p, _p, _p]
+        L.bound_adam.argtypes = [ctypes.c_int64, _p, _p, _p, _p, ctypes.c_int32, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, _p]
+        L.bound_destroy.argtypes = [_p]
+        L.bound_destroy.restype = None
+        L.bound_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED[:-2]:
+            getattr(L, name).restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(status):
+    if status != BOUND_OK:
+        raise BoundError(status, lib().bound_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------- entry points
+def bound_init(layers, max_inst, max_rows, max_save_rows=0, stream=None):
+    """layers: list of dicts with kind/in_shape/out_shape/(stride, pad) and device
+    tensors W, b (kept alive by the caller).  Returns an opaque handle."""
+    arr = (BoundLayer * len(layers))()
+    for i, L in enumerate(layers):
+        W, b = L["W"], L["b"]
+        if L["kind"] == "conv":
+            ci, hi, wi = L["in_shape"]
+            co, ho, wo = L["out_shape"]
+            arr[i] = BoundLayer(BOUND_CONV2D, ci, hi, wi, co, ho, wo, W.shape[2], W.shape[3],
+                                L["stride"], L["pad"], W.data_ptr(), b.data_ptr())
+        else:
+            ishape = tuple(L.get("in_view", L["in_shape"]))
+            ci, hi, wi = (ishape + (1, 1))[:3] if len(ishape) == 1 else ishape
+            arr[i] = BoundLayer(BOUND_LINEAR, ci, hi, wi, L["out_shape"][0], 1, 1, 1, 1, 1, 0,
+                                W.data_ptr(), b.data_ptr())
+    h = _p()
+    _check(lib().bound_init(arr, len(layers), int(max_inst), int(max_rows), int(max_save_rows),
+                            _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def bound_dims(handle, n_layers_max=32):
+    n = ctypes.c_int32()
+    d = (ctypes.c_int32 * (n_layers_max + 1))()
+    nr = ctypes.c_int32()
+    _check(lib().bound_dims(handle, ctypes.byref(n), d, ctypes.byref(nr)))
+    return [d[i] for i in range(n.value + 1)], nr.value
+
+
+def bound_backward(handle, n_inst, rows, target, *, spec=None, lo=None, hi=None, n_bounds=0,
+                   bound_of=None, alpha=None, split_off=None, split_idx=None, split_sign=None,
+                   nnz=0, beta=None, x_lo=None, x_hi=None, flags=0, lower=None, upper=None,
+                   ld=0, coeff=None, offset=None, offset_mag=None, best=None, stream=None):
+    P = BoundPass(int(n_inst), int(rows), int(target), int(n_bounds), _ptr(spec), _ptr(lo), _ptr(hi),
+                  _ptr(bound_of), _ptr(alpha), _ptr(split_off), _ptr(split_idx), _ptr(split_sign),
+                  int(nnz), _ptr(beta), _ptr(x_lo), _ptr(x_hi), int(flags))
+    O = BoundOut(_ptr(lower), _ptr(upper), int(ld), _ptr(coeff), _ptr(offset), _ptr(offset_mag),
+                 _ptr(best))
+    _check(lib().bound_backward(handle, ctypes.byref(P), ctypes.byref(O), _stream(stream)))
+
+
+def bound_concretize(n_inst, rows, d0, coeff, offset, offset_mag, x_lo, x_hi, flags, lower,
+                     stream=None):
+    _check(lib().bound_concretize(int(n_inst), int(rows), int(d0), _ptr(coeff), _ptr(offset),
+                                  _ptr(offset_mag), _ptr(x_lo), _ptr(x_hi), int(flags), _ptr(lower),
+                                  _stream(stream)))
+
+
+def bound_grad(handle, grad_lower, grad_alpha, grad_beta=None, stream=None):
+    _check(lib().bound_grad(handle, _ptr(grad_lower), _ptr(grad_alpha), _ptr(grad_beta),
+                            _stream(stream)))
+
+
+def bound_adam(param, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8, grad_scale=1.0,
+               clip_lo=-float("inf"), clip_hi=float("inf"), stream=None):
+    _check(lib().bound_adam(param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), int(step),
+                            float(lr), float(b1), float(b2), float(eps), float(grad_scale),
+                            float(clip_lo), float(clip_hi), _stream(stream)))
+
+
+def bound_destroy(handle):
+    if handle:
+        lib().bound_destroy(handle)
+
+
+def bound_last_error():
+    return lib().bound_last_error().decode()

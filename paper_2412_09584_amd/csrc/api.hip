@@ -1,0 +1,529 @@
+// Host side of the C ABI declared in include/bound.h: layer validation, weight packing,
+// workspace management, the layer-by-layer schedule of a backward bound pass (Theorem 1
+// with Lemma 1 and Theorem 2 of the paper's Appendix B), its adjoint, and Adam.
+#include "../../include/bound.h"
+#include "bound_internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace bp;
+
+namespace {
+
+thread_local std::string g_err;
+
+bound_status fail(bound_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            return fail(BOUND_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));      \
+    } while (0)
+
+inline long roundup(long x, long m) { return (x + m - 1) / m * m; }
+
+struct LayerInfo {
+    bound_layer L;
+    long din, dout;
+    GeomSet gT;  // backward product Lambda W (transposed convolution for Conv2d)
+    GeomSet gF;  // forward product (adjoint pass)
+};
+
+}  // namespace
+
+struct bound_net {
+    int n_layers = 0;
+    std::vector<LayerInfo> layers;   // index 0 = layer 1
+    std::vector<long> d;             // d_0 .. d_L
+    long n_relu = 0;
+    NetShapes ns{};                  // ReLU layers z_1 .. z_{L-1}
+    int C0 = 0, HW0 = 0;             // input shape
+    int max_inst = 0;
+    long max_rows = 0, max_save_rows = 0, max_d = 0;
+    std::vector<void *> allocs;
+    float *buf[2] = {nullptr, nullptr};
+    float *acc_s = nullptr, *acc_mag = nullptr, *acc_low = nullptr;
+    Relax *tab = nullptr;
+    int32_t *infeas = nullptr;
+    float *cen = nullptr, *rad = nullptr;
+    float *save = nullptr;
+    float *sbar = nullptr;
+    int32_t *sp = nullptr;           // 3 x sp_cap: instance, layer, internal index
+    int8_t *sp_sign = nullptr;
+    long sp_cap = 0;
+    // state of the last SAVE_FOR_GRAD pass
+    bool saved = false;
+    int s_target = 0, s_rows = 0, s_n_inst = 0, s_nnz = 0;
+    std::vector<long> s_off;         // offset of saved G_m (m = 1..k) in the save buffer
+
+    ~bound_net() {
+        for (void *p : allocs) hipFree(p);
+    }
+    template <class T> bool alloc(T **p, long n) {
+        void *q = nullptr;
+        if (n <= 0) n = 1;
+        if (hipMalloc(&q, sizeof(T) * (size_t)n) != hipSuccess) return false;
+        allocs.push_back(q);
+        *p = (T *)q;
+        return true;
+    }
+    const float *bias(int m) const { return layers[m - 1].L.bias; }        // b_m
+    int chan(int m) const { return layers[m - 1].L.out_c; }                // channels of z_m
+    long relu_off(int m) const { return ns.l[m - 1].off; }                 // offset of z_m
+};
+
+namespace {
+
+bound_status build_geoms(bound_net *net, hipStream_t st) {
+    for (int i = 0; i < net->n_layers; ++i) {
+        LayerInfo &li = net->layers[i];
+        const bound_layer &L = li.L;
+        if (L.kind == BOUND_LINEAR) {
+            Geom t{};
+            t.H = t.W = 1; t.C = (int)li.dout; t.OH = t.OW = 1; t.kh = t.kw = 1; t.stride = 1;
+            t.K = (int)li.dout; t.N = (int)li.din; t.Kp = (int)roundup(li.dout, 16);
+            t.DH = t.DW = 1; t.ostr = 1;
+            const long NpT = roundup(li.din, 128);
+            float *bt;
+            if (!net->alloc(&bt, NpT * t.Kp)) return fail(BOUND_E_NOMEM, "weight packing");
+            HIPCHK(launch_pack_T(L.weight, 0, L.in_c, L.in_h, L.in_w, L.out_c, 1, 1, 1, 1, 1, 0, 0, 0,
+                                 0, 0, 1, 1, t.N, t.K, t.Kp, (int)NpT, bt, st));
+            t.Bt = bt;
+            li.gT.g[0] = t; li.gT.n = 1;
+
+            Geom f{};
+            f.H = f.W = 1; f.C = (int)li.din; f.OH = f.OW = 1; f.kh = f.kw = 1; f.stride = 1;
+            f.K = (int)li.din; f.N = (int)li.dout; f.Kp = (int)roundup(li.din, 16);
+            f.DH = f.DW = 1; f.ostr = 1;
+            const long NpF = roundup(li.dout, 128);
+            float *bf;
+            if (!net->alloc(&bf, NpF * f.Kp)) return fail(BOUND_E_NOMEM, "weight packing");
+            HIPCHK(launch_pack_F(L.weight, 0, L.in_c, L.in_h, L.in_w, L.out_c, 1, 1, f.N, f.K, f.Kp,
+                                 (int)NpF, bf, st));
+            f.Bt = bf;
+            li.gF.g[0] = f; li.gF.n = 1;
+        } else {
+            // forward convolution (adjoint)
+            Geom f{};
+            f.H = L.in_h; f.W = L.in_w; f.C = L.in_c; f.OH = L.out_h; f.OW = L.out_w;
+            f.kh = L.kh; f.kw = L.kw; f.stride = L.stride; f.pad_y = f.pad_x = L.pad;
+            f.K = L.kh * L.kw * L.in_c; f.N = L.out_c; f.Kp = (int)roundup(f.K, 16);
+            f.DH = L.out_h; f.DW = L.out_w; f.ostr = 1;
+            const long NpF = roundup(f.N, 128);
+            float *bf;
+            if (!net->alloc(&bf, NpF * f.Kp)) return fail(BOUND_E_NOMEM, "weight packing");
+            HIPCHK(launch_pack_F(L.weight, 1, L.in_c, L.in_h, L.in_w, L.out_c, L.kh, L.kw, f.N, f.K,
+                                 f.Kp, (int)NpF, bf, st));
+            f.Bt = bf;
+            li.gF.g[0] = f; li.gF.n = 1;
+            // transposed convolution, one stride-1 implicit GEMM per output phase
+            const int s = L.stride;
+            int np = 0;
+            for (int py = 0; py < s; ++py) {
+                for (int px = 0; px < s; ++px) {
+                    const int ky0 = (py + L.pad) % s, kx0 = (px + L.pad) % s;
+                    const int Ty = ky0 < L.kh ? (L.kh - ky0 + s - 1) / s : 0;
+                    const int Tx = kx0 < L.kw ? (L.kw - kx0 + s - 1) / s : 0;
+                    const int Ay = (L.in_h - py + s - 1) / s, Ax = (L.in_w - px + s - 1) / s;
+                    if (Ay <= 0 || Ax <= 0) continue;
+                    const int dy = (py + L.pad - ky0) / s, dx = (px + L.pad - kx0) / s;
+                    Geom t{};
+                    t.H = L.out_h; t.W = L.out_w; t.C = L.out_c;
+                    t.OH = Ay; t.OW = Ax;
+                    t.kh = Ty; t.kw = Tx; t.stride = 1;
+                    t.pad_y = Ty - 1 - dy; t.pad_x = Tx - 1 - dx;
+                    t.K = Ty * Tx * L.out_c; t.N = L.in_c; t.Kp = (int)roundup(t.K > 0 ? t.K : 1, 16);
+                    t.DH = L.in_h; t.DW = L.in_w; t.ostr = s; t.oy0 = py; t.ox0 = px;
+                    const long NpT = roundup(t.N, 128);
+                    float *bt;
+                    if (!net->alloc(&bt, NpT * t.Kp)) return fail(BOUND_E_NOMEM, "weight packing");
+                    HIPCHK(launch_pack_T(L.weight, 1, L.in_c, L.in_h, L.in_w, L.out_c, L.out_h,
+                                         L.out_w, L.kh, L.kw, s, L.pad, py, px, ky0, kx0, Ty, Tx,
+                                         t.N, t.K, t.Kp, (int)NpT, bt, st));
+                    t.Bt = bt;
+                    li.gT.g[np++] = t;
+                }
+            }
+            li.gT.n = np;
+        }
+    }
+    return BOUND_OK;
+}
+
+bound_status ensure_split_cap(bound_net *net, long nnz, hipStream_t st) {
+    if (nnz <= net->sp_cap) return BOUND_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return fail(BOUND_E_NOMEM, "split list larger than any earlier pass while the stream is "
+                                   "being captured; run one pass of this size before capturing");
+    const long cap = roundup(nnz, 4096);
+    int32_t *sp;
+    int8_t *sg;
+    if (!net->alloc(&sp, 3 * cap) || !net->alloc(&sg, cap))
+        return fail(BOUND_E_NOMEM, "split scratch");
+    net->sp = sp;
+    net->sp_sign = sg;
+    net->sp_cap = cap;
+    return BOUND_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bound_last_error(void) { return g_err.c_str(); }
+
+bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max_inst,
+                        int64_t max_rows, int64_t max_save_rows, void *stream, bound_net **out) {
+    if (!layers || !out || n_layers < 1 || n_layers > 17 || max_inst < 1 || max_rows < 1 ||
+        max_save_rows < 0 || max_save_rows > max_rows)
+        return fail(BOUND_E_ARG, "bound_init: bad arguments (need 1 <= n_layers <= 17, "
+                                 "max_inst >= 1, 0 <= max_save_rows <= max_rows)");
+    *out = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    auto *net = new bound_net();
+    net->n_layers = n_layers;
+    net->max_inst = max_inst;
+    net->max_rows = max_rows;
+    net->max_save_rows = max_save_rows;
+    net->layers.resize(n_layers);
+    for (int i = 0; i < n_layers; ++i) {
+        const bound_layer &L = layers[i];
+        LayerInfo &li = net->layers[i];
+        li.L = L;
+        if (!L.weight || !L.bias) {
+            delete net;
+            return fail(BOUND_E_ARG, "layer " + std::to_string(i + 1) + ": null weight or bias");
+        }
+        if (L.kind == BOUND_LINEAR) {
+            if (L.in_c < 1 || L.in_h < 1 || L.in_w < 1 || L.out_c < 1 || L.out_h != 1 || L.out_w != 1) {
+                delete net;
+                return fail(BOUND_E_SHAPE, "linear layer " + std::to_string(i + 1) + ": bad shape");
+            }
+        } else if (L.kind == BOUND_CONV2D) {
+            const bool ok = L.in_c >= 1 && L.in_h >= 1 && L.in_w >= 1 && L.out_c >= 1 &&
+                            L.kh >= 1 && L.kh == L.kw && L.stride >= 1 && L.stride <= 2 &&
+                            L.pad >= 0 && L.out_h == (L.in_h + 2 * L.pad - L.kh) / L.stride + 1 &&
+                            L.out_w == (L.in_w + 2 * L.pad - L.kw) / L.stride + 1 && L.out_h >= 1 &&
+                            L.out_w >= 1;
+            if (!ok) {
+                delete net;
+                return fail(BOUND_E_SHAPE, "conv layer " + std::to_string(i + 1) +
+                                               ": bad shape (square kernel, stride 1 or 2, "
+                                               "out = (in + 2 pad - k) / stride + 1)");
+            }
+        } else {
+            delete net;
+            return fail(BOUND_E_ARG, "layer " + std::to_string(i + 1) + ": unknown kind");
+        }
+        li.din = (long)L.in_c * L.in_h * L.in_w;
+        li.dout = (long)L.out_c * L.out_h * L.out_w;
+        if (i > 0) {
+            const bound_layer &P = layers[i - 1];
+            if (P.out_c != L.in_c || P.out_h != L.in_h || P.out_w != L.in_w) {
+                delete net;
+                return fail(BOUND_E_SHAPE, "layer " + std::to_string(i + 1) +
+                                               ": input shape differs from the output of layer " +
+                                               std::to_string(i));
+            }
+        }
+    }
+    if (n_layers - 1 > 16) {
+        delete net;
+        return fail(BOUND_E_ARG, "at most 16 ReLU layers");
+    }
+    net->d.push_back(net->layers[0].din);
+    for (auto &li : net->layers) net->d.push_back(li.dout);
+    net->C0 = layers[0].in_c;
+    net->HW0 = layers[0].in_h * layers[0].in_w;
+    net->ns.n = n_layers - 1;
+    long off = 0;
+    for (int t = 0; t < n_layers - 1; ++t) {
+        const bound_layer &L = layers[t];
+        net->ns.l[t].C = L.out_c;
+        net->ns.l[t].HW = L.out_h * L.out_w;
+        net->ns.l[t].off = off;
+        net->ns.l[t].d = net->d[t + 1];
+        off += net->d[t + 1];
+    }
+    net->n_relu = off;
+    net->max_d = 0;
+    for (long x : net->d) net->max_d = x > net->max_d ? x : net->max_d;
+
+    bool ok = net->alloc(&net->buf[0], max_rows * net->max_d) &&
+              net->alloc(&net->buf[1], max_rows * net->max_d) &&
+              net->alloc(&net->acc_s, max_rows) && net->alloc(&net->acc_mag, max_rows) &&
+              net->alloc(&net->acc_low, max_rows) &&
+              net->alloc(&net->tab, (long)max_inst * (net->n_relu > 0 ? net->n_relu : 1)) &&
+              net->alloc(&net->infeas, max_inst) && net->alloc(&net->cen, (long)max_inst * net->d[0]) &&
+              net->alloc(&net->rad, (long)max_inst * net->d[0]) &&
+              net->alloc(&net->sbar, max_save_rows > 0 ? max_save_rows : 1) &&
+              net->alloc(&net->save, max_save_rows * (net->d[0] + net->n_relu + net->d[n_layers - 1]));
+    if (!ok) {
+        delete net;
+        return fail(BOUND_E_NOMEM, "bound_init: workspace allocation failed");
+    }
+    bound_status s = ensure_split_cap(net, (long)max_inst * 16, st);
+    if (s != BOUND_OK) { delete net; return s; }
+    s = build_geoms(net, st);
+    if (s != BOUND_OK) { delete net; return s; }
+    hipError_t e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete net;
+        return fail(BOUND_E_HIP, std::string("bound_init: ") + hipGetErrorString(e));
+    }
+    *out = net;
+    return BOUND_OK;
+}
+
+bound_status bound_dims(const bound_net *net, int32_t *n_layers, int32_t *d, int32_t *n_relu) {
+    if (!net) return fail(BOUND_E_ARG, "bound_dims: null net");
+    if (n_layers) *n_layers = net->n_layers;
+    if (d)
+        for (size_t i = 0; i < net->d.size(); ++i) d[i] = (int32_t)net->d[i];
+    if (n_relu) *n_relu = (int32_t)net->n_relu;
+    return BOUND_OK;
+}
+
+bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out *out, void *stream) {
+    if (!net || !P || !out) return fail(BOUND_E_ARG, "bound_backward: null argument");
+    hipStream_t st = (hipStream_t)stream;
+    const int L = net->n_layers;
+    const int k = P->target;
+    if (k < 1 || k > L) return fail(BOUND_E_ARG, "target must be in 1..n_layers");
+    if (P->n_inst < 1 || P->n_inst > net->max_inst)
+        return fail(BOUND_E_NOMEM, "n_inst must be in 1..max_inst");
+    if (P->rows < 1) return fail(BOUND_E_ARG, "rows must be >= 1");
+    const bool ident = P->spec == nullptr;
+    const long dk = net->d[k];
+    if (ident && P->rows != dk) return fail(BOUND_E_SHAPE, "identity spec needs rows == d_target");
+    if (k > 1 && (!P->lo || !P->hi)) return fail(BOUND_E_ARG, "lo/hi required when target > 1");
+    if (k > 1 && P->n_bounds < (P->bound_of ? 1 : P->n_inst))
+        return fail(BOUND_E_ARG, "n_bounds too small");
+    const bool both = (P->flags & BOUND_BOTH_SIDES) != 0;
+    const bool save = (P->flags & BOUND_SAVE_FOR_GRAD) != 0;
+    const bool slack = (P->flags & BOUND_NO_SLACK) == 0;
+    const int nnz = P->nnz;
+    if (nnz < 0) return fail(BOUND_E_ARG, "nnz < 0");
+    if (nnz > 0 && (!P->split_off || !P->split_idx || !P->split_sign))
+        return fail(BOUND_E_ARG, "split arrays required when nnz > 0");
+    if (P->beta && nnz == 0) return fail(BOUND_E_ARG, "beta given without splits");
+    if (P->beta && both) return fail(BOUND_E_ARG, "beta cannot be combined with BOTH_SIDES");
+    if ((P->x_lo == nullptr) != (P->x_hi == nullptr)) return fail(BOUND_E_ARG, "x_lo/x_hi: both or neither");
+    const bool conc = P->x_lo != nullptr;
+    if (conc && !out->lower) return fail(BOUND_E_ARG, "lower output required");
+    if (conc && both && !out->upper) return fail(BOUND_E_ARG, "upper output required with BOTH_SIDES");
+    if (!conc && (!out->coeff || !out->offset))
+        return fail(BOUND_E_ARG, "coeff and offset outputs required without a box");
+    const int rpi = P->rows * (both ? 2 : 1);
+    const long total = (long)P->n_inst * rpi;
+    if (save) {
+        if (ident || both || !conc)
+            return fail(BOUND_E_ARG, "SAVE_FOR_GRAD needs an explicit spec, a box and no BOTH_SIDES");
+        if (total > net->max_save_rows) return fail(BOUND_E_NOMEM, "n_inst*rows > max_save_rows");
+    }
+    const long ld = out->ld > 0 ? out->ld : P->rows;
+    net->saved = false;
+
+    // Relaxation tables (Lemma 1) for z_1 .. z_{k-1}, split clamping, box.
+    const int used = k - 1;
+    if (used > 0) {
+        HIPCHK(launch_prep_tables(net->ns, used, P->n_inst, net->n_relu, P->lo, P->hi, P->bound_of,
+                                  P->alpha, net->tab, net->infeas, P->n_bounds, st));
+    } else {
+        HIPCHK(launch_fill((float *)net->infeas, P->n_inst, 0.f, st));
+    }
+    if (nnz > 0) {
+        bound_status s = ensure_split_cap(net, nnz, st);
+        if (s != BOUND_OK) return s;
+    }
+    int32_t *sp_inst = net->sp, *sp_layer = net->sp + net->sp_cap, *sp_j = net->sp + 2 * net->sp_cap;
+    if (nnz > 0 && used > 0) {
+        HIPCHK(launch_prep_splits(net->ns, used, P->n_inst, net->n_relu, P->lo, P->hi, P->bound_of,
+                                  P->split_off, P->split_idx, P->split_sign, net->tab, net->infeas,
+                                  sp_inst, sp_layer, sp_j, P->n_bounds, st));
+    }
+    const long d0 = net->d[0];
+    if (conc) {
+        HIPCHK(launch_prep_box(P->n_inst, net->C0, net->HW0, P->x_lo, P->x_hi, net->cen, net->rad, st));
+    } else {
+        HIPCHK(launch_fill(net->cen, (long)P->n_inst * d0, 0.f, st));
+        HIPCHK(launch_fill(net->rad, (long)P->n_inst * d0, 0.f, st));
+    }
+
+    const long chunk = save ? total : net->max_rows;
+    std::vector<long> soff(k + 2, 0);  // offset of saved G_m for m = 1..k
+    if (save) {
+        long o = 0;
+        for (int m = 1; m <= k; ++m) {
+            soff[m] = o;
+            o += total * net->d[m - 1];
+        }
+    }
+    const bool inject = P->beta != nullptr && used > 0;
+    for (long img0 = 0; img0 < total; img0 += chunk) {
+        const long n_img = total - img0 < chunk ? total - img0 : chunk;
+        float *cur = net->buf[0], *nxt = net->buf[1];
+        int m_start;
+        if (ident) {
+            const LayerInfo &li = net->layers[k - 1];
+            IdentityParams ip{};
+            ip.kind = li.L.kind;
+            ip.W = li.L.weight;
+            ip.bias_k = li.L.bias;
+            ip.ci = li.L.in_c; ip.hi_ = li.L.in_h; ip.wi = li.L.in_w;
+            ip.co = li.L.out_c; ip.ho = li.L.out_h; ip.wo = li.L.out_w;
+            ip.kh = li.L.kh; ip.kw = li.L.kw; ip.stride = li.L.stride; ip.pad = li.L.pad;
+            ip.dk = dk; ip.din = li.din; ip.rpi = rpi; ip.img0 = img0;
+            ip.s = net->acc_s; ip.mag = net->acc_mag; ip.low = net->acc_low;
+            if (k == 1) {
+                ip.cen = net->cen; ip.rad = net->rad;
+                ip.emit = conc ? nullptr : out->coeff + img0 * d0;
+                HIPCHK(launch_init_identity(ip, n_img, true, st));
+                m_start = 0;
+            } else {
+                ip.tab = net->tab + net->relu_off(k - 1);
+                ip.tab_ld = net->n_relu;
+                ip.bias_m = net->bias(k - 1);
+                ip.chan_m = net->chan(k - 1);
+                ip.out = cur;
+                HIPCHK(launch_init_identity(ip, n_img, false, st));
+                if (inject)
+                    HIPCHK(launch_beta_inject(nnz, P->rows, rpi, img0, n_img, k - 2, sp_inst, sp_layer,
+                                              sp_j, P->split_sign, P->beta, cur, net->d[k - 1],
+                                              net->bias(k - 1), net->chan(k - 1), net->acc_s,
+                                              net->acc_mag, st));
+                m_start = k - 1;
+            }
+        } else {
+            const bound_layer &Lk = net->layers[k - 1].L;
+            HIPCHK(launch_init_spec(img0, n_img, P->rows, rpi, P->spec, dk, Lk.out_c,
+                                    Lk.out_h * Lk.out_w, Lk.bias, cur, net->acc_s, net->acc_mag,
+                                    net->acc_low, st));
+            m_start = k;
+        }
+        for (int m = m_start; m >= 2; --m) {
+            RelaxParams rp{};
+            rp.out = nxt;
+            rp.save = save ? net->save + soff[m] : nullptr;
+            rp.tab = net->tab + net->relu_off(m - 1);
+            rp.tab_ld = net->n_relu;
+            rp.bias = net->bias(m - 1);
+            rp.chan = net->chan(m - 1);
+            rp.D = net->d[m - 1];
+            rp.s = net->acc_s;
+            rp.mag = net->acc_mag;
+            rp.img0 = img0;
+            rp.rpi = rpi;
+            HIPCHK(gemm_relax(net->layers[m - 1].gT, cur, n_img, rp, st));
+            if (inject)
+                HIPCHK(launch_beta_inject(nnz, P->rows, rpi, img0, n_img, m - 2, sp_inst, sp_layer, sp_j,
+                                          P->split_sign, P->beta, nxt, net->d[m - 1], net->bias(m - 1),
+                                          net->chan(m - 1), net->acc_s, net->acc_mag, st));
+            float *t = cur; cur = nxt; nxt = t;
+        }
+        if (m_start >= 1) {
+            ConcParams cp{};
+            cp.cen = net->cen; cp.rad = net->rad; cp.D = d0;
+            cp.low = net->acc_low; cp.mag = net->acc_mag;
+            cp.save = save ? net->save + soff[1] : nullptr;
+            cp.emit = conc ? nullptr : out->coeff + img0 * d0;
+            cp.chan = net->C0; cp.hw = net->HW0;
+            cp.img0 = img0; cp.rpi = rpi;
+            HIPCHK(gemm_conc(net->layers[0].gT, cur, n_img, cp, st));
+        }
+        HIPCHK(launch_finalize(img0, n_img, P->rows, rpi, net->acc_s, net->acc_low, net->acc_mag,
+                               net->infeas, slack, conc ? out->lower : nullptr,
+                               conc ? out->upper : nullptr, ld, conc ? nullptr : out->offset,
+                               conc ? nullptr : out->offset_mag, conc ? out->best : nullptr, st));
+    }
+    if (save) {
+        net->saved = true;
+        net->s_target = k;
+        net->s_rows = P->rows;
+        net->s_n_inst = P->n_inst;
+        net->s_nnz = used > 0 ? nnz : 0;
+        net->s_off = soff;
+        if (net->s_nnz > 0) {
+            HIPCHK(hipMemcpyAsync(net->sp_sign, P->split_sign, (size_t)nnz, hipMemcpyDeviceToDevice, st));
+        }
+    }
+    return BOUND_OK;
+}
+
+bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alpha,
+                        float *grad_beta, void *stream) {
+    if (!net || !grad_lower || !grad_alpha) return fail(BOUND_E_ARG, "bound_grad: null argument");
+    if (!net->saved) return fail(BOUND_E_STATE, "bound_grad: no SAVE_FOR_GRAD pass to differentiate");
+    hipStream_t st = (hipStream_t)stream;
+    const int k = net->s_target, rows = net->s_rows;
+    const long n_img = (long)net->s_n_inst * rows;
+    const long d0 = net->d[0];
+    HIPCHK(launch_fill(grad_alpha, (long)net->s_n_inst * net->n_relu, 0.f, st));
+    if (grad_beta && net->s_nnz > 0) HIPCHK(launch_fill(grad_beta, (long)net->s_nnz * rows, 0.f, st));
+    float *cur = net->buf[0], *nxt = net->buf[1];
+    HIPCHK(launch_adj_init(n_img, rows, d0, grad_lower, net->save + net->s_off[1], net->cen, net->rad,
+                           net->infeas, cur, net->sbar, st));
+    int32_t *sp_inst = net->sp, *sp_layer = net->sp + net->sp_cap, *sp_j = net->sp + 2 * net->sp_cap;
+    for (int m = 1; m <= k - 1; ++m) {
+        const LayerInfo &li = net->layers[m - 1];
+        AdjParams ap{};
+        ap.sbar = net->sbar;
+        ap.bias = li.L.bias;
+        ap.chan = li.L.out_c;
+        ap.D = net->d[m];
+        ap.gsave = net->save + net->s_off[m + 1];
+        ap.tab = net->tab + net->relu_off(m);
+        ap.tab_ld = net->n_relu;
+        ap.gout = m + 1 < k ? nxt : nullptr;
+        ap.galpha = grad_alpha;
+        ap.ga_ld = net->n_relu;
+        ap.ga_off = net->relu_off(m);
+        ap.hw = li.L.out_h * li.L.out_w;
+        ap.rpi = rows;
+        HIPCHK(gemm_adj(li.gF, cur, n_img, ap, st));
+        if (grad_beta && net->s_nnz > 0) {
+            BetaGradLayer bl{};
+            bl.kind = li.L.kind; bl.W = li.L.weight; bl.bias = li.L.bias;
+            bl.ci = li.L.in_c; bl.hi_ = li.L.in_h; bl.wi = li.L.in_w;
+            bl.co = li.L.out_c; bl.ho = li.L.out_h; bl.wo = li.L.out_w;
+            bl.kh = li.L.kh; bl.kw = li.L.kw; bl.stride = li.L.stride; bl.pad = li.L.pad;
+            bl.din = li.din; bl.dout = li.dout;
+            HIPCHK(launch_beta_grad(net->s_nnz, rows, m - 1, bl, sp_inst, sp_layer, sp_j, net->sp_sign,
+                                    cur, net->sbar, net->infeas, grad_beta, st));
+        }
+        float *t = cur; cur = nxt; nxt = t;
+    }
+    return BOUND_OK;
+}
+
+bound_status bound_concretize(int32_t n_inst, int32_t rows, int32_t d0, const float *coeff,
+                              const float *offset, const float *offset_mag, const float *x_lo,
+                              const float *x_hi, int32_t flags, float *lower, void *stream) {
+    if (n_inst < 0 || rows < 0 || d0 < 1 || !coeff || !offset || !x_lo || !x_hi || !lower)
+        return fail(BOUND_E_ARG, "bound_concretize: bad arguments");
+    HIPCHK(launch_concretize(n_inst, rows, d0, coeff, offset, offset_mag, x_lo, x_hi,
+                             (flags & BOUND_NO_SLACK) == 0, lower, (hipStream_t)stream));
+    return BOUND_OK;
+}
+
+bound_status bound_adam(int64_t n, float *param, const float *grad, float *m, float *v, int32_t step,
+                        float lr, float b1, float b2, float eps, float grad_scale, float clip_lo,
+                        float clip_hi, void *stream) {
+    if (n < 0 || (n > 0 && (!param || !grad || !m || !v)) || step < 1)
+        return fail(BOUND_E_ARG, "bound_adam: bad arguments");
+    HIPCHK(launch_adam(n, param, grad, m, v, step, lr, b1, b2, eps, grad_scale, clip_lo, clip_hi,
+                       (hipStream_t)stream));
+    return BOUND_OK;
+}
+
+void bound_destroy(bound_net *net) { delete net; }
+
+}  // extern "C"

@@ -1,0 +1,547 @@
+// Element-wise and small kernels around the MFMA products: relaxation tables (Lemma 1),
+// split clamping, box centre / radius, start of a backward pass, split-multiplier
+// injection and gradient, final assembly of the bound, the adjoint's start, the
+// standalone box concretisation (Theorem 2), Adam, and weight packing.
+#include "bound_internal.h"
+
+namespace bp {
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned blocks_for(long n, int per = TPB) { return (unsigned)((n + per - 1) / per); }
+
+__device__ inline float wave_sum(float x) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+// Block-wide sum of two values (256 threads); result valid in thread 0.
+__device__ inline void block_sum2(float &a, float &b) {
+    __shared__ float sa[4], sb[4];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) { sa[w] = a; sb[w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = sa[0] + sa[1] + sa[2] + sa[3];
+        b = sb[0] + sb[1] + sb[2] + sb[3];
+    }
+}
+
+__device__ inline int layer_of(const NetShapes &ns, int used, long jg) {
+    int m = 0;
+    for (int t = 1; t < used; ++t)
+        if (jg >= ns.l[t].off) m = t;
+    return m;
+}
+
+// Row of lo/hi used by an instance; out-of-range indices are clamped so a bad index can
+// never read outside the caller's arrays.
+__device__ inline long bound_row(const int32_t *bound_of, long inst, int n_bounds) {
+    long b = bound_of ? (long)bound_of[inst] : inst;
+    return b < 0 ? 0 : (b >= n_bounds ? n_bounds - 1 : b);
+}
+
+// internal (y, x, c) index -> C-major index within a layer of C channels, HW pixels
+__device__ inline long to_cmajor(long j, int C, int HW) { return (j % C) * HW + j / C; }
+__device__ inline long to_internal(long jn, int C, int HW) { return (jn % HW) * C + jn / HW; }
+
+// Lemma 1 for one neuron (boundary reading: active iff l >= 0, else inactive iff u <= 0).
+__device__ inline Relax relax_of(float l, float u, float a) {
+    if (l >= 0.f) return make_float4(1.f, 1.f, 0.f, 0.f);
+    if (u <= 0.f) return make_float4(0.f, 0.f, 0.f, 0.f);
+    const float su = u / (u - l);
+    return make_float4(a, su, -l * su, 1.f);
+}
+
+__global__ void k_fill(float *p, long n, float v) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_prep_tables(const NetShapes ns, int used, long T, long n_relu,
+                              const float *lo, const float *hi, const int32_t *bound_of,
+                              const float *alpha, Relax *tab, int32_t *infeas, long total,
+                              int n_bounds) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const long inst = e / T, jg = e - inst * T;
+    if (jg == 0) infeas[inst] = 0;
+    const int m = layer_of(ns, used, jg);
+    const LayerShape &L = ns.l[m];
+    const long j = jg - L.off;
+    const long jn = to_cmajor(j, L.C, L.HW);
+    const long b = bound_row(bound_of, inst, n_bounds);
+    const float l = lo[b * n_relu + L.off + jn], u = hi[b * n_relu + L.off + jn];
+    const float a = alpha ? alpha[inst * n_relu + L.off + jn] : (u >= -l ? 1.f : 0.f);
+    tab[inst * n_relu + L.off + j] = relax_of(l, u, a);
+}
+
+__global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, long n_relu,
+                              const float *lo, const float *hi, const int32_t *bound_of,
+                              const int32_t *off, const int32_t *idx, const int8_t *sign,
+                              Relax *tab, int32_t *infeas, int32_t *sp_inst, int32_t *sp_layer,
+                              int32_t *sp_j, int n_bounds) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_inst) return;
+    const long b = bound_row(bound_of, i, n_bounds);
+    const int q0 = off[i], q1 = off[i + 1];
+    for (int q = q0; q < q1; ++q) {
+        const long g = idx[q];
+        sp_inst[q] = i;
+        sp_layer[q] = -1;
+        sp_j[q] = 0;
+        if (g < 0 || g >= T) continue;  // not a layer this pass relaxes
+        const int m = layer_of(ns, used, g);
+        const LayerShape &L = ns.l[m];
+        const long jn = g - L.off;
+        float l = lo[b * n_relu + g], u = hi[b * n_relu + g];
+        for (int q2 = q0; q2 < q1; ++q2) {
+            if (idx[q2] != g) continue;
+            if (sign[q2] > 0) l = fmaxf(l, 0.f);
+            else u = fminf(u, 0.f);
+        }
+        if (l > u) infeas[i] = 1;
+        const long j = to_internal(jn, L.C, L.HW);
+        tab[(long)i * n_relu + L.off + j] = l >= 0.f ? make_float4(1.f, 1.f, 0.f, 0.f)
+                                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+        sp_layer[q] = m;
+        sp_j[q] = (int32_t)j;
+    }
+}
+
+__global__ void k_prep_box(long total, long d0, int C0, int HW0, const float *x_lo,
+                           const float *x_hi, float *cen, float *rad) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const long inst = e / d0, j = e - inst * d0;
+    const long jn = to_cmajor(j, C0, HW0);
+    const float a = x_lo[inst * d0 + jn], b = x_hi[inst * d0 + jn];
+    cen[e] = 0.5f * (a + b);
+    rad[e] = 0.5f * (b - a);
+}
+
+__global__ void k_init_spec(long img0, long n_img, int rows, int rpi, const float *spec, long dk,
+                            int Ck, int HWk, float *lam) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_img * dk) return;
+    const long li = e / dk, j = e - li * dk;
+    const long gimg = img0 + li;
+    const long inst = gimg / rpi;
+    const int rr = (int)(gimg - inst * rpi);
+    const float sg = rr < rows ? 1.f : -1.f;
+    const int r = rr < rows ? rr : rr - rows;
+    lam[e] = sg * spec[(inst * rows + r) * dk + to_cmajor(j, Ck, HWk)];
+}
+
+__global__ void k_init_spec_acc(long img0, long n_img, int rows, int rpi, const float *spec,
+                                long dk, int HWk, const float *bias_k, float *s, float *mag,
+                                float *low) {
+    const long li = blockIdx.x;
+    if (li >= n_img) return;
+    const long gimg = img0 + li;
+    const long inst = gimg / rpi;
+    const int rr = (int)(gimg - inst * rpi);
+    const float sg = rr < rows ? 1.f : -1.f;
+    const int r = rr < rows ? rr : rr - rows;
+    const float *row = spec + (inst * rows + r) * dk;
+    float a = 0.f, b = 0.f;
+    for (long jn = threadIdx.x; jn < dk; jn += blockDim.x) {
+        const float t = row[jn] * bias_k[jn / HWk];
+        a += t;
+        b += fabsf(t);
+    }
+    block_sum2(a, b);
+    if (threadIdx.x == 0) {
+        s[li] = sg * a;
+        mag[li] = b;
+        low[li] = 0.f;
+    }
+}
+
+template <bool CONC>
+__global__ void k_init_identity(const IdentityParams p, long n_img) {
+    const long li = blockIdx.x;
+    if (li >= n_img) return;
+    const long gimg = p.img0 + li;
+    const long inst = gimg / p.rpi;
+    const long rr = gimg - inst * p.rpi;
+    const float sg = rr < p.dk ? 1.f : -1.f;
+    const long nr = rr < p.dk ? rr : rr - p.dk;  // C-major neuron of z_k
+    int co = 0, oy = 0, ox = 0;
+    if (p.kind == 1) {
+        const int hw = p.ho * p.wo;
+        co = (int)(nr / hw);
+        const int q = (int)(nr - (long)co * hw);
+        oy = q / p.wo;
+        ox = q - oy * p.wo;
+    }
+    const int hwin = p.hi_ * p.wi;
+    float a = 0.f, b = 0.f;
+    for (long j = threadIdx.x; j < p.din; j += blockDim.x) {
+        const long pix = j / p.ci;
+        const int c = (int)(j - pix * p.ci);
+        float gval = 0.f;
+        if (p.kind == 0) {
+            gval = p.W[nr * p.din + (long)c * hwin + pix];
+        } else {
+            const int iy = (int)(pix / p.wi), ix = (int)(pix - (long)(pix / p.wi) * p.wi);
+            const int ky = iy - (oy * p.stride - p.pad), kx = ix - (ox * p.stride - p.pad);
+            if (ky >= 0 && ky < p.kh && kx >= 0 && kx < p.kw)
+                gval = p.W[(((long)co * p.ci + c) * p.kh + ky) * p.kw + kx];
+        }
+        gval *= sg;
+        if (CONC) {
+            const float cc = p.cen[inst * p.din + j], rad = p.rad[inst * p.din + j];
+            a += gval * cc - fabsf(gval) * rad;
+            b += fabsf(gval) * (fabsf(cc) + rad);
+            if (p.emit) p.emit[li * p.din + (long)c * hwin + pix] = gval;
+        } else {
+            const Relax t = p.tab[inst * p.tab_ld + j];
+            const float lam = gval >= 0.f ? gval * t.x : gval * t.y;
+            const float off = gval < 0.f ? gval * t.z : 0.f;
+            const float bt = lam * p.bias_m[j % p.chan_m];
+            a += bt + off;
+            b += fabsf(bt) + fabsf(off);
+            p.out[li * p.din + j] = lam;
+        }
+    }
+    block_sum2(a, b);
+    if (threadIdx.x == 0) {
+        const float bk = sg * p.bias_k[p.kind == 1 ? co : nr];
+        if (CONC) {
+            p.s[li] = bk;
+            p.low[li] = a;
+        } else {
+            p.s[li] = bk + a;
+            p.low[li] = 0.f;
+        }
+        p.mag[li] = fabsf(bk) + b;
+    }
+}
+
+__global__ void k_beta_inject(int nnz, int rows, int rpi, long img0, long n_img, int layer,
+                              const int32_t *sp_inst, const int32_t *sp_layer,
+                              const int32_t *sp_j, const int8_t *sign, const float *beta,
+                              float *lam, long D, const float *bias, int chan, float *s,
+                              float *mag) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)nnz * rows) return;
+    const int q = (int)(e / rows), r = (int)(e - (long)q * rows);
+    if (sp_layer[q] != layer) return;
+    const long img = (long)sp_inst[q] * rpi + r - img0;
+    if (img < 0 || img >= n_img) return;
+    const float delta = -beta[(long)q * rows + r] * (float)sign[q];
+    const long j = sp_j[q];
+    atomicAdd(lam + img * D + j, delta);
+    const float bt = delta * bias[j % chan];
+    atomicAdd(s + img, bt);
+    atomicAdd(mag + img, fabsf(bt));
+}
+
+__global__ void k_finalize(long img0, long n_img, int rows, int rpi, const float *s,
+                           const float *low, const float *mag, const int32_t *infeas, int slack,
+                           float *lower, float *upper, long ld, float *offset, float *offset_mag,
+                           float *best) {
+    const long li = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (li >= n_img) return;
+    const long gimg = img0 + li;
+    const long inst = gimg / rpi;
+    const int rr = (int)(gimg - inst * rpi);
+    if (offset) offset[gimg] = s[li];
+    if (offset_mag) offset_mag[gimg] = mag[li];
+    if (!lower) return;
+    float v = s[li] + low[li];
+    if (slack) v -= KAPPA_U * mag[li];
+    if (infeas[inst]) v = INFINITY;
+    if (rr < rows) {
+        lower[inst * ld + rr] = v;
+        if (best) best[inst * ld + rr] = fmaxf(best[inst * ld + rr], v);
+    } else if (upper) {
+        upper[inst * ld + rr - rows] = -v;
+    }
+}
+
+__global__ void k_adj_init(long n_img, int rows, long d0, const float *gl, const float *g1,
+                           const float *cen, const float *rad, const int32_t *infeas,
+                           float *gbar, float *sbar) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_img * d0) return;
+    const long img = e / d0, j = e - img * d0;
+    const long inst = img / rows;
+    const float w = infeas[inst] ? 0.f : gl[img];
+    if (j == 0) sbar[img] = w;
+    const float g = g1[e];
+    const float sg = g > 0.f ? 1.f : (g < 0.f ? -1.f : 0.f);
+    gbar[e] = w * (cen[inst * d0 + j] - sg * rad[inst * d0 + j]);
+}
+
+__global__ void k_beta_grad(int nnz, int rows, int layer, const BetaGradLayer L,
+                            const int32_t *sp_inst, const int32_t *sp_layer, const int32_t *sp_j,
+                            const int8_t *sign, const float *gbar_m, const float *sbar,
+                            float *gbeta) {
+    const long wv = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (wv >= (long)nnz * rows) return;
+    const int q = (int)(wv / rows), r = (int)(wv - (long)q * rows);
+    if (sp_layer[q] != layer) return;
+    const long img = (long)sp_inst[q] * rows + r;
+    const float *gb = gbar_m + img * L.din;
+    const long j = sp_j[q];
+    float acc = 0.f;
+    int bidx;
+    if (L.kind == 0) {
+        const int hwin = L.hi_ * L.wi;
+        const float *wrow = L.W + j * L.din;
+        for (long k = lane; k < L.din; k += 64) {
+            const long pix = k / L.ci;
+            const int c = (int)(k - pix * L.ci);
+            acc += gb[k] * wrow[(long)c * hwin + pix];
+        }
+        bidx = (int)j;
+    } else {
+        const long pix = j / L.co;
+        const int co = (int)(j - pix * L.co);
+        const int oy = (int)(pix / L.wo), ox = (int)(pix - (long)oy * L.wo);
+        const int taps = L.kh * L.kw * L.ci;
+        for (int t = lane; t < taps; t += 64) {
+            const int ci = t % L.ci, kk = t / L.ci;
+            const int ky = kk / L.kw, kx = kk - ky * L.kw;
+            const int y = oy * L.stride - L.pad + ky, x = ox * L.stride - L.pad + kx;
+            if (y < 0 || y >= L.hi_ || x < 0 || x >= L.wi) continue;
+            acc += gb[((long)y * L.wi + x) * L.ci + ci] *
+                   L.W[(((long)co * L.ci + ci) * L.kh + ky) * L.kw + kx];
+        }
+        bidx = co;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) {
+        const float lam_bar = acc + sbar[img] * L.bias[bidx];
+        gbeta[(long)q * rows + r] = -(float)sign[q] * lam_bar;
+    }
+}
+
+__global__ void k_adam(long n, float *p, const float *g, float *m, float *v, float b1, float b2,
+                       float bc1, float bc2s, float lr, float eps, float gs, float lo, float hi) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gr = gs * g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gr;
+    const float vi = b2 * v[i] + (1.f - b2) * gr * gr;
+    m[i] = mi;
+    v[i] = vi;
+    float x = p[i] - (lr / bc1) * mi / (sqrtf(vi) / bc2s + eps);
+    x = fminf(fmaxf(x, lo), hi);
+    p[i] = x;
+}
+
+// One block per (instance, row): reads the row once, coalesced.
+__global__ void k_concretize(int n_inst, int rows, long d0, const float *coeff,
+                             const float *offset, const float *offset_mag, const float *x_lo,
+                             const float *x_hi, int slack, float *lower) {
+    const long row = blockIdx.x;
+    const long inst = row / rows;
+    const float *cr = coeff + row * d0;
+    const float *lo = x_lo + inst * d0, *hi = x_hi + inst * d0;
+    float a = 0.f, b = 0.f;
+    for (long j = threadIdx.x; j < d0; j += blockDim.x) {
+        const float c = 0.5f * (lo[j] + hi[j]), r = 0.5f * (hi[j] - lo[j]);
+        const float w = cr[j];
+        a += w * c - fabsf(w) * r;
+        b += fabsf(w) * (fabsf(c) + r);
+    }
+    block_sum2(a, b);
+    if (threadIdx.x == 0) {
+        float v = a + offset[row];
+        if (slack) v -= KAPPA_U * (b + (offset_mag ? offset_mag[row] : 0.f));
+        lower[row] = v;
+    }
+}
+
+__global__ void k_pack_T(const float *W, int kind, int ci, int hwin, int co, int kh, int kw,
+                         int stride, int ky0, int kx0, int Ty, int Tx, int N, int K, int Kp,
+                         long total, float *Bt) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const long n = e / Kp;
+    const int k = (int)(e - n * Kp);
+    float v = 0.f;
+    if (n < N && k < K) {
+        if (kind == 0) {  // Bt[n][k] = W[k][cmajor(n)]
+            const long pix = n / ci;
+            const int c = (int)(n - pix * ci);
+            v = W[(long)k * N + (long)c * hwin + pix];
+        } else {          // k = (t'y * Tx + t'x) * co + o
+            const int o = k % co, tt = k / co;
+            const int ty = tt / Tx, tx = tt - ty * Tx;
+            const int ky = ky0 + stride * (Ty - 1 - ty), kx = kx0 + stride * (Tx - 1 - tx);
+            if (ky < kh && kx < kw) v = W[(((long)o * ci + n) * kh + ky) * kw + kx];
+        }
+    }
+    Bt[e] = v;
+}
+
+__global__ void k_pack_F(const float *W, int kind, int ci, int hwin, int kh, int kw, int N, int K,
+                         int Kp, long total, float *Bt) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const long n = e / Kp;
+    const int k = (int)(e - n * Kp);
+    float v = 0.f;
+    if (n < N && k < K) {
+        if (kind == 0) {  // Bt[n][k] = W[n][cmajor(k)]
+            const long pix = k / ci;
+            const int c = (int)(k - pix * ci);
+            v = W[n * K + (long)c * hwin + pix];
+        } else {          // k = (ky * kw + kx) * ci + c
+            const int c = k % ci, tt = k / ci;
+            const int ky = tt / kw, kx = tt - ky * kw;
+            v = W[((n * ci + c) * kh + ky) * kw + kx];
+        }
+    }
+    Bt[e] = v;
+}
+
+}  // namespace
+
+hipError_t launch_fill(float *p, long n, float v, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(TPB), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_tables(const NetShapes &ns, int used, int n_inst, long n_relu,
+                              const float *lo, const float *hi, const int32_t *bound_of,
+                              const float *alpha, Relax *tab, int32_t *infeas, int n_bounds,
+                              hipStream_t st) {
+    const long T = used > 0 ? ns.l[used - 1].off + ns.l[used - 1].d : 0;
+    if (T == 0) return launch_fill((float *)infeas, n_inst, 0.f, st);  // 0.0f is all-zero bits
+    const long total = T * n_inst;
+    hipLaunchKernelGGL(k_prep_tables, dim3(blocks_for(total)), dim3(TPB), 0, st, ns, used, T,
+                       n_relu, lo, hi, bound_of, alpha, tab, infeas, total, n_bounds);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_splits(const NetShapes &ns, int used, int n_inst, long n_relu,
+                              const float *lo, const float *hi, const int32_t *bound_of,
+                              const int32_t *off, const int32_t *idx, const int8_t *sign,
+                              Relax *tab, int32_t *infeas, int32_t *sp_inst, int32_t *sp_layer,
+                              int32_t *sp_j, int n_bounds, hipStream_t st) {
+    const long T = used > 0 ? ns.l[used - 1].off + ns.l[used - 1].d : 0;
+    hipLaunchKernelGGL(k_prep_splits, dim3(blocks_for(n_inst, 64)), dim3(64), 0, st, ns, used, T,
+                       n_inst, n_relu, lo, hi, bound_of, off, idx, sign, tab, infeas, sp_inst,
+                       sp_layer, sp_j, n_bounds);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_box(int n_inst, int C0, int HW0, const float *x_lo, const float *x_hi,
+                           float *cen, float *rad, hipStream_t st) {
+    const long d0 = (long)C0 * HW0, total = d0 * n_inst;
+    hipLaunchKernelGGL(k_prep_box, dim3(blocks_for(total)), dim3(TPB), 0, st, total, d0, C0, HW0,
+                       x_lo, x_hi, cen, rad);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_spec(long img0, long n_img, int rows, int rpi, const float *spec, long dk,
+                            int Ck, int HWk, const float *bias_k, float *lam, float *s,
+                            float *mag, float *low, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_spec, dim3(blocks_for(n_img * dk)), dim3(TPB), 0, st, img0, n_img,
+                       rows, rpi, spec, dk, Ck, HWk, lam);
+    hipLaunchKernelGGL(k_init_spec_acc, dim3((unsigned)n_img), dim3(TPB), 0, st, img0, n_img, rows,
+                       rpi, spec, dk, HWk, bias_k, s, mag, low);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_identity(const IdentityParams &p, long n_img, bool conc, hipStream_t st) {
+    if (conc)
+        hipLaunchKernelGGL(k_init_identity<true>, dim3((unsigned)n_img), dim3(TPB), 0, st, p, n_img);
+    else
+        hipLaunchKernelGGL(k_init_identity<false>, dim3((unsigned)n_img), dim3(TPB), 0, st, p, n_img);
+    return hipGetLastError();
+}
+
+hipError_t launch_beta_inject(int nnz, int rows, int rpi, long img0, long n_img, int layer,
+                              const int32_t *sp_inst, const int32_t *sp_layer, const int32_t *sp_j,
+                              const int8_t *sign, const float *beta, float *lam, long D,
+                              const float *bias, int chan, float *s, float *mag, hipStream_t st) {
+    const long total = (long)nnz * rows;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_beta_inject, dim3(blocks_for(total)), dim3(TPB), 0, st, nnz, rows, rpi,
+                       img0, n_img, layer, sp_inst, sp_layer, sp_j, sign, beta, lam, D, bias, chan,
+                       s, mag);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(long img0, long n_img, int rows, int rpi, const float *s,
+                           const float *low, const float *mag, const int32_t *infeas, bool slack,
+                           float *lower, float *upper, long ld, float *offset, float *offset_mag,
+                           float *best, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n_img)), dim3(TPB), 0, st, img0, n_img, rows,
+                       rpi, s, low, mag, infeas, slack ? 1 : 0, lower, upper, ld, offset,
+                       offset_mag, best);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_init(long n_img, int rows, long d0, const float *gl, const float *g1,
+                           const float *cen, const float *rad, const int32_t *infeas, float *gbar,
+                           float *sbar, hipStream_t st) {
+    const long total = n_img * d0;
+    hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(total)), dim3(TPB), 0, st, n_img, rows, d0, gl,
+                       g1, cen, rad, infeas, gbar, sbar);
+    return hipGetLastError();
+}
+
+hipError_t launch_beta_grad(int nnz, int rows, int layer, const BetaGradLayer &L,
+                            const int32_t *sp_inst, const int32_t *sp_layer, const int32_t *sp_j,
+                            const int8_t *sign, const float *gbar_m, const float *sbar,
+                            const int32_t *, float *gbeta, hipStream_t st) {
+    const long waves = (long)nnz * rows;
+    if (waves == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_beta_grad, dim3(blocks_for(waves * 64)), dim3(TPB), 0, st, nnz, rows,
+                       layer, L, sp_inst, sp_layer, sp_j, sign, gbar_m, sbar, gbeta);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int step, float lr,
+                       float b1, float b2, float eps, float gs, float lo, float hi, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const float bc1 = 1.f - powf(b1, (float)step);
+    const float bc2s = sqrtf(1.f - powf(b2, (float)step));
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(TPB), 0, st, n, p, g, m, v, b1, b2, bc1,
+                       bc2s, lr, eps, gs, lo, hi);
+    return hipGetLastError();
+}
+
+hipError_t launch_concretize(int n_inst, int rows, long d0, const float *coeff,
+                             const float *offset, const float *offset_mag, const float *x_lo,
+                             const float *x_hi, bool slack, float *lower, hipStream_t st) {
+    const long nrow = (long)n_inst * rows;
+    if (nrow == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_concretize, dim3((unsigned)nrow), dim3(TPB), 0, st, n_inst, rows, d0,
+                       coeff, offset, offset_mag, x_lo, x_hi, slack ? 1 : 0, lower);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_T(const float *W, int kind, int ci, int hi_, int wi, int co, int ho, int wo,
+                         int kh, int kw, int stride, int pad, int py, int px, int ky0, int kx0,
+                         int Ty, int Tx, int N, int K, int Kp, int Np, float *Bt, hipStream_t st) {
+    (void)ho; (void)wo; (void)pad; (void)py; (void)px;
+    const long total = (long)Np * Kp;
+    hipLaunchKernelGGL(k_pack_T, dim3(blocks_for(total)), dim3(TPB), 0, st, W, kind, ci, hi_ * wi,
+                       co, kh, kw, stride, ky0, kx0, Ty, Tx, N, K, Kp, total, Bt);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_F(const float *W, int kind, int ci, int hi_, int wi, int co, int kh, int kw,
+                         int N, int K, int Kp, int Np, float *Bt, hipStream_t st) {
+    (void)co;
+    const long total = (long)Np * Kp;
+    hipLaunchKernelGGL(k_pack_F, dim3(blocks_for(total)), dim3(TPB), 0, st, W, kind, ci, hi_ * wi,
+                       kh, kw, N, K, Kp, total, Bt);
+    return hipGetLastError();
+}
+
+}  // namespace bp

@@ -1,0 +1,180 @@
+// Internal declarations shared by the gfx950 kernels and the host side of the library.
+//
+// Layout inside the library: every coefficient tensor is [img][H][W][C] (channels last),
+// where img enumerates (instance, spec row) pairs; Linear layers are the 1x1 case.
+// Neuron index j inside a layer is therefore (y * W + x) * C + c ("internal order");
+// the C ABI uses the C-major order c * H * W + y * W + x.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace bp {
+
+// Implicit-GEMM geometry.  Row m of the GEMM is (img, oy, ox) over an OH x OW grid; the
+// A operand gathers A[img][y][x][c] at y = oy*stride - pad_y + ky, x = ox*stride - pad_x
+// + kx for k = (ky*kw + kx)*C + c (zero outside the source); B is packed as Bt[N][Kp];
+// the result element (m, n) goes to destination pixel (oy*ostr + oy0, ox*ostr + ox0)
+// of a [img][DH][DW][N] tensor.
+struct Geom {
+    int H, W, C;
+    int OH, OW;
+    int kh, kw, stride, pad_y, pad_x;
+    int K, N, Kp;
+    int DH, DW, ostr, oy0, ox0;
+    const float *Bt;
+};
+
+struct GeomSet {
+    Geom g[4];
+    int n;
+};
+
+// Per-neuron relaxation record (Lemma 1) for one instance:
+// x = lower slope, y = upper slope, z = upper intercept, w = 1 if unstable (alpha free).
+typedef float4 Relax;
+
+// ----- epilogue parameter blocks -----------------------------------------------------
+struct RelaxParams {       // G_m = Lambda_m W_m  ->  Lambda_{m-1} = relax(G_m)
+    float *out;            // Lambda_{m-1}  [img][D]
+    float *save;           // G_m kept for the gradient (nullable)
+    const Relax *tab;      // relaxation table of layer m-1, row stride tab_ld
+    long tab_ld;
+    const float *bias;     // b_{m-1} per channel
+    int chan;              // channels of layer m-1 (bias index = j % chan)
+    long D;                // width of layer m-1
+    float *s, *mag;        // per-img offset accumulator and |term| accumulator
+    long img0;             // global img index of local img 0
+    int rpi;               // imgs per instance
+};
+
+struct ConcParams {        // G_1 = Lambda_1 W_1  ->  concretise over the box
+    const float *cen, *rad;  // [n_inst][d0] internal order
+    long D;                // d0
+    float *low, *mag;      // per-img accumulators
+    float *save;           // G_1 kept (nullable)
+    float *emit;           // coefficient output in C-major order (nullable)
+    int chan, hw;          // input shape for the C-major index
+    long img0;
+    int rpi;
+};
+
+struct AdjParams {         // Lambda_bar_m = G_bar_m W_m^T + s_bar b_m  -> G_bar_{m+1}
+    const float *sbar;     // per img: gradient of the offset (0 for infeasible instances)
+    const float *bias;     // b_m per channel
+    int chan;
+    long D;                // width of layer m
+    const float *gsave;    // saved G_{m+1} [img][D]
+    const Relax *tab;
+    long tab_ld;
+    float *gout;           // G_bar_{m+1} (nullable at the last layer)
+    float *galpha;         // [n_inst][n_relu] C-major
+    long ga_ld;
+    long ga_off;
+    int hw;                // H*W of layer m (C-major index)
+    int rpi;
+};
+
+// ----- launchers (gemm.hip) ----------------------------------------------------------
+hipError_t gemm_relax(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
+                      hipStream_t st);
+hipError_t gemm_conc(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,
+                     hipStream_t st);
+hipError_t gemm_adj(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
+                    hipStream_t st);
+
+// ----- auxiliary kernels (aux.hip) ---------------------------------------------------
+struct LayerShape {        // output shape of a ReLU layer (for index maps)
+    int C, HW;             // channels, pixels
+    long off;              // offset in the flat ReLU index
+    long d;
+};
+
+struct NetShapes {
+    int n;                 // number of ReLU layers described
+    LayerShape l[16];
+};
+
+hipError_t launch_fill(float *p, long n, float v, hipStream_t st);
+hipError_t launch_prep_tables(const NetShapes &ns, int n_layers_used, int n_inst,
+                              long n_relu, const float *lo, const float *hi,
+                              const int32_t *bound_of, const float *alpha, Relax *tab,
+                              int32_t *infeas, int n_bounds, hipStream_t st);
+hipError_t launch_prep_splits(const NetShapes &ns, int n_layers_used, int n_inst, long n_relu,
+                              const float *lo, const float *hi, const int32_t *bound_of,
+                              const int32_t *off, const int32_t *idx, const int8_t *sign,
+                              Relax *tab, int32_t *infeas, int32_t *sp_inst,
+                              int32_t *sp_layer, int32_t *sp_j, int n_bounds, hipStream_t st);
+hipError_t launch_prep_box(int n_inst, int C0, int HW0, const float *x_lo, const float *x_hi,
+                           float *cen, float *rad, hipStream_t st);
+hipError_t launch_init_spec(long img0, long n_img, int rows, int rpi, const float *spec,
+                            long dk, int Ck, int HWk, const float *bias_k, float *lam,
+                            float *s, float *mag, float *low, hipStream_t st);
+
+struct IdentityParams {
+    // target layer k
+    int kind;                  // 0 linear, 1 conv
+    const float *W;            // user weight of layer k (C-major)
+    const float *bias_k;
+    int ci, hi_, wi;           // input shape of layer k
+    int co, ho, wo;            // output shape of layer k
+    int kh, kw, stride, pad;
+    long dk, din;              // widths of z_k and of the layer's input
+    int rpi;                   // 2*dk (both sides) or dk
+    long img0;
+    // relax mode (k > 1): table and bias of layer k-1
+    const Relax *tab;
+    long tab_ld;
+    const float *bias_m;
+    int chan_m;
+    float *out;                // Lambda_{k-1} [img][din]
+    // concretise mode (k == 1)
+    const float *cen, *rad;
+    float *emit;
+    // accumulators
+    float *s, *mag, *low;
+};
+hipError_t launch_init_identity(const IdentityParams &p, long n_img, bool conc, hipStream_t st);
+
+hipError_t launch_beta_inject(int nnz, int rows, int rpi, long img0, long n_img, int layer,
+                              const int32_t *sp_inst, const int32_t *sp_layer,
+                              const int32_t *sp_j, const int8_t *sign, const float *beta,
+                              float *lam, long D, const float *bias, int chan, float *s,
+                              float *mag, hipStream_t st);
+hipError_t launch_finalize(long img0, long n_img, int rows, int rpi, const float *s,
+                           const float *low, const float *mag, const int32_t *infeas,
+                           bool slack, float *lower, float *upper, long ld, float *offset,
+                           float *offset_mag, float *best, hipStream_t st);
+hipError_t launch_adj_init(long n_img, int rows, long d0, const float *gl, const float *g1,
+                           const float *cen, const float *rad, const int32_t *infeas,
+                           float *gbar, float *sbar, hipStream_t st);
+
+struct BetaGradLayer {         // layer m, for the split-multiplier gradient
+    int kind;
+    const float *W;            // user weight (C-major)
+    const float *bias;
+    int ci, hi_, wi, co, ho, wo, kh, kw, stride, pad;
+    long din, dout;
+};
+hipError_t launch_beta_grad(int nnz, int rows, int layer, const BetaGradLayer &L,
+                            const int32_t *sp_inst, const int32_t *sp_layer,
+                            const int32_t *sp_j, const int8_t *sign, const float *gbar_m,
+                            const float *gl, const int32_t *infeas, float *gbeta,
+                            hipStream_t st);
+hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int step,
+                       float lr, float b1, float b2, float eps, float gs, float lo, float hi,
+                       hipStream_t st);
+hipError_t launch_concretize(int n_inst, int rows, long d0, const float *coeff,
+                             const float *offset, const float *offset_mag, const float *x_lo,
+                             const float *x_hi, bool slack, float *lower, hipStream_t st);
+
+// Packing helpers (aux.hip)
+hipError_t launch_pack_T(const float *W, int kind, int ci, int hi_, int wi, int co, int ho,
+                         int wo, int kh, int kw, int stride, int pad, int py, int px, int ky0,
+                         int kx0, int Ty, int Tx, int N, int K, int Kp, int Np, float *Bt,
+                         hipStream_t st);
+hipError_t launch_pack_F(const float *W, int kind, int ci, int hi_, int wi, int co, int kh,
+                         int kw, int N, int K, int Kp, int Np, float *Bt, hipStream_t st);
+
+constexpr float KAPPA_U = 64.0f / 16777216.0f;   // slack factor: 64 * 2^-24
+
+}  // namespace bp

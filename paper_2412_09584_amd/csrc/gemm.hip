@@ -1,0 +1,402 @@
+// FP32 MFMA implicit-GEMM kernels for gfx950 with fused bound-propagation epilogues.
+//
+// One kernel template covers every product on the bound path:
+//  * the backward step of Theorem 1, G_m = Lambda_m W_m (Linear: a dense GEMM; Conv2d:
+//    the transposed convolution, run as one stride-1 implicit GEMM per output phase),
+//    with Lemma 1's relaxation, the bias / intercept row sums (the offset b~) and the
+//    FP32 rounding-allowance magnitudes fused into the epilogue (EpiRelax);
+//  * the last step G_1 = Lambda_1 W_1 with Theorem 2's box concretisation fused into the
+//    epilogue, so G_1 need not reach HBM (EpiConc);
+//  * the adjoint step Lambda_bar_m = G_bar_m W_m^T (Linear) or the forward convolution
+//    (Conv2d), with the reverse of the relaxation and the alpha-gradient reduction
+//    fused into the epilogue (EpiAdj).
+//
+// Tiling: 256 threads = 4 wave64s; a block owns a BM x BN output tile; K advances in
+// chunks of 16 staged through LDS (A rows and B columns both stored k-contiguous, so a
+// lane fetches its k values with 128-bit LDS reads) with the next chunk's global loads
+// in flight during the MFMAs.  v_mfma_f32_32x32x2f32 serves N >= 32 and
+// v_mfma_f32_16x16x4f32 the narrow N = 16 products.  Within a 16-wide k chunk lane
+// group h of the MFMA supplies k = h*KPL + s at step s, which lets each lane read KPL
+// consecutive k from LDS.
+#include "bound_internal.h"
+
+namespace bp {
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 16;
+constexpr int LDSW = BK + 4;  // LDS row stride in floats (keeps 16-byte alignment)
+
+template <int MF> struct Mma;
+template <> struct Mma<32> {
+    using acc_t = f32x16;
+    static constexpr int NACC = 16;
+    static constexpr int KPL = 8;  // k values per lane per chunk (2 lane groups)
+    static __device__ inline acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+    static __device__ inline int col(int lane) { return lane & 31; }
+    static __device__ inline int grp(int lane) { return lane >> 5; }
+    static __device__ inline int idx(int lane) { return lane & 31; }
+};
+template <> struct Mma<16> {
+    using acc_t = f32x4v;
+    static constexpr int NACC = 4;
+    static constexpr int KPL = 4;  // 4 lane groups
+    static __device__ inline acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ inline int row(int v, int lane) { return 4 * (lane >> 4) + v; }
+    static __device__ inline int col(int lane) { return lane & 15; }
+    static __device__ inline int grp(int lane) { return lane >> 4; }
+    static __device__ inline int idx(int lane) { return lane & 15; }
+};
+
+// ---------------------------------------------------------------------- epilogues
+struct EpiRelax {
+    RelaxParams p;
+    static constexpr int NRED = 2;
+    struct Row { long inst; };
+    __device__ Row row(long img) const { return Row{(p.img0 + img) / p.rpi}; }
+    __device__ float colv(int n) const { return p.bias[n % p.chan]; }
+    __device__ float *red0() const { return p.s; }
+    __device__ float *red1() const { return p.mag; }
+    __device__ void elem(const Row &rc, long img, long dpix, int n, long j, float bcol, float g,
+                         float &r0, float &r1) const {
+        const Relax t = p.tab[rc.inst * p.tab_ld + j];
+        const float lam = g >= 0.f ? g * t.x : g * t.y;
+        const float off = g < 0.f ? g * t.z : 0.f;
+        const float bt = lam * bcol;
+        r0 += bt + off;
+        r1 += fabsf(bt) + fabsf(off);
+        const long o = img * p.D + j;
+        p.out[o] = lam;
+        if (p.save) p.save[o] = g;
+    }
+};
+
+struct EpiConc {
+    ConcParams p;
+    static constexpr int NRED = 2;
+    struct Row { long inst; };
+    __device__ Row row(long img) const { return Row{(p.img0 + img) / p.rpi}; }
+    __device__ float colv(int) const { return 0.f; }
+    __device__ float *red0() const { return p.low; }
+    __device__ float *red1() const { return p.mag; }
+    __device__ void elem(const Row &rc, long img, long dpix, int n, long j, float, float g,
+                         float &r0, float &r1) const {
+        const long ij = rc.inst * p.D + j;
+        const float c = p.cen[ij], r = p.rad[ij];
+        r0 += g * c - fabsf(g) * r;
+        r1 += fabsf(g) * (fabsf(c) + r);
+        if (p.save) p.save[img * p.D + j] = g;
+        if (p.emit) p.emit[img * p.D + (long)n * p.hw + dpix] = g;
+    }
+};
+
+struct EpiAdj {
+    AdjParams p;
+    static constexpr int NRED = 0;
+    struct Row { long inst; float sb; };
+    __device__ Row row(long img) const { return Row{img / p.rpi, p.sbar[img]}; }
+    __device__ float colv(int n) const { return p.bias[n]; }
+    __device__ float *red0() const { return nullptr; }
+    __device__ float *red1() const { return nullptr; }
+    __device__ void elem(const Row &rc, long img, long dpix, int n, long j, float bcol, float acc,
+                         float &, float &) const {
+        const float v = acc + rc.sb * bcol;           // Lambda_bar_m[img, j]
+        const long o = img * p.D + j;
+        const float g = p.gsave[o];                   // G_{m+1}[img, j]
+        const Relax t = p.tab[rc.inst * p.tab_ld + j];
+        if (p.gout) p.gout[o] = v * (g >= 0.f ? t.x : t.y) + (g < 0.f ? rc.sb * t.z : 0.f);
+        if (t.w != 0.f && g >= 0.f) {
+            const float c = g * v;
+            if (c != 0.f) atomicAdd(p.galpha + rc.inst * p.ga_ld + p.ga_off + (long)n * p.hw + dpix, c);
+        }
+    }
+};
+
+// ---------------------------------------------------------------------- the kernel
+template <class Epi, int MF, int BM, int BN, int WGM, int WGN, bool DENSE, bool VEC>
+__global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__restrict__ A,
+                                              const long n_img, const Epi epi) {
+    using MM = Mma<MF>;
+    using acc_t = typename MM::acc_t;
+    constexpr int TM = BM / WGM, TN = BN / WGN, FM = TM / MF, FN = TN / MF;
+    static_assert(WGM * WGN == 4, "4 waves");
+    static_assert(FM >= 1 && FN >= 1, "wave tile");
+    constexpr int KPL = MM::KPL;
+    constexpr int AF4 = BM * BK / 4, BF4 = BN * BK / 4;
+    constexpr int APT = (AF4 + 255) / 256, BPT = (BF4 + 255) / 256;
+    __shared__ __attribute__((aligned(16))) float As[BM * LDSW];
+    __shared__ __attribute__((aligned(16))) float Bs[BN * LDSW];
+
+    const Geom &g = gs.g[blockIdx.z];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WGN, wn = wave % WGN;
+    const long Mimg = (long)g.OH * g.OW;
+    const long M = n_img * Mimg;
+    const long m0 = (long)blockIdx.x * BM;
+    const int n0 = blockIdx.y * BN;
+    if (m0 >= M) return;
+    const int K = g.K;
+
+    // Per-slot source-row state for the A gather (the rows a thread loads never change).
+    const float *abase[APT];
+    int aby[APT], abx[APT], akq[APT], arow[APT];
+    bool aok[APT];
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+        const int f = tid + 256 * i;
+        arow[i] = f >> 2;
+        akq[i] = (f & 3) * 4;
+        const long m = m0 + arow[i];
+        aok[i] = (f < AF4) && (m < M);
+        abase[i] = A;
+        aby[i] = abx[i] = 0;
+        if (aok[i]) {
+            const long img = m / Mimg;
+            const int p = (int)(m - img * Mimg);
+            const int oy = p / g.OW, ox = p - oy * g.OW;
+            if (DENSE) {
+                abase[i] = A + img * K;
+            } else {
+                abase[i] = A + img * (long)g.H * g.W * g.C;
+                aby[i] = oy * g.stride - g.pad_y;
+                abx[i] = ox * g.stride - g.pad_x;
+            }
+        }
+    }
+    const float *bptr[BPT];
+    int brow[BPT], bkq[BPT];
+    bool bok[BPT];
+#pragma unroll
+    for (int i = 0; i < BPT; ++i) {
+        const int f = tid + 256 * i;
+        brow[i] = f >> 2;
+        bkq[i] = (f & 3) * 4;
+        bok[i] = f < BF4;
+        bptr[i] = g.Bt + (long)(n0 + (bok[i] ? brow[i] : 0)) * g.Kp + bkq[i];
+    }
+
+    f32x4v ra[APT], rb[BPT];
+    auto gatherA = [&](int i, int k) -> float {
+        if (DENSE) return k < K ? abase[i][k] : 0.f;
+        if (k >= K) return 0.f;
+        const int tap = k / g.C, c = k - tap * g.C;
+        const int ky = tap / g.kw, kx = tap - ky * g.kw;
+        const int y = aby[i] + ky, x = abx[i] + kx;
+        if ((unsigned)y >= (unsigned)g.H || (unsigned)x >= (unsigned)g.W) return 0.f;
+        return abase[i][((long)y * g.W + x) * g.C + c];
+    };
+    auto loadA = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < APT; ++i) {
+            f32x4v v = {0.f, 0.f, 0.f, 0.f};
+            const int k = k0 + akq[i];
+            if (aok[i]) {
+                if (VEC) {
+                    if (DENSE) {
+                        if (k < K) v = *(const f32x4v *)(abase[i] + k);
+                    } else if (k < K) {
+                        const int tap = k / g.C, c = k - tap * g.C;
+                        const int ky = tap / g.kw, kx = tap - ky * g.kw;
+                        const int y = aby[i] + ky, x = abx[i] + kx;
+                        if ((unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W)
+                            v = *(const f32x4v *)(abase[i] + ((long)y * g.W + x) * g.C + c);
+                    }
+                } else {
+                    v[0] = gatherA(i, k);
+                    v[1] = gatherA(i, k + 1);
+                    v[2] = gatherA(i, k + 2);
+                    v[3] = gatherA(i, k + 3);
+                }
+            }
+            ra[i] = v;
+        }
+    };
+    auto loadB = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < BPT; ++i) {
+            if (bok[i]) rb[i] = *(const f32x4v *)(bptr[i] + k0);
+        }
+    };
+
+    acc_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int v = 0; v < MM::NACC; ++v) acc[i][j][v] = 0.f;
+
+    loadA(0);
+    loadB(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < APT; ++i)
+            if (tid + 256 * i < AF4) *(f32x4v *)(As + arow[i] * LDSW + akq[i]) = ra[i];
+#pragma unroll
+        for (int i = 0; i < BPT; ++i)
+            if (bok[i]) *(f32x4v *)(Bs + brow[i] * LDSW + bkq[i]) = rb[i];
+        __syncthreads();
+        if (k0 + BK < K) {
+            loadA(k0 + BK);
+            loadB(k0 + BK);
+        }
+        float af[FM][KPL], bf[FN][KPL];
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            const float *src = As + (wm * TM + i * MF + MM::idx(lane)) * LDSW + MM::grp(lane) * KPL;
+#pragma unroll
+            for (int q = 0; q < KPL; q += 4) {
+                const f32x4v t = *(const f32x4v *)(src + q);
+                af[i][q] = t[0]; af[i][q + 1] = t[1]; af[i][q + 2] = t[2]; af[i][q + 3] = t[3];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const float *src = Bs + (wn * TN + j * MF + MM::idx(lane)) * LDSW + MM::grp(lane) * KPL;
+#pragma unroll
+            for (int q = 0; q < KPL; q += 4) {
+                const f32x4v t = *(const f32x4v *)(src + q);
+                bf[j][q] = t[0]; bf[j][q + 1] = t[1]; bf[j][q + 2] = t[2]; bf[j][q + 3] = t[3];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < KPL; ++s)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j) acc[i][j] = MM::mma(af[i][s], bf[j][s], acc[i][j]);
+    }
+
+    // ------------------------------------------------------------------ epilogue
+    int ncol[FN];
+    float bcol[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        ncol[j] = n0 + wn * TN + j * MF + MM::col(lane);
+        bcol[j] = ncol[j] < g.N ? epi.colv(ncol[j]) : 0.f;
+    }
+    constexpr int NR = Epi::NRED;
+    const long wrow0 = m0 + wm * TM;
+    const long wlast = (wrow0 + TM - 1 < M ? wrow0 + TM - 1 : M - 1);
+    const bool uniform = NR > 0 && wrow0 < M && (wrow0 / Mimg == wlast / Mimg);
+    float u0 = 0.f, u1 = 0.f;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        float r0[MM::NACC], r1[MM::NACC];
+        long imgs[MM::NACC];
+#pragma unroll
+        for (int v = 0; v < MM::NACC; ++v) {
+            r0[v] = 0.f;
+            r1[v] = 0.f;
+            const long m = wrow0 + i * MF + MM::row(v, lane);
+            imgs[v] = -1;
+            if (m < M) {
+                const long img = m / Mimg;
+                const int p = (int)(m - img * Mimg);
+                const int oy = p / g.OW, ox = p - oy * g.OW;
+                const long dpix = (long)(oy * g.ostr + g.oy0) * g.DW + (ox * g.ostr + g.ox0);
+                imgs[v] = img;
+                const auto rc = epi.row(img);
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    if (ncol[j] < g.N)
+                        epi.elem(rc, img, dpix, ncol[j], dpix * g.N + ncol[j], bcol[j], acc[i][j][v],
+                                 r0[v], r1[v]);
+            }
+        }
+        if (NR > 0) {
+            if (uniform) {
+#pragma unroll
+                for (int v = 0; v < MM::NACC; ++v) {
+                    u0 += r0[v];
+                    u1 += r1[v];
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < MM::NACC; ++v) {
+                    float x0 = r0[v], x1 = r1[v];
+#pragma unroll
+                    for (int mk = 1; mk < MF; mk <<= 1) {
+                        x0 += __shfl_xor(x0, mk, 64);
+                        x1 += __shfl_xor(x1, mk, 64);
+                    }
+                    if (MM::col(lane) == 0 && imgs[v] >= 0) {
+                        atomicAdd(epi.red0() + imgs[v], x0);
+                        atomicAdd(epi.red1() + imgs[v], x1);
+                    }
+                }
+            }
+        }
+    }
+    if (NR > 0 && uniform) {
+#pragma unroll
+        for (int mk = 1; mk < 64; mk <<= 1) {
+            u0 += __shfl_xor(u0, mk, 64);
+            u1 += __shfl_xor(u1, mk, 64);
+        }
+        if (lane == 0) {
+            const long img = wrow0 / Mimg;
+            atomicAdd(epi.red0() + img, u0);
+            atomicAdd(epi.red1() + img, u1);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------- dispatch
+template <class Epi, int MF, int BM, int BN, int WGM, int WGN>
+hipError_t launch_cfg(const GeomSet &gs, const float *A, long n_img, const Epi &epi,
+                      hipStream_t st) {
+    const Geom &g0 = gs.g[0];
+    long Mmax = 0;
+    for (int i = 0; i < gs.n; ++i) {
+        const long M = n_img * (long)gs.g[i].OH * gs.g[i].OW;
+        if (M > Mmax) Mmax = M;
+    }
+    if (Mmax == 0) return hipSuccess;
+    dim3 grid((unsigned)((Mmax + BM - 1) / BM), (unsigned)((g0.N + BN - 1) / BN), (unsigned)gs.n);
+    const bool dense = g0.H == 1 && g0.W == 1 && g0.kh == 1 && g0.kw == 1;
+    const bool vec = (g0.C % 4 == 0) && (g0.K % 4 == 0);
+    if (dense && vec)
+        hipLaunchKernelGGL((k_gemm<Epi, MF, BM, BN, WGM, WGN, true, true>), grid, dim3(256), 0, st, gs, A, n_img, epi);
+    else if (dense)
+        hipLaunchKernelGGL((k_gemm<Epi, MF, BM, BN, WGM, WGN, true, false>), grid, dim3(256), 0, st, gs, A, n_img, epi);
+    else if (vec)
+        hipLaunchKernelGGL((k_gemm<Epi, MF, BM, BN, WGM, WGN, false, true>), grid, dim3(256), 0, st, gs, A, n_img, epi);
+    else
+        hipLaunchKernelGGL((k_gemm<Epi, MF, BM, BN, WGM, WGN, false, false>), grid, dim3(256), 0, st, gs, A, n_img, epi);
+    return hipGetLastError();
+}
+
+template <class Epi>
+hipError_t dispatch(const GeomSet &gs, const float *A, long n_img, const Epi &epi, hipStream_t st) {
+    const int N = gs.g[0].N;
+    if (N >= 128) return launch_cfg<Epi, 32, 128, 128, 2, 2>(gs, A, n_img, epi, st);
+    if (N >= 64) return launch_cfg<Epi, 32, 128, 64, 2, 2>(gs, A, n_img, epi, st);
+    if (N >= 32) return launch_cfg<Epi, 32, 256, 32, 4, 1>(gs, A, n_img, epi, st);
+    return launch_cfg<Epi, 16, 256, 16, 4, 1>(gs, A, n_img, epi, st);
+}
+
+}  // namespace
+
+hipError_t gemm_relax(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
+                      hipStream_t st) {
+    return dispatch(gs, A, n_img, EpiRelax{p}, st);
+}
+hipError_t gemm_conc(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,
+                     hipStream_t st) {
+    return dispatch(gs, A, n_img, EpiConc{p}, st);
+}
+hipError_t gemm_adj(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
+                    hipStream_t st) {
+    return dispatch(gs, A, n_img, EpiAdj{p}, st);
+}
+
+}  // namespace bp

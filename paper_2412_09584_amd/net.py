@@ -1,0 +1,168 @@
+"""Convenience layer over the C ABI: a network handle, full-CROWN intermediate bounds,
+spec bounds, the alpha/beta gradient as a torch.autograd.Function, and the projected
+Adam loop.  It only allocates output tensors and sequences library calls; every step of
+the bound computation runs in libbound.so's kernels.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def _dev(x, device, dtype=torch.float32):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=device)
+
+
+class BoundNet:
+    """A ReLU network (list of layer dicts as produced by ``workloads``) on the GPU."""
+
+    def __init__(self, layers, max_inst, max_rows, max_save_rows=0, device="cuda"):
+        self.device = torch.device(device)
+        self.layers = []
+        prev = None
+        for L in layers:
+            d = dict(L)
+            d["W"] = _dev(L["W"], self.device)
+            d["b"] = _dev(L["b"], self.device)
+            if L["kind"] == "linear" and prev is not None and prev["kind"] == "conv":
+                d["in_view"] = tuple(prev["out_shape"])
+            self.layers.append(d)
+            prev = L
+        self.max_inst, self.max_rows, self.max_save_rows = max_inst, max_rows, max_save_rows
+        self.handle = B.bound_init(self.layers, max_inst, max_rows, max_save_rows)
+        self.d, self.n_relu = B.bound_dims(self.handle)
+        self.L = len(self.layers)
+        self.relu_off = [0]
+        for w in self.d[1:-1]:
+            self.relu_off.append(self.relu_off[-1] + w)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            B.bound_destroy(h)
+            self.handle = None
+
+    # ------------------------------------------------------------------ passes
+    def crown_bounds(self, x_lo, x_hi, slack=True):
+        """Full CROWN pre-activation bounds of z_1 .. z_{L-1}: (lo, hi) [n, n_relu]."""
+        x_lo = _dev(x_lo, self.device)
+        x_hi = _dev(x_hi, self.device)
+        n = x_lo.shape[0]
+        lo = torch.zeros(n, max(self.n_relu, 1), device=self.device)
+        hi = torch.zeros_like(lo)
+        flags = B.BOUND_BOTH_SIDES | (0 if slack else B.BOUND_NO_SLACK)
+        for k in range(1, self.L):
+            off = self.relu_off[k - 1]
+            B.bound_backward(self.handle, n, self.d[k], k, lo=lo, hi=hi, n_bounds=n, x_lo=x_lo,
+                             x_hi=x_hi, flags=flags, lower=lo[:, off:], upper=hi[:, off:],
+                             ld=self.n_relu)
+        return lo, hi
+
+    def spec_bounds(self, C, lo, hi, x_lo, x_hi, *, target=None, alpha=None, bound_of=None,
+                    splits=None, beta=None, both=True, slack=True, save=False, best=None):
+        """Bounds of C z_target.  Returns (lower, upper or None)."""
+        target = self.L if target is None else target
+        C = _dev(C, self.device)
+        n, rows = C.shape[0], C.shape[1]
+        lower = torch.empty(n, rows, device=self.device)
+        upper = torch.empty(n, rows, device=self.device) if both else None
+        flags = (B.BOUND_BOTH_SIDES if both else 0) | (0 if slack else B.BOUND_NO_SLACK) | \
+            (B.BOUND_SAVE_FOR_GRAD if save else 0)
+        kw = {}
+        if splits is not None:
+            kw = dict(split_off=splits["off"], split_idx=splits["idx"], split_sign=splits["sign"],
+                      nnz=int(splits["idx"].numel()))
+        n_bounds = lo.shape[0] if lo is not None else 0
+        B.bound_backward(self.handle, n, rows, target, spec=C, lo=lo, hi=hi, n_bounds=n_bounds,
+                         bound_of=bound_of, alpha=alpha, beta=beta, x_lo=_dev(x_lo, self.device),
+                         x_hi=_dev(x_hi, self.device), flags=flags, lower=lower, upper=upper,
+                         best=best, **kw)
+        return lower, upper
+
+    def coefficients(self, C, lo, hi, *, target=None, alpha=None, both=False):
+        """Coefficient form (W~(1), b~(1), sum |terms| of b~(1)) without concretisation."""
+        target = self.L if target is None else target
+        C = _dev(C, self.device)
+        n, rows = C.shape[0], C.shape[1]
+        tot = n * rows * (2 if both else 1)
+        coeff = torch.empty(tot, self.d[0], device=self.device)
+        offset = torch.empty(tot, device=self.device)
+        mag = torch.empty(tot, device=self.device)
+        B.bound_backward(self.handle, n, rows, target, spec=C, lo=lo, hi=hi,
+                         n_bounds=lo.shape[0] if lo is not None else 0, alpha=alpha,
+                         flags=B.BOUND_BOTH_SIDES if both else 0, coeff=coeff, offset=offset,
+                         offset_mag=mag)
+        return coeff, offset, mag
+
+    def grad(self, grad_lower, nnz=0, rows=None):
+        """d(sum grad_lower * lower_raw)/d(alpha, beta) of the last saved pass."""
+        n = grad_lower.shape[0]
+        ga = torch.empty(n, self.n_relu, device=self.device)
+        gb = torch.empty(nnz, grad_lower.shape[1], device=self.device) if nnz else None
+        B.bound_grad(self.handle, grad_lower.contiguous(), ga, gb)
+        return ga, gb
+
+
+def splits_to_device(sp, device="cuda"):
+    """workloads.Splits -> dict of device tensors for the C ABI."""
+    return {"off": torch.as_tensor(sp.off, dtype=torch.int32, device=device),
+            "idx": torch.as_tensor(sp.neuron, dtype=torch.int32, device=device),
+            "sign": torch.as_tensor(sp.sign, dtype=torch.int8, device=device)}
+
+
+class CrownBound(torch.autograd.Function):
+    """lower = CROWN bound of C z_L as a function of (alpha, beta); backward = bound_grad."""
+
+    @staticmethod
+    def forward(ctx, alpha, beta, net, C, lo, hi, x_lo, x_hi, bound_of, splits, best):
+        lower, _ = net.spec_bounds(C, lo, hi, x_lo, x_hi, alpha=alpha.detach(),
+                                   beta=None if beta is None else beta.detach(),
+                                   bound_of=bound_of, splits=splits, both=False, save=True,
+                                   best=best)
+        ctx.net = net
+        ctx.nnz = 0 if splits is None else int(splits["idx"].numel())
+        ctx.has_beta = beta is not None
+        return lower
+
+    @staticmethod
+    def backward(ctx, grad_lower):
+        ga, gb = ctx.net.grad(grad_lower, ctx.nnz)
+        return (ga, gb if ctx.has_beta else None) + (None,) * 9
+
+
+def optimize_alpha_beta(net, C, lo, hi, x_lo, x_hi, *, steps=10, lr=0.1, alpha0=0.5,
+                        bound_of=None, splits=None, use_beta=True, lower_of_step=None):
+    """Projected Adam on (alpha, beta) maximising sum of lower bounds; returns best lower.
+
+    Each step: bound pass with SAVE_FOR_GRAD (best-so-far fused), bound_grad with
+    grad_lower = 1, then one Adam step each for alpha (clip [0, 1]) and beta (clip >= 0).
+    """
+    dev = net.device
+    C = _dev(C, dev)
+    n, rows = C.shape[0], C.shape[1]
+    nnz = 0 if splits is None else int(splits["idx"].numel())
+    alpha = torch.full((n, net.n_relu), float(alpha0), device=dev)
+    ma, va = torch.zeros_like(alpha), torch.zeros_like(alpha)
+    beta = torch.zeros(nnz, rows, device=dev) if (use_beta and nnz) else None
+    if beta is not None:
+        mb, vb = torch.zeros_like(beta), torch.zeros_like(beta)
+    best = torch.full((n, rows), -float("inf"), device=dev)
+    ones = torch.ones(n, rows, device=dev)
+    ga = torch.empty(n, net.n_relu, device=dev)
+    gb = torch.empty(nnz, rows, device=dev) if beta is not None else None
+    for t in range(1, steps + 1):
+        lower, _ = net.spec_bounds(C, lo, hi, x_lo, x_hi, alpha=alpha, beta=beta, bound_of=bound_of,
+                                   splits=splits, both=False, save=True, best=best)
+        if lower_of_step is not None:
+            lower_of_step.append(lower.clone())
+        B.bound_grad(net.handle, ones, ga, gb)
+        B.bound_adam(alpha, ga, ma, va, t, lr, grad_scale=-1.0, clip_lo=0.0, clip_hi=1.0)
+        if beta is not None:
+            B.bound_adam(beta, gb, mb, vb, t, lr, grad_scale=-1.0, clip_lo=0.0)
+    net.spec_bounds(C, lo, hi, x_lo, x_hi, alpha=alpha, beta=beta, bound_of=bound_of,
+                    splits=splits, both=False, best=best)
+    return best, alpha, beta

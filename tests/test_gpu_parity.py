@@ -1,0 +1,467 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle.
+
+Bar: |gpu - oracle| <= 1e-4 * max(|oracle|, 1) for every bound; gradients
+||g - o||_inf <= 1e-4 * ||o||_inf per instance, at identical alpha / beta.
+Stage-wise checks hand both sides the same (oracle-computed, FP32-rounded)
+intermediate bounds, so the stable / unstable classes agree; end-to-end checks let each
+side compute its own intermediate bounds.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import crown as O
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def mod():
+    _need_gpu()
+    from paper_2412_09584_amd import net as N
+    from paper_2412_09584_amd import binding as B
+    return N, B
+
+
+def close(g, o, rel=1e-4, what=""):
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    both_inf = np.isinf(g) & np.isinf(o) & (np.sign(g) == np.sign(o))
+    err = np.where(both_inf, 0.0, np.abs(g - o))
+    lim = rel * np.maximum(np.abs(np.where(both_inf, 0.0, o)), 1.0)
+    bad = err > lim
+    assert not bad.any(), (f"{what}: {bad.sum()} of {bad.size} beyond tolerance; worst "
+                           f"{float(np.max(err / lim))} x tol, e.g. gpu {g[bad][:3]} oracle {o[bad][:3]}")
+
+
+def np_(t):
+    return t.detach().double().cpu().numpy()
+
+
+def oracle_bounds(net, x_lo, x_hi, slack=True):
+    return [O.crown_bounds(net, x_lo[i], x_hi[i], use_slack=slack) for i in range(len(x_lo))]
+
+
+def flat(bounds_list):
+    lo = np.stack([np.concatenate([b[0] for b in bl]) for bl in bounds_list])
+    hi = np.stack([np.concatenate([b[1] for b in bl]) for bl in bounds_list])
+    return lo, hi
+
+
+def split_layers(net, flat_row):
+    return O.per_layer(net, flat_row)
+
+
+def f32(x):
+    return np.asarray(x, np.float32)
+
+
+def dev(x, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def tiny_cnn(seed=5, H=12, convs=((8, 3, 1), (8, 4, 2), (16, 3, 1), (16, 4, 2)), fc=(32, 5), cin=3):
+    return W.cnn(seed=seed, in_shape=(cin, H, H), spec=list(convs), fc=fc)
+
+
+# ---------------------------------------------------------------------------- passes
+def test_single_linear_layer(mod):
+    N, B = mod
+    net = W.mlp([20, 6], seed=3)
+    x0 = W.uniform_inputs(4, 20, 4)
+    lo_x, hi_x = W.linf_box(x0, 0.05)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    bn = N.BoundNet(net, 8, 256)
+    low, up = bn.spec_bounds(C, None, None, lo_x, hi_x, slack=False)
+    for i in range(4):
+        close(np_(low)[i], O.spec_lower(net, 1, C[i], [], lo_x[i], hi_x[i], use_slack=False), what="lower")
+        close(np_(up)[i], -O.spec_lower(net, 1, -C[i].astype(np.float64), [], lo_x[i], hi_x[i],
+                                       use_slack=False), what="upper")
+
+
+@pytest.mark.parametrize("slack", [True, False])
+def test_mlp_small_stagewise_and_end_to_end(mod, slack):
+    N, B = mod
+    w = W.mlp_small()
+    ob = oracle_bounds(w.net, w.x_lo, w.x_hi, slack)
+    lo, hi = flat(ob)
+    bn = N.BoundNet(w.net, 4, 4096)
+    # stage-wise: every target k with the oracle's bounds of the layers below (FP32)
+    lo32, hi32 = dev(f32(lo)), dev(f32(hi))
+    below = [(l.astype(np.float32).astype(np.float64), u.astype(np.float32).astype(np.float64))
+             for (l, u) in ob[0]]
+    flags = B.BOUND_BOTH_SIDES | (0 if slack else B.BOUND_NO_SLACK)
+    for k in range(1, len(w.net)):
+        d = bn.d[k]
+        glo = torch.empty(1, d, device="cuda")
+        ghi = torch.empty(1, d, device="cuda")
+        B.bound_backward(bn.handle, 1, d, k, lo=lo32, hi=hi32, n_bounds=1, x_lo=dev(w.x_lo),
+                         x_hi=dev(w.x_hi), flags=flags, lower=glo, upper=ghi)
+        I = np.eye(d)
+        olo = O.spec_lower(w.net, k, I, below[:k - 1], w.x_lo[0], w.x_hi[0], use_slack=slack)
+        ohi = -O.spec_lower(w.net, k, -I, below[:k - 1], w.x_lo[0], w.x_hi[0], use_slack=slack)
+        close(np_(glo)[0], olo, what=f"stage lo z{k}")
+        close(np_(ghi)[0], ohi, what=f"stage hi z{k}")
+    gl, gu = bn.spec_bounds(w.spec, lo32, hi32, w.x_lo, w.x_hi, slack=slack)
+    L = len(w.net)
+    close(np_(gl)[0], O.spec_lower(w.net, L, w.spec[0], below, w.x_lo[0], w.x_hi[0], use_slack=slack),
+          what="stage final lower")
+    # end to end
+    glo_all, ghi_all = bn.crown_bounds(w.x_lo, w.x_hi, slack=slack)
+    close(np_(glo_all), lo, what="e2e lo")
+    close(np_(ghi_all), hi, what="e2e hi")
+    el, eu = bn.spec_bounds(w.spec, glo_all, ghi_all, w.x_lo, w.x_hi, slack=slack)
+    ol = O.spec_lower(w.net, L, w.spec[0], ob[0], w.x_lo[0], w.x_hi[0], use_slack=slack)
+    close(np_(el)[0], ol, what="e2e final")
+
+
+def test_mlp_deep_full_batch_sampled(mod):
+    """784-256x6-10, all 256 inputs in one launch; 6 inputs checked against the oracle."""
+    N, B = mod
+    w = W.mlp_deep(256)
+    bn = N.BoundNet(w.net, 256, 256 * 512)
+    glo, ghi = bn.crown_bounds(w.x_lo, w.x_hi)
+    gl, gu = bn.spec_bounds(w.spec, glo, ghi, w.x_lo, w.x_hi)
+    L = len(w.net)
+    for i in (0, 1, 77, 128, 200, 255):
+        ob = O.crown_bounds(w.net, w.x_lo[i], w.x_hi[i])
+        lo, hi = flat([ob])
+        close(np_(glo)[i], lo[0], what=f"lo inst {i}")
+        close(np_(ghi)[i], hi[0], what=f"hi inst {i}")
+        close(np_(gl)[i], O.spec_lower(w.net, L, w.spec[i], ob, w.x_lo[i], w.x_hi[i]), what="final lo")
+        close(np_(gu)[i], -O.spec_lower(w.net, L, -w.spec[i].astype(np.float64), ob, w.x_lo[i],
+                                        w.x_hi[i]), what="final hi")
+
+
+CNN_GEOMS = [
+    dict(H=12, convs=((8, 3, 1), (8, 4, 2), (16, 3, 1), (16, 4, 2)), fc=(32, 5), cin=3),
+    dict(H=7, convs=((4, 3, 2), (6, 3, 1)), fc=(10, 3), cin=2),     # odd size, k3 s2
+    dict(H=9, convs=((5, 4, 2), (3, 2, 2)), fc=(7,), cin=1),        # k4 s2 on odd, k2 s2
+    dict(H=6, convs=((33, 3, 1), (17, 3, 1)), fc=(9, 4), cin=4),    # N not a tile multiple
+]
+
+
+@pytest.mark.parametrize("gi", range(len(CNN_GEOMS)))
+def test_cnn_small_end_to_end(mod, gi):
+    N, B = mod
+    net = tiny_cnn(seed=10 + gi, **CNN_GEOMS[gi])
+    n = 3
+    x0 = W.uniform_inputs(n, W.in_dim(net), 20 + gi)
+    x_lo, x_hi = W.linf_box(x0, 0.03)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    bn = N.BoundNet(net, n, 1 << 16)
+    glo, ghi = bn.crown_bounds(x_lo, x_hi)
+    gl, gu = bn.spec_bounds(C, glo, ghi, x_lo, x_hi)
+    L = len(net)
+    for i in range(n):
+        ob = O.crown_bounds(net, x_lo[i], x_hi[i])
+        lo, hi = flat([ob])
+        close(np_(glo)[i], lo[0], what=f"lo {i}")
+        close(np_(ghi)[i], hi[0], what=f"hi {i}")
+        close(np_(gl)[i], O.spec_lower(net, L, C[i], ob, x_lo[i], x_hi[i]), what="final lo")
+        close(np_(gu)[i], -O.spec_lower(net, L, -C[i].astype(np.float64), ob, x_lo[i], x_hi[i]),
+              what="final hi")
+
+
+def test_chunked_passes_match_unchunked(mod):
+    N, B = mod
+    net = tiny_cnn(seed=31)
+    x0 = W.uniform_inputs(5, W.in_dim(net), 32)
+    x_lo, x_hi = W.linf_box(x0, 0.02)
+    big = N.BoundNet(net, 5, 1 << 16)
+    small = N.BoundNet(net, 5, 97)          # forces ragged chunks inside instances
+    a = big.crown_bounds(x_lo, x_hi)
+    b = small.crown_bounds(x_lo, x_hi)
+    close(np_(b[0]), np_(a[0]), rel=1e-6, what="chunked lo")
+    close(np_(b[1]), np_(a[1]), rel=1e-6, what="chunked hi")
+
+
+def test_coefficients_and_standalone_concretize(mod):
+    N, B = mod
+    w = W.mlp_small()
+    ob = oracle_bounds(w.net, w.x_lo, w.x_hi)
+    lo, hi = flat(ob)
+    lo32, hi32 = dev(f32(lo)), dev(f32(hi))
+    bn = N.BoundNet(w.net, 2, 4096)
+    coeff, offset, mag = bn.coefficients(w.spec, lo32, hi32)
+    below = [(l.astype(np.float32).astype(np.float64), u.astype(np.float32).astype(np.float64))
+             for (l, u) in ob[0]]
+    Wt, bt, omag = O.backward(w.net, len(w.net), w.spec[0], below)
+    close(np_(coeff), Wt, what="coeff")
+    close(np_(offset), bt, what="offset")
+    lower = torch.empty(1, 9, device="cuda")
+    B.bound_concretize(1, 9, bn.d[0], coeff, offset, mag, dev(w.x_lo), dev(w.x_hi), 0, lower)
+    gl, _ = bn.spec_bounds(w.spec, lo32, hi32, w.x_lo, w.x_hi, both=False)
+    close(np_(lower), np_(gl), rel=1e-5, what="standalone vs fused")
+    ol = O.concretize(Wt, bt, w.x_lo[0], w.x_hi[0]) - O.slack(Wt, omag, w.x_lo[0], w.x_hi[0])
+    close(np_(lower)[0], ol, what="standalone vs oracle")
+
+
+def test_eps_zero_and_first_layer(mod):
+    N, B = mod
+    net = tiny_cnn(seed=41)
+    x0 = W.uniform_inputs(2, W.in_dim(net), 42)
+    bn = N.BoundNet(net, 2, 1 << 16)
+    glo, ghi = bn.crown_bounds(x0, x0, slack=False)
+    zs = O.forward(net, x0)
+    off = 0
+    for m in range(len(net) - 1):
+        d = zs[m].shape[1]
+        close(np_(glo)[:, off:off + d], zs[m], what=f"eps0 lo z{m + 1}")
+        close(np_(ghi)[:, off:off + d], zs[m], what=f"eps0 hi z{m + 1}")
+        off += d
+
+
+# ------------------------------------------------------------------ alpha / beta
+def _random_splits(net, bounds_flat_lo, bounds_flat_hi, n_sub, seed, root_of=None):
+    cands = [np.nonzero((l < 0) & (u > 0))[0] for l, u in zip(bounds_flat_lo, bounds_flat_hi)]
+    return W.random_splits(cands, n_sub, 1, 12, seed=seed, root_of=root_of)
+
+
+def _oracle_unit(net, C, lo_row, hi_row, x_lo, x_hi, alpha_row, sp, q0, q1, beta, slack=True):
+    """Oracle lower bound (with slack) and raw gradients for one subdomain."""
+    bounds = list(zip(O.per_layer(net, lo_row), O.per_layer(net, hi_row)))
+    splits = O.split_list(net, sp.neuron[q0:q1], sp.sign[q0:q1])
+    al = O.per_layer(net, alpha_row)
+    be = None if beta is None else beta[q0:q1]
+    L = len(net)
+    low = O.spec_lower(net, L, C, bounds, x_lo, x_hi, al, splits, be, use_slack=slack)
+    _, ga, gb = O.spec_lower_grad(net, L, C, bounds, x_lo, x_hi, al, splits,
+                                  np.zeros((q1 - q0, C.shape[0])) if be is None else be)
+    return low, np.concatenate(ga), gb
+
+
+@pytest.mark.parametrize("kind", ["mlp", "cnn"])
+def test_alpha_beta_pass_and_grad(mod, kind):
+    N, B = mod
+    if kind == "mlp":
+        net = W.mlp([30, 24, 24, 24, 6], seed=51)
+    else:
+        net = tiny_cnn(seed=52)
+    n_roots, per_root = 2, 6
+    x0 = W.uniform_inputs(n_roots, W.in_dim(net), 53)
+    x_lo, x_hi = W.linf_box(x0, 0.05)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    ob = oracle_bounds(net, x_lo, x_hi)
+    lo, hi = flat(ob)
+    lo, hi = f32(lo).astype(np.float64), f32(hi).astype(np.float64)
+    n = n_roots * per_root
+    root_of = np.repeat(np.arange(n_roots), per_root).astype(np.int32)
+    sp = _random_splits(net, lo, hi, n, 54, root_of)
+    n_relu = lo.shape[1]
+    alpha = W.random_alpha(n, n_relu, 55)
+    beta = W.random_beta(sp.nnz, C.shape[1], 56)
+    Cs = C[root_of]
+    bn = N.BoundNet(net, n, 4096, 4096)
+    spd = N.splits_to_device(sp)
+    gl, _ = bn.spec_bounds(Cs, dev(f32(lo)), dev(f32(hi)), x_lo[root_of], x_hi[root_of],
+                           alpha=dev(alpha), bound_of=dev(root_of, torch.int32), splits=spd,
+                           beta=dev(beta), both=False, save=True)
+    ga, gb = bn.grad(torch.ones(n, C.shape[1], device="cuda"), sp.nnz)
+    ga, gb = np_(ga), np_(gb)
+    for i in range(n):
+        r = root_of[i]
+        q0, q1 = sp.off[i], sp.off[i + 1]
+        low, oga, ogb = _oracle_unit(net, C[r], lo[r], hi[r], x_lo[r], x_hi[r], alpha[i], sp, q0, q1,
+                                     beta.astype(np.float64))
+        close(np_(gl)[i], low, what=f"lower {i}")
+        scale = max(np.max(np.abs(oga)), 1e-30)
+        assert np.max(np.abs(ga[i] - oga)) <= 1e-4 * scale, f"grad alpha {i}"
+        if q1 > q0:
+            sb = max(np.max(np.abs(ogb)), 1e-30)
+            assert np.max(np.abs(gb[q0:q1] - ogb)) <= 1e-4 * max(sb, scale), f"grad beta {i}"
+
+
+def test_infeasible_split_gives_inf(mod):
+    N, B = mod
+    net = W.mlp([10, 12, 12, 3], seed=61)
+    x0 = W.uniform_inputs(1, 10, 62)
+    x_lo, x_hi = W.linf_box(x0, 0.1)
+    ob = oracle_bounds(net, x_lo, x_hi)
+    lo, hi = flat(ob)
+    j = int(np.argmin(hi[0]))
+    assert hi[0, j] < 0
+    sp = W.Splits(np.array([0, 1, 2], np.int32), np.array([j, j], np.int32),
+                  np.array([1, -1], np.int8))   # instance 0: infeasible; instance 1: consistent
+    bn = N.BoundNet(net, 2, 256, 256)
+    C = np.eye(3)[None].repeat(2, 0)
+    gl, _ = bn.spec_bounds(C, dev(f32(lo)), dev(f32(hi)), np.repeat(x_lo, 2, 0), np.repeat(x_hi, 2, 0),
+                           bound_of=dev(np.zeros(2), torch.int32), splits=N.splits_to_device(sp),
+                           both=False, save=True)
+    g = np_(gl)
+    assert np.all(np.isinf(g[0])) and np.all(g[0] > 0)
+    assert np.all(np.isfinite(g[1]))
+    ga, _ = bn.grad(torch.ones(2, 3, device="cuda"), 2)
+    assert np.all(np_(ga)[0] == 0)
+
+
+def test_adam_kernel(mod):
+    N, B = mod
+    rng = np.random.default_rng(71)
+    p0 = rng.uniform(0, 1, 1000)
+    p, m, v = dev(p0), torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
+    op, om, ov = p0.astype(np.float32).astype(np.float64), np.zeros(1000), np.zeros(1000)
+    for t in range(1, 6):
+        g = rng.normal(size=1000)
+        B.bound_adam(p, dev(g), m, v, t, 0.1, grad_scale=-1.0, clip_lo=0.0, clip_hi=1.0)
+        op, om, ov = O.adam_step(op, -g.astype(np.float32).astype(np.float64), om, ov, t, 0.1,
+                                 lo=0.0, hi=1.0)
+    close(np_(p), op, rel=1e-5, what="adam")
+
+
+def test_optimisation_loop_improves_and_first_step_matches(mod):
+    N, B = mod
+    net = tiny_cnn(seed=81)
+    n_roots, per_root = 2, 4
+    x0 = W.uniform_inputs(n_roots, W.in_dim(net), 82)
+    x_lo, x_hi = W.linf_box(x0, 0.05)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    ob = oracle_bounds(net, x_lo, x_hi)
+    lo, hi = flat(ob)
+    lo, hi = f32(lo).astype(np.float64), f32(hi).astype(np.float64)
+    n = n_roots * per_root
+    root_of = np.repeat(np.arange(n_roots), per_root).astype(np.int32)
+    sp = _random_splits(net, lo, hi, n, 83, root_of)
+    bn = N.BoundNet(net, n, 4096, 4096)
+    steps = []
+    best, alpha, beta = N.optimize_alpha_beta(bn, C[root_of], dev(f32(lo)), dev(f32(hi)), x_lo[root_of],
+                                              x_hi[root_of], steps=10, lr=0.1,
+                                              bound_of=dev(root_of, torch.int32),
+                                              splits=N.splits_to_device(sp), lower_of_step=steps)
+    first = np_(steps[0])
+    for i in range(n):
+        r = root_of[i]
+        q0, q1 = sp.off[i], sp.off[i + 1]
+        a0 = np.full(lo.shape[1], 0.5)
+        low, _, _ = _oracle_unit(net, C[r], lo[r], hi[r], x_lo[r], x_hi[r], a0, sp, q0, q1,
+                                 np.zeros((sp.nnz, C.shape[1])))
+        close(first[i], low, what=f"step-1 bound {i}")
+    b = np_(best)
+    assert np.all(b >= first - 1e-6)
+    assert np.mean(b - first) > 0
+    al = np_(alpha)
+    assert al.min() >= 0 and al.max() <= 1
+    if beta is not None:
+        assert np_(beta).min() >= 0
+
+
+# -------------------------------------------------------------------------- soundness
+@pytest.mark.parametrize("dims,seed", [([2, 8, 8, 3], 91), ([2, 16, 16, 16, 2], 92), ([2, 12, 3], 93)])
+def test_soundness_tiny_2d(mod, dims, seed):
+    N, B = mod
+    net = W.mlp(dims, seed=seed)
+    x_lo = np.array([[-1.0, -0.5]], np.float32)
+    x_hi = np.array([[0.5, 1.0]], np.float32)
+    rng = np.random.default_rng(seed)
+    pts = np.concatenate([x_lo + (x_hi - x_lo) * rng.uniform(0, 1, (100_000, 2)),
+                          np.stack(np.meshgrid(np.linspace(-1, 0.5, 317), np.linspace(-0.5, 1, 317),
+                                               indexing="ij"), -1).reshape(-1, 2)])
+    zs = O.forward(net, pts)
+    bn = N.BoundNet(net, 64, 4096, 4096)
+    glo, ghi = bn.crown_bounds(x_lo, x_hi)
+    lo_np, hi_np = np_(glo)[0], np_(ghi)[0]
+    off = 0
+    for m in range(len(net) - 1):
+        d = zs[m].shape[1]
+        assert np.all(zs[m] >= lo_np[off:off + d]) and np.all(zs[m] <= hi_np[off:off + d])
+        off += d
+    k = dims[-1]
+    C = np.concatenate([np.eye(k), -np.eye(k)])[None]
+    f = zs[-1] @ C[0].T
+    # random alpha, beta and splits over many subdomains at once
+    n = 48
+    unst = np.nonzero((lo_np < 0) & (hi_np > 0))[0]
+    sp = W.random_splits([unst], n, 1, min(4, len(unst)), seed=seed)
+    alpha = W.random_alpha(n, lo_np.size, seed + 1)
+    beta = W.random_beta(sp.nnz, C.shape[1], seed + 2, scale=2.0)
+    gl, _ = bn.spec_bounds(np.repeat(C, n, 0), glo, ghi, np.repeat(x_lo, n, 0), np.repeat(x_hi, n, 0),
+                           alpha=dev(alpha), bound_of=dev(np.zeros(n), torch.int32),
+                           splits=N.splits_to_device(sp), beta=dev(beta), both=False)
+    g = np_(gl)
+    checked = 0
+    for i in range(n):
+        feas = np.ones(len(pts), bool)
+        for q in range(sp.off[i], sp.off[i + 1]):
+            gidx, sg = int(sp.neuron[q]), int(sp.sign[q])
+            m = int(np.searchsorted(np.cumsum([zz.shape[1] for zz in zs[:-1]]), gidx, side="right"))
+            j = gidx - int(np.sum([zz.shape[1] for zz in zs[:m]]))
+            feas &= sg * zs[m][:, j] >= 0
+        if feas.sum() == 0:
+            continue
+        assert np.all(f[feas].min(axis=0) >= g[i]), f"unsound subdomain {i}"
+        checked += 1
+    assert checked >= 10
+
+
+# ------------------------------------------------------------- full-size workloads
+@pytest.fixture(scope="module")
+def golden_cnn():
+    path = os.path.join(GOLDEN, "cnn_root0.npz")
+    if not os.path.exists(path):
+        pytest.skip("tests/golden/cnn_root0.npz missing (run tests/golden/make_cnn_root.py)")
+    return dict(np.load(path))
+
+
+def test_cnn_full_batch_against_golden(mod, golden_cnn):
+    """3x32x32 CNN, 64 inputs in one full-CROWN launch; input 0 against the stored oracle."""
+    N, B = mod
+    w = W.cnn_cifar(64)
+    bn = N.BoundNet(w.net, 64, 36864)
+    glo, ghi = bn.crown_bounds(w.x_lo, w.x_hi)
+    gl, gu = bn.spec_bounds(w.spec, glo, ghi, w.x_lo, w.x_hi)
+    lo0, hi0 = np_(glo)[0], np_(ghi)[0]
+    flips = int(np.sum(((lo0 < 0) & (hi0 > 0)) != ((golden_cnn["lo"] < 0) & (golden_cnn["hi"] > 0))))
+    print(f"stability flips vs oracle: {flips}")
+    close(lo0, golden_cnn["lo"], what="e2e lo")
+    close(hi0, golden_cnn["hi"], what="e2e hi")
+    close(np_(gl)[0], golden_cnn["lower"], what="e2e final lower")
+    close(np_(gu)[0], golden_cnn["upper"], what="e2e final upper")
+    # stage-wise final pass from the oracle's bounds
+    lo32 = dev(f32(golden_cnn["lo"])[None])
+    hi32 = dev(f32(golden_cnn["hi"])[None])
+    sl, su = bn.spec_bounds(w.spec[:1], lo32, hi32, w.x_lo[:1], w.x_hi[:1])
+    b64 = list(zip(O.per_layer(w.net, f32(golden_cnn["lo"]).astype(np.float64)),
+                   O.per_layer(w.net, f32(golden_cnn["hi"]).astype(np.float64))))
+    close(np_(sl)[0], O.spec_lower(w.net, len(w.net), w.spec[0], b64, w.x_lo[0], w.x_hi[0]),
+          what="stage final")
+
+
+def test_beta_crown_batch_full_size(mod, golden_cnn):
+    """4096 subdomains x 9 rows with 1-12 splits, random alpha / beta, one pass + gradient
+    (the bench's launch); 6 subdomains against the oracle."""
+    N, B = mod
+    w = W.cnn_cifar(1)
+    lo = f32(golden_cnn["lo"]).astype(np.float64)
+    hi = f32(golden_cnn["hi"]).astype(np.float64)
+    n = 4096
+    root_of = np.zeros(n, np.int32)
+    sp = W.random_splits([np.nonzero((lo < 0) & (hi > 0))[0]], n, 1, 12, seed=2, root_of=root_of)
+    n_relu = lo.size
+    alpha = W.random_alpha(n, n_relu, 3)
+    beta = W.random_beta(sp.nnz, 9, 4)
+    bn = N.BoundNet(w.net, n, n * 9, n * 9)
+    Cs = np.repeat(w.spec, n, 0)
+    gl, _ = bn.spec_bounds(Cs, dev(f32(lo)[None]), dev(f32(hi)[None]), np.repeat(w.x_lo, n, 0),
+                           np.repeat(w.x_hi, n, 0), alpha=dev(alpha), bound_of=dev(root_of, torch.int32),
+                           splits=N.splits_to_device(sp), beta=dev(beta), both=False, save=True)
+    ga, gb = bn.grad(torch.ones(n, 9, device="cuda"), sp.nnz)
+    gl, ga, gb = np_(gl), np_(ga), np_(gb)
+    for i in (0, 1, 1000, 2047, 3001, 4095):
+        q0, q1 = sp.off[i], sp.off[i + 1]
+        low, oga, ogb = _oracle_unit(w.net, w.spec[0], lo, hi, w.x_lo[0], w.x_hi[0], alpha[i], sp,
+                                     q0, q1, beta.astype(np.float64))
+        close(gl[i], low, what=f"lower {i}")
+        scale = np.max(np.abs(oga))
+        assert np.max(np.abs(ga[i] - oga)) <= 1e-4 * scale, f"grad alpha {i}"
+        sb = max(np.max(np.abs(ogb)), scale)
+        assert np.max(np.abs(gb[q0:q1] - ogb)) <= 1e-4 * sb, f"grad beta {i}"
