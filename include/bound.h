@@ -187,6 +187,15 @@ bound_status bound_adam(int64_t n, float *param, const float *grad, float *m, fl
                         int32_t step, float lr, float b1, float b2, float eps,
                         float grad_scale, float clip_lo, float clip_hi, void *stream);
 
+/* Per-launch timing: with enable != 0 every kernel the handle launches is bracketed by
+ * HIP events recorded on its own stream (not while the stream is being captured).
+ * bound_profile_read waits for the recorded events, adds their durations per kernel
+ * label since the last read, and fills up to cap entries: names (cap x 48 chars,
+ * NUL-terminated), total_ms and count; returns the number of labels (or < 0 on error). */
+bound_status bound_profile(bound_net *net, int32_t enable);
+int32_t bound_profile_read(bound_net *net, int32_t cap, char *names, double *total_ms,
+                           int32_t *count);
+
 void bound_destroy(bound_net *net);
 const char *bound_last_error(void);
 

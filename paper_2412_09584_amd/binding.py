@@ -18,7 +18,8 @@ BOUND_LINEAR, BOUND_CONV2D = 0, 1
 BOUND_SAVE_FOR_GRAD, BOUND_NO_SLACK, BOUND_BOTH_SIDES = 1, 2, 4
 
 EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "bound_grad",
-            "bound_adam", "bound_destroy", "bound_last_error")
+            "bound_adam", "bound_profile", "bound_profile_read", "bound_destroy",
+            "bound_last_error")
 
 _p = ctypes.c_void_p
 
@@ -71,11 +72,17 @@ def lib():
         L.bound_adam.argtypes = [ctypes.c_int64, _p, _p, _p, _p, ctypes.c_int32, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, _p]
+        L.bound_profile.argtypes = [_p, ctypes.c_int32]
+        L.bound_profile_read.argtypes = [_p, ctypes.c_int32, ctypes.c_char_p,
+                                         ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int32)]
+        L.bound_profile_read.restype = ctypes.c_int32
         L.bound_destroy.argtypes = [_p]
         L.bound_destroy.restype = None
         L.bound_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[:-2]:
-            getattr(L, name).restype = ctypes.c_int
+            if name != "bound_profile_read":
+                getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
 
@@ -155,6 +162,26 @@ def bound_adam(param, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8, grad_sca
     _check(lib().bound_adam(param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), int(step),
                             float(lr), float(b1), float(b2), float(eps), float(grad_scale),
                             float(clip_lo), float(clip_hi), _stream(stream)))
+
+
+def bound_profile(handle, enable=True):
+    _check(lib().bound_profile(handle, 1 if enable else 0))
+
+
+def bound_profile_read(handle, cap=256):
+    """{label: (total_ms, launches)} since the last read."""
+    names = ctypes.create_string_buffer(48 * cap)
+    tot = (ctypes.c_double * cap)()
+    cnt = (ctypes.c_int32 * cap)()
+    n = lib().bound_profile_read(handle, cap, names, tot, cnt)
+    if n < 0:
+        _check(n)
+    raw = names.raw
+    out = {}
+    for i in range(n):
+        nm = raw[48 * i:48 * (i + 1)].split(b"\0", 1)[0].decode()
+        out[nm] = (tot[i], cnt[i])
+    return out
 
 
 def bound_destroy(handle):

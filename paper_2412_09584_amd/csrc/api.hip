@@ -5,7 +5,9 @@
 #include "bound_internal.h"
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -58,13 +60,26 @@ struct bound_net {
     int32_t *sp = nullptr;           // 3 x sp_cap: instance, layer, internal index
     int8_t *sp_sign = nullptr;
     long sp_cap = 0;
+    // per-launch timing
+    bool prof = false;
+    struct ProfRec { std::string label; hipEvent_t a, b; };
+    std::vector<ProfRec> recs;
+    std::vector<hipEvent_t> pool;
     // state of the last SAVE_FOR_GRAD pass
     bool saved = false;
     int s_target = 0, s_rows = 0, s_n_inst = 0, s_nnz = 0;
     std::vector<long> s_off;         // offset of saved G_m (m = 1..k) in the save buffer
 
     ~bound_net() {
+        for (auto &r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
+        for (hipEvent_t e : pool) hipEventDestroy(e);
         for (void *p : allocs) hipFree(p);
+    }
+    hipEvent_t event() {
+        if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+        hipEvent_t e = nullptr;
+        hipEventCreate(&e);
+        return e;
     }
     template <class T> bool alloc(T **p, long n) {
         void *q = nullptr;
@@ -80,6 +95,34 @@ struct bound_net {
 };
 
 namespace {
+
+// Brackets the launches issued in its scope with events on the launch stream when the
+// handle's profiler is on and the stream is not being captured.
+struct ProfScope {
+    bound_net *net;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    std::string label;
+    ProfScope(bound_net *n, hipStream_t s, std::string l) : net(n), st(s), label(std::move(l)) {
+        if (!net->prof) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+        a = net->event();
+        if (a && hipEventRecord(a, st) != hipSuccess) { net->pool.push_back(a); a = nullptr; }
+    }
+    ~ProfScope() {
+        if (!a) return;
+        hipEvent_t b = net->event();
+        if (b && hipEventRecord(b, st) == hipSuccess) net->recs.push_back({label, a, b});
+        else { net->pool.push_back(a); if (b) net->pool.push_back(b); }
+    }
+};
+
+std::string lbl(const char *f, int m) {
+    char buf[48];
+    std::snprintf(buf, sizeof buf, f, m);
+    return buf;
+}
 
 bound_status build_geoms(bound_net *net, hipStream_t st) {
     for (int i = 0; i < net->n_layers; ++i) {
@@ -334,28 +377,31 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
 
     // Relaxation tables (Lemma 1) for z_1 .. z_{k-1}, split clamping, box.
     const int used = k - 1;
+    if (nnz > 0) {
+        bound_status s = ensure_split_cap(net, nnz, st);
+        if (s != BOUND_OK) return s;
+    }
+    int32_t *sp_inst = net->sp, *sp_layer = net->sp + net->sp_cap, *sp_j = net->sp + 2 * net->sp_cap;
+    const long d0 = net->d[0];
+    {
+    ProfScope prof_prep(net, st, "prep");
     if (used > 0) {
         HIPCHK(launch_prep_tables(net->ns, used, P->n_inst, net->n_relu, P->lo, P->hi, P->bound_of,
                                   P->alpha, net->tab, net->infeas, P->n_bounds, st));
     } else {
         HIPCHK(launch_fill((float *)net->infeas, P->n_inst, 0.f, st));
     }
-    if (nnz > 0) {
-        bound_status s = ensure_split_cap(net, nnz, st);
-        if (s != BOUND_OK) return s;
-    }
-    int32_t *sp_inst = net->sp, *sp_layer = net->sp + net->sp_cap, *sp_j = net->sp + 2 * net->sp_cap;
     if (nnz > 0 && used > 0) {
         HIPCHK(launch_prep_splits(net->ns, used, P->n_inst, net->n_relu, P->lo, P->hi, P->bound_of,
                                   P->split_off, P->split_idx, P->split_sign, net->tab, net->infeas,
                                   sp_inst, sp_layer, sp_j, P->n_bounds, st));
     }
-    const long d0 = net->d[0];
     if (conc) {
         HIPCHK(launch_prep_box(P->n_inst, net->C0, net->HW0, P->x_lo, P->x_hi, net->cen, net->rad, st));
     } else {
         HIPCHK(launch_fill(net->cen, (long)P->n_inst * d0, 0.f, st));
         HIPCHK(launch_fill(net->rad, (long)P->n_inst * d0, 0.f, st));
+    }
     }
 
     const long chunk = save ? total : net->max_rows;
@@ -386,6 +432,7 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             if (k == 1) {
                 ip.cen = net->cen; ip.rad = net->rad;
                 ip.emit = conc ? nullptr : out->coeff + img0 * d0;
+                ProfScope ps(net, st, "init_identity_conc");
                 HIPCHK(launch_init_identity(ip, n_img, true, st));
                 m_start = 0;
             } else {
@@ -394,7 +441,10 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
                 ip.bias_m = net->bias(k - 1);
                 ip.chan_m = net->chan(k - 1);
                 ip.out = cur;
-                HIPCHK(launch_init_identity(ip, n_img, false, st));
+                {
+                    ProfScope ps(net, st, lbl("init_identity_L%d", k));
+                    HIPCHK(launch_init_identity(ip, n_img, false, st));
+                }
                 if (inject)
                     HIPCHK(launch_beta_inject(nnz, P->rows, rpi, img0, n_img, k - 2, sp_inst, sp_layer,
                                               sp_j, P->split_sign, P->beta, cur, net->d[k - 1],
@@ -404,6 +454,7 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             }
         } else {
             const bound_layer &Lk = net->layers[k - 1].L;
+            ProfScope ps(net, st, "init_spec");
             HIPCHK(launch_init_spec(img0, n_img, P->rows, rpi, P->spec, dk, Lk.out_c,
                                     Lk.out_h * Lk.out_w, Lk.bias, cur, net->acc_s, net->acc_mag,
                                     net->acc_low, st));
@@ -422,7 +473,11 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             rp.mag = net->acc_mag;
             rp.img0 = img0;
             rp.rpi = rpi;
-            HIPCHK(gemm_relax(net->layers[m - 1].gT, cur, n_img, rp, st));
+            {
+                ProfScope ps(net, st, lbl("bwd_relax_L%d", m));
+                HIPCHK(gemm_relax(net->layers[m - 1].gT, cur, n_img, rp, st));
+            }
+            ProfScope pb(net, st, "beta_inject");
             if (inject)
                 HIPCHK(launch_beta_inject(nnz, P->rows, rpi, img0, n_img, m - 2, sp_inst, sp_layer, sp_j,
                                           P->split_sign, P->beta, nxt, net->d[m - 1], net->bias(m - 1),
@@ -437,8 +492,10 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             cp.emit = conc ? nullptr : out->coeff + img0 * d0;
             cp.chan = net->C0; cp.hw = net->HW0;
             cp.img0 = img0; cp.rpi = rpi;
+            ProfScope ps(net, st, "bwd_conc_L1");
             HIPCHK(gemm_conc(net->layers[0].gT, cur, n_img, cp, st));
         }
+        ProfScope pf(net, st, "finalize");
         HIPCHK(launch_finalize(img0, n_img, P->rows, rpi, net->acc_s, net->acc_low, net->acc_mag,
                                net->infeas, slack, conc ? out->lower : nullptr,
                                conc ? out->upper : nullptr, ld, conc ? nullptr : out->offset,
@@ -466,11 +523,17 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
     const int k = net->s_target, rows = net->s_rows;
     const long n_img = (long)net->s_n_inst * rows;
     const long d0 = net->d[0];
-    HIPCHK(launch_fill(grad_alpha, (long)net->s_n_inst * net->n_relu, 0.f, st));
-    if (grad_beta && net->s_nnz > 0) HIPCHK(launch_fill(grad_beta, (long)net->s_nnz * rows, 0.f, st));
+    {
+        ProfScope pz(net, st, "grad_zero");
+        HIPCHK(launch_fill(grad_alpha, (long)net->s_n_inst * net->n_relu, 0.f, st));
+        if (grad_beta && net->s_nnz > 0) HIPCHK(launch_fill(grad_beta, (long)net->s_nnz * rows, 0.f, st));
+    }
     float *cur = net->buf[0], *nxt = net->buf[1];
-    HIPCHK(launch_adj_init(n_img, rows, d0, grad_lower, net->save + net->s_off[1], net->cen, net->rad,
-                           net->infeas, cur, net->sbar, st));
+    {
+        ProfScope pi(net, st, "adj_init");
+        HIPCHK(launch_adj_init(n_img, rows, d0, grad_lower, net->save + net->s_off[1], net->cen,
+                               net->rad, net->infeas, cur, net->sbar, st));
+    }
     int32_t *sp_inst = net->sp, *sp_layer = net->sp + net->sp_cap, *sp_j = net->sp + 2 * net->sp_cap;
     for (int m = 1; m <= k - 1; ++m) {
         const LayerInfo &li = net->layers[m - 1];
@@ -488,7 +551,10 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
         ap.ga_off = net->relu_off(m);
         ap.hw = li.L.out_h * li.L.out_w;
         ap.rpi = rows;
-        HIPCHK(gemm_adj(li.gF, cur, n_img, ap, st));
+        {
+            ProfScope ps(net, st, lbl("adj_L%d", m));
+            HIPCHK(gemm_adj(li.gF, cur, n_img, ap, st));
+        }
         if (grad_beta && net->s_nnz > 0) {
             BetaGradLayer bl{};
             bl.kind = li.L.kind; bl.W = li.L.weight; bl.bias = li.L.bias;
@@ -496,6 +562,7 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
             bl.co = li.L.out_c; bl.ho = li.L.out_h; bl.wo = li.L.out_w;
             bl.kh = li.L.kh; bl.kw = li.L.kw; bl.stride = li.L.stride; bl.pad = li.L.pad;
             bl.din = li.din; bl.dout = li.dout;
+            ProfScope ps(net, st, "beta_grad");
             HIPCHK(launch_beta_grad(net->s_nnz, rows, m - 1, bl, sp_inst, sp_layer, sp_j, net->sp_sign,
                                     cur, net->sbar, net->infeas, grad_beta, st));
         }
@@ -522,6 +589,44 @@ bound_status bound_adam(int64_t n, float *param, const float *grad, float *m, fl
     HIPCHK(launch_adam(n, param, grad, m, v, step, lr, b1, b2, eps, grad_scale, clip_lo, clip_hi,
                        (hipStream_t)stream));
     return BOUND_OK;
+}
+
+bound_status bound_profile(bound_net *net, int32_t enable) {
+    if (!net) return fail(BOUND_E_ARG, "bound_profile: null net");
+    net->prof = enable != 0;
+    return BOUND_OK;
+}
+
+int32_t bound_profile_read(bound_net *net, int32_t cap, char *names, double *total_ms,
+                           int32_t *count) {
+    if (!net || cap < 0 || (cap > 0 && (!names || !total_ms || !count))) {
+        fail(BOUND_E_ARG, "bound_profile_read: bad arguments");
+        return BOUND_E_ARG;
+    }
+    std::map<std::string, std::pair<double, int>> acc;
+    std::vector<std::string> order;
+    for (auto &r : net->recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            fail(BOUND_E_HIP, "bound_profile_read: event query failed");
+            return BOUND_E_HIP;
+        }
+        if (!acc.count(r.label)) order.push_back(r.label);
+        acc[r.label].first += ms;
+        acc[r.label].second += 1;
+        net->pool.push_back(r.a);
+        net->pool.push_back(r.b);
+    }
+    net->recs.clear();
+    int n = 0;
+    for (const auto &l : order) {
+        if (n >= cap) break;
+        std::snprintf(names + 48 * n, 48, "%s", l.c_str());
+        total_ms[n] = acc[l].first;
+        count[n] = acc[l].second;
+        ++n;
+    }
+    return n;
 }
 
 void bound_destroy(bound_net *net) { delete net; }

@@ -286,51 +286,43 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
     constexpr int NR = Epi::NRED;
     const long wrow0 = m0 + wm * TM;
     const long wlast = (wrow0 + TM - 1 < M ? wrow0 + TM - 1 : M - 1);
+    // All rows of this wave's tile belong to one img (the usual case for convolutions):
+    // reduce the whole tile to one value per accumulator and issue one atomic per wave.
     const bool uniform = NR > 0 && wrow0 < M && (wrow0 / Mimg == wlast / Mimg);
     float u0 = 0.f, u1 = 0.f;
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
-        float r0[MM::NACC], r1[MM::NACC];
-        long imgs[MM::NACC];
 #pragma unroll
         for (int v = 0; v < MM::NACC; ++v) {
-            r0[v] = 0.f;
-            r1[v] = 0.f;
+            float r0 = 0.f, r1 = 0.f;
             const long m = wrow0 + i * MF + MM::row(v, lane);
-            imgs[v] = -1;
+            long img = -1;
             if (m < M) {
-                const long img = m / Mimg;
+                img = m / Mimg;
                 const int p = (int)(m - img * Mimg);
                 const int oy = p / g.OW, ox = p - oy * g.OW;
                 const long dpix = (long)(oy * g.ostr + g.oy0) * g.DW + (ox * g.ostr + g.ox0);
-                imgs[v] = img;
                 const auto rc = epi.row(img);
 #pragma unroll
                 for (int j = 0; j < FN; ++j)
                     if (ncol[j] < g.N)
                         epi.elem(rc, img, dpix, ncol[j], dpix * g.N + ncol[j], bcol[j], acc[i][j][v],
-                                 r0[v], r1[v]);
+                                 r0, r1);
             }
-        }
-        if (NR > 0) {
-            if (uniform) {
-#pragma unroll
-                for (int v = 0; v < MM::NACC; ++v) {
-                    u0 += r0[v];
-                    u1 += r1[v];
-                }
-            } else {
-#pragma unroll
-                for (int v = 0; v < MM::NACC; ++v) {
-                    float x0 = r0[v], x1 = r1[v];
+            if (NR > 0) {
+                if (uniform) {
+                    u0 += r0;
+                    u1 += r1;
+                } else {
+                    // lanes sharing this row differ only in the column bits of the lane id
 #pragma unroll
                     for (int mk = 1; mk < MF; mk <<= 1) {
-                        x0 += __shfl_xor(x0, mk, 64);
-                        x1 += __shfl_xor(x1, mk, 64);
+                        r0 += __shfl_xor(r0, mk, 64);
+                        r1 += __shfl_xor(r1, mk, 64);
                     }
-                    if (MM::col(lane) == 0 && imgs[v] >= 0) {
-                        atomicAdd(epi.red0() + imgs[v], x0);
-                        atomicAdd(epi.red1() + imgs[v], x1);
+                    if (MM::col(lane) == 0 && img >= 0) {
+                        atomicAdd(epi.red0() + img, r0);
+                        atomicAdd(epi.red1() + img, r1);
                     }
                 }
             }
