@@ -54,6 +54,7 @@ def main():
     ap.add_argument("--plain", type=int, default=256, help="subdomains timed one per call")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the kernel autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the batch of subdomains is independent per GPU "
@@ -110,6 +111,15 @@ def main():
                      stream=stream)
         B.bound_adam(beta, gb, mb, vb, t, lr, grad_scale=-1.0, clip_lo=0.0, stream=stream)
 
+    tune_log = None
+    if not args.no_tune:
+        tune_log = B.bound_autotune(bn.handle, n, R, L, grad_lower=ones, spec=C, lo=lo, hi=hi,
+                                    n_bounds=args.roots, bound_of=bof, alpha=alpha,
+                                    split_off=spd["off"], split_idx=spd["idx"],
+                                    split_sign=spd["sign"], nnz=sp.nnz, beta=beta, x_lo=x_lo,
+                                    x_hi=x_hi, flags=B.BOUND_SAVE_FOR_GRAD, lower=lower,
+                                    stream=stream)
+        best.fill_(-float("inf"))
     t = 0
     for _ in range(args.warmup):
         t += 1
@@ -218,8 +228,22 @@ def main():
                       "subdomains": n, "rows": R, "split_nnz": sp.nnz, "parallelism": "none"},
            "tflops_step": tflops, "flop_per_subdomain": flop_unit, "wall_s": wall,
            "plain": plain, "roofline": roofline, "kernel_ms_per_step": breakdown,
+           "autotune": _tuned(tune_log),
            "cpu_baseline": cpu}
     print(json.dumps(rec))
+
+
+def _tuned(log):
+    """Chosen plan per product from the autotuner's log (fastest line per product)."""
+    if not log:
+        return None
+    best = {}
+    for line in log.strip().splitlines():
+        key, path, cfg, cc, ms, _ = line.split()
+        t = float(ms)
+        if key not in best or t < best[key][0]:
+            best[key] = (t, f"{path} {cfg} {cc}")
+    return {k: f"{v[1]} {v[0]:.3f}ms" for k, v in best.items()}
 
 
 def cpu_baseline(w, budget_s):

@@ -187,6 +187,24 @@ bound_status bound_adam(int64_t n, float *param, const float *grad, float *m, fl
                         int32_t step, float lr, float b1, float b2, float eps,
                         float grad_scale, float clip_lo, float clip_hi, void *stream);
 
+/* Kernel selection: BOUND_OPT_GEMM_ONLY runs every product as an implicit GEMM (the
+ * LDS-tiled direct-convolution kernels are otherwise used where the layer geometry fits
+ * them).  Both compute the same bound; the option exists to test and compare them. */
+enum { BOUND_OPT_GEMM_ONLY = 1 };
+bound_status bound_set_options(bound_net *net, int32_t options);
+
+/* Kernel autotuning: runs the given pass (and, if grad_lower is not NULL and the pass
+ * has SAVE_FOR_GRAD, its gradient) once in tuning mode -- every valid kernel variant of
+ * every product (direct-convolution channel chunk, implicit-GEMM tile shape) is timed
+ * on the live data and the fastest is kept for that product on this handle -- then runs
+ * the pass again normally, so `out` and the saved state are those of a normal pass.
+ * Synchronises the stream; must not be called while the stream is being captured.
+ * bound_autotune_report copies the timing log (NUL-terminated, truncated to cap) and
+ * returns its full length. */
+bound_status bound_autotune(bound_net *net, const bound_pass *pass, const bound_out *out,
+                            const float *grad_lower, void *stream);
+int32_t bound_autotune_report(const bound_net *net, char *buf, int32_t cap);
+
 /* Per-launch timing: with enable != 0 every kernel the handle launches is bracketed by
  * HIP events recorded on its own stream (not while the stream is being captured).
  * bound_profile_read waits for the recorded events, adds their durations per kernel

@@ -16,9 +16,11 @@ LIB_PATH = os.path.join(HERE, "libbound.so")
 BOUND_OK, BOUND_E_ARG, BOUND_E_SHAPE, BOUND_E_NOMEM, BOUND_E_HIP, BOUND_E_STATE = 0, -1, -2, -3, -4, -5
 BOUND_LINEAR, BOUND_CONV2D = 0, 1
 BOUND_SAVE_FOR_GRAD, BOUND_NO_SLACK, BOUND_BOTH_SIDES = 1, 2, 4
+BOUND_OPT_GEMM_ONLY = 1
 
 EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "bound_grad",
-            "bound_adam", "bound_profile", "bound_profile_read", "bound_destroy",
+            "bound_adam", "bound_autotune", "bound_autotune_report", "bound_set_options",
+            "bound_profile", "bound_profile_read", "bound_destroy",
             "bound_last_error")
 
 _p = ctypes.c_void_p
@@ -72,6 +74,10 @@ def lib():
         L.bound_adam.argtypes = [ctypes.c_int64, _p, _p, _p, _p, ctypes.c_int32, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, _p]
+        L.bound_autotune.argtypes = [_p, ctypes.POINTER(BoundPass), ctypes.POINTER(BoundOut), _p, _p]
+        L.bound_autotune_report.argtypes = [_p, ctypes.c_char_p, ctypes.c_int32]
+        L.bound_autotune_report.restype = ctypes.c_int32
+        L.bound_set_options.argtypes = [_p, ctypes.c_int32]
         L.bound_profile.argtypes = [_p, ctypes.c_int32]
         L.bound_profile_read.argtypes = [_p, ctypes.c_int32, ctypes.c_char_p,
                                          ctypes.POINTER(ctypes.c_double),
@@ -81,7 +87,7 @@ def lib():
         L.bound_destroy.restype = None
         L.bound_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[:-2]:
-            if name != "bound_profile_read":
+            if name not in ("bound_profile_read", "bound_autotune_report"):
                 getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -133,6 +139,39 @@ def bound_dims(handle, n_layers_max=32):
     return [d[i] for i in range(n.value + 1)], nr.value
 
 
+def _pass_out(n_inst, rows, target, spec, lo, hi, n_bounds, bound_of, alpha, split_off, split_idx,
+              split_sign, nnz, beta, x_lo, x_hi, flags, lower, upper, ld, coeff, offset,
+              offset_mag, best):
+    P = BoundPass(int(n_inst), int(rows), int(target), int(n_bounds), _ptr(spec), _ptr(lo), _ptr(hi),
+                  _ptr(bound_of), _ptr(alpha), _ptr(split_off), _ptr(split_idx), _ptr(split_sign),
+                  int(nnz), _ptr(beta), _ptr(x_lo), _ptr(x_hi), int(flags))
+    O = BoundOut(_ptr(lower), _ptr(upper), int(ld), _ptr(coeff), _ptr(offset), _ptr(offset_mag),
+                 _ptr(best))
+    return P, O
+
+
+def bound_autotune(handle, n_inst, rows, target, *, grad_lower=None, spec=None, lo=None, hi=None,
+                   n_bounds=0, bound_of=None, alpha=None, split_off=None, split_idx=None,
+                   split_sign=None, nnz=0, beta=None, x_lo=None, x_hi=None, flags=0, lower=None,
+                   upper=None, ld=0, coeff=None, offset=None, offset_mag=None, best=None,
+                   stream=None):
+    """Tune every product of this pass (and its gradient); returns the timing log."""
+    P, O = _pass_out(n_inst, rows, target, spec, lo, hi, n_bounds, bound_of, alpha, split_off,
+                     split_idx, split_sign, nnz, beta, x_lo, x_hi, flags, lower, upper, ld, coeff,
+                     offset, offset_mag, best)
+    _check(lib().bound_autotune(handle, ctypes.byref(P), ctypes.byref(O), _ptr(grad_lower),
+                                _stream(stream)))
+    return bound_autotune_report(handle)
+
+
+def bound_autotune_report(handle):
+    """The last autotuning log: one line per (product, candidate) with its time."""
+    n = lib().bound_autotune_report(handle, None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib().bound_autotune_report(handle, buf, n + 1)
+    return buf.value.decode()
+
+
 def bound_backward(handle, n_inst, rows, target, *, spec=None, lo=None, hi=None, n_bounds=0,
                    bound_of=None, alpha=None, split_off=None, split_idx=None, split_sign=None,
                    nnz=0, beta=None, x_lo=None, x_hi=None, flags=0, lower=None, upper=None,
@@ -162,6 +201,10 @@ def bound_adam(param, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8, grad_sca
     _check(lib().bound_adam(param.numel(), _ptr(param), _ptr(grad), _ptr(m), _ptr(v), int(step),
                             float(lr), float(b1), float(b2), float(eps), float(grad_scale),
                             float(clip_lo), float(clip_hi), _stream(stream)))
+
+
+def bound_set_options(handle, options):
+    _check(lib().bound_set_options(handle, int(options)))
 
 
 def bound_profile(handle, enable=True):

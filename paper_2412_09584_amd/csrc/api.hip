@@ -60,6 +60,11 @@ struct bound_net {
     int32_t *sp = nullptr;           // 3 x sp_cap: instance, layer, internal index
     int8_t *sp_sign = nullptr;
     long sp_cap = 0;
+    int options = 0;
+    // kernel plan per product (key: 'R'/'C'/'A' * 256 + layer), chosen by bound_autotune
+    std::map<int, Plan> plans;
+    bool tuning = false;
+    std::string tune_report;
     // per-launch timing
     bool prof = false;
     struct ProfRec { std::string label; hipEvent_t a, b; };
@@ -117,6 +122,55 @@ struct ProfScope {
         else { net->pool.push_back(a); if (b) net->pool.push_back(b); }
     }
 };
+
+// Run one product with its plan.  In tuning mode, time every valid candidate on the
+// live inputs (3 launches each after one warm-up; the product is re-run, so the pass's
+// accumulators are scratch until the normal pass that follows tuning) and keep the
+// fastest.
+template <class F>
+bound_status run_product(bound_net *net, hipStream_t st, int key, const GeomSet &gs, F launch) {
+    if (!net->tuning) {
+        Plan p;
+        if (net->options & BOUND_OPT_GEMM_ONLY) {
+            p.path = 2;
+        } else {
+            auto it = net->plans.find(key);
+            if (it != net->plans.end()) p = it->second;
+        }
+        HIPCHK(launch(p));
+        return BOUND_OK;
+    }
+    Plan cand[kMaxCandidates];
+    const int nc = plan_candidates(gs, cand, kMaxCandidates);
+    hipEvent_t a = net->event(), b = net->event();
+    float best = INFINITY;
+    Plan bestp;
+    char line[160];
+    for (int c = 0; c < nc; ++c) {
+        HIPCHK(launch(cand[c]));
+        HIPCHK(hipEventRecord(a, st));
+        for (int r = 0; r < 3; ++r) HIPCHK(launch(cand[c]));
+        HIPCHK(hipEventRecord(b, st));
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        ms /= 3.f;
+        std::snprintf(line, sizeof line, "%c%d %s cfg=%d cc=%d %.4f ms\n", (char)(key >> 8), key & 255,
+                      cand[c].path == 1 ? "direct" : "gemm", cand[c].cfg, cand[c].cc, ms);
+        net->tune_report += line;
+        if (ms < best) {
+            best = ms;
+            bestp = cand[c];
+        }
+    }
+    net->pool.push_back(a);
+    net->pool.push_back(b);
+    if (nc > 0) net->plans[key] = bestp;
+    HIPCHK(launch(bestp));
+    return BOUND_OK;
+}
+
+inline int pkey(char c, int m) { return ((int)c << 8) | m; }
 
 std::string lbl(const char *f, int m) {
     char buf[48];
@@ -475,7 +529,12 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             rp.rpi = rpi;
             {
                 ProfScope ps(net, st, lbl("bwd_relax_L%d", m));
-                HIPCHK(gemm_relax(net->layers[m - 1].gT, cur, n_img, rp, st));
+                const GeomSet &gs = net->layers[m - 1].gT;
+                const float *A = cur;
+                bound_status bs = run_product(net, st, pkey('R', m), gs, [&](const Plan &pl) {
+                    return gemm_relax(gs, A, n_img, rp, st, pl);
+                });
+                if (bs != BOUND_OK) return bs;
             }
             ProfScope pb(net, st, "beta_inject");
             if (inject)
@@ -493,7 +552,12 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             cp.chan = net->C0; cp.hw = net->HW0;
             cp.img0 = img0; cp.rpi = rpi;
             ProfScope ps(net, st, "bwd_conc_L1");
-            HIPCHK(gemm_conc(net->layers[0].gT, cur, n_img, cp, st));
+            const GeomSet &gs = net->layers[0].gT;
+            const float *A = cur;
+            bound_status bs = run_product(net, st, pkey('C', 1), gs, [&](const Plan &pl) {
+                return gemm_conc(gs, A, n_img, cp, st, pl);
+            });
+            if (bs != BOUND_OK) return bs;
         }
         ProfScope pf(net, st, "finalize");
         HIPCHK(launch_finalize(img0, n_img, P->rows, rpi, net->acc_s, net->acc_low, net->acc_mag,
@@ -553,7 +617,11 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
         ap.rpi = rows;
         {
             ProfScope ps(net, st, lbl("adj_L%d", m));
-            HIPCHK(gemm_adj(li.gF, cur, n_img, ap, st));
+            const float *A = cur;
+            bound_status bs = run_product(net, st, pkey('A', m), li.gF, [&](const Plan &pl) {
+                return gemm_adj(li.gF, A, n_img, ap, st, pl);
+            });
+            if (bs != BOUND_OK) return bs;
         }
         if (grad_beta && net->s_nnz > 0) {
             BetaGradLayer bl{};
@@ -588,6 +656,50 @@ bound_status bound_adam(int64_t n, float *param, const float *grad, float *m, fl
         return fail(BOUND_E_ARG, "bound_adam: bad arguments");
     HIPCHK(launch_adam(n, param, grad, m, v, step, lr, b1, b2, eps, grad_scale, clip_lo, clip_hi,
                        (hipStream_t)stream));
+    return BOUND_OK;
+}
+
+bound_status bound_autotune(bound_net *net, const bound_pass *pass, const bound_out *out,
+                            const float *grad_lower, void *stream) {
+    if (!net || !pass || !out) return fail(BOUND_E_ARG, "bound_autotune: null argument");
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return fail(BOUND_E_STATE, "bound_autotune: the stream is being captured");
+    const bool grad = grad_lower && (pass->flags & BOUND_SAVE_FOR_GRAD);
+    net->tune_report.clear();
+    net->tuning = true;
+    bound_status s = bound_backward(net, pass, out, stream);
+    float *ga = nullptr;
+    if (s == BOUND_OK && grad) {
+        // the adjoint writes an alpha-gradient; tuning uses a buffer of its own for it
+        if (hipMalloc(&ga, sizeof(float) * (size_t)pass->n_inst * (size_t)net->n_relu) != hipSuccess)
+            s = fail(BOUND_E_NOMEM, "bound_autotune: gradient scratch");
+        else
+            s = bound_grad(net, grad_lower, ga, nullptr, stream);
+    }
+    net->tuning = false;
+    if (s == BOUND_OK) s = bound_backward(net, pass, out, stream);   // leave valid outputs
+    if (ga) {
+        hipStreamSynchronize((hipStream_t)stream);
+        hipFree(ga);
+    }
+    return s;
+}
+
+int32_t bound_autotune_report(const bound_net *net, char *buf, int32_t cap) {
+    if (!net) return -1;
+    const int32_t n = (int32_t)net->tune_report.size();
+    if (buf && cap > 0) {
+        const int32_t m = n < cap - 1 ? n : cap - 1;
+        std::memcpy(buf, net->tune_report.data(), (size_t)m);
+        buf[m] = 0;
+    }
+    return n;
+}
+
+bound_status bound_set_options(bound_net *net, int32_t options) {
+    if (!net || (options & ~BOUND_OPT_GEMM_ONLY)) return fail(BOUND_E_ARG, "bound_set_options: bad arguments");
+    net->options = options;
     return BOUND_OK;
 }
 

@@ -74,13 +74,43 @@ struct AdjParams {         // Lambda_bar_m = G_bar_m W_m^T + s_bar b_m  -> G_bar
     int rpi;
 };
 
-// ----- launchers (gemm.hip) ----------------------------------------------------------
+// ----- product launchers ---------------------------------------------------------
+// A plan picks the kernel of one product: path 0 = automatic (direct convolution when
+// the geometry fits, else the implicit GEMM with the default tile), 1 = direct
+// convolution with channel chunk cc (0 = largest that fits), 2 = implicit GEMM with tile
+// configuration cfg (see gemm_candidates).
+struct Plan {
+    int path = 0;
+    int cfg = -1;
+    int cc = 0;
+};
+constexpr int kMaxCandidates = 16;
+
 hipError_t gemm_relax(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
-                      hipStream_t st);
+                      hipStream_t st, const Plan &plan);
 hipError_t gemm_conc(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,
-                     hipStream_t st);
+                     hipStream_t st, const Plan &plan);
 hipError_t gemm_adj(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
-                    hipStream_t st);
+                    hipStream_t st, const Plan &plan);
+// Valid plans for a product (direct variants first, then GEMM tiles); returns the count.
+int plan_candidates(const GeomSet &gs, Plan *out, int cap);
+// gemm.hip: implicit GEMM with an explicit tile configuration (cfg < 0: default)
+hipError_t gemm_relax_cfg(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
+                          hipStream_t st, int cfg);
+hipError_t gemm_conc_cfg(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,
+                         hipStream_t st, int cfg);
+hipError_t gemm_adj_cfg(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
+                        hipStream_t st, int cfg);
+int gemm_candidates(const GeomSet &gs, int *cfgs, int cap);
+// conv.hip: direct convolution (cc = 0: largest chunk that fits); *used = false when the
+// geometry does not fit
+hipError_t direct_relax(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
+                        hipStream_t st, int cc, bool *used);
+hipError_t direct_conc(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,
+                       hipStream_t st, int cc, bool *used);
+hipError_t direct_adj(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
+                      hipStream_t st, int cc, bool *used);
+int direct_candidates(const GeomSet &gs, int *cc, int cap);
 
 // ----- auxiliary kernels (aux.hip) ---------------------------------------------------
 struct LayerShape {        // output shape of a ReLU layer (for index maps)

@@ -1,0 +1,465 @@
+// LDS-tiled direct convolution kernels for gfx950, used for the convolutional products
+// of the bound pass and its adjoint when the layer geometry fits (otherwise the
+// implicit-GEMM kernel in gemm.hip runs).
+//
+// A block owns 256 output pixels -- whole images when an image has <= 256 pixels,
+// otherwise a band of full-width output rows -- and all BN output channels.  For each
+// chunk of CC input channels it stages the input tile with its halo and the chunk's
+// weights (all taps) in LDS once; every tap of the convolution then reads its operands
+// from LDS, so each input element is fetched from L2/HBM once per block instead of once
+// per tap.  v_mfma_f32_32x32x2f32 serves BN >= 32, v_mfma_f32_16x16x4f32 BN = 16.
+// The same fused epilogues as the GEMM kernel apply (device_common.h).
+//
+// k_conv_valu covers products with at most 4 output channels (the first layer's
+// transposed convolution back to a 3-channel input), where a 16-wide MFMA tile would
+// waste most of its work: one thread per output pixel, plain FP32 FMAs from LDS.
+#include "device_common.h"
+
+namespace bp {
+namespace {
+
+using namespace dev;
+
+struct ConvTile {
+    int G;         // images per block (whole-image tiles), else 1
+    int TR;        // output rows per block
+    int tiles_y;   // row bands per image
+    int IH, IW;    // LDS input tile
+    int CS;        // LDS channel stride (>= CC)
+    int CC, lcc;   // channels per chunk (power of two) and its log2; CC = C when C < 4
+    int nchunk;
+    int T;         // taps kh * kw
+    int KB;        // padded k per chunk (multiple of 16)
+    int WS;        // LDS weight row stride
+    int in_floats; // G * IH * IW * CS
+};
+
+// Stage the input tile (channels [c0, c0+CC)) of images img0.. into LDS, zero outside.
+template <bool VEC>
+__device__ inline void stage_input(float *In, const ConvTile &ct, const Geom &g, const float *X,
+                                   long img0, long n_img, int iy0, int ix0, int c0) {
+    const int tid = threadIdx.x;
+    if (VEC) {
+        const int c4n = ct.CC >> 2;
+        const int total = ct.G * ct.IH * ct.IW * c4n;
+        for (int e = tid; e < total; e += 256) {
+            const int c4 = e % c4n, pix = e / c4n;
+            const int ix = pix % ct.IW, t2 = pix / ct.IW;
+            const int iy = t2 % ct.IH, gi = t2 / ct.IH;
+            const long img = img0 + gi;
+            const int y = iy0 + iy, x = ix0 + ix;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (img < n_img && (unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W)
+                v = *(const float4 *)(X + ((img * g.H + y) * (long)g.W + x) * g.C + c0 + 4 * c4);
+            *(float4 *)(In + ((gi * ct.IH + iy) * ct.IW + ix) * ct.CS + 4 * c4) = v;
+        }
+    } else {  // C < 4: one chunk, channels padded with zeros up to CS = 4
+        const int total = ct.G * ct.IH * ct.IW;
+        for (int e = tid; e < total; e += 256) {
+            const int ix = e % ct.IW, t2 = e / ct.IW;
+            const int iy = t2 % ct.IH, gi = t2 / ct.IH;
+            const long img = img0 + gi;
+            const int y = iy0 + iy, x = ix0 + ix;
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            if (img < n_img && (unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W) {
+                const float *src = X + ((img * g.H + y) * (long)g.W + x) * g.C;
+                for (int c = 0; c < g.C; ++c) v[c] = src[c];
+            }
+            *(float4 *)(In + ((gi * ct.IH + iy) * ct.IW + ix) * ct.CS) = make_float4(v[0], v[1], v[2], v[3]);
+        }
+    }
+}
+
+// Stage weights of output channels [n0, n0+BN) for channels [c0, c0+CC), all taps:
+// Wl[n][t*CC + c] = Bt[n0+n][t*C + c0 + c]; zero for k >= T*CC (padding to KB).
+__device__ inline void stage_weights(float *Wl, const ConvTile &ct, const Geom &g, int BN, int n0, int c0) {
+    const int total = BN * ct.KB;
+    const int TC = ct.T * ct.CC;
+    for (int e = threadIdx.x; e < total; e += 256) {
+        const int n = e / ct.KB, k = e - n * ct.KB;
+        float v = 0.f;
+        if (k < TC) {
+            const int t = k / ct.CC, c = k - t * ct.CC;
+            v = g.Bt[(long)(n0 + n) * g.Kp + t * g.C + c0 + c];
+        }
+        Wl[n * ct.WS + k] = v;
+    }
+}
+
+template <class Epi, int MF, int BN, bool VEC>
+__global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile ct,
+                                              const float *__restrict__ X, const long n_img,
+                                              const Epi epi) {
+    using MM = Mma<MF>;
+    using acc_t = typename MM::acc_t;
+    constexpr int FM = 64 / MF, FN = BN / MF, KPL = MM::KPL;
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    float *In = smem;
+    float *Wl = smem + ct.in_floats;
+
+    const Geom &g = gs.g[blockIdx.z];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const long grp = blockIdx.x / ct.tiles_y;
+    const int band = blockIdx.x - (int)(grp * ct.tiles_y);
+    const long img0 = grp * ct.G;
+    if (img0 >= n_img) return;
+    const int oyb = band * ct.TR;
+    const int n0 = blockIdx.y * BN;
+    const int tile_px = ct.TR * g.OW;
+    const int iy0 = oyb * g.stride - g.pad_y, ix0 = -g.pad_x;
+
+    // LDS offset of the top-left input of each A row this lane supplies.
+    int abase[FM];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+        const int lr = wave * 64 + i * MF + MM::idx(lane);
+        const int gi = lr / tile_px, q = lr - gi * tile_px;
+        const int py = q / g.OW, px = q - py * g.OW;
+        abase[i] = ((gi * ct.IH + py * g.stride) * ct.IW + px * g.stride) * ct.CS;
+    }
+    acc_t acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int v = 0; v < MM::NACC; ++v) acc[i][j][v] = 0.f;
+
+    const int kgrp = MM::grp(lane) * KPL;   // this lane's first k inside a 16-wide k block
+    const int TC = ct.T * ct.CC;
+    for (int ch = 0; ch < ct.nchunk; ++ch) {
+        const int c0 = ch * ct.CC;
+        __syncthreads();
+        stage_input<VEC>(In, ct, g, X, img0, n_img, iy0, ix0, c0);
+        stage_weights(Wl, ct, g, BN, n0, c0);
+        __syncthreads();
+        for (int kb = 0; kb < ct.KB; kb += 16) {
+            const int k = kb + kgrp;               // KPL consecutive k of one tap (VEC)
+            float af[FM][KPL], bf[FN][KPL];
+            if (VEC) {
+                const int t = k < TC ? (k >> ct.lcc) : 0;
+                const int c = k - (t << ct.lcc);
+                const int ty = t / g.kw, tx = t - ty * g.kw;
+                const int off = (ty * ct.IW + tx) * ct.CS + (k < TC ? c : 0);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int q = 0; q < KPL; q += 4) {
+                        const f32x4v a = *(const f32x4v *)(In + abase[i] + off + q);
+                        af[i][q] = a[0]; af[i][q + 1] = a[1]; af[i][q + 2] = a[2]; af[i][q + 3] = a[3];
+                    }
+            } else {
+#pragma unroll
+                for (int q = 0; q < KPL; ++q) {
+                    const int kk = k + q;
+                    const int t = kk < TC ? kk / ct.CC : 0;
+                    const int c = kk < TC ? kk - t * ct.CC : 0;
+                    const int ty = t / g.kw, tx = t - ty * g.kw;
+                    const int off = (ty * ct.IW + tx) * ct.CS + c;
+#pragma unroll
+                    for (int i = 0; i < FM; ++i) af[i][q] = In[abase[i] + off];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int q = 0; q < KPL; q += 4) {
+                    const f32x4v b = *(const f32x4v *)(Wl + (j * MF + MM::idx(lane)) * ct.WS + k + q);
+                    bf[j][q] = b[0]; bf[j][q + 1] = b[1]; bf[j][q + 2] = b[2]; bf[j][q + 3] = b[3];
+                }
+#pragma unroll
+            for (int s = 0; s < KPL; ++s)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) acc[i][j] = MM::mma(af[i][s], bf[j][s], acc[i][j]);
+        }
+    }
+
+    // ---------------------------------------------------------------- epilogue
+    int ncol[FN];
+    float bcol[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        ncol[j] = n0 + j * MF + MM::col(lane);
+        bcol[j] = ncol[j] < g.N ? epi.colv(ncol[j]) : 0.f;
+    }
+    constexpr int NR = Epi::NRED;
+    const int gfirst = (wave * 64) / tile_px, glast = (wave * 64 + 63) / tile_px;
+    const bool uniform = NR > 0 && gfirst == glast;
+    float u0 = 0.f, u1 = 0.f;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int v = 0; v < MM::NACC; ++v) {
+            float r0 = 0.f, r1 = 0.f;
+            const int lr = wave * 64 + i * MF + MM::row(v, lane);
+            const int gi = lr / tile_px, q = lr - gi * tile_px;
+            const int py = q / g.OW, px = q - py * g.OW;
+            const long img = img0 + gi;
+            const bool ok = img < n_img;
+            if (ok) {
+                const int oy = oyb + py;
+                const long dpix = (long)(oy * g.ostr + g.oy0) * g.DW + (px * g.ostr + g.ox0);
+                const auto rc = epi.row(img);
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    if (ncol[j] < g.N)
+                        epi.elem(rc, img, dpix, ncol[j], dpix * g.N + ncol[j], bcol[j], acc[i][j][v], r0, r1);
+            }
+            if (NR > 0) {
+                if (uniform) {
+                    u0 += r0;
+                    u1 += r1;
+                } else {
+                    reduce_row_atomic<MF>(r0, r1, ok ? img : -1, lane, epi.red0(), epi.red1());
+                }
+            }
+        }
+    }
+    if (NR > 0 && uniform && img0 + gfirst < n_img)
+        reduce_wave_atomic(u0, u1, img0 + gfirst, lane, epi.red0(), epi.red1());
+}
+
+// One thread per output pixel, up to NMAX output channels, VALU FMAs from LDS.
+template <class Epi, int NMAX>
+__global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvTile ct,
+                                                   const float *__restrict__ X, const long n_img,
+                                                   const Epi epi) {
+    extern __shared__ __attribute__((aligned(16))) float smem[];
+    float *In = smem;
+    float *Wl = smem + ct.in_floats;  // [NMAX][T*C]
+    const Geom &g = gs.g[blockIdx.z];
+    const int tid = threadIdx.x;
+    const long grp = blockIdx.x / ct.tiles_y;
+    const int band = blockIdx.x - (int)(grp * ct.tiles_y);
+    const long img0 = grp * ct.G;
+    if (img0 >= n_img) return;
+    const int oyb = band * ct.TR;
+    const int tile_px = ct.TR * g.OW;
+    const int TK = ct.T * g.C;
+    stage_input<true>(In, ct, g, X, img0, n_img, oyb * g.stride - g.pad_y, -g.pad_x, 0);
+    for (int e = tid; e < NMAX * TK; e += 256) {
+        const int n = e / TK, k = e - n * TK;
+        Wl[e] = n < g.N ? g.Bt[(long)n * g.Kp + k] : 0.f;
+    }
+    __syncthreads();
+    const int gi = tid / tile_px, q = tid - gi * tile_px;
+    const int py = q / g.OW, px = q - py * g.OW;
+    const int base = ((gi * ct.IH + py * g.stride) * ct.IW + px * g.stride) * ct.CS;
+    float acc[NMAX];
+#pragma unroll
+    for (int n = 0; n < NMAX; ++n) acc[n] = 0.f;
+    for (int t = 0; t < ct.T; ++t) {
+        const int ty = t / g.kw, tx = t - ty * g.kw;
+        const float *a = In + base + (ty * ct.IW + tx) * ct.CS;
+        const float *w = Wl + t * g.C;
+        for (int c = 0; c < g.C; c += 4) {
+            const float4 av = *(const float4 *)(a + c);
+#pragma unroll
+            for (int n = 0; n < NMAX; ++n) {
+                const float4 wv = *(const float4 *)(w + n * TK + c);
+                acc[n] = fmaf(av.x, wv.x, acc[n]);
+                acc[n] = fmaf(av.y, wv.y, acc[n]);
+                acc[n] = fmaf(av.z, wv.z, acc[n]);
+                acc[n] = fmaf(av.w, wv.w, acc[n]);
+            }
+        }
+    }
+    const long img = img0 + gi;
+    float r0 = 0.f, r1 = 0.f;
+    if (img < n_img) {
+        const long dpix = (long)((oyb + py) * g.ostr + g.oy0) * g.DW + (px * g.ostr + g.ox0);
+        const auto rc = epi.row(img);
+#pragma unroll
+        for (int n = 0; n < NMAX; ++n)
+            if (n < g.N) epi.elem(rc, img, dpix, n, dpix * g.N + n, epi.colv(n), acc[n], r0, r1);
+    }
+    if (Epi::NRED > 0) {
+        // a wave's 64 pixels lie in one image whenever an image has >= 64 pixels
+        const int lane = tid & 63;
+        const int wave = tid >> 6;
+        const int gf = (wave * 64) / tile_px, gl = (wave * 64 + 63) / tile_px;
+        if (gf == gl) {
+            if (img0 + gf < n_img) reduce_wave_atomic(r0, r1, img0 + gf, lane, epi.red0(), epi.red1());
+        } else {
+            if (img < n_img) {
+                atomicAdd(epi.red0() + img, r0);
+                atomicAdd(epi.red1() + img, r1);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------- planning
+constexpr int LDS_BUDGET = 80 * 1024;
+
+// Tile the 256-pixel block over the output grid; false if the grid does not divide.
+bool plan_tile(const Geom &g, ConvTile &ct) {
+    const int px = g.OH * g.OW;
+    if (px <= 256) {
+        if (256 % px != 0) return false;
+        ct.G = 256 / px;
+        ct.TR = g.OH;
+        ct.tiles_y = 1;
+    } else {
+        if (256 % g.OW != 0) return false;
+        const int tr = 256 / g.OW;
+        if (g.OH % tr != 0) return false;
+        ct.G = 1;
+        ct.TR = tr;
+        ct.tiles_y = g.OH / tr;
+    }
+    ct.IH = (ct.TR - 1) * g.stride + g.kh;
+    ct.IW = (g.OW - 1) * g.stride + g.kw;
+    ct.T = g.kh * g.kw;
+    return true;
+}
+
+bool same_shape(const GeomSet &gs) {
+    for (int i = 1; i < gs.n; ++i)
+        if (gs.g[i].OH != gs.g[0].OH || gs.g[i].OW != gs.g[0].OW || gs.g[i].kh != gs.g[0].kh ||
+            gs.g[i].kw != gs.g[0].kw || gs.g[i].N != gs.g[0].N || gs.g[i].C != gs.g[0].C)
+            return false;
+    return true;
+}
+
+// Choose the channel chunk for the MFMA kernel (want = 0: the largest that fits, else
+// exactly want); returns LDS bytes or 0 if nothing fits.
+size_t plan_chunk(const Geom &g, int BN, int KPL, ConvTile &ct, int want = 0) {
+    if (g.C < 4) {
+        ct.CC = g.C;
+        ct.lcc = 0;
+        ct.CS = 4;
+        ct.nchunk = 1;
+    } else {
+        int best = 0;
+        for (int cc = 64; cc >= KPL; cc >>= 1) {
+            if (g.C % cc || (want && cc != want)) continue;
+            const int cs = cc + 4;
+            const size_t in = (size_t)ct.G * ct.IH * ct.IW * cs;
+            const int kb = ((ct.T * cc + 15) / 16) * 16;
+            const size_t w = (size_t)BN * (kb + 4);
+            if ((in + w) * 4 <= LDS_BUDGET) { best = cc; break; }
+        }
+        if (!best) return 0;
+        ct.CC = best;
+        ct.lcc = __builtin_ctz(best);
+        ct.CS = best + 4;
+        ct.nchunk = g.C / best;
+    }
+    ct.KB = ((ct.T * ct.CC + 15) / 16) * 16;
+    ct.WS = ct.KB + 4;
+    ct.in_floats = ct.G * ct.IH * ct.IW * ct.CS;
+    const size_t bytes = ((size_t)ct.in_floats + (size_t)BN * ct.WS) * 4;
+    return bytes <= LDS_BUDGET ? bytes : 0;
+}
+
+// Allow the kernel the dynamic LDS it is planned with (above the default limit).
+template <class K> hipError_t allow_lds(K kern) {
+    return hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               LDS_BUDGET);
+}
+
+template <class Epi, int MF, int BN>
+hipError_t launch_mfma(const GeomSet &gs, const ConvTile &ct, size_t lds, const float *X, long n_img,
+                       const Epi &epi, hipStream_t st) {
+    const long groups = (n_img + ct.G - 1) / ct.G;
+    dim3 grid((unsigned)(groups * ct.tiles_y), (unsigned)(gs.g[0].N / BN), (unsigned)gs.n);
+    if (gs.g[0].C % 4 == 0) {
+        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, true>);
+        if (ok != hipSuccess) return ok;
+        hipLaunchKernelGGL((k_conv<Epi, MF, BN, true>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+    } else {
+        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, false>);
+        if (ok != hipSuccess) return ok;
+        hipLaunchKernelGGL((k_conv<Epi, MF, BN, false>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+    }
+    return hipGetLastError();
+}
+
+int bn_for(int N) {
+    if (N == 16) return 16;
+    if (N == 32) return 32;
+    if (N % 64 == 0) return 64;
+    return 0;
+}
+
+template <class Epi>
+hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &epi, hipStream_t st,
+                      int want_cc, bool *used) {
+    *used = false;
+    const Geom &g = gs.g[0];
+    if (g.H == 1 && g.W == 1 && g.kh == 1 && g.kw == 1) return hipSuccess;  // dense: GEMM
+    if (!same_shape(gs) || n_img <= 0) return hipSuccess;
+    ConvTile ct{};
+    if (!plan_tile(g, ct)) return hipSuccess;
+    const long groups = (n_img + ct.G - 1) / ct.G;
+    if (groups * ct.tiles_y > 0x7fffffffL) return hipSuccess;
+    if (g.N <= 4 && g.C % 4 == 0) {      // narrow output: VALU kernel
+        ct.CC = g.C;
+        ct.CS = g.C + 4;
+        ct.in_floats = ct.G * ct.IH * ct.IW * ct.CS;
+        const size_t lds = ((size_t)ct.in_floats + 4 * (size_t)ct.T * g.C) * 4;
+        if (lds > LDS_BUDGET) return hipSuccess;
+        dim3 grid((unsigned)(groups * ct.tiles_y), 1, (unsigned)gs.n);
+        static const hipError_t ok = allow_lds(k_conv_valu<Epi, 4>);
+        if (ok != hipSuccess) return ok;
+        hipLaunchKernelGGL((k_conv_valu<Epi, 4>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+        *used = true;
+        return hipGetLastError();
+    }
+    const int BN = bn_for(g.N);
+    if (!BN) return hipSuccess;
+    const int KPL = BN == 16 ? Mma<16>::KPL : Mma<32>::KPL;
+    const size_t lds = plan_chunk(g, BN, KPL, ct, want_cc);
+    if (!lds) return hipSuccess;
+    *used = true;
+    if (BN == 16) return launch_mfma<Epi, 16, 16>(gs, ct, lds, X, n_img, epi, st);
+    if (BN == 32) return launch_mfma<Epi, 32, 32>(gs, ct, lds, X, n_img, epi, st);
+    return launch_mfma<Epi, 32, 64>(gs, ct, lds, X, n_img, epi, st);
+}
+
+}  // namespace
+
+hipError_t direct_relax(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
+                        hipStream_t st, int cc, bool *used) {
+    return try_direct(gs, A, n_img, EpiRelax{p}, st, cc, used);
+}
+hipError_t direct_conc(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,
+                       hipStream_t st, int cc, bool *used) {
+    return try_direct(gs, A, n_img, EpiConc{p}, st, cc, used);
+}
+hipError_t direct_adj(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
+                      hipStream_t st, int cc, bool *used) {
+    return try_direct(gs, A, n_img, EpiAdj{p}, st, cc, used);
+}
+
+int direct_candidates(const GeomSet &gs, int *cc, int cap) {
+    const Geom &g = gs.g[0];
+    if (g.H == 1 && g.W == 1 && g.kh == 1 && g.kw == 1) return 0;
+    if (!same_shape(gs)) return 0;
+    ConvTile ct{};
+    if (!plan_tile(g, ct)) return 0;
+    if (g.N <= 4) {
+        if (g.C % 4 != 0) return 0;
+        cc[0] = 0;
+        return cap > 0 ? 1 : 0;
+    }
+    const int BN = bn_for(g.N);
+    if (!BN) return 0;
+    const int KPL = BN == 16 ? Mma<16>::KPL : Mma<32>::KPL;
+    if (g.C < 4) {
+        if (!plan_chunk(g, BN, KPL, ct)) return 0;
+        cc[0] = 0;
+        return cap > 0 ? 1 : 0;
+    }
+    int n = 0;
+    for (int c = 64; c >= KPL && n < cap; c >>= 1) {
+        ConvTile t = ct;
+        if (g.C % c == 0 && plan_chunk(g, BN, KPL, t, c)) cc[n++] = c;
+    }
+    return n;
+}
+
+}  // namespace bp

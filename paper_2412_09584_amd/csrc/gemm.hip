@@ -18,106 +18,15 @@
 // v_mfma_f32_16x16x4f32 the narrow N = 16 products.  Within a 16-wide k chunk lane
 // group h of the MFMA supplies k = h*KPL + s at step s, which lets each lane read KPL
 // consecutive k from LDS.
-#include "bound_internal.h"
+#include "device_common.h"
 
 namespace bp {
 namespace {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4v __attribute__((ext_vector_type(4)));
-
 constexpr int BK = 16;
 constexpr int LDSW = BK + 4;  // LDS row stride in floats (keeps 16-byte alignment)
 
-template <int MF> struct Mma;
-template <> struct Mma<32> {
-    using acc_t = f32x16;
-    static constexpr int NACC = 16;
-    static constexpr int KPL = 8;  // k values per lane per chunk (2 lane groups)
-    static __device__ inline acc_t mma(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ inline int row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
-    static __device__ inline int col(int lane) { return lane & 31; }
-    static __device__ inline int grp(int lane) { return lane >> 5; }
-    static __device__ inline int idx(int lane) { return lane & 31; }
-};
-template <> struct Mma<16> {
-    using acc_t = f32x4v;
-    static constexpr int NACC = 4;
-    static constexpr int KPL = 4;  // 4 lane groups
-    static __device__ inline acc_t mma(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ inline int row(int v, int lane) { return 4 * (lane >> 4) + v; }
-    static __device__ inline int col(int lane) { return lane & 15; }
-    static __device__ inline int grp(int lane) { return lane >> 4; }
-    static __device__ inline int idx(int lane) { return lane & 15; }
-};
-
-// ---------------------------------------------------------------------- epilogues
-struct EpiRelax {
-    RelaxParams p;
-    static constexpr int NRED = 2;
-    struct Row { long inst; };
-    __device__ Row row(long img) const { return Row{(p.img0 + img) / p.rpi}; }
-    __device__ float colv(int n) const { return p.bias[n % p.chan]; }
-    __device__ float *red0() const { return p.s; }
-    __device__ float *red1() const { return p.mag; }
-    __device__ void elem(const Row &rc, long img, long dpix, int n, long j, float bcol, float g,
-                         float &r0, float &r1) const {
-        const Relax t = p.tab[rc.inst * p.tab_ld + j];
-        const float lam = g >= 0.f ? g * t.x : g * t.y;
-        const float off = g < 0.f ? g * t.z : 0.f;
-        const float bt = lam * bcol;
-        r0 += bt + off;
-        r1 += fabsf(bt) + fabsf(off);
-        const long o = img * p.D + j;
-        p.out[o] = lam;
-        if (p.save) p.save[o] = g;
-    }
-};
-
-struct EpiConc {
-    ConcParams p;
-    static constexpr int NRED = 2;
-    struct Row { long inst; };
-    __device__ Row row(long img) const { return Row{(p.img0 + img) / p.rpi}; }
-    __device__ float colv(int) const { return 0.f; }
-    __device__ float *red0() const { return p.low; }
-    __device__ float *red1() const { return p.mag; }
-    __device__ void elem(const Row &rc, long img, long dpix, int n, long j, float, float g,
-                         float &r0, float &r1) const {
-        const long ij = rc.inst * p.D + j;
-        const float c = p.cen[ij], r = p.rad[ij];
-        r0 += g * c - fabsf(g) * r;
-        r1 += fabsf(g) * (fabsf(c) + r);
-        if (p.save) p.save[img * p.D + j] = g;
-        if (p.emit) p.emit[img * p.D + (long)n * p.hw + dpix] = g;
-    }
-};
-
-struct EpiAdj {
-    AdjParams p;
-    static constexpr int NRED = 0;
-    struct Row { long inst; float sb; };
-    __device__ Row row(long img) const { return Row{img / p.rpi, p.sbar[img]}; }
-    __device__ float colv(int n) const { return p.bias[n]; }
-    __device__ float *red0() const { return nullptr; }
-    __device__ float *red1() const { return nullptr; }
-    __device__ void elem(const Row &rc, long img, long dpix, int n, long j, float bcol, float acc,
-                         float &, float &) const {
-        const float v = acc + rc.sb * bcol;           // Lambda_bar_m[img, j]
-        const long o = img * p.D + j;
-        const float g = p.gsave[o];                   // G_{m+1}[img, j]
-        const Relax t = p.tab[rc.inst * p.tab_ld + j];
-        if (p.gout) p.gout[o] = v * (g >= 0.f ? t.x : t.y) + (g < 0.f ? rc.sb * t.z : 0.f);
-        if (t.w != 0.f && g >= 0.f) {
-            const float c = g * v;
-            if (c != 0.f) atomicAdd(p.galpha + rc.inst * p.ga_ld + p.ga_off + (long)n * p.hw + dpix, c);
-        }
-    }
-};
+using namespace dev;
 
 // ---------------------------------------------------------------------- the kernel
 template <class Epi, int MF, int BM, int BN, int WGM, int WGN, bool DENSE, bool VEC>
@@ -367,28 +276,91 @@ hipError_t launch_cfg(const GeomSet &gs, const float *A, long n_img, const Epi &
     return hipGetLastError();
 }
 
+// Tile configurations: {MFMA size, BM, BN, wave grid}.
+//   0: 32x32 MFMA, 128x128, 2x2   1: 32, 128x64, 2x2    2: 32, 256x32, 4x1
+//   3: 16x16 MFMA, 256x16, 4x1    4: 32, 256x64, 4x1    5: 32, 256x128, 4x1
+constexpr int kGemmCfgs = 6;
+const int kCfgBN[kGemmCfgs] = {128, 64, 32, 16, 64, 128};
+
+int default_cfg(int N) {
+    if (N >= 128) return 0;
+    if (N >= 64) return 1;
+    if (N >= 32) return 2;
+    return 3;
+}
+
 template <class Epi>
-hipError_t dispatch(const GeomSet &gs, const float *A, long n_img, const Epi &epi, hipStream_t st) {
-    const int N = gs.g[0].N;
-    if (N >= 128) return launch_cfg<Epi, 32, 128, 128, 2, 2>(gs, A, n_img, epi, st);
-    if (N >= 64) return launch_cfg<Epi, 32, 128, 64, 2, 2>(gs, A, n_img, epi, st);
-    if (N >= 32) return launch_cfg<Epi, 32, 256, 32, 4, 1>(gs, A, n_img, epi, st);
-    return launch_cfg<Epi, 16, 256, 16, 4, 1>(gs, A, n_img, epi, st);
+hipError_t dispatch(const GeomSet &gs, const float *A, long n_img, const Epi &epi, hipStream_t st,
+                    int cfg) {
+    if (cfg < 0 || cfg >= kGemmCfgs) cfg = default_cfg(gs.g[0].N);
+    switch (cfg) {
+    case 0: return launch_cfg<Epi, 32, 128, 128, 2, 2>(gs, A, n_img, epi, st);
+    case 1: return launch_cfg<Epi, 32, 128, 64, 2, 2>(gs, A, n_img, epi, st);
+    case 2: return launch_cfg<Epi, 32, 256, 32, 4, 1>(gs, A, n_img, epi, st);
+    case 3: return launch_cfg<Epi, 16, 256, 16, 4, 1>(gs, A, n_img, epi, st);
+    case 4: return launch_cfg<Epi, 32, 256, 64, 4, 1>(gs, A, n_img, epi, st);
+    default: return launch_cfg<Epi, 32, 256, 128, 4, 1>(gs, A, n_img, epi, st);
+    }
 }
 
 }  // namespace
 
-hipError_t gemm_relax(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
-                      hipStream_t st) {
-    return dispatch(gs, A, n_img, EpiRelax{p}, st);
+int gemm_candidates(const GeomSet &gs, int *cfgs, int cap) {
+    // a tile wider than the padded N only repeats zero columns
+    const int N = gs.g[0].N;
+    int n = 0;
+    for (int c = 0; c < kGemmCfgs && n < cap; ++c)
+        if (kCfgBN[c] <= 16 * ((N + 15) / 16) || c == default_cfg(N)) cfgs[n++] = c;
+    return n;
 }
-hipError_t gemm_conc(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,
-                     hipStream_t st) {
-    return dispatch(gs, A, n_img, EpiConc{p}, st);
+
+hipError_t gemm_relax_cfg(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
+                          hipStream_t st, int cfg) {
+    return dispatch(gs, A, n_img, dev::EpiRelax{p}, st, cfg);
 }
-hipError_t gemm_adj(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
-                    hipStream_t st) {
-    return dispatch(gs, A, n_img, EpiAdj{p}, st);
+hipError_t gemm_conc_cfg(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,
+                         hipStream_t st, int cfg) {
+    return dispatch(gs, A, n_img, dev::EpiConc{p}, st, cfg);
 }
+hipError_t gemm_adj_cfg(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
+                        hipStream_t st, int cfg) {
+    return dispatch(gs, A, n_img, dev::EpiAdj{p}, st, cfg);
+}
+
+int plan_candidates(const GeomSet &gs, Plan *out, int cap) {
+    int n = 0;
+    int cc[kMaxCandidates];
+    const int nd = direct_candidates(gs, cc, kMaxCandidates);
+    for (int i = 0; i < nd && n < cap; ++i) {
+        out[n].path = 1;
+        out[n].cfg = -1;
+        out[n].cc = cc[i];
+        ++n;
+    }
+    int cf[kMaxCandidates];
+    const int ng = gemm_candidates(gs, cf, kMaxCandidates);
+    for (int i = 0; i < ng && n < cap; ++i) {
+        out[n].path = 2;
+        out[n].cfg = cf[i];
+        out[n].cc = 0;
+        ++n;
+    }
+    return n;
+}
+
+#define BOUND_PRODUCT(NAME, PARAMS, DIRECT, CFG)                                             \
+    hipError_t NAME(const GeomSet &gs, const float *A, long n_img, const PARAMS &p,          \
+                    hipStream_t st, const Plan &plan) {                                      \
+        if (plan.path != 2) {                                                                \
+            bool used = false;                                                               \
+            const hipError_t e = DIRECT(gs, A, n_img, p, st, plan.path == 1 ? plan.cc : 0, &used); \
+            if (used || e != hipSuccess) return e;                                           \
+        }                                                                                    \
+        return CFG(gs, A, n_img, p, st, plan.path == 2 ? plan.cfg : -1);                     \
+    }
+BOUND_PRODUCT(gemm_relax, RelaxParams, direct_relax, gemm_relax_cfg)
+BOUND_PRODUCT(gemm_conc, ConcParams, direct_conc, gemm_conc_cfg)
+BOUND_PRODUCT(gemm_adj, AdjParams, direct_adj, gemm_adj_cfg)
+#undef BOUND_PRODUCT
 
 }  // namespace bp

@@ -166,3 +166,85 @@ def optimize_alpha_beta(net, C, lo, hi, x_lo, x_hi, *, steps=10, lr=0.1, alpha0=
     net.spec_bounds(C, lo, hi, x_lo, x_hi, alpha=alpha, beta=beta, bound_of=bound_of,
                     splits=splits, both=False, best=best)
     return best, alpha, beta
+
+
+class AlphaBetaOptimizer:
+    """The alpha/beta optimisation of one batch of subdomains as a replayable unit.
+
+    run() issues, on the current stream: reset of alpha / beta / Adam state / best bound,
+    then `steps` x (bound pass with SAVE_FOR_GRAD and best-so-far, gradient, Adam on
+    alpha and on beta), then a last bound pass.  capture() records exactly that sequence
+    into a HIP graph (through torch.cuda.CUDAGraph on a capture stream) after one eager
+    warm-up run, so a whole optimisation is one graph launch; replay() launches it.
+    The library allocates nothing inside a pass, and clears memory with kernels only, so
+    the captured sequence is the eager one.
+    """
+
+    def __init__(self, net, C, lo, hi, x_lo, x_hi, *, bound_of=None, splits=None, steps=10,
+                 lr=0.1, alpha0=0.5, use_beta=True):
+        dev = net.device
+        self.net, self.steps, self.lr, self.alpha0 = net, int(steps), float(lr), float(alpha0)
+        self.C = _dev(C, dev)
+        self.n, self.rows = self.C.shape[0], self.C.shape[1]
+        self.lo, self.hi = lo, hi
+        self.x_lo, self.x_hi = _dev(x_lo, dev), _dev(x_hi, dev)
+        self.bound_of, self.splits = bound_of, splits
+        self.nnz = 0 if splits is None else int(splits["idx"].numel())
+        self.alpha = torch.empty(self.n, net.n_relu, device=dev)
+        self.ma, self.va = torch.empty_like(self.alpha), torch.empty_like(self.alpha)
+        self.ga = torch.empty_like(self.alpha)
+        self.use_beta = bool(use_beta and self.nnz)
+        if self.use_beta:
+            self.beta = torch.empty(self.nnz, self.rows, device=dev)
+            self.mb, self.vb = torch.empty_like(self.beta), torch.empty_like(self.beta)
+            self.gb = torch.empty_like(self.beta)
+        else:
+            self.beta = self.gb = None
+        self.best = torch.empty(self.n, self.rows, device=dev)
+        self.lower = torch.empty(self.n, self.rows, device=dev)
+        self.ones = torch.ones(self.n, self.rows, device=dev)
+        self.graph = None
+
+    def _pass(self, save):
+        kw = {}
+        if self.splits is not None:
+            kw = dict(split_off=self.splits["off"], split_idx=self.splits["idx"],
+                      split_sign=self.splits["sign"], nnz=self.nnz)
+        B.bound_backward(self.net.handle, self.n, self.rows, self.net.L, spec=self.C, lo=self.lo,
+                         hi=self.hi, n_bounds=self.lo.shape[0], bound_of=self.bound_of,
+                         alpha=self.alpha, beta=self.beta, x_lo=self.x_lo, x_hi=self.x_hi,
+                         flags=B.BOUND_SAVE_FOR_GRAD if save else 0, lower=self.lower,
+                         best=self.best, **kw)
+
+    def run(self):
+        self.alpha.fill_(self.alpha0)
+        self.ma.zero_()
+        self.va.zero_()
+        if self.use_beta:
+            self.beta.zero_()
+            self.mb.zero_()
+            self.vb.zero_()
+        self.best.fill_(-float("inf"))
+        for t in range(1, self.steps + 1):
+            self._pass(True)
+            B.bound_grad(self.net.handle, self.ones, self.ga, self.gb)
+            B.bound_adam(self.alpha, self.ga, self.ma, self.va, t, self.lr, grad_scale=-1.0,
+                         clip_lo=0.0, clip_hi=1.0)
+            if self.use_beta:
+                B.bound_adam(self.beta, self.gb, self.mb, self.vb, t, self.lr, grad_scale=-1.0,
+                             clip_lo=0.0)
+        self._pass(False)
+        return self.best
+
+    def capture(self):
+        self.run()                       # warm-up: sizes scratch, sets kernel attributes
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+        return self.best

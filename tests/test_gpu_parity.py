@@ -144,6 +144,10 @@ def test_mlp_deep_full_batch_sampled(mod):
 
 
 CNN_GEOMS = [
+    # channel counts 3 / 16 / 32 and power-of-two image sizes take the direct-convolution
+    # kernels (LDS-tiled MFMA, VALU for the 3-channel input); the others the implicit GEMM
+    dict(H=8, convs=((16, 3, 1), (16, 4, 2), (32, 3, 1)), fc=(16, 5), cin=3),
+    dict(H=8, convs=((32, 3, 1), (16, 4, 2), (64, 3, 1)), fc=(10, 4), cin=16),
     dict(H=12, convs=((8, 3, 1), (8, 4, 2), (16, 3, 1), (16, 4, 2)), fc=(32, 5), cin=3),
     dict(H=7, convs=((4, 3, 2), (6, 3, 1)), fc=(10, 3), cin=2),     # odd size, k3 s2
     dict(H=9, convs=((5, 4, 2), (3, 2, 2)), fc=(7,), cin=1),        # k4 s2 on odd, k2 s2
@@ -151,8 +155,18 @@ CNN_GEOMS = [
 ]
 
 
+_ORACLE_CACHE = {}
+
+
+def _cached_crown(key, net, x_lo, x_hi):
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = O.crown_bounds(net, x_lo, x_hi)
+    return _ORACLE_CACHE[key]
+
+
+@pytest.mark.parametrize("path", ["auto", "gemm"])
 @pytest.mark.parametrize("gi", range(len(CNN_GEOMS)))
-def test_cnn_small_end_to_end(mod, gi):
+def test_cnn_small_end_to_end(mod, gi, path):
     N, B = mod
     net = tiny_cnn(seed=10 + gi, **CNN_GEOMS[gi])
     n = 3
@@ -160,11 +174,13 @@ def test_cnn_small_end_to_end(mod, gi):
     x_lo, x_hi = W.linf_box(x0, 0.03)
     C = W.margin_spec(W.clean_logits(net, x0))
     bn = N.BoundNet(net, n, 1 << 16)
+    if path == "gemm":
+        B.bound_set_options(bn.handle, B.BOUND_OPT_GEMM_ONLY)
     glo, ghi = bn.crown_bounds(x_lo, x_hi)
     gl, gu = bn.spec_bounds(C, glo, ghi, x_lo, x_hi)
     L = len(net)
     for i in range(n):
-        ob = O.crown_bounds(net, x_lo[i], x_hi[i])
+        ob = _cached_crown(("geom", gi, i), net, x_lo[i], x_hi[i])
         lo, hi = flat([ob])
         close(np_(glo)[i], lo[0], what=f"lo {i}")
         close(np_(ghi)[i], hi[0], what=f"hi {i}")
@@ -241,13 +257,15 @@ def _oracle_unit(net, C, lo_row, hi_row, x_lo, x_hi, alpha_row, sp, q0, q1, beta
     return low, np.concatenate(ga), gb
 
 
-@pytest.mark.parametrize("kind", ["mlp", "cnn"])
+@pytest.mark.parametrize("kind", ["mlp", "cnn", "cnn_direct", "cnn_direct_gemm"])
 def test_alpha_beta_pass_and_grad(mod, kind):
     N, B = mod
     if kind == "mlp":
         net = W.mlp([30, 24, 24, 24, 6], seed=51)
-    else:
+    elif kind == "cnn":
         net = tiny_cnn(seed=52)
+    else:
+        net = tiny_cnn(seed=57, **CNN_GEOMS[0])
     n_roots, per_root = 2, 6
     x0 = W.uniform_inputs(n_roots, W.in_dim(net), 53)
     x_lo, x_hi = W.linf_box(x0, 0.05)
@@ -263,6 +281,8 @@ def test_alpha_beta_pass_and_grad(mod, kind):
     beta = W.random_beta(sp.nnz, C.shape[1], 56)
     Cs = C[root_of]
     bn = N.BoundNet(net, n, 4096, 4096)
+    if kind.endswith("_gemm"):
+        B.bound_set_options(bn.handle, B.BOUND_OPT_GEMM_ONLY)
     spd = N.splits_to_device(sp)
     gl, _ = bn.spec_bounds(Cs, dev(f32(lo)), dev(f32(hi)), x_lo[root_of], x_hi[root_of],
                            alpha=dev(alpha), bound_of=dev(root_of, torch.int32), splits=spd,
@@ -465,3 +485,116 @@ def test_beta_crown_batch_full_size(mod, golden_cnn):
         assert np.max(np.abs(ga[i] - oga)) <= 1e-4 * scale, f"grad alpha {i}"
         sb = max(np.max(np.abs(ogb)), scale)
         assert np.max(np.abs(gb[q0:q1] - ogb)) <= 1e-4 * sb, f"grad beta {i}"
+
+
+def test_direct_and_gemm_paths_agree_full_size(mod, golden_cnn):
+    """The 4096-subdomain pass + gradient through both kernel paths (same inputs)."""
+    N, B = mod
+    w = W.cnn_cifar(1)
+    lo = f32(golden_cnn["lo"])[None]
+    hi = f32(golden_cnn["hi"])[None]
+    n = 4096
+    root_of = np.zeros(n, np.int32)
+    sp = W.random_splits([np.nonzero((lo[0] < 0) & (hi[0] > 0))[0]], n, 1, 12, seed=5,
+                         root_of=root_of)
+    alpha = dev(W.random_alpha(n, lo.shape[1], 6))
+    beta = dev(W.random_beta(sp.nnz, 9, 7))
+    bn = N.BoundNet(w.net, n, n * 9, n * 9)
+    out = []
+    for opt in (0, B.BOUND_OPT_GEMM_ONLY):
+        B.bound_set_options(bn.handle, opt)
+        gl, _ = bn.spec_bounds(np.repeat(w.spec, n, 0), dev(lo), dev(hi), np.repeat(w.x_lo, n, 0),
+                               np.repeat(w.x_hi, n, 0), alpha=alpha, bound_of=dev(root_of, torch.int32),
+                               splits=N.splits_to_device(sp), beta=beta, both=False, save=True)
+        ga, gb = bn.grad(torch.ones(n, 9, device="cuda"), sp.nnz)
+        out.append((np_(gl), np_(ga), np_(gb)))
+    # Both paths round differently; where a coefficient lies within rounding of zero the
+    # relaxation branch (and its adjoint mask) can flip, so a few gradient entries may
+    # differ by more than rounding.  Bounds: rounding only; gradients: almost all
+    # entries to 1e-5, none beyond 1e-3 of the instance's largest entry.
+    close(out[0][0], out[1][0], rel=1e-5, what="lower direct vs gemm")
+    da = np.abs(out[0][1] - out[1][1])
+    sa = np.maximum(np.max(np.abs(out[1][1]), axis=1, keepdims=True), 1e-30)
+    db = np.abs(out[0][2] - out[1][2])
+    sb = max(np.max(np.abs(out[1][2])), 1e-30)
+    print(f"alpha-grad entries off by >1e-5: {np.mean(da > 1e-5 * sa):.2e}; "
+          f"beta-grad: {np.mean(db > 1e-5 * sb):.2e}; worst {np.max(da / sa):.2e} / {np.max(db) / sb:.2e}")
+    assert np.mean(da > 1e-5 * sa) <= 1e-4 and np.max(da / sa) <= 1e-3
+    assert np.mean(db > 1e-5 * sb) <= 1e-3 and np.max(db) / sb <= 1e-3
+
+
+def test_graph_captured_optimisation_matches_eager(mod):
+    """The whole 10-step alpha/beta optimisation captured as one HIP graph: every replay,
+    with eager work and synchronisations in between, equals the eager run."""
+    N, B = mod
+    net = tiny_cnn(seed=91, **CNN_GEOMS[0])
+    n_roots, per_root = 2, 24
+    x0 = W.uniform_inputs(n_roots, W.in_dim(net), 92)
+    x_lo, x_hi = W.linf_box(x0, 0.05)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    bn = N.BoundNet(net, n_roots * per_root, 1 << 14, 1 << 12)
+    glo, ghi = bn.crown_bounds(x_lo, x_hi)
+    lo_np, hi_np = np_(glo), np_(ghi)
+    n = n_roots * per_root
+    root_of = np.repeat(np.arange(n_roots), per_root).astype(np.int32)
+    sp = _random_splits(net, lo_np, hi_np, n, 93, root_of)
+    opt = N.AlphaBetaOptimizer(bn, C[root_of], glo, ghi, x_lo[root_of], x_hi[root_of],
+                               bound_of=dev(root_of, torch.int32), splits=N.splits_to_device(sp),
+                               steps=10)
+    eager = np_(opt.run()).copy()
+    ea, eb = np_(opt.alpha).copy(), np_(opt.beta).copy()
+    # float atomics make two eager runs differ in the last bits; replays are held to the
+    # parity tolerance (a wrong replay is off by far more)
+    eager2 = np_(opt.run()).copy()
+    close(eager2, eager, rel=1e-4, what="eager vs eager")
+    opt.capture()
+    for rep in range(3):
+        opt.alpha.fill_(0.123)           # eager work between replays
+        opt.best.fill_(7.0)
+        torch.cuda.synchronize()
+        got = np_(opt.replay()).copy()
+        torch.cuda.synchronize()
+        close(got, eager, rel=1e-4, what=f"replay {rep} best bound")
+        np.testing.assert_allclose(np_(opt.alpha), ea, atol=2e-3)
+        np.testing.assert_allclose(np_(opt.beta), eb, atol=2e-3, rtol=1e-3)
+        bn.crown_bounds(x_lo, x_hi)      # an unrelated eager pass on the same handle
+
+
+def test_autotuned_plans_keep_the_bound(mod):
+    """After bound_autotune picks a kernel per product, pass and gradient are unchanged
+    (to rounding) and the timing log covers every product."""
+    N, B = mod
+    net = tiny_cnn(seed=95, **CNN_GEOMS[0])
+    n = 64
+    x0 = W.uniform_inputs(1, W.in_dim(net), 96)
+    x_lo, x_hi = W.linf_box(x0, 0.05)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    bn = N.BoundNet(net, n, 1 << 14, 1 << 14)
+    glo, ghi = bn.crown_bounds(x_lo, x_hi)
+    lo_np, hi_np = np_(glo), np_(ghi)
+    sp = _random_splits(net, lo_np, hi_np, n, 97, np.zeros(n, np.int32))
+    spd = N.splits_to_device(sp)
+    alpha = dev(W.random_alpha(n, bn.n_relu, 98))
+    beta = dev(W.random_beta(sp.nnz, C.shape[1], 99))
+    args = (np.repeat(C, n, 0), glo, ghi, np.repeat(x_lo, n, 0), np.repeat(x_hi, n, 0))
+    kw = dict(alpha=alpha, bound_of=dev(np.zeros(n), torch.int32), splits=spd, beta=beta,
+              both=False, save=True)
+    l0, _ = bn.spec_bounds(*args, **kw)
+    g0 = bn.grad(torch.ones(n, C.shape[1], device="cuda"), sp.nnz)
+    ref = (np_(l0), np_(g0[0]), np_(g0[1]))
+    lower = torch.empty(n, C.shape[1], device="cuda")
+    log = B.bound_autotune(bn.handle, n, C.shape[1], len(net), grad_lower=torch.ones(n, C.shape[1], device="cuda"),
+                           spec=dev(np.repeat(C, n, 0)), lo=glo, hi=ghi, n_bounds=1,
+                           bound_of=dev(np.zeros(n), torch.int32), alpha=alpha,
+                           split_off=spd["off"], split_idx=spd["idx"], split_sign=spd["sign"],
+                           nnz=sp.nnz, beta=beta, x_lo=dev(np.repeat(x_lo, n, 0)),
+                           x_hi=dev(np.repeat(x_hi, n, 0)), flags=B.BOUND_SAVE_FOR_GRAD, lower=lower)
+    keys = {line.split()[0] for line in log.strip().splitlines()}
+    assert {f"R{m}" for m in range(2, len(net) + 1)} <= keys and "C1" in keys
+    assert {f"A{m}" for m in range(1, len(net))} <= keys
+    close(np_(lower), ref[0], rel=1e-5, what="autotune call output")
+    l1, _ = bn.spec_bounds(*args, **kw)
+    g1 = bn.grad(torch.ones(n, C.shape[1], device="cuda"), sp.nnz)
+    close(np_(l1), ref[0], rel=1e-5, what="tuned lower")
+    s = np.max(np.abs(ref[1]), axis=1, keepdims=True) + 1e-30
+    assert np.mean(np.abs(np_(g1[0]) - ref[1]) > 1e-5 * s) <= 1e-3
