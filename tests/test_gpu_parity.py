@@ -598,3 +598,37 @@ def test_autotuned_plans_keep_the_bound(mod):
     close(np_(l1), ref[0], rel=1e-5, what="tuned lower")
     s = np.max(np.abs(ref[1]), axis=1, keepdims=True) + 1e-30
     assert np.mean(np.abs(np_(g1[0]) - ref[1]) > 1e-5 * s) <= 1e-3
+
+
+def test_alpha_crown_cnn_64_instances(mod, golden_cnn):
+    """alpha-CROWN on the CNN (64 instances, random alpha in [0, 1]): the bound and its
+    alpha-gradient at identical alpha, 4 instances against the oracle; then 20 Adam steps
+    (lr 0.1, alpha0 = 0.5) never lower the best bound."""
+    N, B = mod
+    w = W.cnn_cifar(1)
+    lo = f32(golden_cnn["lo"]).astype(np.float64)
+    hi = f32(golden_cnn["hi"]).astype(np.float64)
+    n = 64
+    alpha = W.random_alpha(n, lo.size, 11)
+    bn = N.BoundNet(w.net, n, n * 9, n * 9)
+    args = (np.repeat(w.spec, n, 0), dev(f32(lo)[None]), dev(f32(hi)[None]), np.repeat(w.x_lo, n, 0),
+            np.repeat(w.x_hi, n, 0))
+    gl, _ = bn.spec_bounds(*args, alpha=dev(alpha), bound_of=dev(np.zeros(n), torch.int32),
+                           both=False, save=True)
+    ga, _ = bn.grad(torch.ones(n, 9, device="cuda"))
+    gl, ga = np_(gl), np_(ga)
+    bounds = list(zip(O.per_layer(w.net, lo), O.per_layer(w.net, hi)))
+    for i in (0, 21, 42, 63):
+        al = O.per_layer(w.net, alpha[i])
+        ol = O.spec_lower(w.net, len(w.net), w.spec[0], bounds, w.x_lo[0], w.x_hi[0], al)
+        _, oga, _ = O.spec_lower_grad(w.net, len(w.net), w.spec[0], bounds, w.x_lo[0], w.x_hi[0], al)
+        oga = np.concatenate(oga)
+        close(gl[i], ol, what=f"alpha-CROWN lower {i}")
+        assert np.max(np.abs(ga[i] - oga)) <= 1e-4 * np.max(np.abs(oga)), f"alpha grad {i}"
+    steps = []
+    best, a, _ = N.optimize_alpha_beta(bn, *args[:1], args[1], args[2], args[3], args[4], steps=20,
+                                       lr=0.1, bound_of=dev(np.zeros(n), torch.int32),
+                                       lower_of_step=steps)
+    b, first = np_(best), np_(steps[0])
+    assert np.all(b >= first - 1e-6) and np.mean(b - first) > 0
+    assert 0.0 <= np_(a).min() and np_(a).max() <= 1.0

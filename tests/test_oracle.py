@@ -491,3 +491,36 @@ def test_slack_is_outward_and_small():
     for (l0, u0), (l1, u1) in zip(b_raw, b_sl):
         assert np.all(l1 <= l0) and np.all(u1 >= u0)
         assert np.all(l0 - l1 <= 1e-4 * (1 + np.abs(l0)))
+
+
+# ----------------------------------------------------------- full-size alpha-CROWN
+def test_adjoint_fd_full_cnn_32_coordinates():
+    """The 3x32x32 CNN with its full-CROWN root bounds (stored oracle output): the adjoint
+    of the final margin bound against central differences (h = 1e-6) at 32 random alpha
+    coordinates of unstable neurons, FP64."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cnn_root0.npz")
+    g = np.load(path)
+    w = W.cnn_cifar(1)
+    net = w.net
+    lo = g["lo"].astype(np.float32).astype(np.float64)
+    hi = g["hi"].astype(np.float32).astype(np.float64)
+    bounds = list(zip(O.per_layer(net, lo), O.per_layer(net, hi)))
+    rng = np.random.default_rng(7)
+    alpha = [rng.uniform(0.05, 0.95, len(l)) for (l, _) in bounds]
+    C = w.spec[0].astype(np.float64)
+    L = len(net)
+    _, ga, _ = O.spec_lower_grad(net, L, C, bounds, w.x_lo[0], w.x_hi[0], alpha)
+    unst = [(m, j) for m, (l, u) in enumerate(bounds) for j in np.nonzero((l < 0) & (u > 0))[0]]
+    pick = rng.choice(len(unst), size=32, replace=False)
+    h = 1e-6
+    for i in pick:
+        m, j = unst[i]
+        ap = [a.copy() for a in alpha]
+        am = [a.copy() for a in alpha]
+        ap[m][j] += h
+        am[m][j] -= h
+        fp = O.spec_lower(net, L, C, bounds, w.x_lo[0], w.x_hi[0], ap, use_slack=False).sum()
+        fm = O.spec_lower(net, L, C, bounds, w.x_lo[0], w.x_hi[0], am, use_slack=False).sum()
+        fd = (fp - fm) / (2 * h)
+        assert ga[m][j] == pytest.approx(fd, rel=1e-5, abs=1e-7 * (1 + abs(fd)))
