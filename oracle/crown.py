@@ -35,6 +35,13 @@ Readings where the text is silent or garbled (each is listed in the design notes
   * Adam with PyTorch's default moments, followed by projection of alpha to [0, 1] and
     beta to [0, inf).  Parity of optimiser trajectories is unpinned: only single steps
     at identical alpha / beta are compared.
+  * Propagation early stop (Appendix B.2, the early-stop algorithm): the backward
+    search ends at an early-stop node and the bound is concretised against that node's
+    box.  On a layer chain the node is either the ReLU of layer s (its propagation step
+    is skipped, so the bound is linear in h_s and is concretised over
+    [ReLU(l_s), ReLU(u_s)]) or the linear node producing z_s (the ReLU of layer s is
+    relaxed first, then the bound is concretised over [l_s, u_s]).  The text's worked
+    example describes both; both are provided (stop_mode "relu" / "linear").
 """
 from __future__ import annotations
 
@@ -305,6 +312,64 @@ def crown(net, C, x_lo, x_hi, use_slack=True):
     upper = -spec_lower(net, L, -np.asarray(C, F64), bounds, x_lo, x_hi,
                         use_slack=use_slack)
     return bounds, lower, upper
+
+
+# --------------------------------------------------------------------------------------
+# Propagation early stop (Appendix B.2).
+# --------------------------------------------------------------------------------------
+def backward_to(net, k, A, bounds, stop, mode, alpha=None, splits=(), beta=None):
+    """Theorem 1's recursion from z_k down to the early-stop node of layer `stop`.
+
+    mode "relu":   stop before relaxing z_stop; returns (coefficients on h_stop, offset,
+                   mag).
+    mode "linear": relax z_stop (Lemma 1, alpha, beta) and stop; returns (coefficients on
+                   z_stop, offset, mag).
+    """
+    A = np.asarray(A, F64)
+    layer = net[k - 1]
+    Wt = linear_T(layer, A)
+    bfull = bias_full(layer)
+    bt = A @ bfull
+    mag = np.abs(A) @ np.abs(bfull)
+    for m in range(k - 1, stop - 1, -1):
+        if mode == "relu" and m == stop:
+            return Wt, bt, mag
+        l, u = bounds[m - 1]
+        a_m = adaptive_alpha(l, u) if alpha is None else alpha[m - 1]
+        D_lo, D_up, b_lo, b_up, _ = relax(l, u, a_m)
+        pos = Wt >= 0
+        Am = np.where(pos, Wt * D_lo, Wt * D_up)
+        off = np.where(pos, Wt * b_lo, Wt * b_up)
+        bt = off.sum(axis=1) + bt
+        mag = mag + np.abs(off).sum(axis=1)
+        for q, (ms, j, sg) in enumerate(splits):
+            if ms == m and beta is not None:
+                Am[:, j] -= np.asarray(beta[q], F64) * sg
+        if m == stop:
+            return Am, bt, mag
+        layer = net[m - 1]
+        bfull = bias_full(layer)
+        Wt = linear_T(layer, Am)
+        bt = Am @ bfull + bt
+        mag = mag + np.abs(Am) @ np.abs(bfull)
+    raise ValueError("stop layer must be in 1..k-1")
+
+
+def spec_lower_early_stop(net, k, A, bounds, stop, mode, alpha=None, splits=(), beta=None,
+                          use_slack=True):
+    """Lower bound of A z_k with the backward pass stopped at layer `stop`, concretised
+    over that node's box (Theorem 2 with the node in place of the input)."""
+    cb, feasible = clamp_splits(bounds, splits)
+    if not feasible:
+        return np.full(np.asarray(A).shape[0], np.inf)
+    Wt, bt, mag = backward_to(net, k, A, cb, stop, mode, alpha, splits, beta)
+    l, u = cb[stop - 1]
+    if mode == "relu":
+        l, u = np.maximum(l, 0.0), np.maximum(u, 0.0)
+    lower = concretize(Wt, bt, l, u)
+    if use_slack:
+        lower = lower - slack(Wt, mag, l, u)
+    return lower
 
 
 # --------------------------------------------------------------------------------------

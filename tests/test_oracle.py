@@ -524,3 +524,64 @@ def test_adjoint_fd_full_cnn_32_coordinates():
         fm = O.spec_lower(net, L, C, bounds, w.x_lo[0], w.x_hi[0], am, use_slack=False).sum()
         fd = (fp - fm) / (2 * h)
         assert ga[m][j] == pytest.approx(fd, rel=1e-5, abs=1e-7 * (1 + abs(fd)))
+
+
+# ------------------------------------------------------------------ early stop (B.2)
+def test_early_stop_relu_node_is_interval_arithmetic_of_the_layers_above():
+    """Stopping at the last ReLU node of a 2-layer net leaves C W2 h + C b2 over the box of
+    h = ReLU(z_1): exactly the interval bound of the last layer (the oracle's IBP)."""
+    net = tiny_mlp([5, 9, 4], 101)
+    lo, hi = W.linf_box(W.uniform_inputs(1, 5, 102)[0], 0.3)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    C = np.eye(4)
+    got = O.spec_lower_early_stop(net, 2, C, bounds, 1, "relu", use_slack=False)
+    l1, u1 = bounds[0]
+    last = dict(net[1])
+    ib = O.ibp([last], np.maximum(l1, 0), np.maximum(u1, 0))
+    np.testing.assert_allclose(got, ib[0][0], rtol=1e-12, atol=1e-12)
+
+
+def test_early_stop_linear_node_is_vertex_minimum_of_relaxed_function():
+    """Stopping at the linear node below the ReLU (relax, then concretise over [l, u]) equals
+    the brute-force minimum, over the vertices of the pre-activation box, of the relaxed
+    linear function (Theorem 2 is exact for a box)."""
+    net = tiny_mlp([4, 6, 3], 103)
+    lo, hi = W.linf_box(W.uniform_inputs(1, 4, 104)[0], 0.4)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    l1, u1 = bounds[0]
+    rng = np.random.default_rng(105)
+    alpha = [rng.uniform(0, 1, 6)]
+    C = np.array([[1.0, -1.0, 0.0], [0.0, 1.0, -1.0]])
+    got = O.spec_lower_early_stop(net, 2, C, bounds, 1, "linear", alpha, use_slack=False)
+    W2 = net[1]["W"].astype(np.float64)
+    b2 = net[1]["b"].astype(np.float64)
+    D_lo, D_up, _, b_up, _ = O.relax(l1, u1, alpha[0])
+    verts = np.array(list(itertools.product(*[(l1[j], u1[j]) for j in range(6)])))
+    for r in range(2):
+        g = C[r] @ W2
+        # per-neuron relaxed value: lower line where the coefficient is >= 0, upper otherwise
+        vals = np.where(g >= 0, g * D_lo * verts, g * (D_up * verts + b_up)).sum(1) + C[r] @ b2
+        assert got[r] == pytest.approx(vals.min(), rel=1e-12, abs=1e-12)
+
+
+@pytest.mark.parametrize("dims,seed", [([2, 8, 8, 3], 111), ([2, 16, 16, 16, 2], 112)])
+def test_early_stop_is_sound_and_ordered(dims, seed):
+    """With exact intermediate bounds every early-stop bound is sound; stopping at the
+    ReLU node is never looser than relaxing it first (per neuron, the interval of
+    ReLU(z) is the tightest), and full propagation is a separate valid bound."""
+    net = tiny_mlp(dims, seed)
+    lo = np.array([-1.0, -0.5], np.float32)
+    hi = np.array([0.5, 1.0], np.float32)
+    pts = np.concatenate([sample_box(lo, hi, 100_000, seed), grid_2d(lo, hi)])
+    f = O.forward(net, pts)[-1]
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    L = len(net)
+    C = np.concatenate([np.eye(dims[-1]), -np.eye(dims[-1])])
+    fmin = (f @ C.T).min(axis=0)
+    rng = np.random.default_rng(seed)
+    alpha = [rng.uniform(0, 1, len(l)) for (l, _) in bounds]
+    for s in range(1, L):
+        a = O.spec_lower_early_stop(net, L, C, bounds, s, "relu", alpha, use_slack=False)
+        b = O.spec_lower_early_stop(net, L, C, bounds, s, "linear", alpha, use_slack=False)
+        assert np.all(fmin >= a - 1e-9) and np.all(fmin >= b - 1e-9)
+        assert np.all(a >= b - 1e-9)
