@@ -95,7 +95,18 @@ typedef struct {
  *           writes the coefficient form (bound_out.coeff / offset / offset_mag).
  * flags     BOUND_SAVE_FOR_GRAD (requires an explicit spec, no BOTH_SIDES, and
  *           n_inst*rows <= max_save_rows), BOUND_NO_SLACK, BOUND_BOTH_SIDES (not
- *           with beta). */
+ *           with beta).
+ * stop_layer, stop_mode  propagation early stop (Appendix B.2, the early-stop
+ *           algorithm): 0 = propagate to the input and concretise over the input box.
+ *           1 <= stop_layer < target: the backward search ends at the early-stop node
+ *           of ReLU layer s = stop_layer and the bound is concretised over that node's
+ *           box taken from lo / hi (after split clamping):
+ *             BOUND_STOP_RELU   the node is the ReLU of layer s: its relaxation is not
+ *                               applied; the box is [ReLU(l_s), ReLU(u_s)];
+ *             BOUND_STOP_LINEAR the node is the linear layer producing z_s: the ReLU of
+ *                               layer s is relaxed (alpha, beta) first; the box is
+ *                               [l_s, u_s].
+ *           x_lo / x_hi are still required (their values are not used). */
 typedef struct {
     int32_t n_inst;
     int32_t rows;
@@ -114,7 +125,11 @@ typedef struct {
     const float *x_lo;
     const float *x_hi;
     int32_t flags;
+    int32_t stop_layer;
+    int32_t stop_mode;
 } bound_pass;
+
+enum { BOUND_STOP_RELU = 1, BOUND_STOP_LINEAR = 2 };
 
 /* Outputs of a pass.
  * lower  [n_inst, ld] lower bound of spec row r at lower[i*ld + r];

@@ -376,9 +376,10 @@ def spec_lower_early_stop(net, k, A, bounds, stop, mode, alpha=None, splits=(), 
 # Adjoint: gradient of the raw lower bound w.r.t. alpha and beta.
 # --------------------------------------------------------------------------------------
 def spec_lower_grad(net, k, A, bounds, x_lo, x_hi, alpha, splits=(), beta=None,
-                    gbar=None):
+                    gbar=None, stop=0, mode=None):
     """Return (lower_raw [R], d(sum_r gbar_r lower_r)/d alpha (list per layer),
-    d(...)/d beta [nnz, R]).  gbar defaults to ones."""
+    d(...)/d beta [nnz, R]).  gbar defaults to ones.  With stop > 0 the bound is the
+    early-stop bound of spec_lower_early_stop(stop, mode)."""
     A = np.asarray(A, F64)
     R = A.shape[0]
     cb, feasible = clamp_splits(bounds, splits)
@@ -387,7 +388,14 @@ def spec_lower_grad(net, k, A, bounds, x_lo, x_hi, alpha, splits=(), beta=None,
         return (np.full(R, np.inf), [np.zeros(len(l)) for (l, _) in bounds[:k - 1]],
                 np.zeros((nnz, R)))
     tape = []
-    Wt1, bt1, _ = backward(net, k, A, cb, alpha, splits, beta, tape=tape)
+    if stop > 0:
+        Wt1, bt1 = _backward_taped(net, k, A, cb, alpha, splits, beta, tape, stop, mode)
+        l, u = cb[stop - 1]
+        if mode == "relu":
+            l, u = np.maximum(l, 0.0), np.maximum(u, 0.0)
+        x_lo, x_hi = l, u
+    else:
+        Wt1, bt1, _ = backward(net, k, A, cb, alpha, splits, beta, tape=tape)
     lower = concretize(Wt1, bt1, x_lo, x_hi)
     gbar = np.ones(R) if gbar is None else np.asarray(gbar, F64)
     x_lo = np.asarray(x_lo, F64)
@@ -398,11 +406,16 @@ def spec_lower_grad(net, k, A, bounds, x_lo, x_hi, alpha, splits=(), beta=None,
     bbar = gbar.copy()
     g_alpha = [np.zeros(len(l)) for (l, _) in cb[:k - 1]]
     g_beta = np.zeros((nnz, R))
-    for rec in reversed(tape):           # m = 1, 2, ..., k-1
+    first = True
+    for rec in reversed(tape):           # m = lowest, ..., k-1
         m = rec["m"]
-        layer = net[m - 1]
-        # Wt_m = A_m W_m and bt_m = A_m b_m + d_m  ->  A_m bar:
-        Abar = linear_fwd(layer, Wbar) + bbar[:, None] * bias_full(layer)[None, :]
+        if first and stop > 0 and mode == "linear":
+            Abar = Wbar                  # the concretised coefficients are A_stop itself
+        else:
+            layer = net[m - 1]
+            # Wt_m = A_m W_m and bt_m = A_m b_m + d_m  ->  A_m bar:
+            Abar = linear_fwd(layer, Wbar) + bbar[:, None] * bias_full(layer)[None, :]
+        first = False
         for q, (ms, j, sg) in enumerate(splits):
             if ms == m and beta is not None:
                 g_beta[q] += -sg * Abar[:, j]
@@ -415,6 +428,33 @@ def spec_lower_grad(net, k, A, bounds, x_lo, x_hi, alpha, splits=(), beta=None,
         Wbar = Abar * np.where(pos, rec["D_lo"][None, :], rec["D_up"][None, :]) + \
             bbar[:, None] * np.where(pos, 0.0, rec["b_up"][None, :])
     return lower, g_alpha, g_beta
+
+
+def _backward_taped(net, k, A, bounds, alpha, splits, beta, tape, stop, mode):
+    """backward_to with the per-layer values the adjoint needs appended to tape."""
+    A = np.asarray(A, F64)
+    layer = net[k - 1]
+    Wt = linear_T(layer, A)
+    bt = A @ bias_full(layer)
+    for m in range(k - 1, stop - 1, -1):
+        if mode == "relu" and m == stop:
+            return Wt, bt
+        l, u = bounds[m - 1]
+        a_m = adaptive_alpha(l, u) if alpha is None else alpha[m - 1]
+        D_lo, D_up, b_lo, b_up, unstable = relax(l, u, a_m)
+        pos = Wt >= 0
+        Am = np.where(pos, Wt * D_lo, Wt * D_up)
+        bt = np.where(pos, Wt * b_lo, Wt * b_up).sum(axis=1) + bt
+        for q, (ms, j, sg) in enumerate(splits):
+            if ms == m and beta is not None:
+                Am[:, j] -= np.asarray(beta[q], F64) * sg
+        tape.append(dict(m=m, Wt=Wt, D_lo=D_lo, D_up=D_up, b_up=b_up, unstable=unstable))
+        if m == stop:
+            return Am, bt
+        layer = net[m - 1]
+        Wt = linear_T(layer, Am)
+        bt = Am @ bias_full(layer) + bt
+    raise ValueError("stop layer must be in 1..k-1")
 
 
 # --------------------------------------------------------------------------------------

@@ -17,6 +17,7 @@ BOUND_OK, BOUND_E_ARG, BOUND_E_SHAPE, BOUND_E_NOMEM, BOUND_E_HIP, BOUND_E_STATE 
 BOUND_LINEAR, BOUND_CONV2D = 0, 1
 BOUND_SAVE_FOR_GRAD, BOUND_NO_SLACK, BOUND_BOTH_SIDES = 1, 2, 4
 BOUND_OPT_GEMM_ONLY = 1
+BOUND_STOP_RELU, BOUND_STOP_LINEAR = 1, 2
 
 EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "bound_grad",
             "bound_adam", "bound_autotune", "bound_autotune_report", "bound_set_options",
@@ -38,7 +39,8 @@ class BoundPass(ctypes.Structure):
                 ("n_bounds", ctypes.c_int32), ("spec", _p), ("lo", _p), ("hi", _p),
                 ("bound_of", _p), ("alpha", _p), ("split_off", _p), ("split_idx", _p),
                 ("split_sign", _p), ("nnz", ctypes.c_int32), ("beta", _p), ("x_lo", _p),
-                ("x_hi", _p), ("flags", ctypes.c_int32)]
+                ("x_hi", _p), ("flags", ctypes.c_int32), ("stop_layer", ctypes.c_int32),
+                ("stop_mode", ctypes.c_int32)]
 
 
 class BoundOut(ctypes.Structure):
@@ -141,10 +143,11 @@ def bound_dims(handle, n_layers_max=32):
 
 def _pass_out(n_inst, rows, target, spec, lo, hi, n_bounds, bound_of, alpha, split_off, split_idx,
               split_sign, nnz, beta, x_lo, x_hi, flags, lower, upper, ld, coeff, offset,
-              offset_mag, best):
+              offset_mag, best, stop_layer=0, stop_mode=0):
     P = BoundPass(int(n_inst), int(rows), int(target), int(n_bounds), _ptr(spec), _ptr(lo), _ptr(hi),
                   _ptr(bound_of), _ptr(alpha), _ptr(split_off), _ptr(split_idx), _ptr(split_sign),
-                  int(nnz), _ptr(beta), _ptr(x_lo), _ptr(x_hi), int(flags))
+                  int(nnz), _ptr(beta), _ptr(x_lo), _ptr(x_hi), int(flags), int(stop_layer),
+                  int(stop_mode))
     O = BoundOut(_ptr(lower), _ptr(upper), int(ld), _ptr(coeff), _ptr(offset), _ptr(offset_mag),
                  _ptr(best))
     return P, O
@@ -154,11 +157,11 @@ def bound_autotune(handle, n_inst, rows, target, *, grad_lower=None, spec=None, 
                    n_bounds=0, bound_of=None, alpha=None, split_off=None, split_idx=None,
                    split_sign=None, nnz=0, beta=None, x_lo=None, x_hi=None, flags=0, lower=None,
                    upper=None, ld=0, coeff=None, offset=None, offset_mag=None, best=None,
-                   stream=None):
+                   stop_layer=0, stop_mode=0, stream=None):
     """Tune every product of this pass (and its gradient); returns the timing log."""
     P, O = _pass_out(n_inst, rows, target, spec, lo, hi, n_bounds, bound_of, alpha, split_off,
                      split_idx, split_sign, nnz, beta, x_lo, x_hi, flags, lower, upper, ld, coeff,
-                     offset, offset_mag, best)
+                     offset, offset_mag, best, stop_layer, stop_mode)
     _check(lib().bound_autotune(handle, ctypes.byref(P), ctypes.byref(O), _ptr(grad_lower),
                                 _stream(stream)))
     return bound_autotune_report(handle)
@@ -175,10 +178,12 @@ def bound_autotune_report(handle):
 def bound_backward(handle, n_inst, rows, target, *, spec=None, lo=None, hi=None, n_bounds=0,
                    bound_of=None, alpha=None, split_off=None, split_idx=None, split_sign=None,
                    nnz=0, beta=None, x_lo=None, x_hi=None, flags=0, lower=None, upper=None,
-                   ld=0, coeff=None, offset=None, offset_mag=None, best=None, stream=None):
+                   ld=0, coeff=None, offset=None, offset_mag=None, best=None, stop_layer=0,
+                   stop_mode=0, stream=None):
     P = BoundPass(int(n_inst), int(rows), int(target), int(n_bounds), _ptr(spec), _ptr(lo), _ptr(hi),
                   _ptr(bound_of), _ptr(alpha), _ptr(split_off), _ptr(split_idx), _ptr(split_sign),
-                  int(nnz), _ptr(beta), _ptr(x_lo), _ptr(x_hi), int(flags))
+                  int(nnz), _ptr(beta), _ptr(x_lo), _ptr(x_hi), int(flags), int(stop_layer),
+                  int(stop_mode))
     O = BoundOut(_ptr(lower), _ptr(upper), int(ld), _ptr(coeff), _ptr(offset), _ptr(offset_mag),
                  _ptr(best))
     _check(lib().bound_backward(handle, ctypes.byref(P), ctypes.byref(O), _stream(stream)))

@@ -57,6 +57,9 @@ struct bound_net {
     float *cen = nullptr, *rad = nullptr;
     float *save = nullptr;
     float *sbar = nullptr;
+    float *stop_cen = nullptr, *stop_rad = nullptr;  // early-stop node box [max_inst][max relu width]
+    float *zeros = nullptr;                         // [max channels]: "no bias" at a linear stop
+    long max_relu_d = 0, max_chan = 0;
     int32_t *sp = nullptr;           // 3 x sp_cap: instance, layer, internal index
     int8_t *sp_sign = nullptr;
     long sp_cap = 0;
@@ -72,8 +75,9 @@ struct bound_net {
     std::vector<hipEvent_t> pool;
     // state of the last SAVE_FOR_GRAD pass
     bool saved = false;
-    int s_target = 0, s_rows = 0, s_n_inst = 0, s_nnz = 0;
+    int s_target = 0, s_rows = 0, s_n_inst = 0, s_nnz = 0, s_stop = 0, s_mode = 0;
     std::vector<long> s_off;         // offset of saved G_m (m = 1..k) in the save buffer
+    long s_lam_off = 0;              // saved Lambda at a linear early stop
 
     ~bound_net() {
         for (auto &r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
@@ -353,6 +357,12 @@ bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max
     net->n_relu = off;
     net->max_d = 0;
     for (long x : net->d) net->max_d = x > net->max_d ? x : net->max_d;
+    net->max_relu_d = 1;
+    net->max_chan = 1;
+    for (int t = 0; t < n_layers - 1; ++t)
+        net->max_relu_d = net->d[t + 1] > net->max_relu_d ? net->d[t + 1] : net->max_relu_d;
+    for (int i = 0; i < n_layers; ++i)
+        net->max_chan = layers[i].out_c > net->max_chan ? layers[i].out_c : net->max_chan;
 
     bool ok = net->alloc(&net->buf[0], max_rows * net->max_d) &&
               net->alloc(&net->buf[1], max_rows * net->max_d) &&
@@ -362,7 +372,10 @@ bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max
               net->alloc(&net->infeas, max_inst) && net->alloc(&net->cen, (long)max_inst * net->d[0]) &&
               net->alloc(&net->rad, (long)max_inst * net->d[0]) &&
               net->alloc(&net->sbar, max_save_rows > 0 ? max_save_rows : 1) &&
-              net->alloc(&net->save, max_save_rows * (net->d[0] + net->n_relu + net->d[n_layers - 1]));
+              net->alloc(&net->save, max_save_rows * (net->d[0] + net->n_relu + net->max_relu_d)) &&
+              net->alloc(&net->stop_cen, (long)max_inst * net->max_relu_d) &&
+              net->alloc(&net->stop_rad, (long)max_inst * net->max_relu_d) &&
+              net->alloc(&net->zeros, net->max_chan);
     if (!ok) {
         delete net;
         return fail(BOUND_E_NOMEM, "bound_init: workspace allocation failed");
@@ -371,6 +384,10 @@ bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max
     if (s != BOUND_OK) { delete net; return s; }
     s = build_geoms(net, st);
     if (s != BOUND_OK) { delete net; return s; }
+    if (launch_fill(net->zeros, net->max_chan, 0.f, st) != hipSuccess) {
+        delete net;
+        return fail(BOUND_E_HIP, "bound_init: fill");
+    }
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         delete net;
@@ -426,8 +443,19 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             return fail(BOUND_E_ARG, "SAVE_FOR_GRAD needs an explicit spec, a box and no BOTH_SIDES");
         if (total > net->max_save_rows) return fail(BOUND_E_NOMEM, "n_inst*rows > max_save_rows");
     }
+    const int sl = P->stop_layer, smode = sl > 0 ? P->stop_mode : 0;
+    if (sl < 0 || (sl > 0 && (sl >= k || (smode != BOUND_STOP_RELU && smode != BOUND_STOP_LINEAR))))
+        return fail(BOUND_E_ARG, "stop_layer must be 0 or in 1..target-1 with a stop_mode");
+    if (sl > 0 && !conc) return fail(BOUND_E_ARG, "early stop needs x_lo/x_hi (coefficient output is on x)");
     const long ld = out->ld > 0 ? out->ld : P->rows;
     net->saved = false;
+    // Bottom of the backward chain: the product of layer conc_m gets the concretising
+    // epilogue (input box, or the ReLU-node box at a ReLU stop); relax_low is the lowest
+    // product with the relaxation epilogue; at a linear stop the relaxed coefficients on
+    // z_sl are concretised by a separate reduction.
+    const int conc_m = smode == BOUND_STOP_LINEAR ? -1 : (smode == BOUND_STOP_RELU ? sl + 1 : 1);
+    const int relax_low = smode == BOUND_STOP_LINEAR ? sl + 1 : (smode == BOUND_STOP_RELU ? sl + 2 : 2);
+    const LayerShape *SL = sl > 0 ? &net->ns.l[sl - 1] : nullptr;
 
     // Relaxation tables (Lemma 1) for z_1 .. z_{k-1}, split clamping, box.
     const int used = k - 1;
@@ -446,9 +474,19 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
         HIPCHK(launch_fill((float *)net->infeas, P->n_inst, 0.f, st));
     }
     if (nnz > 0 && used > 0) {
+        if (sl > 0)
+            HIPCHK(launch_prep_stop_box(P->n_inst, *SL, net->n_relu, P->lo, P->hi, P->bound_of,
+                                        P->n_bounds, smode == BOUND_STOP_RELU, net->stop_cen,
+                                        net->stop_rad, st));
         HIPCHK(launch_prep_splits(net->ns, used, P->n_inst, net->n_relu, P->lo, P->hi, P->bound_of,
                                   P->split_off, P->split_idx, P->split_sign, net->tab, net->infeas,
-                                  sp_inst, sp_layer, sp_j, P->n_bounds, st));
+                                  sp_inst, sp_layer, sp_j, P->n_bounds, sl - 1,
+                                  smode == BOUND_STOP_RELU, sl > 0 ? net->stop_cen : nullptr,
+                                  sl > 0 ? net->stop_rad : nullptr, st));
+    } else if (sl > 0) {
+        HIPCHK(launch_prep_stop_box(P->n_inst, *SL, net->n_relu, P->lo, P->hi, P->bound_of,
+                                    P->n_bounds, smode == BOUND_STOP_RELU, net->stop_cen,
+                                    net->stop_rad, st));
     }
     if (conc) {
         HIPCHK(launch_prep_box(P->n_inst, net->C0, net->HW0, P->x_lo, P->x_hi, net->cen, net->rad, st));
@@ -460,12 +498,14 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
 
     const long chunk = save ? total : net->max_rows;
     std::vector<long> soff(k + 2, 0);  // offset of saved G_m for m = 1..k
+    long lam_off = 0;                  // saved Lambda on z_sl at a linear stop
     if (save) {
         long o = 0;
         for (int m = 1; m <= k; ++m) {
             soff[m] = o;
             o += total * net->d[m - 1];
         }
+        lam_off = o;
     }
     const bool inject = P->beta != nullptr && used > 0;
     for (long img0 = 0; img0 < total; img0 += chunk) {
@@ -483,8 +523,9 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             ip.kh = li.L.kh; ip.kw = li.L.kw; ip.stride = li.L.stride; ip.pad = li.L.pad;
             ip.dk = dk; ip.din = li.din; ip.rpi = rpi; ip.img0 = img0;
             ip.s = net->acc_s; ip.mag = net->acc_mag; ip.low = net->acc_low;
-            if (k == 1) {
-                ip.cen = net->cen; ip.rad = net->rad;
+            if (conc_m == k) {
+                ip.cen = sl > 0 ? net->stop_cen : net->cen;
+                ip.rad = sl > 0 ? net->stop_rad : net->rad;
                 ip.emit = conc ? nullptr : out->coeff + img0 * d0;
                 ProfScope ps(net, st, "init_identity_conc");
                 HIPCHK(launch_init_identity(ip, n_img, true, st));
@@ -492,7 +533,7 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             } else {
                 ip.tab = net->tab + net->relu_off(k - 1);
                 ip.tab_ld = net->n_relu;
-                ip.bias_m = net->bias(k - 1);
+                ip.bias_m = (smode == BOUND_STOP_LINEAR && sl == k - 1) ? net->zeros : net->bias(k - 1);
                 ip.chan_m = net->chan(k - 1);
                 ip.out = cur;
                 {
@@ -502,7 +543,7 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
                 if (inject)
                     HIPCHK(launch_beta_inject(nnz, P->rows, rpi, img0, n_img, k - 2, sp_inst, sp_layer,
                                               sp_j, P->split_sign, P->beta, cur, net->d[k - 1],
-                                              net->bias(k - 1), net->chan(k - 1), net->acc_s,
+                                              ip.bias_m, net->chan(k - 1), net->acc_s,
                                               net->acc_mag, st));
                 m_start = k - 1;
             }
@@ -514,13 +555,14 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
                                     net->acc_low, st));
             m_start = k;
         }
-        for (int m = m_start; m >= 2; --m) {
+        for (int m = m_start; m >= relax_low; --m) {
             RelaxParams rp{};
             rp.out = nxt;
             rp.save = save ? net->save + soff[m] : nullptr;
             rp.tab = net->tab + net->relu_off(m - 1);
             rp.tab_ld = net->n_relu;
-            rp.bias = net->bias(m - 1);
+            // at a linear stop the box is on z_sl itself, so its bias is not added
+            rp.bias = (smode == BOUND_STOP_LINEAR && m - 1 == sl) ? net->zeros : net->bias(m - 1);
             rp.chan = net->chan(m - 1);
             rp.D = net->d[m - 1];
             rp.s = net->acc_s;
@@ -539,22 +581,30 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             ProfScope pb(net, st, "beta_inject");
             if (inject)
                 HIPCHK(launch_beta_inject(nnz, P->rows, rpi, img0, n_img, m - 2, sp_inst, sp_layer, sp_j,
-                                          P->split_sign, P->beta, nxt, net->d[m - 1], net->bias(m - 1),
+                                          P->split_sign, P->beta, nxt, net->d[m - 1], rp.bias,
                                           net->chan(m - 1), net->acc_s, net->acc_mag, st));
             float *t = cur; cur = nxt; nxt = t;
         }
-        if (m_start >= 1) {
+        if (smode == BOUND_STOP_LINEAR) {
+            ProfScope ps(net, st, "stop_conc");
+            HIPCHK(launch_box_conc(img0, n_img, rpi, SL->d, cur, net->stop_cen, net->stop_rad,
+                                   net->acc_low, net->acc_mag, save ? net->save + lam_off : nullptr, st));
+        } else if (m_start >= conc_m) {
             ConcParams cp{};
-            cp.cen = net->cen; cp.rad = net->rad; cp.D = d0;
+            const long Dc = net->d[conc_m - 1];
+            cp.cen = sl > 0 ? net->stop_cen : net->cen;
+            cp.rad = sl > 0 ? net->stop_rad : net->rad;
+            cp.D = Dc;
             cp.low = net->acc_low; cp.mag = net->acc_mag;
-            cp.save = save ? net->save + soff[1] : nullptr;
+            cp.save = save ? net->save + soff[conc_m] : nullptr;
             cp.emit = conc ? nullptr : out->coeff + img0 * d0;
-            cp.chan = net->C0; cp.hw = net->HW0;
+            cp.chan = sl > 0 ? SL->C : net->C0;
+            cp.hw = sl > 0 ? SL->HW : net->HW0;
             cp.img0 = img0; cp.rpi = rpi;
-            ProfScope ps(net, st, "bwd_conc_L1");
-            const GeomSet &gs = net->layers[0].gT;
+            ProfScope ps(net, st, lbl("bwd_conc_L%d", conc_m));
+            const GeomSet &gs = net->layers[conc_m - 1].gT;
             const float *A = cur;
-            bound_status bs = run_product(net, st, pkey('C', 1), gs, [&](const Plan &pl) {
+            bound_status bs = run_product(net, st, pkey('C', conc_m), gs, [&](const Plan &pl) {
                 return gemm_conc(gs, A, n_img, cp, st, pl);
             });
             if (bs != BOUND_OK) return bs;
@@ -572,6 +622,9 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
         net->s_n_inst = P->n_inst;
         net->s_nnz = used > 0 ? nnz : 0;
         net->s_off = soff;
+        net->s_stop = sl;
+        net->s_mode = smode;
+        net->s_lam_off = lam_off;
         if (net->s_nnz > 0) {
             HIPCHK(hipMemcpyAsync(net->sp_sign, P->split_sign, (size_t)nnz, hipMemcpyDeviceToDevice, st));
         }
@@ -593,13 +646,37 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
         if (grad_beta && net->s_nnz > 0) HIPCHK(launch_fill(grad_beta, (long)net->s_nnz * rows, 0.f, st));
     }
     float *cur = net->buf[0], *nxt = net->buf[1];
-    {
-        ProfScope pi(net, st, "adj_init");
-        HIPCHK(launch_adj_init(n_img, rows, d0, grad_lower, net->save + net->s_off[1], net->cen,
-                               net->rad, net->infeas, cur, net->sbar, st));
-    }
     int32_t *sp_inst = net->sp, *sp_layer = net->sp + net->sp_cap, *sp_j = net->sp + 2 * net->sp_cap;
-    for (int m = 1; m <= k - 1; ++m) {
+    const int sl = net->s_stop, smode = net->s_mode;
+    int m0 = 1;  // first adjoint product
+    if (smode == BOUND_STOP_LINEAR) {
+        // reverse of the box concretisation of Lambda_sl and of the relaxation of z_sl
+        const LayerShape &S = net->ns.l[sl - 1];
+        const long Ds = S.d;
+        ProfScope pi(net, st, "adj_init");
+        HIPCHK(launch_adj_stop_linear(n_img, rows, Ds, net->save + net->s_lam_off,
+                                      net->save + net->s_off[sl + 1], net->stop_cen, net->stop_rad,
+                                      grad_lower, net->infeas, net->sbar,
+                                      net->tab + net->relu_off(sl), net->n_relu,
+                                      sl + 1 < k ? cur : nullptr, grad_alpha, net->n_relu,
+                                      net->relu_off(sl), S.C, S.HW, st));
+        if (grad_beta && net->s_nnz > 0)
+            HIPCHK(launch_beta_grad_stop(net->s_nnz, rows, sl - 1, Ds, sp_inst, sp_layer, sp_j,
+                                         net->sp_sign, net->save + net->s_lam_off, net->stop_cen,
+                                         net->stop_rad, net->sbar, grad_beta, st));
+        m0 = sl + 1;
+    } else {
+        // d lower / d (coefficients at the concretised node) = s_bar (c - sign(.) r)
+        const int cm = smode == BOUND_STOP_RELU ? sl + 1 : 1;
+        const long Dc = net->d[cm - 1];
+        ProfScope pi(net, st, "adj_init");
+        HIPCHK(launch_adj_init(n_img, rows, Dc, grad_lower, net->save + net->s_off[cm],
+                               sl > 0 ? net->stop_cen : net->cen, sl > 0 ? net->stop_rad : net->rad,
+                               net->infeas, cur, net->sbar, st));
+        m0 = cm;
+    }
+    (void)d0;
+    for (int m = m0; m <= k - 1; ++m) {
         const LayerInfo &li = net->layers[m - 1];
         AdjParams ap{};
         ap.sbar = net->sbar;

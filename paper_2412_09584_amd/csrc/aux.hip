@@ -84,7 +84,8 @@ __global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, 
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const int32_t *off, const int32_t *idx, const int8_t *sign,
                               Relax *tab, int32_t *infeas, int32_t *sp_inst, int32_t *sp_layer,
-                              int32_t *sp_j, int n_bounds) {
+                              int32_t *sp_j, int n_bounds, int stop_m, int stop_relu,
+                              float *stop_cen, float *stop_rad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_inst) return;
     const long b = bound_row(bound_of, i, n_bounds);
@@ -108,9 +109,33 @@ __global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, 
         const long j = to_internal(jn, L.C, L.HW);
         tab[(long)i * n_relu + L.off + j] = l >= 0.f ? make_float4(1.f, 1.f, 0.f, 0.f)
                                                      : make_float4(0.f, 0.f, 0.f, 0.f);
+        if (m == stop_m && stop_cen) {  // the early-stop node's box sees the clamp too
+            const float a = stop_relu ? fmaxf(l, 0.f) : l, c = stop_relu ? fmaxf(u, 0.f) : u;
+            stop_cen[(long)i * L.d + j] = 0.5f * (a + c);
+            stop_rad[(long)i * L.d + j] = 0.5f * (c - a);
+        }
         sp_layer[q] = m;
         sp_j[q] = (int32_t)j;
     }
+}
+
+// Box of the early-stop node of ReLU layer `L` (internal order): [l, u] of z_s, or
+// [ReLU(l), ReLU(u)] of h_s when relu != 0.
+__global__ void k_prep_stop_box(long total, LayerShape L, long n_relu, const float *lo,
+                                const float *hi, const int32_t *bound_of, int n_bounds, int relu,
+                                float *cen, float *rad) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const long inst = e / L.d, j = e - inst * L.d;
+    const long b = bound_row(bound_of, inst, n_bounds);
+    const long jn = to_cmajor(j, L.C, L.HW);
+    float l = lo[b * n_relu + L.off + jn], u = hi[b * n_relu + L.off + jn];
+    if (relu) {
+        l = fmaxf(l, 0.f);
+        u = fmaxf(u, 0.f);
+    }
+    cen[e] = 0.5f * (l + u);
+    rad[e] = 0.5f * (u - l);
 }
 
 __global__ void k_prep_box(long total, long d0, int C0, int HW0, const float *x_lo,
@@ -324,6 +349,69 @@ __global__ void k_beta_grad(int nnz, int rows, int layer, const BetaGradLayer L,
     }
 }
 
+// lower/mag[img] += sum_j lam c - |lam| r, sum_j |lam| (|c| + r) over one row of internal-order
+// coefficients, c / r the per-instance box (early stop over a pre-activation box).
+__global__ void k_box_conc(long img0, int rpi, long D, const float *lam, const float *cen,
+                           const float *rad, float *low, float *mag, float *save) {
+    const long li = blockIdx.x;
+    const long inst = (img0 + li) / rpi;
+    const float *row = lam + li * D;
+    const float *c = cen + inst * D, *r = rad + inst * D;
+    float a = 0.f, b = 0.f;
+    for (long j = threadIdx.x; j < D; j += blockDim.x) {
+        const float w = row[j];
+        a += w * c[j] - fabsf(w) * r[j];
+        b += fabsf(w) * (fabsf(c[j]) + r[j]);
+        if (save) save[li * D + j] = w;
+    }
+    block_sum2(a, b);
+    if (threadIdx.x == 0) {
+        low[li] += a;
+        mag[li] += b;
+    }
+}
+
+// Adjoint at an early stop over the pre-activation box of layer m: lam_bar = s_bar (c -
+// sign(lam) r), then the reverse of the relaxation of layer m (G_bar_{m+1}, alpha-grad).
+__global__ void k_adj_stop_linear(long n_img, int rows, long D, const float *lam, const float *g,
+                                  const float *cen, const float *rad, const float *gl,
+                                  const int32_t *infeas, float *sbar, const Relax *tab, long tab_ld,
+                                  float *gout, float *galpha, long ga_ld, long ga_off, int C, int HW) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_img * D) return;
+    const long img = e / D, j = e - img * D;
+    const long inst = img / rows;
+    const float sb = infeas[inst] ? 0.f : gl[img];
+    if (j == 0) sbar[img] = sb;
+    const float l = lam[e];
+    const float sg = l > 0.f ? 1.f : (l < 0.f ? -1.f : 0.f);
+    const float v = sb * (cen[inst * D + j] - sg * rad[inst * D + j]);
+    const float gv = g[e];
+    const Relax t = tab[inst * tab_ld + j];
+    if (gout) gout[e] = v * (gv >= 0.f ? t.x : t.y) + (gv < 0.f ? sb * t.z : 0.f);
+    if (t.w != 0.f && gv >= 0.f) {
+        const float c = gv * v;
+        if (c != 0.f) atomicAdd(galpha + inst * ga_ld + ga_off + to_cmajor(j, C, HW), c);
+    }
+}
+
+__global__ void k_beta_grad_stop(int nnz, int rows, int layer, long D, const int32_t *sp_inst,
+                                 const int32_t *sp_layer, const int32_t *sp_j, const int8_t *sign,
+                                 const float *lam, const float *cen, const float *rad,
+                                 const float *sbar, float *gbeta) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)nnz * rows) return;
+    const int q = (int)(e / rows), r = (int)(e - (long)q * rows);
+    if (sp_layer[q] != layer) return;
+    const long inst = sp_inst[q];
+    const long img = inst * rows + r;
+    const long j = sp_j[q];
+    const float l = lam[img * D + j];
+    const float sg = l > 0.f ? 1.f : (l < 0.f ? -1.f : 0.f);
+    const float lam_bar = sbar[img] * (cen[inst * D + j] - sg * rad[inst * D + j]);
+    gbeta[(long)q * rows + r] = -(float)sign[q] * lam_bar;
+}
+
 __global__ void k_adam(long n, float *p, const float *g, float *m, float *v, float b1, float b2,
                        float bc1, float bc2s, float lr, float eps, float gs, float lo, float hi) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -429,11 +517,12 @@ hipError_t launch_prep_splits(const NetShapes &ns, int used, int n_inst, long n_
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const int32_t *off, const int32_t *idx, const int8_t *sign,
                               Relax *tab, int32_t *infeas, int32_t *sp_inst, int32_t *sp_layer,
-                              int32_t *sp_j, int n_bounds, hipStream_t st) {
+                              int32_t *sp_j, int n_bounds, int stop_m, int stop_relu,
+                              float *stop_cen, float *stop_rad, hipStream_t st) {
     const long T = used > 0 ? ns.l[used - 1].off + ns.l[used - 1].d : 0;
     hipLaunchKernelGGL(k_prep_splits, dim3(blocks_for(n_inst, 64)), dim3(64), 0, st, ns, used, T,
                        n_inst, n_relu, lo, hi, bound_of, off, idx, sign, tab, infeas, sp_inst,
-                       sp_layer, sp_j, n_bounds);
+                       sp_layer, sp_j, n_bounds, stop_m, stop_relu, stop_cen, stop_rad);
     return hipGetLastError();
 }
 
@@ -502,6 +591,46 @@ hipError_t launch_beta_grad(int nnz, int rows, int layer, const BetaGradLayer &L
     if (waves == 0) return hipSuccess;
     hipLaunchKernelGGL(k_beta_grad, dim3(blocks_for(waves * 64)), dim3(TPB), 0, st, nnz, rows,
                        layer, L, sp_inst, sp_layer, sp_j, sign, gbar_m, sbar, gbeta);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_stop_box(int n_inst, const LayerShape &L, long n_relu, const float *lo,
+                                const float *hi, const int32_t *bound_of, int n_bounds, bool relu,
+                                float *cen, float *rad, hipStream_t st) {
+    const long total = (long)n_inst * L.d;
+    hipLaunchKernelGGL(k_prep_stop_box, dim3(blocks_for(total)), dim3(TPB), 0, st, total, L, n_relu,
+                       lo, hi, bound_of, n_bounds, relu ? 1 : 0, cen, rad);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_conc(long img0, long n_img, int rpi, long D, const float *lam, const float *cen,
+                           const float *rad, float *low, float *mag, float *save, hipStream_t st) {
+    if (n_img <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_box_conc, dim3((unsigned)n_img), dim3(TPB), 0, st, img0, rpi, D, lam, cen,
+                       rad, low, mag, save);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_stop_linear(long n_img, int rows, long D, const float *lam, const float *g,
+                                  const float *cen, const float *rad, const float *gl,
+                                  const int32_t *infeas, float *sbar, const Relax *tab, long tab_ld,
+                                  float *gout, float *galpha, long ga_ld, long ga_off, int C, int HW,
+                                  hipStream_t st) {
+    const long total = n_img * D;
+    hipLaunchKernelGGL(k_adj_stop_linear, dim3(blocks_for(total)), dim3(TPB), 0, st, n_img, rows, D,
+                       lam, g, cen, rad, gl, infeas, sbar, tab, tab_ld, gout, galpha, ga_ld, ga_off,
+                       C, HW);
+    return hipGetLastError();
+}
+
+hipError_t launch_beta_grad_stop(int nnz, int rows, int layer, long D, const int32_t *sp_inst,
+                                 const int32_t *sp_layer, const int32_t *sp_j, const int8_t *sign,
+                                 const float *lam, const float *cen, const float *rad,
+                                 const float *sbar, float *gbeta, hipStream_t st) {
+    const long total = (long)nnz * rows;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_beta_grad_stop, dim3(blocks_for(total)), dim3(TPB), 0, st, nnz, rows, layer,
+                       D, sp_inst, sp_layer, sp_j, sign, lam, cen, rad, sbar, gbeta);
     return hipGetLastError();
 }
 

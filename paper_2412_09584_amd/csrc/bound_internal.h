@@ -133,7 +133,22 @@ hipError_t launch_prep_splits(const NetShapes &ns, int n_layers_used, int n_inst
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const int32_t *off, const int32_t *idx, const int8_t *sign,
                               Relax *tab, int32_t *infeas, int32_t *sp_inst,
-                              int32_t *sp_layer, int32_t *sp_j, int n_bounds, hipStream_t st);
+                              int32_t *sp_layer, int32_t *sp_j, int n_bounds, int stop_m,
+                              int stop_relu, float *stop_cen, float *stop_rad, hipStream_t st);
+hipError_t launch_prep_stop_box(int n_inst, const LayerShape &L, long n_relu, const float *lo,
+                                const float *hi, const int32_t *bound_of, int n_bounds, bool relu,
+                                float *cen, float *rad, hipStream_t st);
+hipError_t launch_box_conc(long img0, long n_img, int rpi, long D, const float *lam, const float *cen,
+                           const float *rad, float *low, float *mag, float *save, hipStream_t st);
+hipError_t launch_adj_stop_linear(long n_img, int rows, long D, const float *lam, const float *g,
+                                  const float *cen, const float *rad, const float *gl,
+                                  const int32_t *infeas, float *sbar, const Relax *tab, long tab_ld,
+                                  float *gout, float *galpha, long ga_ld, long ga_off, int C, int HW,
+                                  hipStream_t st);
+hipError_t launch_beta_grad_stop(int nnz, int rows, int layer, long D, const int32_t *sp_inst,
+                                 const int32_t *sp_layer, const int32_t *sp_j, const int8_t *sign,
+                                 const float *lam, const float *cen, const float *rad,
+                                 const float *sbar, float *gbeta, hipStream_t st);
 hipError_t launch_prep_box(int n_inst, int C0, int HW0, const float *x_lo, const float *x_hi,
                            float *cen, float *rad, hipStream_t st);
 hipError_t launch_init_spec(long img0, long n_img, int rows, int rpi, const float *spec,

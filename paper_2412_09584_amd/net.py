@@ -63,7 +63,8 @@ class BoundNet:
         return lo, hi
 
     def spec_bounds(self, C, lo, hi, x_lo, x_hi, *, target=None, alpha=None, bound_of=None,
-                    splits=None, beta=None, both=True, slack=True, save=False, best=None):
+                    splits=None, beta=None, both=True, slack=True, save=False, best=None,
+                    stop_layer=0, stop_mode=0):
         """Bounds of C z_target.  Returns (lower, upper or None)."""
         target = self.L if target is None else target
         C = _dev(C, self.device)
@@ -80,7 +81,7 @@ class BoundNet:
         B.bound_backward(self.handle, n, rows, target, spec=C, lo=lo, hi=hi, n_bounds=n_bounds,
                          bound_of=bound_of, alpha=alpha, beta=beta, x_lo=_dev(x_lo, self.device),
                          x_hi=_dev(x_hi, self.device), flags=flags, lower=lower, upper=upper,
-                         best=best, **kw)
+                         best=best, stop_layer=stop_layer, stop_mode=stop_mode, **kw)
         return lower, upper
 
     def coefficients(self, C, lo, hi, *, target=None, alpha=None, both=False):

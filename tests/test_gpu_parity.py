@@ -632,3 +632,53 @@ def test_alpha_crown_cnn_64_instances(mod, golden_cnn):
     b, first = np_(best), np_(steps[0])
     assert np.all(b >= first - 1e-6) and np.mean(b - first) > 0
     assert 0.0 <= np_(a).min() and np_(a).max() <= 1.0
+
+
+@pytest.mark.parametrize("mode", ["relu", "linear"])
+@pytest.mark.parametrize("kind", ["mlp", "cnn"])
+def test_early_stop_pass_and_grad(mod, mode, kind):
+    """Propagation early stop at every layer: bound and alpha/beta gradients at identical
+    alpha / beta against the oracle (splits clamp the stop node's box too)."""
+    N, B = mod
+    net = W.mlp([30, 24, 24, 24, 6], seed=131) if kind == "mlp" else tiny_cnn(seed=132, **CNN_GEOMS[0])
+    n_roots, per_root = 2, 5
+    x0 = W.uniform_inputs(n_roots, W.in_dim(net), 133)
+    x_lo, x_hi = W.linf_box(x0, 0.05)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    ob = oracle_bounds(net, x_lo, x_hi)
+    lo, hi = flat(ob)
+    lo, hi = f32(lo).astype(np.float64), f32(hi).astype(np.float64)
+    n = n_roots * per_root
+    root_of = np.repeat(np.arange(n_roots), per_root).astype(np.int32)
+    sp = _random_splits(net, lo, hi, n, 134, root_of)
+    alpha = W.random_alpha(n, lo.shape[1], 135)
+    beta = W.random_beta(sp.nnz, C.shape[1], 136)
+    bn = N.BoundNet(net, n, 4096, 4096)
+    sm = B.BOUND_STOP_RELU if mode == "relu" else B.BOUND_STOP_LINEAR
+    L = len(net)
+    for stop in range(1, L):
+        gl, _ = bn.spec_bounds(C[root_of], dev(f32(lo)), dev(f32(hi)), x_lo[root_of], x_hi[root_of],
+                               alpha=dev(alpha), bound_of=dev(root_of, torch.int32),
+                               splits=N.splits_to_device(sp), beta=dev(beta), both=False, save=True,
+                               stop_layer=stop, stop_mode=sm)
+        ga, gb = bn.grad(torch.ones(n, C.shape[1], device="cuda"), sp.nnz)
+        gl, ga, gb = np_(gl), np_(ga), np_(gb)
+        for i in range(n):
+            r = root_of[i]
+            q0, q1 = sp.off[i], sp.off[i + 1]
+            bounds = list(zip(O.per_layer(net, lo[r]), O.per_layer(net, hi[r])))
+            splits = O.split_list(net, sp.neuron[q0:q1], sp.sign[q0:q1])
+            al = O.per_layer(net, alpha[i])
+            be = beta[q0:q1].astype(np.float64)
+            ol = O.spec_lower_early_stop(net, L, C[r], bounds, stop, mode, al, splits, be)
+            close(gl[i], ol, what=f"stop {stop} lower {i}")
+            if np.all(np.isinf(ol)):
+                continue
+            _, oga, ogb = O.spec_lower_grad(net, L, C[r], bounds, x_lo[r], x_hi[r], al, splits, be,
+                                            stop=stop, mode=mode)
+            oga = np.concatenate(oga)
+            sa = max(np.max(np.abs(oga)), 1e-30)
+            assert np.max(np.abs(ga[i] - oga)) <= 1e-4 * sa, f"stop {stop} alpha grad {i}"
+            if q1 > q0:
+                sb = max(np.max(np.abs(ogb)), sa)
+                assert np.max(np.abs(gb[q0:q1] - ogb)) <= 1e-4 * sb, f"stop {stop} beta grad {i}"

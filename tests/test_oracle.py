@@ -585,3 +585,45 @@ def test_early_stop_is_sound_and_ordered(dims, seed):
         b = O.spec_lower_early_stop(net, L, C, bounds, s, "linear", alpha, use_slack=False)
         assert np.all(fmin >= a - 1e-9) and np.all(fmin >= b - 1e-9)
         assert np.all(a >= b - 1e-9)
+
+
+@pytest.mark.parametrize("mode", ["relu", "linear"])
+def test_early_stop_adjoint_fd(mode):
+    net = tiny_mlp([5, 12, 12, 12, 4], 121)
+    lo, hi = W.linf_box(W.uniform_inputs(1, 5, 122)[0], 0.3)
+    bounds = O.crown_bounds(net, lo, hi, use_slack=False)
+    unst = [(m + 1, j) for m, (l, u) in enumerate(bounds) for j in range(len(l)) if l[j] < 0 < u[j]]
+    C = np.array([[1.0, -1.0, 0, 0], [1.0, 0, -1.0, 0], [1.0, 0, 0, -1.0]])
+    rng = np.random.default_rng(123)
+    L = len(net)
+    for stop in (1, 2):
+        splits = [u_ for u_ in unst if u_[0] >= stop][:3]
+        splits = [(m, j, int(rng.choice([-1, 1]))) for (m, j) in splits]
+        alpha = [rng.uniform(0.05, 0.95, len(l)) for (l, _) in bounds]
+        beta = rng.uniform(0.05, 1.0, size=(len(splits), 3))
+        gbar = rng.uniform(0.5, 1.5, 3)
+        low, ga, gb = O.spec_lower_grad(net, L, C, bounds, lo, hi, alpha, splits, beta, gbar,
+                                        stop=stop, mode=mode)
+        np.testing.assert_allclose(low, O.spec_lower_early_stop(net, L, C, bounds, stop, mode, alpha,
+                                                                splits, beta, use_slack=False), rtol=1e-12)
+
+        def val(al, be):
+            return float(gbar @ O.spec_lower_early_stop(net, L, C, bounds, stop, mode, al, splits, be,
+                                                        use_slack=False))
+        h = 1e-6
+        cb, _ = O.clamp_splits(bounds, splits)
+        lowest = stop + 1 if mode == "relu" else stop
+        coords = [(m, j) for m, (l, u) in enumerate(cb) for j in np.nonzero((l < 0) & (u > 0))[0]
+                  if m + 1 >= lowest]
+        for i in rng.choice(len(coords), size=min(16, len(coords)), replace=False):
+            m, j = coords[i]
+            ap = [x.copy() for x in alpha]; am = [x.copy() for x in alpha]
+            ap[m][j] += h; am[m][j] -= h
+            fd = (val(ap, beta) - val(am, beta)) / (2 * h)
+            assert ga[m][j] == pytest.approx(fd, rel=1e-5, abs=1e-7)
+        for q in range(len(splits)):
+            for r in range(3):
+                bp = beta.copy(); bm = beta.copy()
+                bp[q, r] += h; bm[q, r] -= h
+                fd = (val(alpha, bp) - val(alpha, bm)) / (2 * h)
+                assert gb[q, r] == pytest.approx(fd, rel=1e-5, abs=1e-7)
