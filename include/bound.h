@@ -171,6 +171,19 @@ bound_status bound_dims(const bound_net *net, int32_t *n_layers, int32_t *d, int
 bound_status bound_backward(bound_net *net, const bound_pass *pass, const bound_out *out,
                             void *stream);
 
+/* Search-integrated (empirical) pre-activation bounds (Section 3.2, approach 2): the
+ * network is evaluated on per_sub sample inputs of each of n_sub subdomains and every
+ * pre-activation z_1 .. z_{L-1} gets the minimum / maximum over its subdomain's samples.
+ * x   [n_sub * per_sub, d_0] sample inputs (subdomain-major);
+ * lo, hi [n_sub, n_relu] outputs in the lo/hi layout of bound_pass (both or neither);
+ * out [n_sub * per_sub, d_L] network outputs z_L, or NULL.
+ * These bounds hold for the samples, not for every point of the subdomain (the paper
+ * accepts that for planning); they are meant as the early-stop node's box.
+ * per_sub must not exceed max_rows; larger n_sub are processed in chunks.  Invalidates
+ * the state kept for bound_grad. */
+bound_status bound_sample_bounds(bound_net *net, int32_t n_sub, int32_t per_sub, const float *x,
+                                 float *lo, float *hi, float *out, void *stream);
+
 /* Standalone concretisation (Theorem 2 for a box) of coefficient rows:
  * lower[i*rows + r] = coeff[i,r,:] . c - |coeff[i,r,:]| . rad + offset[i,r]
  *                     - (unless BOUND_NO_SLACK) 64 * 2^-24 * (|coeff| . (|c| + rad)

@@ -372,6 +372,13 @@ def spec_lower_early_stop(net, k, A, bounds, stop, mode, alpha=None, splits=(), 
     return lower
 
 
+def sample_bounds(net, samples):
+    """Search-integrated (empirical) pre-activation bounds of one subdomain (Section 3.2,
+    approach 2): per neuron of z_1 .. z_{L-1}, the min and max over the sample inputs."""
+    zs = forward(net, samples)
+    return [(z.min(axis=0), z.max(axis=0)) for z in zs[:-1]]
+
+
 # --------------------------------------------------------------------------------------
 # Adjoint: gradient of the raw lower bound w.r.t. alpha and beta.
 # --------------------------------------------------------------------------------------

@@ -20,7 +20,7 @@ BOUND_OPT_GEMM_ONLY = 1
 BOUND_STOP_RELU, BOUND_STOP_LINEAR = 1, 2
 
 EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "bound_grad",
-            "bound_adam", "bound_autotune", "bound_autotune_report", "bound_set_options",
+            "bound_adam", "bound_sample_bounds", "bound_autotune", "bound_autotune_report", "bound_set_options",
             "bound_profile", "bound_profile_read", "bound_destroy",
             "bound_last_error")
 
@@ -73,6 +73,7 @@ def lib():
         L.bound_concretize.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _p, _p, _p,
                                        _p, _p, ctypes.c_int32, _p, _p]
         L.bound_grad.argtypes = [_p, _p, _p, _p, _p]
+        L.bound_sample_bounds.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p, _p]
         L.bound_adam.argtypes = [ctypes.c_int64, _p, _p, _p, _p, ctypes.c_int32, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, _p]
@@ -194,6 +195,11 @@ def bound_concretize(n_inst, rows, d0, coeff, offset, offset_mag, x_lo, x_hi, fl
     _check(lib().bound_concretize(int(n_inst), int(rows), int(d0), _ptr(coeff), _ptr(offset),
                                   _ptr(offset_mag), _ptr(x_lo), _ptr(x_hi), int(flags), _ptr(lower),
                                   _stream(stream)))
+
+
+def bound_sample_bounds(handle, n_sub, per_sub, x, lo=None, hi=None, out=None, stream=None):
+    _check(lib().bound_sample_bounds(handle, int(n_sub), int(per_sub), _ptr(x), _ptr(lo), _ptr(hi),
+                                     _ptr(out), _stream(stream)))
 
 
 def bound_grad(handle, grad_lower, grad_alpha, grad_beta=None, stream=None):

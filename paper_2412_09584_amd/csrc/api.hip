@@ -716,6 +716,56 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
     return BOUND_OK;
 }
 
+bound_status bound_sample_bounds(bound_net *net, int32_t n_sub, int32_t per_sub, const float *x,
+                                 float *lo, float *hi, float *out, void *stream) {
+    if (!net || n_sub < 1 || per_sub < 1 || !x || (!lo) != (!hi) || (!lo && !out))
+        return fail(BOUND_E_ARG, "bound_sample_bounds: bad arguments");
+    if ((long)per_sub > net->max_rows)
+        return fail(BOUND_E_NOMEM, "bound_sample_bounds: per_sub > max_rows");
+    hipStream_t st = (hipStream_t)stream;
+    net->saved = false;
+    const int L = net->n_layers;
+    const long subs_per_chunk = net->max_rows / per_sub;
+    for (long s0 = 0; s0 < n_sub; s0 += subs_per_chunk) {
+        const long ns = n_sub - s0 < subs_per_chunk ? n_sub - s0 : subs_per_chunk;
+        const long n_img = ns * per_sub;
+        float *cur = net->buf[0], *nxt = net->buf[1];
+        {
+            ProfScope ps(net, st, "fwd_input");
+            HIPCHK(launch_to_internal(n_img, net->C0, net->HW0, x + s0 * per_sub * net->d[0], cur, st));
+        }
+        for (int m = 1; m <= L; ++m) {
+            const LayerInfo &li = net->layers[m - 1];
+            FwdParams fp{};
+            fp.out = nxt;
+            fp.bias = li.L.bias;
+            fp.D = net->d[m];
+            {
+                ProfScope ps(net, st, lbl("fwd_L%d", m));
+                const float *A = cur;
+                bound_status bs = run_product(net, st, pkey('F', m), li.gF, [&](const Plan &pl) {
+                    return gemm_fwd(li.gF, A, n_img, fp, st, pl);
+                });
+                if (bs != BOUND_OK) return bs;
+            }
+            const bool last = m == L;
+            const int C = li.L.out_c, HW = li.L.out_h * li.L.out_w;
+            ProfScope pm(net, st, "fwd_minmax");
+            if (!last) {
+                HIPCHK(launch_sample_minmax(ns, per_sub, net->d[m], C, HW, nxt,
+                                            lo ? lo + s0 * net->n_relu + net->relu_off(m) : nullptr,
+                                            hi ? hi + s0 * net->n_relu + net->relu_off(m) : nullptr,
+                                            net->n_relu, true, nullptr, st));
+            } else if (out) {
+                HIPCHK(launch_sample_minmax(ns, per_sub, net->d[m], C, HW, nxt, nullptr, nullptr, 0,
+                                            false, out + s0 * per_sub * net->d[L], st));
+            }
+            float *t = cur; cur = nxt; nxt = t;
+        }
+    }
+    return BOUND_OK;
+}
+
 bound_status bound_concretize(int32_t n_inst, int32_t rows, int32_t d0, const float *coeff,
                               const float *offset, const float *offset_mag, const float *x_lo,
                               const float *x_hi, int32_t flags, float *lower, void *stream) {

@@ -412,6 +412,37 @@ __global__ void k_beta_grad_stop(int nnz, int rows, int layer, long D, const int
     gbeta[(long)q * rows + r] = -(float)sign[q] * lam_bar;
 }
 
+// C-major rows -> internal (channels-last) rows.
+__global__ void k_to_internal(long total, long D, int C, int HW, const float *x, float *y) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const long img = e / D, j = e - img * D;
+    y[e] = x[img * D + to_cmajor(j, C, HW)];
+}
+
+// Per subdomain and neuron: min / max of z over its per_sub sample rows (written C-major
+// at lo/hi[sub*ld + j]); then z <- ReLU(z) in place for the next layer, or a copy of the
+// last layer's output to `out` (C-major).
+__global__ void k_sample_minmax(long n_sub, int per_sub, long D, int C, int HW, float *z, float *lo,
+                                float *hi, long ld, int relu, float *out) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_sub * D) return;
+    const long sub = e / D, j = e - sub * D;
+    float mn = INFINITY, mx = -INFINITY;
+    for (int s = 0; s < per_sub; ++s) {
+        const long o = (sub * per_sub + s) * D + j;
+        const float v = z[o];
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+        if (relu) z[o] = fmaxf(v, 0.f);
+        if (out) out[(sub * per_sub + s) * D + to_cmajor(j, C, HW)] = v;
+    }
+    if (lo) {
+        lo[sub * ld + to_cmajor(j, C, HW)] = mn;
+        hi[sub * ld + to_cmajor(j, C, HW)] = mx;
+    }
+}
+
 __global__ void k_adam(long n, float *p, const float *g, float *m, float *v, float b1, float b2,
                        float bc1, float bc2s, float lr, float eps, float gs, float lo, float hi) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -631,6 +662,22 @@ hipError_t launch_beta_grad_stop(int nnz, int rows, int layer, long D, const int
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_beta_grad_stop, dim3(blocks_for(total)), dim3(TPB), 0, st, nnz, rows, layer,
                        D, sp_inst, sp_layer, sp_j, sign, lam, cen, rad, sbar, gbeta);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_internal(long n_img, int C, int HW, const float *x, float *y, hipStream_t st) {
+    const long D = (long)C * HW, total = n_img * D;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_internal, dim3(blocks_for(total)), dim3(TPB), 0, st, total, D, C, HW, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_minmax(long n_sub, int per_sub, long D, int C, int HW, float *z, float *lo,
+                                float *hi, long ld, bool relu, float *out, hipStream_t st) {
+    const long total = n_sub * D;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sample_minmax, dim3(blocks_for(total)), dim3(TPB), 0, st, n_sub, per_sub, D,
+                       C, HW, z, lo, hi, ld, relu ? 1 : 0, out);
     return hipGetLastError();
 }
 

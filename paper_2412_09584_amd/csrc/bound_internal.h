@@ -74,6 +74,12 @@ struct AdjParams {         // Lambda_bar_m = G_bar_m W_m^T + s_bar b_m  -> G_bar
     int rpi;
 };
 
+struct FwdParams {         // z_m = W_m h_{m-1} + b_m for sample rows
+    float *out;            // z_m [img][D]
+    const float *bias;     // b_m per channel
+    long D;
+};
+
 // ----- product launchers ---------------------------------------------------------
 // A plan picks the kernel of one product: path 0 = automatic (direct convolution when
 // the geometry fits, else the implicit GEMM with the default tile), 1 = direct
@@ -92,6 +98,8 @@ hipError_t gemm_conc(const GeomSet &gs, const float *A, long n_img, const ConcPa
                      hipStream_t st, const Plan &plan);
 hipError_t gemm_adj(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
                     hipStream_t st, const Plan &plan);
+hipError_t gemm_fwd(const GeomSet &gs, const float *A, long n_img, const FwdParams &p,
+                    hipStream_t st, const Plan &plan);
 // Valid plans for a product (direct variants first, then GEMM tiles); returns the count.
 int plan_candidates(const GeomSet &gs, Plan *out, int cap);
 // gemm.hip: implicit GEMM with an explicit tile configuration (cfg < 0: default)
@@ -101,6 +109,8 @@ hipError_t gemm_conc_cfg(const GeomSet &gs, const float *A, long n_img, const Co
                          hipStream_t st, int cfg);
 hipError_t gemm_adj_cfg(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
                         hipStream_t st, int cfg);
+hipError_t gemm_fwd_cfg(const GeomSet &gs, const float *A, long n_img, const FwdParams &p,
+                        hipStream_t st, int cfg);
 int gemm_candidates(const GeomSet &gs, int *cfgs, int cap);
 // conv.hip: direct convolution (cc = 0: largest chunk that fits); *used = false when the
 // geometry does not fit
@@ -109,6 +119,8 @@ hipError_t direct_relax(const GeomSet &gs, const float *A, long n_img, const Rel
 hipError_t direct_conc(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,
                        hipStream_t st, int cc, bool *used);
 hipError_t direct_adj(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
+                      hipStream_t st, int cc, bool *used);
+hipError_t direct_fwd(const GeomSet &gs, const float *A, long n_img, const FwdParams &p,
                       hipStream_t st, int cc, bool *used);
 int direct_candidates(const GeomSet &gs, int *cc, int cap);
 
@@ -205,6 +217,9 @@ hipError_t launch_beta_grad(int nnz, int rows, int layer, const BetaGradLayer &L
                             const int32_t *sp_j, const int8_t *sign, const float *gbar_m,
                             const float *gl, const int32_t *infeas, float *gbeta,
                             hipStream_t st);
+hipError_t launch_to_internal(long n_img, int C, int HW, const float *x, float *y, hipStream_t st);
+hipError_t launch_sample_minmax(long n_sub, int per_sub, long D, int C, int HW, float *z,
+                                float *lo, float *hi, long ld, bool relu, float *out, hipStream_t st);
 hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int step,
                        float lr, float b1, float b2, float eps, float gs, float lo, float hi,
                        hipStream_t st);

@@ -435,6 +435,11 @@ hipError_t direct_adj(const GeomSet &gs, const float *A, long n_img, const AdjPa
     return try_direct(gs, A, n_img, EpiAdj{p}, st, cc, used);
 }
 
+hipError_t direct_fwd(const GeomSet &gs, const float *A, long n_img, const FwdParams &p,
+                      hipStream_t st, int cc, bool *used) {
+    return try_direct(gs, A, n_img, EpiFwd{p}, st, cc, used);
+}
+
 int direct_candidates(const GeomSet &gs, int *cc, int cap) {
     const Geom &g = gs.g[0];
     if (g.H == 1 && g.W == 1 && g.kh == 1 && g.kw == 1) return 0;

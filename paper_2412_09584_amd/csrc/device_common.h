@@ -100,6 +100,21 @@ struct EpiAdj {
     }
 };
 
+// Forward pass of sample rows (search-integrated bounds): z = W h + b.
+struct EpiFwd {
+    FwdParams p;
+    static constexpr int NRED = 0;
+    struct Row {};
+    __device__ Row row(long) const { return Row{}; }
+    __device__ float colv(int n) const { return p.bias[n]; }
+    __device__ float *red0() const { return nullptr; }
+    __device__ float *red1() const { return nullptr; }
+    __device__ void elem(const Row &, long img, long, int, long j, float bcol, float acc, float &,
+                         float &) const {
+        p.out[img * p.D + j] = acc + bcol;
+    }
+};
+
 // Sum of r0 / r1 over the lanes that hold the same output row (they differ only in the
 // column bits of the lane id), then one atomic per row from the column-0 lane.
 template <int MF>

@@ -326,6 +326,10 @@ hipError_t gemm_adj_cfg(const GeomSet &gs, const float *A, long n_img, const Adj
                         hipStream_t st, int cfg) {
     return dispatch(gs, A, n_img, dev::EpiAdj{p}, st, cfg);
 }
+hipError_t gemm_fwd_cfg(const GeomSet &gs, const float *A, long n_img, const FwdParams &p,
+                        hipStream_t st, int cfg) {
+    return dispatch(gs, A, n_img, dev::EpiFwd{p}, st, cfg);
+}
 
 int plan_candidates(const GeomSet &gs, Plan *out, int cap) {
     int n = 0;
@@ -361,6 +365,7 @@ int plan_candidates(const GeomSet &gs, Plan *out, int cap) {
 BOUND_PRODUCT(gemm_relax, RelaxParams, direct_relax, gemm_relax_cfg)
 BOUND_PRODUCT(gemm_conc, ConcParams, direct_conc, gemm_conc_cfg)
 BOUND_PRODUCT(gemm_adj, AdjParams, direct_adj, gemm_adj_cfg)
+BOUND_PRODUCT(gemm_fwd, FwdParams, direct_fwd, gemm_fwd_cfg)
 #undef BOUND_PRODUCT
 
 }  // namespace bp

@@ -682,3 +682,41 @@ def test_early_stop_pass_and_grad(mod, mode, kind):
             if q1 > q0:
                 sb = max(np.max(np.abs(ogb)), sa)
                 assert np.max(np.abs(gb[q0:q1] - ogb)) <= 1e-4 * sb, f"stop {stop} beta grad {i}"
+
+
+@pytest.mark.parametrize("kind", ["mlp", "cnn"])
+def test_sample_bounds_and_early_stop_over_them(mod, kind):
+    """Search-integrated bounds (min / max over each subdomain's samples) against the
+    oracle's forward pass; then an early-stop pass over (oracle) empirical bounds."""
+    N, B = mod
+    net = W.mlp([30, 24, 24, 24, 6], seed=151) if kind == "mlp" else tiny_cnn(seed=152, **CNN_GEOMS[0])
+    n_sub, per = 6, 40
+    x0 = W.uniform_inputs(n_sub, W.in_dim(net), 153)
+    x_lo, x_hi = W.linf_box(x0, 0.05)
+    rng = np.random.default_rng(154)
+    samples = (x_lo[:, None, :] + (x_hi - x_lo)[:, None, :] *
+               rng.uniform(0, 1, (n_sub, per, x_lo.shape[1]))).astype(np.float32)
+    bn = N.BoundNet(net, n_sub, 4096, 1024)
+    lo = torch.empty(n_sub, bn.n_relu, device="cuda")
+    hi = torch.empty_like(lo)
+    out = torch.empty(n_sub * per, bn.d[-1], device="cuda")
+    B.bound_sample_bounds(bn.handle, n_sub, per, dev(samples.reshape(n_sub * per, -1)), lo, hi, out)
+    emp = []
+    for i in range(n_sub):
+        eb = O.sample_bounds(net, samples[i].astype(np.float64))
+        e_lo = np.concatenate([b[0] for b in eb])
+        e_hi = np.concatenate([b[1] for b in eb])
+        close(np_(lo)[i], e_lo, what=f"sample lo {i}")
+        close(np_(hi)[i], e_hi, what=f"sample hi {i}")
+        close(np_(out)[i * per:(i + 1) * per], O.forward(net, samples[i])[-1], what="outputs")
+        emp.append((e_lo, e_hi))
+    e_lo = f32(np.stack([e[0] for e in emp])).astype(np.float64)
+    e_hi = f32(np.stack([e[1] for e in emp])).astype(np.float64)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    L = len(net)
+    for mode, sm in (("relu", B.BOUND_STOP_RELU), ("linear", B.BOUND_STOP_LINEAR)):
+        gl, _ = bn.spec_bounds(C, dev(f32(e_lo)), dev(f32(e_hi)), x_lo, x_hi, both=False,
+                               stop_layer=L - 1, stop_mode=sm)
+        for i in range(n_sub):
+            b = list(zip(O.per_layer(net, e_lo[i]), O.per_layer(net, e_hi[i])))
+            close(np_(gl)[i], O.spec_lower_early_stop(net, L, C[i], b, L - 1, mode), what=f"{mode} {i}")

@@ -627,3 +627,19 @@ def test_early_stop_adjoint_fd(mode):
                 bp[q, r] += h; bm[q, r] -= h
                 fd = (val(alpha, bp) - val(alpha, bm)) / (2 * h)
                 assert gb[q, r] == pytest.approx(fd, rel=1e-5, abs=1e-7)
+
+
+# ------------------------------------------------------- search-integrated bounds
+def test_sample_bounds_inside_sound_bounds_and_exact_on_vertices():
+    net = tiny_mlp([3, 10, 10, 2], 141)
+    lo, hi = W.linf_box(W.uniform_inputs(1, 3, 142)[0], 0.2)
+    crown_b = O.crown_bounds(net, lo, hi, use_slack=False)
+    pts = sample_box(lo, hi, 20_000, 143)
+    emp = O.sample_bounds(net, pts)
+    for (el, eu), (cl, cu) in zip(emp, crown_b):
+        assert np.all(el >= cl - 1e-12) and np.all(eu <= cu + 1e-12)
+    # first layer: z_1 is affine in x, so its extremes over the box sit at vertices
+    verts = np.array(list(itertools.product(*[(lo[j], hi[j]) for j in range(3)])), np.float64)
+    ev = O.sample_bounds(net, verts)
+    np.testing.assert_allclose(ev[0][0], crown_b[0][0], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(ev[0][1], crown_b[0][1], rtol=1e-12, atol=1e-12)
