@@ -55,6 +55,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the kernel autotuner")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one plain 1 GiB device-to-device copy (a known-size kernel "
+                         "for scaling the HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the batch of subdomains is independent per GPU "
@@ -69,6 +72,12 @@ def main():
     from paper_2412_09584_amd import net as N
 
     dev = torch.device("cuda")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, device=dev)          # 1 GiB of float32
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = W.beta_cnn(args.roots, args.per_root)
     net = w.net
     L = len(net)
@@ -120,6 +129,7 @@ def main():
                                     x_hi=x_hi, flags=B.BOUND_SAVE_FOR_GRAD, lower=lower,
                                     stream=stream)
         best.fill_(-float("inf"))
+        print(tune_log, file=sys.stderr)
     t = 0
     for _ in range(args.warmup):
         t += 1

@@ -60,8 +60,9 @@ typedef struct bound_net bound_net; /* opaque, owned by the library */
  *          input is the flattened output of a conv layer (then in_c/in_h/in_w give
  *          that shape and the weight has in_c*in_h*in_w columns).
  * Conv2d : weight [out_c, in_c, kh, kw], bias [out_c]; square kernel (kh == kw),
- *          symmetric zero padding `pad`, stride `stride`;
- *          out_h = (in_h + 2 pad - kh) / stride + 1 (likewise out_w). */
+ *          symmetric zero padding `pad`, stride 1 or 2,
+ *          out_h = (in_h + 2 pad - kh) / stride + 1 (likewise out_w),
+ *          kh * kw * in_c <= 1024 and kh * kw * out_c <= 1024. */
 typedef struct {
     int32_t kind;
     int32_t in_c, in_h, in_w;

@@ -320,6 +320,11 @@ bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max
                                                ": bad shape (square kernel, stride 1 or 2, "
                                                "out = (in + 2 pad - k) / stride + 1)");
             }
+            if (L.kh * L.kw * L.in_c > 1024 || L.kh * L.kw * L.out_c > 1024) {
+                delete net;
+                return fail(BOUND_E_SHAPE, "conv layer " + std::to_string(i + 1) +
+                                               ": kh*kw*channels must not exceed 1024");
+            }
         } else {
             delete net;
             return fail(BOUND_E_ARG, "layer " + std::to_string(i + 1) + ": unknown kind");

@@ -86,6 +86,30 @@ __device__ inline void stage_weights(float *Wl, const ConvTile &ct, const Geom &
     }
 }
 
+// Register prefetch capacity per thread (float4s) for the next chunk's input tile and
+// weights; plan_chunk keeps every tile within it.
+constexpr int MAX_IN4 = 8, MAX_W4 = 6;
+
+// Element walk over a [rows][P] float4 grid: thread tid visits e = tid, tid + 256, ...;
+// the row / column of each visit advance incrementally (one division per thread).
+struct Walk {
+    int r, p, dr, dp, P;
+    __device__ Walk(int P_) : P(P_) {
+        r = threadIdx.x / P;
+        p = threadIdx.x - r * P;
+        dr = 256 / P;
+        dp = 256 - dr * P;
+    }
+    __device__ void next() {
+        p += dp;
+        r += dr;
+        if (p >= P) {
+            p -= P;
+            ++r;
+        }
+    }
+};
+
 template <class Epi, int MF, int BN, bool VEC>
 __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile ct,
                                               const float *__restrict__ X, const long n_img,
@@ -96,6 +120,7 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     extern __shared__ __attribute__((aligned(16))) float smem[];
     float *In = smem;
     float *Wl = smem + ct.in_floats;
+    int *koff = (int *)(Wl + BN * ct.WS);     // [KB] A-operand offset of k inside the tile
 
     const Geom &g = gs.g[blockIdx.z];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -107,6 +132,19 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     const int n0 = blockIdx.y * BN;
     const int tile_px = ct.TR * g.OW;
     const int iy0 = oyb * g.stride - g.pad_y, ix0 = -g.pad_x;
+    const int TC = ct.T * ct.CC;
+
+    // k -> offset of (tap, channel) inside the LDS input tile; padding k reads offset 0
+    // against zero weights.
+    for (int k = tid; k < ct.KB; k += 256) {
+        int o = 0;
+        if (k < TC) {
+            const int t = k / ct.CC, c = k - t * ct.CC;
+            const int ty = t / g.kw, tx = t - ty * g.kw;
+            o = (ty * ct.IW + tx) * ct.CS + c;
+        }
+        koff[k] = o;
+    }
 
     // LDS offset of the top-left input of each A row this lane supplies.
     int abase[FM];
@@ -125,22 +163,80 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
 #pragma unroll
             for (int v = 0; v < MM::NACC; ++v) acc[i][j][v] = 0.f;
 
+    // Staging of one channel chunk through registers (VEC: CC is a power of two >= 4).
+    // The tile position of each staged float4 is the same for every chunk; only the
+    // channel offset c0 changes, so global and LDS offsets are computed once here
+    // (global offsets relative to the block's first image; -1 marks zero padding).
+    const int c4s = VEC ? ct.lcc - 2 : 0;             // log2(CC / 4)
+    const int Pin = ct.IW << c4s, Rin = ct.G * ct.IH;  // input grid [G*IH][IW*CC/4]
+    const int Pw = ct.KB >> 2;                         // weight grid [BN][KB/4]
+    const float *Xb = X + img0 * (long)g.H * g.W * g.C;
+    const float *Bb = g.Bt + (long)n0 * g.Kp;
+    int gin[MAX_IN4], lin[MAX_IN4], gw[MAX_W4], lw[MAX_W4];
+    if (VEC) {
+        Walk w(Pin);
+#pragma unroll
+        for (int i = 0; i < MAX_IN4; ++i) {
+            gin[i] = -1;
+            lin[i] = -1;
+            if (w.r < Rin) {
+                const int gi = w.r / ct.IH, iy = w.r - gi * ct.IH;
+                const int ix = w.p >> c4s, c4 = w.p & ((1 << c4s) - 1);
+                const int y = iy0 + iy, x = ix0 + ix;
+                lin[i] = (w.r * ct.IW + ix) * ct.CS + 4 * c4;
+                if (img0 + gi < n_img && (unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W)
+                    gin[i] = ((gi * g.H + y) * g.W + x) * g.C + 4 * c4;
+            }
+            w.next();
+        }
+        Walk ww(Pw);
+#pragma unroll
+        for (int i = 0; i < MAX_W4; ++i) {
+            gw[i] = -1;
+            lw[i] = -1;
+            const int k = ww.p << 2;
+            if (ww.r < BN) {
+                lw[i] = ww.r * ct.WS + k;
+                if (k < TC) gw[i] = ww.r * g.Kp + (k >> ct.lcc) * g.C + (k & (ct.CC - 1));
+            }
+            ww.next();
+        }
+    }
+    float4 rin[MAX_IN4], rw[MAX_W4];
+    auto load_chunk = [&](int c0) {
+#pragma unroll
+        for (int i = 0; i < MAX_IN4; ++i)
+            rin[i] = gin[i] >= 0 ? *(const float4 *)(Xb + gin[i] + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int i = 0; i < MAX_W4; ++i)
+            rw[i] = gw[i] >= 0 ? *(const float4 *)(Bb + gw[i] + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int i = 0; i < MAX_IN4; ++i)
+            if (lin[i] >= 0) *(float4 *)(In + lin[i]) = rin[i];
+#pragma unroll
+        for (int i = 0; i < MAX_W4; ++i)
+            if (lw[i] >= 0) *(float4 *)(Wl + lw[i]) = rw[i];
+    };
+
     const int kgrp = MM::grp(lane) * KPL;   // this lane's first k inside a 16-wide k block
-    const int TC = ct.T * ct.CC;
+    if (VEC) {
+        load_chunk(0);
+        store_chunk();
+    } else {
+        stage_input<false>(In, ct, g, X, img0, n_img, iy0, ix0, 0);
+        stage_weights(Wl, ct, g, BN, n0, 0);
+    }
+    __syncthreads();
     for (int ch = 0; ch < ct.nchunk; ++ch) {
-        const int c0 = ch * ct.CC;
-        __syncthreads();
-        stage_input<VEC>(In, ct, g, X, img0, n_img, iy0, ix0, c0);
-        stage_weights(Wl, ct, g, BN, n0, c0);
-        __syncthreads();
+        const bool more = VEC && ch + 1 < ct.nchunk;
+        if (more) load_chunk((ch + 1) * ct.CC);      // in flight during this chunk's MFMAs
         for (int kb = 0; kb < ct.KB; kb += 16) {
-            const int k = kb + kgrp;               // KPL consecutive k of one tap (VEC)
+            const int k = kb + kgrp;
             float af[FM][KPL], bf[FN][KPL];
-            if (VEC) {
-                const int t = k < TC ? (k >> ct.lcc) : 0;
-                const int c = k - (t << ct.lcc);
-                const int ty = t / g.kw, tx = t - ty * g.kw;
-                const int off = (ty * ct.IW + tx) * ct.CS + (k < TC ? c : 0);
+            if (VEC) {   // KPL consecutive k share a tap: contiguous channels
+                const int off = koff[k];
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -151,11 +247,7 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
             } else {
 #pragma unroll
                 for (int q = 0; q < KPL; ++q) {
-                    const int kk = k + q;
-                    const int t = kk < TC ? kk / ct.CC : 0;
-                    const int c = kk < TC ? kk - t * ct.CC : 0;
-                    const int ty = t / g.kw, tx = t - ty * g.kw;
-                    const int off = (ty * ct.IW + tx) * ct.CS + c;
+                    const int off = koff[k + q];
 #pragma unroll
                     for (int i = 0; i < FM; ++i) af[i][q] = In[abase[i] + off];
                 }
@@ -174,6 +266,11 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
 #pragma unroll
                     for (int j = 0; j < FN; ++j) acc[i][j] = MM::mma(af[i][s], bf[j][s], acc[i][j]);
         }
+        if (more) {
+            __syncthreads();
+            store_chunk();
+            __syncthreads();
+        }
     }
 
     // ---------------------------------------------------------------- epilogue
@@ -184,41 +281,17 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
         ncol[j] = n0 + j * MF + MM::col(lane);
         bcol[j] = ncol[j] < g.N ? epi.colv(ncol[j]) : 0.f;
     }
-    constexpr int NR = Epi::NRED;
     const int gfirst = (wave * 64) / tile_px, glast = (wave * 64 + 63) / tile_px;
-    const bool uniform = NR > 0 && gfirst == glast;
-    float u0 = 0.f, u1 = 0.f;
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-        for (int v = 0; v < MM::NACC; ++v) {
-            float r0 = 0.f, r1 = 0.f;
-            const int lr = wave * 64 + i * MF + MM::row(v, lane);
-            const int gi = lr / tile_px, q = lr - gi * tile_px;
-            const int py = q / g.OW, px = q - py * g.OW;
-            const long img = img0 + gi;
-            const bool ok = img < n_img;
-            if (ok) {
-                const int oy = oyb + py;
-                const long dpix = (long)(oy * g.ostr + g.oy0) * g.DW + (px * g.ostr + g.ox0);
-                const auto rc = epi.row(img);
-#pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    if (ncol[j] < g.N)
-                        epi.elem(rc, img, dpix, ncol[j], dpix * g.N + ncol[j], bcol[j], acc[i][j][v], r0, r1);
-            }
-            if (NR > 0) {
-                if (uniform) {
-                    u0 += r0;
-                    u1 += r1;
-                } else {
-                    reduce_row_atomic<MF>(r0, r1, ok ? img : -1, lane, epi.red0(), epi.red1());
-                }
-            }
-        }
-    }
-    if (NR > 0 && uniform && img0 + gfirst < n_img)
-        reduce_wave_atomic(u0, u1, img0 + gfirst, lane, epi.red0(), epi.red1());
+    const bool uniform = gfirst == glast && img0 + gfirst < n_img;
+    auto rowfn = [&](int i, int v, int &img, long &dpix) {
+        const int lr = wave * 64 + i * MF + MM::row(v, lane);
+        const int gi = lr / tile_px, q = lr - gi * tile_px;
+        const int py = q / g.OW, px = q - py * g.OW;
+        img = img0 + gi < n_img ? (int)(img0 + gi) : -1;
+        dpix = (long)((oyb + py) * g.ostr + g.oy0) * g.DW + (px * g.ostr + g.ox0);
+    };
+    tile_epilogue<Epi, MF, FM, FN>(epi, acc, ncol, bcol, g.N, rowfn, lane, uniform,
+                                   uniform ? img0 + gfirst : -1);
 }
 
 // One thread per output pixel, up to NMAX output channels, VALU FMAs from LDS.
@@ -270,10 +343,14 @@ __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvT
     float r0 = 0.f, r1 = 0.f;
     if (img < n_img) {
         const long dpix = (long)((oyb + py) * g.ostr + g.oy0) * g.DW + (px * g.ostr + g.ox0);
-        const auto rc = epi.row(img);
+        const auto rc = epi.row((int)img);
+        typename Epi::Pre pre[NMAX];
 #pragma unroll
         for (int n = 0; n < NMAX; ++n)
-            if (n < g.N) epi.elem(rc, img, dpix, n, dpix * g.N + n, epi.colv(n), acc[n], r0, r1);
+            if (n < g.N) pre[n] = epi.pre(rc, (int)img, dpix * g.N + n);
+#pragma unroll
+        for (int n = 0; n < NMAX; ++n)
+            if (n < g.N) epi.post(pre[n], rc, (int)img, dpix, n, dpix * g.N + n, epi.colv(n), acc[n], r0, r1);
     }
     if (Epi::NRED > 0) {
         // a wave's 64 pixels lie in one image whenever an image has >= 64 pixels
@@ -340,7 +417,9 @@ size_t plan_chunk(const Geom &g, int BN, int KPL, ConvTile &ct, int want = 0) {
             const size_t in = (size_t)ct.G * ct.IH * ct.IW * cs;
             const int kb = ((ct.T * cc + 15) / 16) * 16;
             const size_t w = (size_t)BN * (kb + 4);
-            if ((in + w) * 4 <= LDS_BUDGET) { best = cc; break; }
+            const bool regs = (size_t)ct.G * ct.IH * ct.IW * (cc / 4) <= 256 * MAX_IN4 &&
+                              (size_t)BN * (kb / 4) <= 256 * MAX_W4;
+            if (regs && (in + w + kb) * 4 <= LDS_BUDGET) { best = cc; break; }
         }
         if (!best) return 0;
         ct.CC = best;
@@ -351,7 +430,7 @@ size_t plan_chunk(const Geom &g, int BN, int KPL, ConvTile &ct, int want = 0) {
     ct.KB = ((ct.T * ct.CC + 15) / 16) * 16;
     ct.WS = ct.KB + 4;
     ct.in_floats = ct.G * ct.IH * ct.IW * ct.CS;
-    const size_t bytes = ((size_t)ct.in_floats + (size_t)BN * ct.WS) * 4;
+    const size_t bytes = ((size_t)ct.in_floats + (size_t)BN * ct.WS + ct.KB) * 4;
     return bytes <= LDS_BUDGET ? bytes : 0;
 }
 

@@ -37,65 +37,83 @@ template <> struct Mma<16> {
 };
 
 // ---------------------------------------------------------------------- epilogues
+// Each epilogue splits its per-element work into pre() -- the global loads it needs
+// (relaxation record, box, saved coefficient) -- and post() -- arithmetic, stores and
+// atomics -- so that tile_epilogue can issue a group's loads before any of its stores.
 struct EpiRelax {
     RelaxParams p;
     static constexpr int NRED = 2;
-    struct Row { long inst; };
-    __device__ Row row(long img) const { return Row{(p.img0 + img) / p.rpi}; }
+    using Pre = Relax;
+    struct Row { const Relax *tb; float *out, *save; };
+    __device__ Row row(int img) const {
+        const long inst = (p.img0 + img) / p.rpi;
+        const long o = (long)img * p.D;
+        return Row{p.tab + inst * p.tab_ld, p.out + o, p.save ? p.save + o : nullptr};
+    }
     __device__ float colv(int n) const { return p.bias[n % p.chan]; }
     __device__ float *red0() const { return p.s; }
     __device__ float *red1() const { return p.mag; }
-    __device__ void elem(const Row &rc, long img, long dpix, int n, long j, float bcol, float g,
+    __device__ Pre pre(const Row &rc, int, long j) const { return rc.tb[j]; }
+    __device__ void post(const Pre &t, const Row &rc, int, long, int, long j, float bcol, float g,
                          float &r0, float &r1) const {
-        const Relax t = p.tab[rc.inst * p.tab_ld + j];
         const float lam = g >= 0.f ? g * t.x : g * t.y;
         const float off = g < 0.f ? g * t.z : 0.f;
         const float bt = lam * bcol;
         r0 += bt + off;
         r1 += fabsf(bt) + fabsf(off);
-        const long o = img * p.D + j;
-        p.out[o] = lam;
-        if (p.save) p.save[o] = g;
+        rc.out[j] = lam;
+        if (rc.save) rc.save[j] = g;
     }
 };
 
 struct EpiConc {
     ConcParams p;
     static constexpr int NRED = 2;
-    struct Row { long inst; };
-    __device__ Row row(long img) const { return Row{(p.img0 + img) / p.rpi}; }
+    using Pre = float2;
+    struct Row { const float *cen, *rad; float *save, *emit; };
+    __device__ Row row(int img) const {
+        const long inst = (p.img0 + img) / p.rpi;
+        const long o = (long)img * p.D;
+        return Row{p.cen + inst * p.D, p.rad + inst * p.D, p.save ? p.save + o : nullptr,
+                   p.emit ? p.emit + o : nullptr};
+    }
     __device__ float colv(int) const { return 0.f; }
     __device__ float *red0() const { return p.low; }
     __device__ float *red1() const { return p.mag; }
-    __device__ void elem(const Row &rc, long img, long dpix, int n, long j, float, float g,
-                         float &r0, float &r1) const {
-        const long ij = rc.inst * p.D + j;
-        const float c = p.cen[ij], r = p.rad[ij];
-        r0 += g * c - fabsf(g) * r;
-        r1 += fabsf(g) * (fabsf(c) + r);
-        if (p.save) p.save[img * p.D + j] = g;
-        if (p.emit) p.emit[img * p.D + (long)n * p.hw + dpix] = g;
+    __device__ Pre pre(const Row &rc, int, long j) const { return make_float2(rc.cen[j], rc.rad[j]); }
+    __device__ void post(const Pre &cr, const Row &rc, int, long dpix, int n, long j, float,
+                         float g, float &r0, float &r1) const {
+        r0 += g * cr.x - fabsf(g) * cr.y;
+        r1 += fabsf(g) * (fabsf(cr.x) + cr.y);
+        if (rc.save) rc.save[j] = g;
+        if (rc.emit) rc.emit[(long)n * p.hw + dpix] = g;
     }
 };
 
 struct EpiAdj {
     AdjParams p;
     static constexpr int NRED = 0;
-    struct Row { long inst; float sb; };
-    __device__ Row row(long img) const { return Row{img / p.rpi, p.sbar[img]}; }
+    struct Pre { Relax t; float g; };
+    struct Row { const Relax *tb; const float *gs; float *go; float *ga; float sb; };
+    __device__ Row row(int img) const {
+        const long inst = img / p.rpi;
+        const long o = (long)img * p.D;
+        return Row{p.tab + inst * p.tab_ld, p.gsave + o, p.gout ? p.gout + o : nullptr,
+                   p.galpha + inst * p.ga_ld + p.ga_off, p.sbar[img]};
+    }
     __device__ float colv(int n) const { return p.bias[n]; }
     __device__ float *red0() const { return nullptr; }
     __device__ float *red1() const { return nullptr; }
-    __device__ void elem(const Row &rc, long img, long dpix, int n, long j, float bcol, float acc,
-                         float &, float &) const {
+    __device__ Pre pre(const Row &rc, int, long j) const { return Pre{rc.tb[j], rc.gs[j]}; }
+    __device__ void post(const Pre &q, const Row &rc, int, long dpix, int n, long j, float bcol,
+                         float acc, float &, float &) const {
         const float v = acc + rc.sb * bcol;           // Lambda_bar_m[img, j]
-        const long o = img * p.D + j;
-        const float g = p.gsave[o];                   // G_{m+1}[img, j]
-        const Relax t = p.tab[rc.inst * p.tab_ld + j];
-        if (p.gout) p.gout[o] = v * (g >= 0.f ? t.x : t.y) + (g < 0.f ? rc.sb * t.z : 0.f);
+        const float g = q.g;                          // G_{m+1}[img, j]
+        const Relax &t = q.t;
+        if (rc.go) rc.go[j] = v * (g >= 0.f ? t.x : t.y) + (g < 0.f ? rc.sb * t.z : 0.f);
         if (t.w != 0.f && g >= 0.f) {
             const float c = g * v;
-            if (c != 0.f) atomicAdd(p.galpha + rc.inst * p.ga_ld + p.ga_off + (long)n * p.hw + dpix, c);
+            if (c != 0.f) atomicAdd(rc.ga + (long)n * p.hw + dpix, c);
         }
     }
 };
@@ -104,14 +122,16 @@ struct EpiAdj {
 struct EpiFwd {
     FwdParams p;
     static constexpr int NRED = 0;
-    struct Row {};
-    __device__ Row row(long) const { return Row{}; }
+    struct Pre {};
+    struct Row { float *out; };
+    __device__ Row row(int img) const { return Row{p.out + (long)img * p.D}; }
     __device__ float colv(int n) const { return p.bias[n]; }
     __device__ float *red0() const { return nullptr; }
     __device__ float *red1() const { return nullptr; }
-    __device__ void elem(const Row &, long img, long, int, long j, float bcol, float acc, float &,
-                         float &) const {
-        p.out[img * p.D + j] = acc + bcol;
+    __device__ Pre pre(const Row &, int, long) const { return Pre{}; }
+    __device__ void post(const Pre &, const Row &rc, int, long, int, long j, float bcol, float acc,
+                         float &, float &) const {
+        rc.out[j] = acc + bcol;
     }
 };
 
@@ -142,6 +162,60 @@ __device__ inline void reduce_wave_atomic(float u0, float u1, long img, int lane
         atomicAdd(red0 + img, u0);
         atomicAdd(red1 + img, u1);
     }
+}
+
+// Epilogue of one wave's accumulator tile.  rowfn(i, v, img, dpix) maps accumulator
+// row (i, v) of this lane to its local image (-1 if out of range) and destination pixel.
+// Rows are handled four at a time (one MFMA row group); a group's loads are issued before
+// its stores.  With `uniform` every row of the wave belongs to image uimg and the row
+// sums collapse into one atomic per wave.
+template <class Epi, int MF, int FM, int FN, class Acc, class RowFn>
+__device__ inline void tile_epilogue(const Epi &epi, Acc (&acc)[FM][FN], const int (&ncol)[FN],
+                                     const float (&bcol)[FN], int N, const RowFn &rowfn, int lane,
+                                     bool uniform, long uimg) {
+    constexpr int NACC = Mma<MF>::NACC;
+    constexpr int NR = Epi::NRED;
+    float u0 = 0.f, u1 = 0.f;
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+#pragma unroll
+        for (int vg = 0; vg < NACC / 4; ++vg) {
+            int img[4];
+            long dp[4];
+            typename Epi::Row rc[4];
+            float r0[4] = {0.f, 0.f, 0.f, 0.f}, r1[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                rowfn(i, vg * 4 + q, img[q], dp[q]);
+                if (img[q] >= 0) rc[q] = epi.row(img[q]);
+            }
+            typename Epi::Pre pre[FN][4];
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (img[q] >= 0 && ncol[j] < N) pre[j][q] = epi.pre(rc[q], img[q], dp[q] * N + ncol[j]);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (img[q] >= 0 && ncol[j] < N)
+                        epi.post(pre[j][q], rc[q], img[q], dp[q], ncol[j], dp[q] * N + ncol[j], bcol[j],
+                                 acc[i][j][vg * 4 + q], r0[q], r1[q]);
+            if (NR > 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (uniform) {
+                        u0 += r0[q];
+                        u1 += r1[q];
+                    } else {
+                        reduce_row_atomic<MF>(r0[q], r1[q], img[q], lane, epi.red0(), epi.red1());
+                    }
+                }
+            }
+        }
+    }
+    if (NR > 0 && uniform && uimg >= 0) reduce_wave_atomic(u0, u1, uimg, lane, epi.red0(), epi.red1());
 }
 
 }  // namespace dev

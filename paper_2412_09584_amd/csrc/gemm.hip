@@ -29,6 +29,10 @@ constexpr int LDSW = BK + 4;  // LDS row stride in floats (keeps 16-byte alignme
 using namespace dev;
 
 // ---------------------------------------------------------------------- the kernel
+// k -> (ky, kx, c) of the implicit-GEMM gather, decoded once per block into LDS:
+// .x = offset of (ky, kx, c) from the row's top-left source element, .y = ky << 16 | kx.
+constexpr int KDEC_MAX = 1024;
+
 template <class Epi, int MF, int BM, int BN, int WGM, int WGN, bool DENSE, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__restrict__ A,
                                               const long n_img, const Epi epi) {
@@ -42,6 +46,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
     constexpr int APT = (AF4 + 255) / 256, BPT = (BF4 + 255) / 256;
     __shared__ __attribute__((aligned(16))) float As[BM * LDSW];
     __shared__ __attribute__((aligned(16))) float Bs[BN * LDSW];
+    __shared__ int2 kdec[DENSE ? 1 : KDEC_MAX];
 
     const Geom &g = gs.g[blockIdx.z];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -52,6 +57,15 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
     const int n0 = blockIdx.y * BN;
     if (m0 >= M) return;
     const int K = g.K;
+
+    if (!DENSE) {
+        for (int k = tid; k < K; k += 256) {
+            const int tap = k / g.C, c = k - tap * g.C;
+            const int ky = tap / g.kw, kx = tap - ky * g.kw;
+            kdec[k] = make_int2((ky * g.W + kx) * g.C + c, (ky << 16) | kx);
+        }
+        // visible to every thread after the first barrier of the k loop
+    }
 
     // Per-slot source-row state for the A gather (the rows a thread loads never change).
     const float *abase[APT];
@@ -73,9 +87,11 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
             if (DENSE) {
                 abase[i] = A + img * K;
             } else {
-                abase[i] = A + img * (long)g.H * g.W * g.C;
+                // top-left source element of this row (may lie outside the image; only
+                // in-range elements are ever dereferenced)
                 aby[i] = oy * g.stride - g.pad_y;
                 abx[i] = ox * g.stride - g.pad_x;
+                abase[i] = A + img * (long)g.H * g.W * g.C + ((long)aby[i] * g.W + abx[i]) * g.C;
             }
         }
     }
@@ -95,11 +111,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
     auto gatherA = [&](int i, int k) -> float {
         if (DENSE) return k < K ? abase[i][k] : 0.f;
         if (k >= K) return 0.f;
-        const int tap = k / g.C, c = k - tap * g.C;
-        const int ky = tap / g.kw, kx = tap - ky * g.kw;
-        const int y = aby[i] + ky, x = abx[i] + kx;
+        const int2 d = kdec[k];
+        const int y = aby[i] + (d.y >> 16), x = abx[i] + (d.y & 0xffff);
         if ((unsigned)y >= (unsigned)g.H || (unsigned)x >= (unsigned)g.W) return 0.f;
-        return abase[i][((long)y * g.W + x) * g.C + c];
+        return abase[i][d.x];
     };
     auto loadA = [&](int k0) {
 #pragma unroll
@@ -111,11 +126,10 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
                     if (DENSE) {
                         if (k < K) v = *(const f32x4v *)(abase[i] + k);
                     } else if (k < K) {
-                        const int tap = k / g.C, c = k - tap * g.C;
-                        const int ky = tap / g.kw, kx = tap - ky * g.kw;
-                        const int y = aby[i] + ky, x = abx[i] + kx;
+                        const int2 d = kdec[k];
+                        const int y = aby[i] + (d.y >> 16), x = abx[i] + (d.y & 0xffff);
                         if ((unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W)
-                            v = *(const f32x4v *)(abase[i] + ((long)y * g.W + x) * g.C + c);
+                            v = *(const f32x4v *)(abase[i] + d.x);
                     }
                 } else {
                     v[0] = gatherA(i, k);
@@ -142,6 +156,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
 #pragma unroll
             for (int v = 0; v < MM::NACC; ++v) acc[i][j][v] = 0.f;
 
+    if (!DENSE) __syncthreads();   // decode table complete
     loadA(0);
     loadB(0);
     for (int k0 = 0; k0 < K; k0 += BK) {
@@ -192,63 +207,25 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
         ncol[j] = n0 + wn * TN + j * MF + MM::col(lane);
         bcol[j] = ncol[j] < g.N ? epi.colv(ncol[j]) : 0.f;
     }
-    constexpr int NR = Epi::NRED;
     const long wrow0 = m0 + wm * TM;
     const long wlast = (wrow0 + TM - 1 < M ? wrow0 + TM - 1 : M - 1);
     // All rows of this wave's tile belong to one img (the usual case for convolutions):
-    // reduce the whole tile to one value per accumulator and issue one atomic per wave.
-    const bool uniform = NR > 0 && wrow0 < M && (wrow0 / Mimg == wlast / Mimg);
-    float u0 = 0.f, u1 = 0.f;
-#pragma unroll
-    for (int i = 0; i < FM; ++i) {
-#pragma unroll
-        for (int v = 0; v < MM::NACC; ++v) {
-            float r0 = 0.f, r1 = 0.f;
-            const long m = wrow0 + i * MF + MM::row(v, lane);
-            long img = -1;
-            if (m < M) {
-                img = m / Mimg;
-                const int p = (int)(m - img * Mimg);
-                const int oy = p / g.OW, ox = p - oy * g.OW;
-                const long dpix = (long)(oy * g.ostr + g.oy0) * g.DW + (ox * g.ostr + g.ox0);
-                const auto rc = epi.row(img);
-#pragma unroll
-                for (int j = 0; j < FN; ++j)
-                    if (ncol[j] < g.N)
-                        epi.elem(rc, img, dpix, ncol[j], dpix * g.N + ncol[j], bcol[j], acc[i][j][v],
-                                 r0, r1);
-            }
-            if (NR > 0) {
-                if (uniform) {
-                    u0 += r0;
-                    u1 += r1;
-                } else {
-                    // lanes sharing this row differ only in the column bits of the lane id
-#pragma unroll
-                    for (int mk = 1; mk < MF; mk <<= 1) {
-                        r0 += __shfl_xor(r0, mk, 64);
-                        r1 += __shfl_xor(r1, mk, 64);
-                    }
-                    if (MM::col(lane) == 0 && img >= 0) {
-                        atomicAdd(epi.red0() + img, r0);
-                        atomicAdd(epi.red1() + img, r1);
-                    }
-                }
-            }
+    // the row sums collapse into one atomic per wave.
+    const bool uniform = wrow0 < M && (wrow0 / Mimg == wlast / Mimg);
+    auto rowfn = [&](int i, int v, int &img, long &dpix) {
+        const long m = wrow0 + i * MF + MM::row(v, lane);
+        img = -1;
+        dpix = 0;
+        if (m < M) {
+            const long im = m / Mimg;
+            const int p = (int)(m - im * Mimg);
+            const int oy = p / g.OW, ox = p - oy * g.OW;
+            img = (int)im;
+            dpix = (long)(oy * g.ostr + g.oy0) * g.DW + (ox * g.ostr + g.ox0);
         }
-    }
-    if (NR > 0 && uniform) {
-#pragma unroll
-        for (int mk = 1; mk < 64; mk <<= 1) {
-            u0 += __shfl_xor(u0, mk, 64);
-            u1 += __shfl_xor(u1, mk, 64);
-        }
-        if (lane == 0) {
-            const long img = wrow0 / Mimg;
-            atomicAdd(epi.red0() + img, u0);
-            atomicAdd(epi.red1() + img, u1);
-        }
-    }
+    };
+    tile_epilogue<Epi, MF, FM, FN>(epi, acc, ncol, bcol, g.N, rowfn, lane, uniform,
+                                   uniform ? wrow0 / Mimg : -1);
 }
 
 // ---------------------------------------------------------------------- dispatch
@@ -265,6 +242,8 @@ hipError_t launch_cfg(const GeomSet &gs, const float *A, long n_img, const Epi &
     dim3 grid((unsigned)((Mmax + BM - 1) / BM), (unsigned)((g0.N + BN - 1) / BN), (unsigned)gs.n);
     const bool dense = g0.H == 1 && g0.W == 1 && g0.kh == 1 && g0.kw == 1;
     const bool vec = (g0.C % 4 == 0) && (g0.K % 4 == 0);
+    for (int i = 0; i < gs.n; ++i)
+        if (!dense && gs.g[i].K > KDEC_MAX) return hipErrorInvalidValue;  // layer too wide
     if (dense && vec)
         hipLaunchKernelGGL((k_gemm<Epi, MF, BM, BN, WGM, WGN, true, true>), grid, dim3(256), 0, st, gs, A, n_img, epi);
     else if (dense)
