@@ -16,6 +16,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off: only scalar / MFMA FP32 is generated
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in ordinary VGPRs: the AGPR form made the register
+         # allocator rotate accumulators through copies inside the k-loops, which
+         # serialised each iteration on the previous MFMA chain
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
 
 

@@ -95,7 +95,7 @@ constexpr int MAX_IN4 = 8, MAX_W4 = 6;
 struct Walk {
     int r, p, dr, dp, P;
     __device__ Walk(int P_) : P(P_) {
-        r = threadIdx.x / P;
+        r = qdiv(threadIdx.x, 1.0f / (float)P);
         p = threadIdx.x - r * P;
         dr = 256 / P;
         dp = 256 - dr * P;
@@ -122,14 +122,15 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     float *Wl = smem + ct.in_floats;
     int *koff = (int *)(Wl + BN * ct.WS);     // [KB] A-operand offset of k inside the tile
 
-    const Geom &g = gs.g[blockIdx.z];
+    const TileIdx ti = xcd_tile(gs.g[0].N / BN, gs.n);
+    const Geom &g = gs.g[ti.z];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const long grp = blockIdx.x / ct.tiles_y;
-    const int band = blockIdx.x - (int)(grp * ct.tiles_y);
+    const long grp = ldiv_by(ti.x, ct.tiles_y, 1.0f / (float)ct.tiles_y);
+    const int band = (int)(ti.x - grp * ct.tiles_y);
     const long img0 = grp * ct.G;
     if (img0 >= n_img) return;
     const int oyb = band * ct.TR;
-    const int n0 = blockIdx.y * BN;
+    const int n0 = ti.y * BN;
     const int tile_px = ct.TR * g.OW;
     const int iy0 = oyb * g.stride - g.pad_y, ix0 = -g.pad_x;
     const int TC = ct.T * ct.CC;
@@ -139,8 +140,8 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     for (int k = tid; k < ct.KB; k += 256) {
         int o = 0;
         if (k < TC) {
-            const int t = k / ct.CC, c = k - t * ct.CC;
-            const int ty = t / g.kw, tx = t - ty * g.kw;
+            const int t = qdiv(k, 1.0f / (float)ct.CC), c = k - t * ct.CC;
+            const int ty = qdiv(t, 1.0f / (float)g.kw), tx = t - ty * g.kw;
             o = (ty * ct.IW + tx) * ct.CS + c;
         }
         koff[k] = o;
@@ -151,8 +152,8 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int lr = wave * 64 + i * MF + MM::idx(lane);
-        const int gi = lr / tile_px, q = lr - gi * tile_px;
-        const int py = q / g.OW, px = q - py * g.OW;
+        const int gi = qdiv(lr, 1.0f / (float)tile_px), q = lr - gi * tile_px;
+        const int py = qdiv(q, 1.0f / (float)g.OW), px = q - py * g.OW;
         abase[i] = ((gi * ct.IH + py * g.stride) * ct.IW + px * g.stride) * ct.CS;
     }
     acc_t acc[FM][FN];
@@ -180,7 +181,7 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
             gin[i] = -1;
             lin[i] = -1;
             if (w.r < Rin) {
-                const int gi = w.r / ct.IH, iy = w.r - gi * ct.IH;
+                const int gi = qdiv(w.r, 1.0f / (float)ct.IH), iy = w.r - gi * ct.IH;
                 const int ix = w.p >> c4s, c4 = w.p & ((1 << c4s) - 1);
                 const int y = iy0 + iy, x = ix0 + ix;
                 lin[i] = (w.r * ct.IW + ix) * ct.CS + 4 * c4;
@@ -281,17 +282,34 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
         ncol[j] = n0 + j * MF + MM::col(lane);
         bcol[j] = ncol[j] < g.N ? epi.colv(ncol[j]) : 0.f;
     }
-    const int gfirst = (wave * 64) / tile_px, glast = (wave * 64 + 63) / tile_px;
+    const float rTP = 1.0f / (float)tile_px;
+    const int gfirst = qdiv(wave * 64, rTP), glast = qdiv(wave * 64 + 63, rTP);
     const bool uniform = gfirst == glast && img0 + gfirst < n_img;
-    auto rowfn = [&](int i, int v, int &img, long &dpix) {
-        const int lr = wave * 64 + i * MF + MM::row(v, lane);
-        const int gi = lr / tile_px, q = lr - gi * tile_px;
-        const int py = q / g.OW, px = q - py * g.OW;
-        img = img0 + gi < n_img ? (int)(img0 + gi) : -1;
-        dpix = (long)((oyb + py) * g.ostr + g.oy0) * g.DW + (px * g.ostr + g.ox0);
+    // Local row lr < 256 -> (image of the block, pixel); with OW a multiple of 4 a group
+    // of four consecutive rows is four neighbouring pixels of one output row.
+    const float rOW = 1.0f / (float)g.OW;
+    const bool quad = g.OW % 4 == 0;
+    auto rowfn4 = [&](int i, int vg, int (&img)[4], int (&dp)[4]) -> bool {
+        const int lr0 = wave * 64 + i * MF + MM::row(4 * vg, lane);
+#pragma unroll
+        for (int q = 0; q < (quad ? 1 : 4); ++q) {
+            const int lr = lr0 + q;
+            const int gi = qdiv(lr, rTP), r = lr - gi * tile_px;
+            const int py = qdiv(r, rOW), px = r - py * g.OW;
+            img[q] = img0 + gi < n_img ? (int)(img0 + gi) : -1;
+            dp[q] = ((oyb + py) * g.ostr + g.oy0) * g.DW + (px * g.ostr + g.ox0);
+        }
+        if (quad) {
+#pragma unroll
+            for (int q = 1; q < 4; ++q) {
+                img[q] = img[0];
+                dp[q] = dp[0] + q * g.ostr;
+            }
+        }
+        return quad;
     };
-    tile_epilogue<Epi, MF, FM, FN>(epi, acc, ncol, bcol, g.N, rowfn, lane, uniform,
-                                   uniform ? img0 + gfirst : -1);
+    tile_epilogue<Epi, MF, FM, FN>(epi, acc, ncol, bcol, g.N, rowfn4, lane, uniform && quad,
+                                   (int)(img0 + gfirst));
 }
 
 // One thread per output pixel, up to NMAX output channels, VALU FMAs from LDS.
@@ -302,10 +320,11 @@ __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvT
     extern __shared__ __attribute__((aligned(16))) float smem[];
     float *In = smem;
     float *Wl = smem + ct.in_floats;  // [NMAX][T*C]
-    const Geom &g = gs.g[blockIdx.z];
+    const TileIdx ti = xcd_tile(1, gs.n);
+    const Geom &g = gs.g[ti.z];
     const int tid = threadIdx.x;
-    const long grp = blockIdx.x / ct.tiles_y;
-    const int band = blockIdx.x - (int)(grp * ct.tiles_y);
+    const long grp = ti.x / ct.tiles_y;
+    const int band = (int)(ti.x - grp * ct.tiles_y);
     const long img0 = grp * ct.G;
     if (img0 >= n_img) return;
     const int oyb = band * ct.TR;
@@ -342,15 +361,15 @@ __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvT
     const long img = img0 + gi;
     float r0 = 0.f, r1 = 0.f;
     if (img < n_img) {
-        const long dpix = (long)((oyb + py) * g.ostr + g.oy0) * g.DW + (px * g.ostr + g.ox0);
+        const int dpix = ((oyb + py) * g.ostr + g.oy0) * g.DW + (px * g.ostr + g.ox0);
         const auto rc = epi.row((int)img);
         typename Epi::Pre pre[NMAX];
 #pragma unroll
         for (int n = 0; n < NMAX; ++n)
-            if (n < g.N) pre[n] = epi.pre(rc, (int)img, dpix * g.N + n);
+            if (n < g.N) pre[n] = epi.pre(rc, dpix * g.N + n);
 #pragma unroll
         for (int n = 0; n < NMAX; ++n)
-            if (n < g.N) epi.post(pre[n], rc, (int)img, dpix, n, dpix * g.N + n, epi.colv(n), acc[n], r0, r1);
+            if (n < g.N) epi.post(pre[n], rc, dpix, n, dpix * g.N + n, epi.colv(n), acc[n], r0, r1);
     }
     if (Epi::NRED > 0) {
         // a wave's 64 pixels lie in one image whenever an image has >= 64 pixels
@@ -444,7 +463,7 @@ template <class Epi, int MF, int BN>
 hipError_t launch_mfma(const GeomSet &gs, const ConvTile &ct, size_t lds, const float *X, long n_img,
                        const Epi &epi, hipStream_t st) {
     const long groups = (n_img + ct.G - 1) / ct.G;
-    dim3 grid((unsigned)(groups * ct.tiles_y), (unsigned)(gs.g[0].N / BN), (unsigned)gs.n);
+    const dim3 grid((unsigned)(groups * ct.tiles_y * (gs.g[0].N / BN) * gs.n));   // xcd_tile order
     if (gs.g[0].C % 4 == 0) {
         static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, true>);
         if (ok != hipSuccess) return ok;
@@ -474,14 +493,14 @@ hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &
     ConvTile ct{};
     if (!plan_tile(g, ct)) return hipSuccess;
     const long groups = (n_img + ct.G - 1) / ct.G;
-    if (groups * ct.tiles_y > 0x7fffffffL) return hipSuccess;
+    if (groups * ct.tiles_y * (g.N / 4 + 1) * gs.n > 0x7fffffffL) return hipSuccess;
     if (g.N <= 4 && g.C % 4 == 0) {      // narrow output: VALU kernel
         ct.CC = g.C;
         ct.CS = g.C + 4;
         ct.in_floats = ct.G * ct.IH * ct.IW * ct.CS;
         const size_t lds = ((size_t)ct.in_floats + 4 * (size_t)ct.T * g.C) * 4;
         if (lds > LDS_BUDGET) return hipSuccess;
-        dim3 grid((unsigned)(groups * ct.tiles_y), 1, (unsigned)gs.n);
+        const dim3 grid((unsigned)(groups * ct.tiles_y * gs.n));   // xcd_tile order
         static const hipError_t ok = allow_lds(k_conv_valu<Epi, 4>);
         if (ok != hipSuccess) return ok;
         hipLaunchKernelGGL((k_conv_valu<Epi, 4>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);

@@ -36,25 +36,60 @@ template <> struct Mma<16> {
     static __device__ inline int idx(int lane) { return lane & 15; }
 };
 
+// ---------------------------------------------------------------------- tile order
+// Logical tile (x, y, z) of this workgroup in an [nx][ny][nz] tile grid launched as a
+// one-dimensional grid of nx * ny * nz workgroups.  Workgroups are dispatched to the 8
+// XCDs round-robin (workgroup b to XCD b mod 8) and every XCD has its own L2, so the
+// renumbering hands XCD k the k-th contiguous range of logical tiles, z (the output
+// phase of a transposed convolution) fastest and y (the column tile) next: tiles that
+// gather the same input rows, and the rows of one instance, which share its relaxation
+// records, then meet in one L2 at about the same time.
+struct TileIdx {
+    long x;
+    int y, z;
+};
+__device__ inline TileIdx xcd_tile(int ny, int nz) {
+    const unsigned T = gridDim.x, b = blockIdx.x;
+    const unsigned q = T >> 3, r = T & 7, xcd = b & 7, slot = b >> 3;
+    unsigned t = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    TileIdx ti;
+    ti.z = (int)(t % (unsigned)nz);
+    t /= (unsigned)nz;
+    ti.y = (int)(t % (unsigned)ny);
+    ti.x = (long)(t / (unsigned)ny);
+    return ti;
+}
+
+// ---------------------------------------------------------------------- index helpers
+// n / d for 0 <= n < 2^21 through one FP32 multiply by rd = fl(1/d): (n + 0.5) / d lies
+// at least 0.5/d away from an integer, and the two roundings move the product by less
+// than (n + 0.5)/d * 2^-23 < 0.5/d, so truncation gives the exact quotient.
+__device__ inline int qdiv(int n, float rd) { return (int)(((float)n + 0.5f) * rd); }
+__device__ inline long ldiv_by(long n, int d, float rd) {
+    return n < (1L << 21) ? (long)qdiv((int)n, rd) : n / d;
+}
+
 // ---------------------------------------------------------------------- epilogues
 // Each epilogue splits its per-element work into pre() -- the global loads it needs
 // (relaxation record, box, saved coefficient) -- and post() -- arithmetic, stores and
 // atomics -- so that tile_epilogue can issue a group's loads before any of its stores.
+// Row(img) resolves the per-img pointers once per row group; j is the element's offset
+// inside its img (dpix * N + n), dpix the destination pixel.
 struct EpiRelax {
     RelaxParams p;
     static constexpr int NRED = 2;
     using Pre = Relax;
     struct Row { const Relax *tb; float *out, *save; };
     __device__ Row row(int img) const {
-        const long inst = (p.img0 + img) / p.rpi;
+        const long inst = ldiv_by(p.img0 + img, p.rpi, 1.0f / (float)p.rpi);
         const long o = (long)img * p.D;
         return Row{p.tab + inst * p.tab_ld, p.out + o, p.save ? p.save + o : nullptr};
     }
     __device__ float colv(int n) const { return p.bias[n % p.chan]; }
     __device__ float *red0() const { return p.s; }
     __device__ float *red1() const { return p.mag; }
-    __device__ Pre pre(const Row &rc, int, long j) const { return rc.tb[j]; }
-    __device__ void post(const Pre &t, const Row &rc, int, long, int, long j, float bcol, float g,
+    __device__ Pre pre(const Row &rc, int j) const { return rc.tb[j]; }
+    __device__ void post(const Pre &t, const Row &rc, int, int, int j, float bcol, float g,
                          float &r0, float &r1) const {
         const float lam = g >= 0.f ? g * t.x : g * t.y;
         const float off = g < 0.f ? g * t.z : 0.f;
@@ -72,7 +107,7 @@ struct EpiConc {
     using Pre = float2;
     struct Row { const float *cen, *rad; float *save, *emit; };
     __device__ Row row(int img) const {
-        const long inst = (p.img0 + img) / p.rpi;
+        const long inst = ldiv_by(p.img0 + img, p.rpi, 1.0f / (float)p.rpi);
         const long o = (long)img * p.D;
         return Row{p.cen + inst * p.D, p.rad + inst * p.D, p.save ? p.save + o : nullptr,
                    p.emit ? p.emit + o : nullptr};
@@ -80,13 +115,13 @@ struct EpiConc {
     __device__ float colv(int) const { return 0.f; }
     __device__ float *red0() const { return p.low; }
     __device__ float *red1() const { return p.mag; }
-    __device__ Pre pre(const Row &rc, int, long j) const { return make_float2(rc.cen[j], rc.rad[j]); }
-    __device__ void post(const Pre &cr, const Row &rc, int, long dpix, int n, long j, float,
-                         float g, float &r0, float &r1) const {
+    __device__ Pre pre(const Row &rc, int j) const { return make_float2(rc.cen[j], rc.rad[j]); }
+    __device__ void post(const Pre &cr, const Row &rc, int dpix, int n, int j, float, float g,
+                         float &r0, float &r1) const {
         r0 += g * cr.x - fabsf(g) * cr.y;
         r1 += fabsf(g) * (fabsf(cr.x) + cr.y);
         if (rc.save) rc.save[j] = g;
-        if (rc.emit) rc.emit[(long)n * p.hw + dpix] = g;
+        if (rc.emit) rc.emit[n * p.hw + dpix] = g;
     }
 };
 
@@ -96,7 +131,7 @@ struct EpiAdj {
     struct Pre { Relax t; float g; };
     struct Row { const Relax *tb; const float *gs; float *go; float *ga; float sb; };
     __device__ Row row(int img) const {
-        const long inst = img / p.rpi;
+        const long inst = ldiv_by(img, p.rpi, 1.0f / (float)p.rpi);
         const long o = (long)img * p.D;
         return Row{p.tab + inst * p.tab_ld, p.gsave + o, p.gout ? p.gout + o : nullptr,
                    p.galpha + inst * p.ga_ld + p.ga_off, p.sbar[img]};
@@ -104,16 +139,16 @@ struct EpiAdj {
     __device__ float colv(int n) const { return p.bias[n]; }
     __device__ float *red0() const { return nullptr; }
     __device__ float *red1() const { return nullptr; }
-    __device__ Pre pre(const Row &rc, int, long j) const { return Pre{rc.tb[j], rc.gs[j]}; }
-    __device__ void post(const Pre &q, const Row &rc, int, long dpix, int n, long j, float bcol,
-                         float acc, float &, float &) const {
+    __device__ Pre pre(const Row &rc, int j) const { return Pre{rc.tb[j], rc.gs[j]}; }
+    __device__ void post(const Pre &q, const Row &rc, int dpix, int n, int j, float bcol, float acc,
+                         float &, float &) const {
         const float v = acc + rc.sb * bcol;           // Lambda_bar_m[img, j]
         const float g = q.g;                          // G_{m+1}[img, j]
         const Relax &t = q.t;
         if (rc.go) rc.go[j] = v * (g >= 0.f ? t.x : t.y) + (g < 0.f ? rc.sb * t.z : 0.f);
         if (t.w != 0.f && g >= 0.f) {
             const float c = g * v;
-            if (c != 0.f) atomicAdd(rc.ga + (long)n * p.hw + dpix, c);
+            if (c != 0.f) atomicAdd(rc.ga + n * p.hw + dpix, c);
         }
     }
 };
@@ -128,8 +163,8 @@ struct EpiFwd {
     __device__ float colv(int n) const { return p.bias[n]; }
     __device__ float *red0() const { return nullptr; }
     __device__ float *red1() const { return nullptr; }
-    __device__ Pre pre(const Row &, int, long) const { return Pre{}; }
-    __device__ void post(const Pre &, const Row &rc, int, long, int, long j, float bcol, float acc,
+    __device__ Pre pre(const Row &, int) const { return Pre{}; }
+    __device__ void post(const Pre &, const Row &rc, int, int, int j, float bcol, float acc,
                          float &, float &) const {
         rc.out[j] = acc + bcol;
     }
@@ -138,7 +173,7 @@ struct EpiFwd {
 // Sum of r0 / r1 over the lanes that hold the same output row (they differ only in the
 // column bits of the lane id), then one atomic per row from the column-0 lane.
 template <int MF>
-__device__ inline void reduce_row_atomic(float r0, float r1, long img, int lane, float *red0,
+__device__ inline void reduce_row_atomic(float r0, float r1, int img, int lane, float *red0,
                                          float *red1) {
 #pragma unroll
     for (int mk = 1; mk < MF; mk <<= 1) {
@@ -164,58 +199,77 @@ __device__ inline void reduce_wave_atomic(float u0, float u1, long img, int lane
     }
 }
 
-// Epilogue of one wave's accumulator tile.  rowfn(i, v, img, dpix) maps accumulator
-// row (i, v) of this lane to its local image (-1 if out of range) and destination pixel.
-// Rows are handled four at a time (one MFMA row group); a group's loads are issued before
-// its stores.  With `uniform` every row of the wave belongs to image uimg and the row
-// sums collapse into one atomic per wave.
-template <class Epi, int MF, int FM, int FN, class Acc, class RowFn>
-__device__ inline void tile_epilogue(const Epi &epi, Acc (&acc)[FM][FN], const int (&ncol)[FN],
-                                     const float (&bcol)[FN], int N, const RowFn &rowfn, int lane,
-                                     bool uniform, long uimg) {
+// Epilogue of one wave's accumulator tile.  The accumulator rows of a lane come in
+// groups of four consecutive tile rows (MFMA row groups); rowfn4(i, vg, img, dp) maps
+// group vg of fragment i to the local img of each row (-1 if out of range) and its
+// destination pixel, and returns true when all four rows lie in one img (then the
+// per-img pointers are resolved once).  A group's loads are issued before its stores.
+// FAST: every row of the wave lies in img uimg and every column is in range (the
+// common case of a convolution tile), so the pointers are resolved once per wave, no
+// element is masked and the row sums collapse into one atomic pair per wave.
+template <bool FAST, class Epi, int MF, int FM, int FN, class Acc, class RowFn>
+__device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], const int (&ncol)[FN],
+                                          const float (&bcol)[FN], int N, const RowFn &rowfn4,
+                                          int lane, int uimg) {
     constexpr int NACC = Mma<MF>::NACC;
     constexpr int NR = Epi::NRED;
     float u0 = 0.f, u1 = 0.f;
+    typename Epi::Row rw;
+    if (FAST) rw = epi.row(uimg);
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
         for (int vg = 0; vg < NACC / 4; ++vg) {
-            int img[4];
-            long dp[4];
+            int img[4], dp[4];
             typename Epi::Row rc[4];
-            float r0[4] = {0.f, 0.f, 0.f, 0.f}, r1[4] = {0.f, 0.f, 0.f, 0.f};
+            const bool one = rowfn4(i, vg, img, dp);
+            if (FAST) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                rowfn(i, vg * 4 + q, img[q], dp[q]);
-                if (img[q] >= 0) rc[q] = epi.row(img[q]);
+                for (int q = 0; q < 4; ++q) {
+                    img[q] = uimg;
+                    rc[q] = rw;
+                }
+            } else if (one) {
+                if (img[0] >= 0) rc[0] = epi.row(img[0]);
+                rc[1] = rc[2] = rc[3] = rc[0];
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (img[q] >= 0) rc[q] = epi.row(img[q]);
             }
+            float r0[4] = {0.f, 0.f, 0.f, 0.f}, r1[4] = {0.f, 0.f, 0.f, 0.f};
             typename Epi::Pre pre[FN][4];
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (img[q] >= 0 && ncol[j] < N) pre[j][q] = epi.pre(rc[q], img[q], dp[q] * N + ncol[j]);
+                    if (FAST || (img[q] >= 0 && ncol[j] < N)) pre[j][q] = epi.pre(rc[q], dp[q] * N + ncol[j]);
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (img[q] >= 0 && ncol[j] < N)
-                        epi.post(pre[j][q], rc[q], img[q], dp[q], ncol[j], dp[q] * N + ncol[j], bcol[j],
-                                 acc[i][j][vg * 4 + q], r0[q], r1[q]);
-            if (NR > 0) {
+                    if (FAST || (img[q] >= 0 && ncol[j] < N))
+                        epi.post(pre[j][q], rc[q], dp[q], ncol[j], dp[q] * N + ncol[j], bcol[j],
+                                 acc[i][j][vg * 4 + q], FAST ? u0 : r0[q], FAST ? u1 : r1[q]);
+            if (NR > 0 && !FAST) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (uniform) {
-                        u0 += r0[q];
-                        u1 += r1[q];
-                    } else {
-                        reduce_row_atomic<MF>(r0[q], r1[q], img[q], lane, epi.red0(), epi.red1());
-                    }
-                }
+                for (int q = 0; q < 4; ++q)
+                    reduce_row_atomic<MF>(r0[q], r1[q], img[q], lane, epi.red0(), epi.red1());
             }
         }
     }
-    if (NR > 0 && uniform && uimg >= 0) reduce_wave_atomic(u0, u1, uimg, lane, epi.red0(), epi.red1());
+    if (NR > 0 && FAST) reduce_wave_atomic(u0, u1, uimg, lane, epi.red0(), epi.red1());
+}
+
+// fast: see tile_epilogue_impl (wave-uniform).
+template <class Epi, int MF, int FM, int FN, class Acc, class RowFn>
+__device__ inline void tile_epilogue(const Epi &epi, Acc (&acc)[FM][FN], const int (&ncol)[FN],
+                                     const float (&bcol)[FN], int N, const RowFn &rowfn4, int lane,
+                                     bool fast, int uimg) {
+    if (fast)
+        tile_epilogue_impl<true, Epi, MF, FM, FN>(epi, acc, ncol, bcol, N, rowfn4, lane, uimg);
+    else
+        tile_epilogue_impl<false, Epi, MF, FM, FN>(epi, acc, ncol, bcol, N, rowfn4, lane, -1);
 }
 
 }  // namespace dev

@@ -48,13 +48,14 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
     __shared__ __attribute__((aligned(16))) float Bs[BN * LDSW];
     __shared__ int2 kdec[DENSE ? 1 : KDEC_MAX];
 
-    const Geom &g = gs.g[blockIdx.z];
+    const TileIdx ti = xcd_tile((gs.g[0].N + BN - 1) / BN, gs.n);
+    const Geom &g = gs.g[ti.z];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
     const long Mimg = (long)g.OH * g.OW;
     const long M = n_img * Mimg;
-    const long m0 = (long)blockIdx.x * BM;
-    const int n0 = blockIdx.y * BN;
+    const long m0 = ti.x * BM;
+    const int n0 = ti.y * BN;
     if (m0 >= M) return;
     const int K = g.K;
 
@@ -68,9 +69,13 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
     }
 
     // Per-slot source-row state for the A gather (the rows a thread loads never change).
+    // Rows are decomposed from the block's first row (one wide division per thread).
     const float *abase[APT];
     int aby[APT], abx[APT], akq[APT], arow[APT];
     bool aok[APT];
+    const long bimg = DENSE ? m0 : m0 / Mimg;
+    const int bp0 = (int)(m0 - bimg * Mimg);
+    const float rMb = 1.0f / (float)Mimg, rOWb = 1.0f / (float)g.OW;
 #pragma unroll
     for (int i = 0; i < APT; ++i) {
         const int f = tid + 256 * i;
@@ -81,12 +86,14 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
         abase[i] = A;
         aby[i] = abx[i] = 0;
         if (aok[i]) {
-            const long img = m / Mimg;
-            const int p = (int)(m - img * Mimg);
-            const int oy = p / g.OW, ox = p - oy * g.OW;
             if (DENSE) {
-                abase[i] = A + img * K;
+                abase[i] = A + m * K;
             } else {
+                int p = bp0 + arow[i];
+                const int kq = qdiv(p, rMb);
+                p -= kq * (int)Mimg;
+                const long img = bimg + kq;
+                const int oy = qdiv(p, rOWb), ox = p - oy * g.OW;
                 // top-left source element of this row (may lie outside the image; only
                 // in-range elements are ever dereferenced)
                 aby[i] = oy * g.stride - g.pad_y;
@@ -208,24 +215,54 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
         bcol[j] = ncol[j] < g.N ? epi.colv(ncol[j]) : 0.f;
     }
     const long wrow0 = m0 + wm * TM;
-    const long wlast = (wrow0 + TM - 1 < M ? wrow0 + TM - 1 : M - 1);
-    // All rows of this wave's tile belong to one img (the usual case for convolutions):
-    // the row sums collapse into one atomic per wave.
-    const bool uniform = wrow0 < M && (wrow0 / Mimg == wlast / Mimg);
-    auto rowfn = [&](int i, int v, int &img, long &dpix) {
-        const long m = wrow0 + i * MF + MM::row(v, lane);
-        img = -1;
-        dpix = 0;
-        if (m < M) {
-            const long im = m / Mimg;
-            const int p = (int)(m - im * Mimg);
-            const int oy = p / g.OW, ox = p - oy * g.OW;
-            img = (int)im;
-            dpix = (long)(oy * g.ostr + g.oy0) * g.DW + (ox * g.ostr + g.ox0);
+    // Row m = wrow0 + off (off < TM) is decomposed from the wave's first row, so only
+    // small quotients (qdiv) are needed per row group.  With Mimg and OW multiples of 4
+    // a group of four consecutive rows is four neighbouring pixels of one output row.
+    const long imgw = wrow0 / Mimg;
+    const int pw = (int)(wrow0 - imgw * Mimg);
+    // every row of the wave's tile exists and belongs to img imgw (the usual case for
+    // convolutions): the fast epilogue applies
+    const bool uniform = wrow0 + TM <= M && pw + TM <= Mimg;
+    const float rM = 1.0f / (float)Mimg, rOW = 1.0f / (float)g.OW;
+    const bool quad = (Mimg % 4 == 0) && (g.OW % 4 == 0);
+    auto rowfn4 = [&](int i, int vg, int (&img)[4], int (&dp)[4]) -> bool {
+        const int off = i * MF + MM::row(4 * vg, lane);
+        if (DENSE) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                img[q] = wrow0 + off + q < M ? (int)(wrow0 + off + q) : -1;
+                dp[q] = 0;
+            }
+            return false;
         }
+        if (quad) {
+            int p = pw + off;
+            const int k = qdiv(p, rM);
+            p -= k * (int)Mimg;
+            const int oy = qdiv(p, rOW), ox = p - oy * g.OW;
+            const int iv = imgw + k < n_img ? (int)(imgw + k) : -1;
+            const int b = (oy * g.ostr + g.oy0) * g.DW + ox * g.ostr + g.ox0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                img[q] = iv;
+                dp[q] = b + q * g.ostr;
+            }
+            return true;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            int p = pw + off + q;
+            const int k = qdiv(p, rM);
+            p -= k * (int)Mimg;
+            const int oy = qdiv(p, rOW), ox = p - oy * g.OW;
+            img[q] = imgw + k < n_img ? (int)(imgw + k) : -1;
+            dp[q] = (oy * g.ostr + g.oy0) * g.DW + ox * g.ostr + g.ox0;
+        }
+        return false;
     };
-    tile_epilogue<Epi, MF, FM, FN>(epi, acc, ncol, bcol, g.N, rowfn, lane, uniform,
-                                   uniform ? wrow0 / Mimg : -1);
+    const bool fast = !DENSE && uniform && quad && n0 + BN <= g.N;
+    tile_epilogue<Epi, MF, FM, FN>(epi, acc, ncol, bcol, g.N, rowfn4, lane, fast,
+                                   fast ? (int)imgw : -1);
 }
 
 // ---------------------------------------------------------------------- dispatch
@@ -239,11 +276,15 @@ hipError_t launch_cfg(const GeomSet &gs, const float *A, long n_img, const Epi &
         if (M > Mmax) Mmax = M;
     }
     if (Mmax == 0) return hipSuccess;
-    dim3 grid((unsigned)((Mmax + BM - 1) / BM), (unsigned)((g0.N + BN - 1) / BN), (unsigned)gs.n);
+    const long tiles = ((Mmax + BM - 1) / BM) * ((g0.N + BN - 1) / BN) * gs.n;
+    if (tiles > 0x7fffffffL) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)tiles);   // tile order: xcd_tile
     const bool dense = g0.H == 1 && g0.W == 1 && g0.kh == 1 && g0.kw == 1;
     const bool vec = (g0.C % 4 == 0) && (g0.K % 4 == 0);
-    for (int i = 0; i < gs.n; ++i)
+    for (int i = 0; i < gs.n; ++i) {
         if (!dense && gs.g[i].K > KDEC_MAX) return hipErrorInvalidValue;  // layer too wide
+        if ((long)gs.g[i].OH * gs.g[i].OW > (1L << 20)) return hipErrorInvalidValue;  // qdiv range
+    }
     if (dense && vec)
         hipLaunchKernelGGL((k_gemm<Epi, MF, BM, BN, WGM, WGN, true, true>), grid, dim3(256), 0, st, gs, A, n_img, epi);
     else if (dense)

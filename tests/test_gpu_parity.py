@@ -198,8 +198,11 @@ def test_chunked_passes_match_unchunked(mod):
     small = N.BoundNet(net, 5, 97)          # forces ragged chunks inside instances
     a = big.crown_bounds(x_lo, x_hi)
     b = small.crown_bounds(x_lo, x_hi)
-    close(np_(b[0]), np_(a[0]), rel=1e-6, what="chunked lo")
-    close(np_(b[1]), np_(a[1]), rel=1e-6, what="chunked hi")
+    # Both runs are FP32 with atomic row sums whose order follows the tile schedule, so
+    # they may differ by a few ulps of the summed magnitudes (which exceed the results
+    # several-fold); a chunking mistake shows up as an O(1) difference.
+    close(np_(b[0]), np_(a[0]), rel=1e-5, what="chunked lo")
+    close(np_(b[1]), np_(a[1]), rel=1e-5, what="chunked hi")
 
 
 def test_coefficients_and_standalone_concretize(mod):
