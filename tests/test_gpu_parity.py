@@ -490,6 +490,46 @@ def test_beta_crown_batch_full_size(mod, golden_cnn):
         assert np.max(np.abs(gb[q0:q1] - ogb)) <= 1e-4 * sb, f"grad beta {i}"
 
 
+def test_ragged_batch_one_launch_vs_chunked(mod, golden_cnn):
+    """1023 subdomains (9207 imgs, so image groups of the direct kernels and GEMM row
+    tiles end part-way): one launch per layer against the same pass cut into launches
+    of 1500 imgs (cutting instances); pass and gradient of three subdomains against the
+    oracle."""
+    N, B = mod
+    w = W.cnn_cifar(1)
+    lo = f32(golden_cnn["lo"]).astype(np.float64)
+    hi = f32(golden_cnn["hi"]).astype(np.float64)
+    n = 1023
+    root_of = np.zeros(n, np.int32)
+    sp = W.random_splits([np.nonzero((lo < 0) & (hi > 0))[0]], n, 1, 12, seed=8, root_of=root_of)
+    alpha = W.random_alpha(n, lo.size, 9)
+    beta = W.random_beta(sp.nnz, 9, 10)
+    res = []
+    for rows, save in ((n * 9, n * 9), (1500, 0)):
+        bn = N.BoundNet(w.net, n, rows, save)
+        gl, _ = bn.spec_bounds(np.repeat(w.spec, n, 0), dev(f32(lo)[None]), dev(f32(hi)[None]),
+                               np.repeat(w.x_lo, n, 0), np.repeat(w.x_hi, n, 0), alpha=dev(alpha),
+                               bound_of=dev(root_of, torch.int32), splits=N.splits_to_device(sp),
+                               beta=dev(beta), both=False, save=save > 0)
+        if save:
+            ga, gb = bn.grad(torch.ones(n, 9, device="cuda"), sp.nnz)
+            ga, gb = np_(ga), np_(gb)
+        res.append(np_(gl))
+        del bn
+    # same tiles and k order; only the order of the atomic row sums differs
+    close(res[0], res[1], rel=1e-5, what="lower grouped vs chunked")
+    gl = res[0]
+    for i in (0, 511, n - 1):
+        q0, q1 = sp.off[i], sp.off[i + 1]
+        low, oga, ogb = _oracle_unit(w.net, w.spec[0], lo, hi, w.x_lo[0], w.x_hi[0], alpha[i], sp,
+                                     q0, q1, beta.astype(np.float64))
+        close(gl[i], low, what=f"lower {i}")
+        scale = np.max(np.abs(oga))
+        assert np.max(np.abs(ga[i] - oga)) <= 1e-4 * scale, f"grad alpha {i}"
+        sb = max(np.max(np.abs(ogb)), scale)
+        assert np.max(np.abs(gb[q0:q1] - ogb)) <= 1e-4 * sb, f"grad beta {i}"
+
+
 def test_direct_and_gemm_paths_agree_full_size(mod, golden_cnn):
     """The 4096-subdomain pass + gradient through both kernel paths (same inputs)."""
     N, B = mod
