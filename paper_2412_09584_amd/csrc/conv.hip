@@ -501,9 +501,15 @@ hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &
         const size_t lds = ((size_t)ct.in_floats + 4 * (size_t)ct.T * g.C) * 4;
         if (lds > LDS_BUDGET) return hipSuccess;
         const dim3 grid((unsigned)(groups * ct.tiles_y * gs.n));   // xcd_tile order
-        static const hipError_t ok = allow_lds(k_conv_valu<Epi, 4>);
-        if (ok != hipSuccess) return ok;
-        hipLaunchKernelGGL((k_conv_valu<Epi, 4>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+        if (g.N == 3) {   // RGB input layers: no idle fourth output
+            static const hipError_t ok3 = allow_lds(k_conv_valu<Epi, 3>);
+            if (ok3 != hipSuccess) return ok3;
+            hipLaunchKernelGGL((k_conv_valu<Epi, 3>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+        } else {
+            static const hipError_t ok = allow_lds(k_conv_valu<Epi, 4>);
+            if (ok != hipSuccess) return ok;
+            hipLaunchKernelGGL((k_conv_valu<Epi, 4>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+        }
         *used = true;
         return hipGetLastError();
     }

@@ -215,7 +215,51 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
     constexpr int NR = Epi::NRED;
     float u0 = 0.f, u1 = 0.f;
     typename Epi::Row rw;
-    if (FAST) rw = epi.row(uimg);
+    if (FAST) {
+        // Two-stage pipeline over the row groups: the loads of group g + 1 are issued
+        // before the stores of group g (the records and saved coefficients never alias
+        // the outputs), so one memory latency is exposed per tile rather than one per
+        // group -- when two groups' loads fit in about 48 registers.
+        rw = epi.row(uimg);
+        constexpr int NG = FM * (NACC / 4);
+        constexpr bool PIPE = FN * 4 * sizeof(typename Epi::Pre) <= 48 * 4;
+        using PreG = typename Epi::Pre[FN][4];
+        auto load_group = [&](int g, int (&dp)[4], PreG &pre) {
+            int img[4];
+            rowfn4(g / (NACC / 4), g % (NACC / 4), img, dp);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) pre[j][q] = epi.pre(rw, dp[q] * N + ncol[j]);
+        };
+        int dpA[4];
+        PreG preA;
+        load_group(0, dpA, preA);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            int dpB[4];
+            PreG preB;
+            if (PIPE && g + 1 < NG) load_group(g + 1, dpB, preB);
+            const int i = g / (NACC / 4), vg = g % (NACC / 4);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    epi.post(preA[j][q], rw, dpA[q], ncol[j], dpA[q] * N + ncol[j], bcol[j],
+                             acc[i][j][vg * 4 + q], u0, u1);
+            if (!PIPE && g + 1 < NG) load_group(g + 1, dpB, preB);
+            if (g + 1 < NG) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    dpA[q] = dpB[q];
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) preA[j][q] = preB[j][q];
+                }
+            }
+        }
+        if (NR > 0) reduce_wave_atomic(u0, u1, uimg, lane, epi.red0(), epi.red1());
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
