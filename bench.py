@@ -17,6 +17,7 @@ the timed steps), and the FP64 CPU oracle timed on a bounded sample of the same 
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import os
 import sys
@@ -68,6 +69,7 @@ def main():
     import torch
 
     import workloads as W
+    from paper_2412_09584_amd import rocprof_summary
     from paper_2412_09584_amd import binding as B
     from paper_2412_09584_amd import net as N
 
@@ -170,9 +172,17 @@ def main():
     dom_ms = gemm[dom][0] / gemm[dom][1]
     dom_flops = launch_flops(dom)
     achieved = dom_flops / (dom_ms / 1e3)
+    # HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE /
+    # WRITE_SIZE summary, if it was taken from the current kernel sources
+    traffic = None
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        rec_t = rocprof_summary.read_traffic(path, dom)
+        if rec_t is not None:
+            traffic = rec_t["bytes"]
+            break
     roofline = {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12,
                 "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
+                "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic,
                 "avg_launch_ms": dom_ms, "flop_per_launch": dom_flops}
     breakdown = {k: round(v[0] / args.steps, 4) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
 

@@ -1,0 +1,174 @@
+"""Summaries of rocprofv3 CSV output for the kernel profiles kept with the library.
+
+Two reports, each printed as Markdown that records the command which produced the data:
+
+``trace``   per-kernel totals from a ``--kernel-trace`` CSV, plus the average duration of
+            one kernel (name + grid size) over its last N dispatches -- the launches of
+            the timed steps when the traced command ends with them.
+``traffic`` HBM bytes of that kernel's last dispatch from a ``--pmc FETCH_SIZE`` run and
+            a ``--pmc WRITE_SIZE`` run (KiB per dispatch), each scaled by what the same
+            counter reads for a plain copy of known size in the same run (the largest
+            ``copyBuffer`` dispatch: it reads and writes ``--copy-bytes`` bytes).  The
+            report ends with a JSON comment that bench.py reads, together with a hash
+            of the kernel sources, so the figure is dropped once the kernels change.
+
+Usage::
+
+    python -m paper_2412_09584_amd.rocprof_summary trace --csv T.csv --kernel NAME \\
+        --grid G --last N --title ... --cmd ...
+    python -m paper_2412_09584_amd.rocprof_summary traffic --fetch F.csv --write W.csv \\
+        --kernel NAME --grid G --label LABEL --title ... --cmd ...
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def source_hash() -> str:
+    """sha256 over the kernel sources (csrc/*.hip, csrc/*.h), in name order."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) +
+                    glob.glob(os.path.join(HERE, "csrc", "*.h"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _short(name: str) -> str:
+    for pre in ("bp::(anonymous namespace)::", "bp::dev::"):
+        name = name.replace(pre, "")
+    name = name.split("(bp::GeomSet")[0].split("(const bp::")[0]
+    return name.strip()
+
+
+def _dispatches(path: str):
+    """Rows of a kernel-trace or counter CSV folded to one record per dispatch."""
+    out = collections.OrderedDict()
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            did = int(r.get("Dispatch_Id") or r.get("Correlation_Id"))
+            d = out.get(did)
+            if d is None:
+                d = out[did] = {
+                    "name": r["Kernel_Name"],
+                    "grid": int(r.get("Grid_Size") or r.get("Grid_Size_X") or 0),
+                    "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"]),
+                    "value": 0.0,
+                }
+            if "Counter_Value" in r:
+                d["value"] += float(r["Counter_Value"])
+    return list(out.values())
+
+
+def _match(ds, kernel: str, grid: int):
+    return [d for d in ds if _short(d["name"]) == kernel and (grid <= 0 or d["grid"] == grid)]
+
+
+def report_trace(a) -> str:
+    ds = _dispatches(a.csv)
+    tot = collections.defaultdict(lambda: [0, 0])
+    for d in ds:
+        t = tot[_short(d["name"])]
+        t[0] += d["ns"]
+        t[1] += 1
+    allns = sum(v[0] for v in tot.values()) or 1
+    sel = _match(ds, a.kernel, a.grid)[-a.last:]
+    avg = sum(d["ns"] for d in sel) / max(len(sel), 1) / 1e6
+    lines = [f"# {a.title}", "", "Command (TMPDIR=/tmp; <repo> is the repository root):", "",
+             f"    {a.cmd}", "",
+             f"Dominant kernel `{a.kernel}` (grid {a.grid}): average {avg:.4f} ms over its "
+             f"last {len(sel)} dispatches (the timed steps).", "",
+             "| total ms | calls | avg us | % | kernel |", "|---:|---:|---:|---:|---|"]
+    for k, (ns, n) in sorted(tot.items(), key=lambda kv: -kv[1][0])[: a.top]:
+        lines.append(f"| {ns / 1e6:.2f} | {n} | {ns / n / 1e3:.1f} | {100 * ns / allns:.1f} | `{k[:90]}` |")
+    lines += ["", f"<!-- trace: {json.dumps({'kernel': a.kernel, 'grid': a.grid, 'avg_ms': avg, 'n': len(sel)})} -->"]
+    return "\n".join(lines) + "\n"
+
+
+def report_traffic(a) -> str:
+    fd, wd = _dispatches(a.fetch), _dispatches(a.write)
+
+    def calib(ds):
+        cps = [d for d in ds if "copyBuffer" in d["name"]]
+        if not cps:
+            raise SystemExit("no copyBuffer dispatch for the calibration")
+        big = max(cps, key=lambda d: d["value"])
+        return big["value"] * 1024.0
+
+    fc, wc = calib(fd), calib(wd)
+    fs, ws = a.copy_bytes / fc, a.copy_bytes / wc
+    fsel, wsel = _match(fd, a.kernel, a.grid), _match(wd, a.kernel, a.grid)
+    if not fsel or not wsel:
+        raise SystemExit(f"kernel {a.kernel!r} grid {a.grid} not found")
+    fb, wb = fsel[-1]["value"] * 1024.0, wsel[-1]["value"] * 1024.0
+    rec = {"label": a.label, "kernel": a.kernel, "grid": a.grid, "fetch_bytes": fb * fs,
+           "write_bytes": wb * ws, "fetch_scale": fs, "write_scale": ws,
+           "bytes": fb * fs + wb * ws, "src_sha256": source_hash()}
+    lines = [f"# {a.title}", "", "Commands (one counter per run; TMPDIR=/tmp; <repo> is the "
+             "repository root):", ""]
+    lines += [f"    {c}" for c in a.cmd]
+    lines += ["", f"Calibration: the {a.copy_bytes / 2**30:.0f} GiB device copy in the same run reads "
+              f"FETCH_SIZE = {fc / 2**30:.3f} GiB and WRITE_SIZE = {wc / 2**30:.3f} GiB, so the "
+              f"counters are scaled by {fs:.3f} (fetch) and {ws:.3f} (write).", "",
+              f"Kernel `{a.kernel}` (grid {a.grid}, `{a.label}`), last dispatch:", "",
+              "| counter | raw GB | scaled GB |", "|---|---:|---:|",
+              f"| FETCH_SIZE | {fb / 1e9:.3f} | {fb * fs / 1e9:.3f} |",
+              f"| WRITE_SIZE | {wb / 1e9:.3f} | {wb * ws / 1e9:.3f} |",
+              f"| total | {(fb + wb) / 1e9:.3f} | {(fb * fs + wb * ws) / 1e9:.3f} |", "",
+              f"<!-- traffic: {json.dumps(rec)} -->"]
+    return "\n".join(lines) + "\n"
+
+
+def read_traffic(path: str, label: str):
+    """The traffic record of a summary, or None if missing, for another kernel, or taken
+    from kernel sources other than the current ones."""
+    try:
+        with open(path) as f:
+            txt = f.read()
+    except OSError:
+        return None
+    key = "<!-- traffic: "
+    i = txt.find(key)
+    if i < 0:
+        return None
+    rec = json.loads(txt[i + len(key): txt.index(" -->", i)])
+    if rec.get("label") != label or rec.get("src_sha256") != source_hash():
+        return None
+    return rec
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="what", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("--csv", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--grid", type=int, default=0)
+    t.add_argument("--last", type=int, default=20)
+    t.add_argument("--top", type=int, default=25)
+    t.add_argument("--title", required=True)
+    t.add_argument("--cmd", required=True)
+    r = sub.add_parser("traffic")
+    r.add_argument("--fetch", required=True)
+    r.add_argument("--write", required=True)
+    r.add_argument("--kernel", required=True)
+    r.add_argument("--grid", type=int, default=0)
+    r.add_argument("--label", required=True)
+    r.add_argument("--copy-bytes", type=float, default=float(2**30))
+    r.add_argument("--title", required=True)
+    r.add_argument("--cmd", action="append", required=True)
+    a = ap.parse_args(argv)
+    print(report_trace(a) if a.what == "trace" else report_traffic(a), end="")
+
+
+if __name__ == "__main__":
+    main()
