@@ -53,6 +53,7 @@ struct bound_net {
     float *buf[2] = {nullptr, nullptr};
     float *acc_s = nullptr, *acc_mag = nullptr, *acc_low = nullptr;
     Relax *tab = nullptr;
+    int32_t *slot = nullptr;         // compact save slots of the unstable neurons per bound row
     int32_t *infeas = nullptr;
     float *cen = nullptr, *rad = nullptr;
     float *save = nullptr;
@@ -374,6 +375,7 @@ bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max
               net->alloc(&net->acc_s, max_rows) && net->alloc(&net->acc_mag, max_rows) &&
               net->alloc(&net->acc_low, max_rows) &&
               net->alloc(&net->tab, (long)max_inst * (net->n_relu > 0 ? net->n_relu : 1)) &&
+              net->alloc(&net->slot, (long)max_inst * (net->n_relu > 0 ? net->n_relu : 1)) &&
               net->alloc(&net->infeas, max_inst) && net->alloc(&net->cen, (long)max_inst * net->d[0]) &&
               net->alloc(&net->rad, (long)max_inst * net->d[0]) &&
               net->alloc(&net->sbar, max_save_rows > 0 ? max_save_rows : 1) &&
@@ -474,7 +476,8 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
     ProfScope prof_prep(net, st, "prep");
     if (used > 0) {
         HIPCHK(launch_prep_tables(net->ns, used, P->n_inst, net->n_relu, P->lo, P->hi, P->bound_of,
-                                  P->alpha, net->tab, net->infeas, P->n_bounds, st));
+                                  P->alpha, net->tab, net->infeas, P->n_bounds, net->slot,
+                                  net->max_inst, st));
     } else {
         HIPCHK(launch_fill((float *)net->infeas, P->n_inst, 0.f, st));
     }

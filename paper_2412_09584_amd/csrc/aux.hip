@@ -49,12 +49,53 @@ __device__ inline long bound_row(const int32_t *bound_of, long inst, int n_bound
 __device__ inline long to_cmajor(long j, int C, int HW) { return (j % C) * HW + j / C; }
 __device__ inline long to_internal(long jn, int C, int HW) { return (jn % HW) * C + jn / HW; }
 
-// Lemma 1 for one neuron (boundary reading: active iff l >= 0, else inactive iff u <= 0).
-__device__ inline Relax relax_of(float l, float u, float a) {
+// Lemma 1 for one neuron (boundary reading: active iff l >= 0, else inactive iff u <= 0);
+// an unstable neuron's record carries w = k + 1, k its slot in the compact rows of saved
+// coefficients (see k_prep_slots).
+__device__ inline Relax relax_of(float l, float u, float a, int k) {
     if (l >= 0.f) return make_float4(1.f, 1.f, 0.f, 0.f);
     if (u <= 0.f) return make_float4(0.f, 0.f, 0.f, 0.f);
     const float su = u / (u - l);
-    return make_float4(a, su, -l * su, 1.f);
+    return make_float4(a, su, -l * su, (float)(k + 1));
+}
+
+// Slots of the unstable neurons of one ReLU layer under one bound row: the unstable
+// neurons in internal order get 0, 1, 2, ... (stable: -1).  The adjoint needs a saved
+// coefficient only where the neuron is unstable, so a pass saves G at these slots only.
+// Block (row r, layer m); each thread counts a contiguous segment, then the segment
+// bases come from a scan of the 256 counts.
+__global__ void k_prep_slots(const NetShapes ns, long n_relu, const float *lo, const float *hi,
+                             const int32_t *bound_of, int n_bounds, int per_inst, int32_t *slot) {
+    __shared__ int cnt[256];
+    const long r = blockIdx.x;
+    const LayerShape &L = ns.l[blockIdx.y];
+    const long b = per_inst ? bound_row(bound_of, r, n_bounds) : r;
+    const float *lr = lo + b * n_relu + L.off, *hr = hi + b * n_relu + L.off;
+    const long seg = (L.d + 255) / 256, j0 = threadIdx.x * seg;
+    const long j1 = j0 + seg < L.d ? j0 + seg : L.d;
+    int c = 0;
+    for (long j = j0; j < j1; ++j) {
+        const long jn = to_cmajor(j, L.C, L.HW);
+        c += (!(lr[jn] >= 0.f) && !(hr[jn] <= 0.f)) ? 1 : 0;
+    }
+    cnt[threadIdx.x] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < 256; ++t) {
+            const int v = cnt[t];
+            cnt[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int k = cnt[threadIdx.x];
+    int32_t *out = slot + r * n_relu + L.off;
+    for (long j = j0; j < j1; ++j) {
+        const long jn = to_cmajor(j, L.C, L.HW);
+        const bool un = !(lr[jn] >= 0.f) && !(hr[jn] <= 0.f);
+        out[j] = un ? k++ : -1;
+    }
 }
 
 __global__ void k_fill(float *p, long n, float v) {
@@ -65,7 +106,7 @@ __global__ void k_fill(float *p, long n, float v) {
 __global__ void k_prep_tables(const NetShapes ns, int used, long T, long n_relu,
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const float *alpha, Relax *tab, int32_t *infeas, long total,
-                              int n_bounds) {
+                              int n_bounds, const int32_t *slot, int per_inst) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     const long inst = e / T, jg = e - inst * T;
@@ -77,7 +118,8 @@ __global__ void k_prep_tables(const NetShapes ns, int used, long T, long n_relu,
     const long b = bound_row(bound_of, inst, n_bounds);
     const float l = lo[b * n_relu + L.off + jn], u = hi[b * n_relu + L.off + jn];
     const float a = alpha ? alpha[inst * n_relu + L.off + jn] : (u >= -l ? 1.f : 0.f);
-    tab[inst * n_relu + L.off + j] = relax_of(l, u, a);
+    const int k = slot[(per_inst ? inst : b) * n_relu + L.off + j];
+    tab[inst * n_relu + L.off + j] = relax_of(l, u, a, k);
 }
 
 __global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, long n_relu,
@@ -386,8 +428,10 @@ __global__ void k_adj_stop_linear(long n_img, int rows, long D, const float *lam
     const float l = lam[e];
     const float sg = l > 0.f ? 1.f : (l < 0.f ? -1.f : 0.f);
     const float v = sb * (cen[inst * D + j] - sg * rad[inst * D + j]);
-    const float gv = g[e];
     const Relax t = tab[inst * tab_ld + j];
+    // saved coefficients exist at the unstable neurons only (slot w - 1); elsewhere the
+    // record has equal slopes and no intercept, so the sign of G does not matter
+    const float gv = t.w != 0.f ? g[img * D + (int)t.w - 1] : 0.f;
     if (gout) gout[e] = v * (gv >= 0.f ? t.x : t.y) + (gv < 0.f ? sb * t.z : 0.f);
     if (t.w != 0.f && gv >= 0.f) {
         const float c = gv * v;
@@ -535,12 +579,18 @@ hipError_t launch_fill(float *p, long n, float v, hipStream_t st) {
 hipError_t launch_prep_tables(const NetShapes &ns, int used, int n_inst, long n_relu,
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const float *alpha, Relax *tab, int32_t *infeas, int n_bounds,
-                              hipStream_t st) {
+                              int32_t *slot, int max_rows, hipStream_t st) {
     const long T = used > 0 ? ns.l[used - 1].off + ns.l[used - 1].d : 0;
     if (T == 0) return launch_fill((float *)infeas, n_inst, 0.f, st);  // 0.0f is all-zero bits
+    // slots per bound row when the rows fit the slot table, else per instance
+    const bool per_inst = bound_of == nullptr || n_bounds > max_rows;
+    const int rows = per_inst ? n_inst : n_bounds;
+    hipLaunchKernelGGL(k_prep_slots, dim3((unsigned)rows, (unsigned)used), dim3(256), 0, st, ns,
+                       n_relu, lo, hi, bound_of, n_bounds, per_inst ? 1 : 0, slot);
     const long total = T * n_inst;
     hipLaunchKernelGGL(k_prep_tables, dim3(blocks_for(total)), dim3(TPB), 0, st, ns, used, T,
-                       n_relu, lo, hi, bound_of, alpha, tab, infeas, total, n_bounds);
+                       n_relu, lo, hi, bound_of, alpha, tab, infeas, total, n_bounds, slot,
+                       per_inst ? 1 : 0);
     return hipGetLastError();
 }
 

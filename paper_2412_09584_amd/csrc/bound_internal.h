@@ -30,13 +30,16 @@ struct GeomSet {
 };
 
 // Per-neuron relaxation record (Lemma 1) for one instance:
-// x = lower slope, y = upper slope, z = upper intercept, w = 1 if unstable (alpha free).
+// x = lower slope, y = upper slope, z = upper intercept; w = 0 for a stable (or split)
+// neuron, else k + 1 with k the neuron's slot in the compact rows of saved coefficients
+// (alpha free).  Records with w = 0 have x = y and z = 0.
 typedef float4 Relax;
 
 // ----- epilogue parameter blocks -----------------------------------------------------
 struct RelaxParams {       // G_m = Lambda_m W_m  ->  Lambda_{m-1} = relax(G_m)
     float *out;            // Lambda_{m-1}  [img][D]
-    float *save;           // G_m kept for the gradient (nullable)
+    float *save;           // G_m kept for the gradient (nullable): per img, the unstable
+                           // neurons only, at slot w - 1 of their record
     const Relax *tab;      // relaxation table of layer m-1, row stride tab_ld
     long tab_ld;
     const float *bias;     // b_{m-1} per channel
@@ -63,7 +66,7 @@ struct AdjParams {         // Lambda_bar_m = G_bar_m W_m^T + s_bar b_m  -> G_bar
     const float *bias;     // b_m per channel
     int chan;
     long D;                // width of layer m
-    const float *gsave;    // saved G_{m+1} [img][D]
+    const float *gsave;    // saved G_{m+1} [img][D], compact (slot w - 1 of the record)
     const Relax *tab;
     long tab_ld;
     float *gout;           // G_bar_{m+1} (nullable at the last layer)
@@ -140,7 +143,8 @@ hipError_t launch_fill(float *p, long n, float v, hipStream_t st);
 hipError_t launch_prep_tables(const NetShapes &ns, int n_layers_used, int n_inst,
                               long n_relu, const float *lo, const float *hi,
                               const int32_t *bound_of, const float *alpha, Relax *tab,
-                              int32_t *infeas, int n_bounds, hipStream_t st);
+                              int32_t *infeas, int n_bounds, int32_t *slot, int max_rows,
+                              hipStream_t st);
 hipError_t launch_prep_splits(const NetShapes &ns, int n_layers_used, int n_inst, long n_relu,
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const int32_t *off, const int32_t *idx, const int8_t *sign,

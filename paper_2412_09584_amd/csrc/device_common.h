@@ -97,7 +97,7 @@ struct EpiRelax {
         r0 += bt + off;
         r1 += fabsf(bt) + fabsf(off);
         rc.out[j] = lam;
-        if (rc.save) rc.save[j] = g;
+        if (rc.save && t.w != 0.f) rc.save[(int)t.w - 1] = g;   // unstable: compact slot
     }
 };
 
@@ -139,7 +139,12 @@ struct EpiAdj {
     __device__ float colv(int n) const { return p.bias[n]; }
     __device__ float *red0() const { return nullptr; }
     __device__ float *red1() const { return nullptr; }
-    __device__ Pre pre(const Row &rc, int j) const { return Pre{rc.tb[j], rc.gs[j]}; }
+    // G is saved at the unstable neurons only; elsewhere x = y and z = 0, so its sign
+    // does not matter
+    __device__ Pre pre(const Row &rc, int j) const {
+        const Relax t = rc.tb[j];
+        return Pre{t, t.w != 0.f ? rc.gs[(int)t.w - 1] : 0.f};
+    }
     __device__ void post(const Pre &q, const Row &rc, int dpix, int n, int j, float bcol, float acc,
                          float &, float &) const {
         const float v = acc + rc.sb * bcol;           // Lambda_bar_m[img, j]
