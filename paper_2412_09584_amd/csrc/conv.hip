@@ -366,7 +366,10 @@ __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvT
         typename Epi::Pre pre[NMAX];
 #pragma unroll
         for (int n = 0; n < NMAX; ++n)
-            if (n < g.N) pre[n] = epi.pre(rc, dpix * g.N + n);
+            if (n < g.N) {
+                pre[n] = epi.pre(rc, dpix * g.N + n);
+                epi.pre2(rc, pre[n]);
+            }
 #pragma unroll
         for (int n = 0; n < NMAX; ++n)
             if (n < g.N) epi.post(pre[n], rc, dpix, n, dpix * g.N + n, epi.colv(n), acc[n], r0, r1);

@@ -71,8 +71,9 @@ __device__ inline long ldiv_by(long n, int d, float rd) {
 
 // ---------------------------------------------------------------------- epilogues
 // Each epilogue splits its per-element work into pre() -- the global loads it needs
-// (relaxation record, box, saved coefficient) -- and post() -- arithmetic, stores and
-// atomics -- so that tile_epilogue can issue a group's loads before any of its stores.
+// (relaxation record, box) --, pre2() -- loads whose address depends on pre()'s result
+// (the saved coefficient of the adjoint) -- and post() -- arithmetic, stores and
+// atomics -- so that tile_epilogue can issue loads ahead of earlier groups' stores.
 // Row(img) resolves the per-img pointers once per row group; j is the element's offset
 // inside its img (dpix * N + n), dpix the destination pixel.
 struct EpiRelax {
@@ -89,6 +90,7 @@ struct EpiRelax {
     __device__ float *red0() const { return p.s; }
     __device__ float *red1() const { return p.mag; }
     __device__ Pre pre(const Row &rc, int j) const { return rc.tb[j]; }
+    __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &t, const Row &rc, int, int, int j, float bcol, float g,
                          float &r0, float &r1) const {
         const float lam = g >= 0.f ? g * t.x : g * t.y;
@@ -116,6 +118,7 @@ struct EpiConc {
     __device__ float *red0() const { return p.low; }
     __device__ float *red1() const { return p.mag; }
     __device__ Pre pre(const Row &rc, int j) const { return make_float2(rc.cen[j], rc.rad[j]); }
+    __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &cr, const Row &rc, int dpix, int n, int j, float, float g,
                          float &r0, float &r1) const {
         r0 += g * cr.x - fabsf(g) * cr.y;
@@ -139,11 +142,12 @@ struct EpiAdj {
     __device__ float colv(int n) const { return p.bias[n]; }
     __device__ float *red0() const { return nullptr; }
     __device__ float *red1() const { return nullptr; }
-    // G is saved at the unstable neurons only; elsewhere x = y and z = 0, so its sign
-    // does not matter
-    __device__ Pre pre(const Row &rc, int j) const {
-        const Relax t = rc.tb[j];
-        return Pre{t, t.w != 0.f ? rc.gs[(int)t.w - 1] : 0.f};
+    // G is saved at the unstable neurons only (slot w - 1), a load that depends on the
+    // record: pre() fetches the record, pre2() the saved coefficient.  Elsewhere x = y
+    // and z = 0, so the sign of G does not matter.
+    __device__ Pre pre(const Row &rc, int j) const { return Pre{rc.tb[j], 0.f}; }
+    __device__ void pre2(const Row &rc, Pre &q) const {
+        if (q.t.w != 0.f) q.g = rc.gs[(int)q.t.w - 1];
     }
     __device__ void post(const Pre &q, const Row &rc, int dpix, int n, int j, float bcol, float acc,
                          float &, float &) const {
@@ -169,6 +173,7 @@ struct EpiFwd {
     __device__ float *red0() const { return nullptr; }
     __device__ float *red1() const { return nullptr; }
     __device__ Pre pre(const Row &, int) const { return Pre{}; }
+    __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &, const Row &rc, int, int, int j, float bcol, float acc,
                          float &, float &) const {
         rc.out[j] = acc + bcol;
@@ -221,15 +226,17 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
     float u0 = 0.f, u1 = 0.f;
     typename Epi::Row rw;
     if (FAST) {
-        // Two-stage pipeline over the row groups: the loads of group g + 1 are issued
-        // before the stores of group g (the records and saved coefficients never alias
-        // the outputs), so one memory latency is exposed per tile rather than one per
-        // group -- when two groups' loads fit in about 48 registers.
+        // Pipeline over the row groups: the first loads of group g + 2 and the dependent
+        // loads of group g + 1 are issued before the stores of group g (records and saved
+        // coefficients never alias the outputs), so about one memory latency is exposed
+        // per tile rather than one or two per group -- when three groups' loads fit in
+        // about 64 registers (else two stages, or none).
         rw = epi.row(uimg);
         constexpr int NG = FM * (NACC / 4);
-        constexpr bool PIPE = FN * 4 * sizeof(typename Epi::Pre) <= 48 * 4;
+        constexpr int GREG = FN * 4 * (int)sizeof(typename Epi::Pre) / 4;
+        constexpr int DEPTH = 3 * GREG <= 64 ? 2 : (2 * GREG <= 48 ? 1 : 0);
         using PreG = typename Epi::Pre[FN][4];
-        auto load_group = [&](int g, int (&dp)[4], PreG &pre) {
+        auto load1 = [&](int g, int (&dp)[4], PreG &pre) {
             int img[4];
             rowfn4(g / (NACC / 4), g % (NACC / 4), img, dp);
 #pragma unroll
@@ -237,14 +244,36 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
 #pragma unroll
                 for (int q = 0; q < 4; ++q) pre[j][q] = epi.pre(rw, dp[q] * N + ncol[j]);
         };
-        int dpA[4];
-        PreG preA;
-        load_group(0, dpA, preA);
+        auto load2 = [&](PreG &pre) {
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) epi.pre2(rw, pre[j][q]);
+        };
+        auto copy = [&](int (&dd)[4], PreG &pd, const int (&ds)[4], const PreG &ps) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                dd[q] = ds[q];
+#pragma unroll
+                for (int j = 0; j < FN; ++j) pd[j][q] = ps[j][q];
+            }
+        };
+        int dpA[4], dpB[4];
+        PreG preA, preB;
+        load1(0, dpA, preA);
+        load2(preA);
+        if (DEPTH == 2 && NG > 1) load1(1, dpB, preB);
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-            int dpB[4];
-            PreG preB;
-            if (PIPE && g + 1 < NG) load_group(g + 1, dpB, preB);
+            int dpC[4];
+            PreG preC;
+            if (DEPTH == 2) {
+                if (g + 2 < NG) load1(g + 2, dpC, preC);
+                if (g + 1 < NG) load2(preB);
+            } else if (DEPTH == 1 && g + 1 < NG) {
+                load1(g + 1, dpB, preB);
+                load2(preB);
+            }
             const int i = g / (NACC / 4), vg = g % (NACC / 4);
 #pragma unroll
             for (int j = 0; j < FN; ++j)
@@ -252,15 +281,12 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
                 for (int q = 0; q < 4; ++q)
                     epi.post(preA[j][q], rw, dpA[q], ncol[j], dpA[q] * N + ncol[j], bcol[j],
                              acc[i][j][vg * 4 + q], u0, u1);
-            if (!PIPE && g + 1 < NG) load_group(g + 1, dpB, preB);
-            if (g + 1 < NG) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    dpA[q] = dpB[q];
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) preA[j][q] = preB[j][q];
-                }
+            if (DEPTH == 0 && g + 1 < NG) {
+                load1(g + 1, dpB, preB);
+                load2(preB);
             }
+            if (g + 1 < NG) copy(dpA, preA, dpB, preB);
+            if (DEPTH == 2 && g + 2 < NG) copy(dpB, preB, dpC, preC);
         }
         if (NR > 0) reduce_wave_atomic(u0, u1, uimg, lane, epi.red0(), epi.red1());
         return;
@@ -292,7 +318,10 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    if (FAST || (img[q] >= 0 && ncol[j] < N)) pre[j][q] = epi.pre(rc[q], dp[q] * N + ncol[j]);
+                    if (FAST || (img[q] >= 0 && ncol[j] < N)) {
+                        pre[j][q] = epi.pre(rc[q], dp[q] * N + ncol[j]);
+                        epi.pre2(rc[q], pre[j][q]);
+                    }
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
