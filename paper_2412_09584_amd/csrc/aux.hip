@@ -103,23 +103,28 @@ __global__ void k_fill(float *p, long n, float v) {
     if (i < n) p[i] = v;
 }
 
+// A block writes PREP_SPAN consecutive records (internal order): the C-major reads of
+// alpha / lo / hi then revisit the same cache lines within one block, on one XCD.
+constexpr int PREP_SPAN = 2048;
+
 __global__ void k_prep_tables(const NetShapes ns, int used, long T, long n_relu,
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const float *alpha, Relax *tab, int32_t *infeas, long total,
                               int n_bounds, const int32_t *slot, int per_inst) {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
-    const long inst = e / T, jg = e - inst * T;
-    if (jg == 0) infeas[inst] = 0;
-    const int m = layer_of(ns, used, jg);
-    const LayerShape &L = ns.l[m];
-    const long j = jg - L.off;
-    const long jn = to_cmajor(j, L.C, L.HW);
-    const long b = bound_row(bound_of, inst, n_bounds);
-    const float l = lo[b * n_relu + L.off + jn], u = hi[b * n_relu + L.off + jn];
-    const float a = alpha ? alpha[inst * n_relu + L.off + jn] : (u >= -l ? 1.f : 0.f);
-    const int k = slot[(per_inst ? inst : b) * n_relu + L.off + j];
-    tab[inst * n_relu + L.off + j] = relax_of(l, u, a, k);
+    const long e0 = (long)blockIdx.x * PREP_SPAN;
+    for (long e = e0 + threadIdx.x; e < e0 + PREP_SPAN && e < total; e += TPB) {
+        const long inst = e / T, jg = e - inst * T;
+        if (jg == 0) infeas[inst] = 0;
+        const int m = layer_of(ns, used, jg);
+        const LayerShape &L = ns.l[m];
+        const long j = jg - L.off;
+        const long jn = to_cmajor(j, L.C, L.HW);
+        const long b = bound_row(bound_of, inst, n_bounds);
+        const float l = lo[b * n_relu + L.off + jn], u = hi[b * n_relu + L.off + jn];
+        const float a = alpha ? alpha[inst * n_relu + L.off + jn] : (u >= -l ? 1.f : 0.f);
+        const int k = slot[(per_inst ? inst : b) * n_relu + L.off + j];
+        tab[inst * n_relu + L.off + j] = relax_of(l, u, a, k);
+    }
 }
 
 __global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, long n_relu,
@@ -588,7 +593,7 @@ hipError_t launch_prep_tables(const NetShapes &ns, int used, int n_inst, long n_
     hipLaunchKernelGGL(k_prep_slots, dim3((unsigned)rows, (unsigned)used), dim3(256), 0, st, ns,
                        n_relu, lo, hi, bound_of, n_bounds, per_inst ? 1 : 0, slot);
     const long total = T * n_inst;
-    hipLaunchKernelGGL(k_prep_tables, dim3(blocks_for(total)), dim3(TPB), 0, st, ns, used, T,
+    hipLaunchKernelGGL(k_prep_tables, dim3(blocks_for(total, PREP_SPAN)), dim3(TPB), 0, st, ns, used, T,
                        n_relu, lo, hi, bound_of, alpha, tab, infeas, total, n_bounds, slot,
                        per_inst ? 1 : 0);
     return hipGetLastError();
