@@ -1,0 +1,156 @@
+"""Plain CPU oracle for the branch-and-bound planning loop over input boxes: the loop of
+Algorithms 1-2, the subdomain pick-out and split heuristics of Section 3.3 (Eq. lf_pick),
+the search summary and the pruner.
+
+TEST INFRASTRUCTURE. Only tests/, the smoke check of the package entry file and the
+cpu_baseline leg of the bench may import this module.  The HIP library never calls it,
+and it shares no code with the HIP library: only the seeded input generators in
+``workloads`` serve both.  Random numbers the method draws (Gumbel uniforms for the
+pick-out, uniforms for the search samples) are inputs.
+
+Readings where the text leaves a choice (each is listed in the design notes):
+  * batch_pick_out: n = min(n, |P|) and n1 = floor(eta * n) (in double precision).
+    The first n1 picks are the subdomains with the smallest upper bound f_hi (ties:
+    lower index).  The other n - n1 are drawn without replacement from the rest with
+    p_i proportional to exp(-s_i / T), s_i = (f_lo_i - min) / (max - min) over the rest
+    (min-max scaling; s = 0 when max = min).  Drawing without replacement uses the
+    Gumbel-top-k construction -- the n - n1 largest of -s_i / T + G_i, G_i = -log(-log
+    U_i) with U_i the supplied uniforms (ties: lower index) -- which yields the ordered
+    sample of successive softmax draws.  A subdomain with a non-finite f_lo comes after
+    every finite one.
+  * batch_split: the box coordinates are FP32 and so is the midpoint (lo + hi) * 0.5.
+    The top samples are the k = max(1, ceil(w / 100 * M)) samples of the box's search
+    with the smallest objective (ties: lower index); a sample counts on the lower side
+    of dimension j iff u_j <= mid_j.  score_j = (hi_j - lo_j) * |n_lo_j - n_up_j| in
+    FP32; j* = argmax (ties: lower j); if every score is 0, the widest dimension.
+  * batch_search: M samples per box, u = lo + (hi - lo) * U with supplied uniforms U
+    (the paper uses CEM; its refits are a plug not built here); f_hi = the smallest
+    objective among them and u~ its sample (ties: lower index).
+  * Pruner: a subdomain is kept iff f_lo <= f_hi_best (pruned iff f_lo > f_hi_best).
+  * Loop: Algorithm 2's order (search, then bound, on the new subdomains); the best
+    (f_hi, u~) is updated from the children; the pruner tests only the children, which
+    join the rest of P.  It stops after a given number of iterations or when P is empty.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+F32 = np.float32
+
+
+def pick_out(f_lo, f_hi, u, n, eta, T):
+    """Indices picked (in pick order) and the rest (in original order)."""
+    f_lo = np.asarray(f_lo, np.float64)
+    f_hi = np.asarray(f_hi, np.float64)
+    N = f_lo.size
+    n = min(int(n), N)
+    n1 = int(math.floor(float(eta) * n))
+    first = list(np.argsort(f_hi, kind="stable")[:n1])
+    taken = np.zeros(N, bool)
+    taken[first] = True
+    rest = np.nonzero(~taken)[0]
+    fin = rest[np.isfinite(f_lo[rest])]
+    picks = []
+    if n - n1 > 0 and rest.size:
+        lo = f_lo[fin].min() if fin.size else 0.0
+        hi = f_lo[fin].max() if fin.size else 0.0
+        score = np.full(N, -np.inf)
+        for i in fin:
+            s = (f_lo[i] - lo) / (hi - lo) if hi > lo else 0.0
+            uu = min(max(float(u[i]), 1e-30), 1.0 - 2.0 ** -24)
+            score[i] = -s / T - math.log(-math.log(uu))
+        order = sorted(rest, key=lambda i: (-score[i] if np.isfinite(f_lo[i]) else math.inf, i))
+        picks = list(order[: n - n1])
+    picked = [int(i) for i in first] + [int(i) for i in picks]
+    mark = np.zeros(N, bool)
+    mark[picked] = True
+    return np.array(picked, np.int64), np.nonzero(~mark)[0]
+
+
+def search_summary(values, samples, k):
+    """Per box: f_hi = smallest objective, u~ and the k best samples (ascending objective,
+    ties: lower index).  values [n, M], samples [n, M, d]."""
+    values = np.asarray(values)
+    n, M = values.shape
+    order = np.argsort(values, axis=1, kind="stable")
+    f_hi = values[np.arange(n), order[:, 0]]
+    top = np.stack([samples[i, order[i, :k]] for i in range(n)])
+    return f_hi, top
+
+
+def n_top(w, M):
+    return max(1, min(M, int(math.ceil(float(w) / 100.0 * M))))
+
+
+def split(lo, hi, top):
+    """Bisect each box [lo, hi] (FP32, [n, d]) along the dimension chosen from its top
+    samples top [n, k, d]; returns (child_lo, child_hi) [2n, d] (lower child 2i, upper
+    child 2i + 1) and the chosen dimensions."""
+    lo = np.asarray(lo, F32)
+    hi = np.asarray(hi, F32)
+    n, d = lo.shape
+    mid = (lo + hi) * F32(0.5)
+    clo = np.repeat(lo, 2, axis=0)
+    chi = np.repeat(hi, 2, axis=0)
+    dims = np.zeros(n, np.int64)
+    for i in range(n):
+        t = np.asarray(top[i], F32)
+        nlo = np.sum(t <= mid[i][None, :], axis=0)
+        nup = t.shape[0] - nlo
+        width = hi[i] - lo[i]
+        score = width * np.abs(nlo - nup).astype(F32)
+        j = int(np.argmax(score)) if np.max(score) > 0 else int(np.argmax(width))
+        dims[i] = j
+        chi[2 * i, j] = mid[i, j]
+        clo[2 * i + 1, j] = mid[i, j]
+    return clo, chi, dims
+
+
+def prune(f_lo, best):
+    """Indices kept (in order): f_lo <= best."""
+    f_lo = np.asarray(f_lo, np.float64)
+    return np.nonzero(f_lo <= best)[0]
+
+
+def bab_plan(objective, bound, lo0, hi0, n_pick, M, iters, eta, T, w, uniforms):
+    """Algorithm 2 with the heuristics above.  objective(u [m, d]) -> [m] values;
+    bound(lo [b, d], hi [b, d]) -> [b] lower bounds of the objective over each box;
+    uniforms(tag, shape) -> the supplied random numbers (tag 'search0', ('search', t),
+    ('pick', t)).  Returns the best value, its sample and the per-iteration trace."""
+    lo0 = np.asarray(lo0, F32)[None]
+    hi0 = np.asarray(hi0, F32)[None]
+    d = lo0.shape[1]
+    k = n_top(w, M)
+
+    def search(lo, hi, tag):
+        U = np.asarray(uniforms(tag, (lo.shape[0], M, d)), F32)
+        S = lo[:, None, :] + (hi - lo)[:, None, :] * U
+        vals = np.asarray(objective(S.reshape(-1, d)), np.float64).reshape(lo.shape[0], M)
+        return search_summary(vals, S, k)
+
+    f_hi, top = search(lo0, hi0, "search0")
+    f_lo = np.asarray(bound(lo0, hi0), np.float64)
+    best, ubest = float(f_hi[0]), top[0, 0]
+    P = dict(lo=lo0, hi=hi0, f_lo=f_lo, f_hi=f_hi, top=top)
+    trace = []
+    for t in range(iters):
+        N = P["lo"].shape[0]
+        if N == 0:
+            break
+        picked, rest = pick_out(P["f_lo"], P["f_hi"], uniforms(("pick", t), (N,)), n_pick, eta, T)
+        clo, chi, dims = split(P["lo"][picked], P["hi"][picked], P["top"][picked])
+        c_fhi, c_top = search(clo, chi, ("search", t))
+        c_flo = np.asarray(bound(clo, chi), np.float64)
+        j = int(np.argmin(c_fhi))
+        if c_fhi[j] < best:
+            best, ubest = float(c_fhi[j]), c_top[j, 0]
+        keep = prune(c_flo, best)
+        P = dict(lo=np.concatenate([P["lo"][rest], clo[keep]]),
+                 hi=np.concatenate([P["hi"][rest], chi[keep]]),
+                 f_lo=np.concatenate([P["f_lo"][rest], c_flo[keep]]),
+                 f_hi=np.concatenate([P["f_hi"][rest], c_fhi[keep]]),
+                 top=np.concatenate([P["top"][rest], c_top[keep]]))
+        trace.append(dict(picked=picked, dims=dims, kept=keep, best=best, size=P["lo"].shape[0]))
+    return best, ubest, trace, P

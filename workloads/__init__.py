@@ -238,3 +238,31 @@ def beta_cnn(n_roots=64, per_root=64):
     w.name = f"beta-crown_cnn_{n_roots}x{per_root}_steps10"
     w.extra.update(steps=10, lr=0.1, alpha0=0.5, per_root=per_root, kmin=1, kmax=12)
     return w
+
+
+# ----------------------------------------------------------------- planning (BaB) inputs
+PLAN_SEED = 3
+
+
+def plan_objective(d=8, hidden=(64, 64), seed=WEIGHT_SEED):
+    """A scalar ReLU objective f(u) over an action box (stands in for the paper's cost of
+    unrolled learned dynamics, which is not available): MLP d -> hidden -> 1, He-normal
+    weights.  Returns the net and the box [-1, 1]^d."""
+    net = mlp([d, *hidden, 1], seed=seed)
+    return net, -np.ones(d, np.float32), np.ones(d, np.float32)
+
+
+def plan_uniforms(seed=PLAN_SEED):
+    """uniforms(tag, shape): float32 uniforms in [0, 1) for the planning loop's random
+    draws, one independent stream per tag ('search0', ('search', t), ('pick', t))."""
+    def code(tag):
+        if tag == "search0":
+            return 0
+        kind, t = tag
+        return 1 + 2 * int(t) + (0 if kind == "search" else 1)
+
+    def draw(tag, shape):
+        rng = np.random.default_rng([seed, code(tag)])
+        return rng.random(shape, dtype=np.float64).astype(np.float32)
+
+    return draw
