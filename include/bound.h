@@ -246,6 +246,69 @@ int32_t bound_profile_read(bound_net *net, int32_t cap, char *names, double *tot
 void bound_destroy(bound_net *net);
 const char *bound_last_error(void);
 
+/* ------------------------------------------------------------------------------------
+ * Branch and bound over input boxes (the planning loop of Algorithms 1-2 and the
+ * branching heuristics of Section 3.1): the per-iteration steps around the bound pass.
+ * A subdomain is a box [lo, hi] of dim coordinates with a lower bound f_lo of the
+ * objective (bound_backward on the box) and an upper bound f_hi (the best objective its
+ * search found).  Random numbers are inputs (uniforms in [0, 1)).  Ties are always
+ * broken toward the lower index; -0.0 counts as +0.0 and NaN as +inf in comparisons.
+ * ------------------------------------------------------------------------------------ */
+typedef struct bound_bab bound_bab;
+
+/* Workspace for up to max_dom subdomains of dim coordinates and up to max_samples
+ * (<= 2048) search samples per subdomain.  Allocates device memory once. */
+bound_status bound_bab_init(int32_t max_dom, int32_t dim, int32_t max_samples, bound_bab **out);
+void bound_bab_destroy(bound_bab *bab);
+
+/* batch_pick_out (Section 3.1, Eq. lf_pick): with n = min(n_pick, n_dom) and
+ * n1 = floor(eta * n) (host double precision), picked[0 .. n1) are the n1 subdomains
+ * with the smallest f_hi; picked[n1 .. n) are drawn without replacement from the
+ * others with probability proportional to exp(-s_i / temperature), s_i = f_lo min-max
+ * scaled over those others (0 if all equal), by the Gumbel-top-k rule: the n - n1
+ * largest -s_i / T - log(-log u_i) (u clamped to [1e-30, 1 - 2^-24]); subdomains with
+ * non-finite f_lo come last.  rest [n_dom - n] lists the others in ascending order.
+ * f_lo, f_hi, u [n_dom]; temperature > 0; 0 <= eta <= 1; n_dom <= max_dom. */
+bound_status bound_bab_pick_out(bound_bab *bab, int32_t n_dom, const float *f_lo,
+                                const float *f_hi, const float *u, int32_t n_pick, float eta,
+                                float temperature, int32_t *picked, int32_t *rest, void *stream);
+
+/* batch_search, sampling: samples[i, m, :] = lo[i] + (hi[i] - lo[i]) * U[i, m, :], each
+ * operation rounded separately in FP32.  lo, hi [n, dim]; U, samples [n, M, dim]. */
+bound_status bound_bab_samples(bound_bab *bab, int32_t n, int32_t M, const float *lo,
+                               const float *hi, const float *U, float *samples, void *stream);
+
+/* batch_search, summary: per subdomain the smallest objective over its M samples
+ * (f_hi [n]) and its k best samples in ascending order of objective (top [n, k, dim];
+ * top[i, 0] is the best sample u~).  values [n, M] (the objective at the samples),
+ * samples [n, M, dim]; 1 <= k <= M <= max_samples. */
+bound_status bound_bab_search_summary(bound_bab *bab, int32_t n, int32_t M, const float *values,
+                                      const float *samples, int32_t k, float *f_hi, float *top,
+                                      void *stream);
+
+/* batch_split (Section 3.1): for each subdomain i the dimension j* maximising
+ * (hi_j - lo_j) * |n_lo_j - n_up_j| over its k top samples (a sample is on the lower side
+ * iff u_j <= mid_j, mid = (lo + hi) * 0.5 in FP32; if every score is 0, the widest
+ * dimension), then the two halves: child 2i = [lo, hi with hi_j* = mid], child 2i + 1 =
+ * [lo with lo_j* = mid, hi].  lo, hi [n, dim]; top [n, k, dim]; child_lo, child_hi
+ * [2n, dim]; split_dim [n] (may be NULL). */
+bound_status bound_bab_split(bound_bab *bab, int32_t n, const float *lo, const float *hi,
+                             const float *top, int32_t k, float *child_lo, float *child_hi,
+                             int32_t *split_dim, void *stream);
+
+/* The best solution so far: if min_i f_hi[i] < *best (device scalar), *best takes that
+ * value and u_best [dim] the sample top[i*, 0] of its subdomain i*.  f_hi [n];
+ * top [n, k, dim]. */
+bound_status bound_bab_update_best(bound_bab *bab, int32_t n, const float *f_hi,
+                                   const float *top, int32_t k, float *best, float *u_best,
+                                   void *stream);
+
+/* Pruner: keep [*n_keep] = the indices i (ascending) with f_lo[i] <= *best, i.e. the
+ * subdomains that may still hold a better solution (a subdomain is pruned iff
+ * f_lo > best).  f_lo [n]; best and n_keep are device scalars; keep [n]. */
+bound_status bound_bab_prune(bound_bab *bab, int32_t n, const float *f_lo, const float *best,
+                             int32_t *keep, int32_t *n_keep, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

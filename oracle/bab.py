@@ -1,6 +1,6 @@
 """Plain CPU oracle for the branch-and-bound planning loop over input boxes: the loop of
-Algorithms 1-2, the subdomain pick-out and split heuristics of Section 3.3 (Eq. lf_pick),
-the search summary and the pruner.
+Algorithms 1-2, the subdomain pick-out and split heuristics of Section 3.1 (Eq. lf_pick),
+the search summary (Section 3.3) and the pruner (Section 3).
 
 TEST INFRASTRUCTURE. Only tests/, the smoke check of the package entry file and the
 cpu_baseline leg of the bench may import this module.  The HIP library never calls it,

@@ -1,0 +1,119 @@
+"""Branch and bound over input boxes for planning (Algorithm 2's order: search, then
+bound, on the new subdomains), driven from Python over library calls: the pick-out,
+split, sampling, search summary, best update and pruner run in libbound.so's kernels
+(`bound_bab_*`), the objective's forward passes in its product kernels
+(`bound_sample_bounds`), and each subdomain's lower bound is a full CROWN pass
+(`bound_backward`).  This module keeps the candidate set as device tensors and gathers
+rows by the index lists the kernels return.
+
+The objective is the scalar output of a ReLU network over an action box.  Random
+numbers are drawn by the caller's ``uniforms(tag, shape)`` (the same stream layout as
+the test oracle: 'search0', ('search', t), ('pick', t)).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .net import BoundNet
+
+
+class BaBPlanner:
+    def __init__(self, layers, box_lo, box_hi, *, n_pick=64, samples=64, eta=0.75,
+                 temperature=0.05, w=1.0, max_dom=1 << 16, device="cuda"):
+        self.device = torch.device(device)
+        self.lo0 = torch.as_tensor(np.asarray(box_lo, np.float32), device=self.device)[None]
+        self.hi0 = torch.as_tensor(np.asarray(box_hi, np.float32), device=self.device)[None]
+        self.d = self.lo0.shape[1]
+        self.n_pick, self.M = int(n_pick), int(samples)
+        self.eta, self.T, self.w = float(eta), float(temperature), float(w)
+        self.k = max(1, min(self.M, int(math.ceil(self.w / 100.0 * self.M))))
+        self.max_dom = int(max_dom)
+        widths = [int(np.prod(L["out_shape"])) for L in layers]
+        rows = 2 * max(widths[:-1] + [1]) * 2 * self.n_pick
+        self.net = BoundNet(layers, max_inst=max(2 * self.n_pick, 1),
+                            max_rows=max(rows, 2 * self.n_pick * self.M))
+        if self.net.d[-1] != 1:
+            raise ValueError("the objective network must have a scalar output")
+        self.bab = B.bound_bab_init(self.max_dom, self.d, self.M)
+
+    def __del__(self):
+        h = getattr(self, "bab", None)
+        if h:
+            B.bound_bab_destroy(h)
+            self.bab = None
+
+    # ------------------------------------------------------------------ steps
+    def bound(self, lo, hi):
+        """CROWN lower bound of the objective over each box [n]."""
+        n = lo.shape[0]
+        blo, bhi = self.net.crown_bounds(lo, hi)
+        C = torch.ones(n, 1, 1, device=self.device)
+        lower, _ = self.net.spec_bounds(C, blo, bhi, lo, hi, both=False)
+        return lower[:, 0].contiguous()
+
+    def search(self, lo, hi, U):
+        """M samples per box from the uniforms U [n, M, d]: (f_hi [n], top [n, k, d])."""
+        n = lo.shape[0]
+        S = torch.empty(n, self.M, self.d, device=self.device)
+        B.bound_bab_samples(self.bab, n, self.M, lo, hi, U, S)
+        vals = torch.empty(n * self.M, 1, device=self.device)
+        B.bound_sample_bounds(self.net.handle, n, self.M, S.view(n * self.M, self.d), out=vals)
+        f_hi = torch.empty(n, device=self.device)
+        top = torch.empty(n, self.k, self.d, device=self.device)
+        B.bound_bab_search_summary(self.bab, n, self.M, vals, S, self.k, f_hi, top)
+        return f_hi, top
+
+    def _u(self, uniforms, tag, shape):
+        return torch.as_tensor(np.asarray(uniforms(tag, shape), np.float32), device=self.device)
+
+    # ------------------------------------------------------------------ the loop
+    def run(self, iters, uniforms, trace=False):
+        """Returns (best value, its sample [d], candidate set dict, per-iteration trace)."""
+        dev = self.device
+        f_hi, top = self.search(self.lo0, self.hi0, self._u(uniforms, "search0", (1, self.M, self.d)))
+        f_lo = self.bound(self.lo0, self.hi0)
+        best = f_hi[:1].clone()
+        ubest = top[0, 0].clone()
+        P = dict(lo=self.lo0, hi=self.hi0, f_lo=f_lo, f_hi=f_hi, top=top)
+        log = []
+        n_keep = torch.zeros(1, dtype=torch.int32, device=dev)
+        for t in range(iters):
+            N = P["lo"].shape[0]
+            if N == 0:
+                break
+            if N > self.max_dom:
+                raise RuntimeError(f"candidate set ({N}) exceeds max_dom ({self.max_dom})")
+            n = min(self.n_pick, N)
+            picked = torch.empty(n, dtype=torch.int32, device=dev)
+            rest = torch.empty(max(N - n, 1), dtype=torch.int32, device=dev)
+            B.bound_bab_pick_out(self.bab, N, P["f_lo"], P["f_hi"], self._u(uniforms, ("pick", t), (N,)),
+                                 self.n_pick, self.eta, self.T, picked, rest)
+            rest = rest[: N - n]
+            pl = P["lo"].index_select(0, picked).contiguous()
+            ph = P["hi"].index_select(0, picked).contiguous()
+            pt = P["top"].index_select(0, picked).contiguous()
+            clo = torch.empty(2 * n, self.d, device=dev)
+            chi = torch.empty(2 * n, self.d, device=dev)
+            dims = torch.empty(n, dtype=torch.int32, device=dev)
+            B.bound_bab_split(self.bab, n, pl, ph, pt, self.k, clo, chi, dims)
+            c_fhi, c_top = self.search(clo, chi, self._u(uniforms, ("search", t), (2 * n, self.M, self.d)))
+            c_flo = self.bound(clo, chi)
+            B.bound_bab_update_best(self.bab, 2 * n, c_fhi, c_top, self.k, best, ubest)
+            keep = torch.empty(2 * n, dtype=torch.int32, device=dev)
+            B.bound_bab_prune(self.bab, 2 * n, c_flo, best, keep, n_keep)
+            nk = int(n_keep.item())
+            keep = keep[:nk]
+            P = dict(lo=torch.cat([P["lo"].index_select(0, rest), clo.index_select(0, keep)]),
+                     hi=torch.cat([P["hi"].index_select(0, rest), chi.index_select(0, keep)]),
+                     f_lo=torch.cat([P["f_lo"].index_select(0, rest), c_flo.index_select(0, keep)]),
+                     f_hi=torch.cat([P["f_hi"].index_select(0, rest), c_fhi.index_select(0, keep)]),
+                     top=torch.cat([P["top"].index_select(0, rest), c_top.index_select(0, keep)]))
+            if trace:
+                log.append(dict(picked=picked.cpu().numpy(), dims=dims.cpu().numpy(),
+                                kept=keep.cpu().numpy(), best=float(best.item()),
+                                size=P["lo"].shape[0]))
+        return float(best.item()), ubest, P, log

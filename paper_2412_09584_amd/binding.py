@@ -22,6 +22,8 @@ BOUND_STOP_RELU, BOUND_STOP_LINEAR = 1, 2
 EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "bound_grad",
             "bound_adam", "bound_sample_bounds", "bound_autotune", "bound_autotune_report", "bound_set_options",
             "bound_profile", "bound_profile_read", "bound_destroy",
+            "bound_bab_init", "bound_bab_pick_out", "bound_bab_samples", "bound_bab_search_summary",
+            "bound_bab_split", "bound_bab_update_best", "bound_bab_prune", "bound_bab_destroy",
             "bound_last_error")
 
 _p = ctypes.c_void_p
@@ -88,9 +90,20 @@ def lib():
         L.bound_profile_read.restype = ctypes.c_int32
         L.bound_destroy.argtypes = [_p]
         L.bound_destroy.restype = None
+        i32, f32 = ctypes.c_int32, ctypes.c_float
+        L.bound_bab_init.argtypes = [i32, i32, i32, ctypes.POINTER(_p)]
+        L.bound_bab_destroy.argtypes = [_p]
+        L.bound_bab_destroy.restype = None
+        L.bound_bab_pick_out.argtypes = [_p, i32, _p, _p, _p, i32, f32, f32, _p, _p, _p]
+        L.bound_bab_samples.argtypes = [_p, i32, i32, _p, _p, _p, _p, _p]
+        L.bound_bab_search_summary.argtypes = [_p, i32, i32, _p, _p, i32, _p, _p, _p]
+        L.bound_bab_split.argtypes = [_p, i32, _p, _p, _p, i32, _p, _p, _p, _p]
+        L.bound_bab_update_best.argtypes = [_p, i32, _p, _p, i32, _p, _p, _p]
+        L.bound_bab_prune.argtypes = [_p, i32, _p, _p, _p, _p, _p]
         L.bound_last_error.restype = ctypes.c_char_p
-        for name in EXPORTED[:-2]:
-            if name not in ("bound_profile_read", "bound_autotune_report"):
+        for name in EXPORTED[:-1]:
+            if name not in ("bound_profile_read", "bound_autotune_report", "bound_destroy",
+                            "bound_bab_destroy"):
                 getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -241,6 +254,50 @@ def bound_profile_read(handle, cap=256):
 def bound_destroy(handle):
     if handle:
         lib().bound_destroy(handle)
+
+
+# ------------------------------------------------------- branch and bound over input boxes
+def bound_bab_init(max_dom, dim, max_samples):
+    h = _p()
+    _check(lib().bound_bab_init(int(max_dom), int(dim), int(max_samples), ctypes.byref(h)))
+    return h
+
+
+def bound_bab_destroy(handle):
+    if handle:
+        lib().bound_bab_destroy(handle)
+
+
+def bound_bab_pick_out(handle, n_dom, f_lo, f_hi, u, n_pick, eta, temperature, picked, rest,
+                       stream=None):
+    _check(lib().bound_bab_pick_out(handle, int(n_dom), _ptr(f_lo), _ptr(f_hi), _ptr(u),
+                                    int(n_pick), float(eta), float(temperature), _ptr(picked),
+                                    _ptr(rest), _stream(stream)))
+
+
+def bound_bab_samples(handle, n, M, lo, hi, U, samples, stream=None):
+    _check(lib().bound_bab_samples(handle, int(n), int(M), _ptr(lo), _ptr(hi), _ptr(U),
+                                   _ptr(samples), _stream(stream)))
+
+
+def bound_bab_search_summary(handle, n, M, values, samples, k, f_hi, top, stream=None):
+    _check(lib().bound_bab_search_summary(handle, int(n), int(M), _ptr(values), _ptr(samples),
+                                          int(k), _ptr(f_hi), _ptr(top), _stream(stream)))
+
+
+def bound_bab_split(handle, n, lo, hi, top, k, child_lo, child_hi, split_dim=None, stream=None):
+    _check(lib().bound_bab_split(handle, int(n), _ptr(lo), _ptr(hi), _ptr(top), int(k),
+                                 _ptr(child_lo), _ptr(child_hi), _ptr(split_dim), _stream(stream)))
+
+
+def bound_bab_update_best(handle, n, f_hi, top, k, best, u_best, stream=None):
+    _check(lib().bound_bab_update_best(handle, int(n), _ptr(f_hi), _ptr(top), int(k), _ptr(best),
+                                       _ptr(u_best), _stream(stream)))
+
+
+def bound_bab_prune(handle, n, f_lo, best, keep, n_keep, stream=None):
+    _check(lib().bound_bab_prune(handle, int(n), _ptr(f_lo), _ptr(best), _ptr(keep), _ptr(n_keep),
+                                 _stream(stream)))
 
 
 def bound_last_error():

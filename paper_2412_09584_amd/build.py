@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbound.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["api.hip", "gemm.hip", "conv.hip", "aux.hip"]
+SOURCES = ["api.hip", "gemm.hip", "conv.hip", "aux.hip", "bab.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions stay off: only scalar / MFMA FP32 is generated

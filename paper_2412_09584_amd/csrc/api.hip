@@ -879,3 +879,8 @@ int32_t bound_profile_read(bound_net *net, int32_t cap, char *names, double *tot
 void bound_destroy(bound_net *net) { delete net; }
 
 }  // extern "C"
+
+namespace bp {
+// status + message for the other translation units of the library (bab.hip)
+bound_status set_error(bound_status s, const std::string &msg) { return fail(s, msg); }
+}  // namespace bp

@@ -55,6 +55,17 @@ def test_error_paths_without_device(L):
     assert "max_save_rows" in B.bound_last_error()
 
 
+def test_bab_error_paths_without_device(L):
+    from paper_2412_09584_amd import binding as B
+    out = ctypes.c_void_p()
+    assert L.bound_bab_init(0, 2, 8, ctypes.byref(out)) == B.BOUND_E_ARG
+    assert L.bound_bab_init(4, 2, 4096, ctypes.byref(out)) == B.BOUND_E_ARG   # > 2048 samples
+    assert L.bound_bab_pick_out(None, 1, None, None, None, 1, 0.5, 0.05, None, None, None) == B.BOUND_E_ARG
+    assert L.bound_bab_split(None, 1, None, None, None, 1, None, None, None, None) == B.BOUND_E_ARG
+    assert L.bound_bab_prune(None, 1, None, None, None, None, None) == B.BOUND_E_ARG
+    assert "bad arguments" in B.bound_last_error()
+
+
 def test_shape_validation_without_device(L):
     from paper_2412_09584_amd import binding as B
     out = ctypes.c_void_p()
