@@ -56,6 +56,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the kernel autotuner")
+    ap.add_argument("--bab-iters", type=int, default=10,
+                    help="iterations of the branch-and-bound planning loop timed after the "
+                         "main measurement (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (a known-size kernel "
                          "for scaling the HBM traffic counters)")
@@ -233,6 +236,9 @@ def main():
         plain = {"value": m / (pms / 1e3), "unit": "subdomains/s", "sample": m,
                  "ms_per_subdomain": pms / m, "batched_speedup": value / (m / (pms / 1e3))}
 
+    # ---- branch-and-bound planning loop (pick-out, split, search, bound, prune)
+    bab = bab_loop(args.bab_iters) if args.bab_iters > 0 else None
+
     # ---- CPU oracle on a bounded sample (rank 0, N=1)
     cpu = None
     if not args.no_cpu:
@@ -248,9 +254,34 @@ def main():
                       "subdomains": n, "rows": R, "split_nnz": sp.nnz, "parallelism": "none"},
            "tflops_step": tflops, "flop_per_subdomain": flop_unit, "wall_s": wall,
            "plain": plain, "roofline": roofline, "kernel_ms_per_step": breakdown,
-           "autotune": _tuned(tune_log),
+           "autotune": _tuned(tune_log), "bab_loop": bab,
            "cpu_baseline": cpu}
     print(json.dumps(rec))
+
+
+def bab_loop(iters, d=16, hidden=(256, 256, 256), n_pick=1024, samples=64):
+    """Throughput of the planning loop (Algorithm 2) on a seeded scalar ReLU objective over
+    [-1, 1]^d: each iteration picks n_pick subdomains, splits them, searches the 2 n_pick
+    children (samples each) and bounds them with full CROWN, then prunes."""
+    import torch
+
+    import workloads as W
+    from paper_2412_09584_amd.bab import BaBPlanner
+    net, lo, hi = W.plan_objective(d=d, hidden=hidden)
+    pl = BaBPlanner(net, lo, hi, n_pick=n_pick, samples=samples)
+    uni = W.plan_uniforms()
+    pl.run(2, uni)                                   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best, _, P, log = pl.run(iters, uni, trace=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    bounded = sum(2 * len(e["picked"]) for e in log)          # children searched and bounded
+    return {"objective": f"MLP {d}-{'-'.join(map(str, hidden))}-1 over [-1,1]^{d}",
+            "n_pick": n_pick, "samples": samples, "iters": len(log),
+            "ms_per_iter": 1e3 * dt / max(len(log), 1),
+            "subdomains_bounded_per_s": bounded / dt if log else None,
+            "best": best, "candidates": int(P["lo"].shape[0])}
 
 
 def _tuned(log):
