@@ -89,7 +89,7 @@ typedef struct {
  *           constraints sign * z_j >= 0 (j a global ReLU index: relu_off(m) + neuron);
  *           each neuron at most once per instance.  A split clamps l or u to 0; an
  *           instance whose clamped box is empty gets lower = +inf (upper = -inf).
- *           All three NULL and nnz = 0 when there are no splits.
+ *           All three NULL and nnz = 0 when there are no splits; nnz < 2^24.
  * beta      [nnz, rows] Lagrange multipliers (>= 0) of the splits, or NULL (= 0):
  *           each adds -beta * sign to the coefficient of its split neuron.
  * x_lo,x_hi [n_inst, d_0] the input box.  NULL: do not concretise; the pass then

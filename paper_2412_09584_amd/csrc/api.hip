@@ -54,6 +54,10 @@ struct bound_net {
     float *acc_s = nullptr, *acc_mag = nullptr, *acc_low = nullptr;
     Relax *tab = nullptr;
     int32_t *slot = nullptr;         // compact save slots of the unstable neurons per bound row
+    int32_t *slot_inv = nullptr;     // slot -> internal neuron index, per bound row
+    int32_t *slot_count = nullptr;   // unstable neurons per (bound row, ReLU layer)
+    int32_t *srow = nullptr;         // bound row of each instance
+    float *gcbuf = nullptr;          // per-img alpha-gradient contributions of one layer
     int32_t *infeas = nullptr;
     float *cen = nullptr, *rad = nullptr;
     float *save = nullptr;
@@ -61,7 +65,7 @@ struct bound_net {
     float *stop_cen = nullptr, *stop_rad = nullptr;  // early-stop node box [max_inst][max relu width]
     float *zeros = nullptr;                         // [max channels]: "no bias" at a linear stop
     long max_relu_d = 0, max_chan = 0;
-    int32_t *sp = nullptr;           // 3 x sp_cap: instance, layer, internal index
+    int32_t *sp = nullptr;           // 4 x sp_cap: instance, layer, internal index, repeated entry
     int8_t *sp_sign = nullptr;
     long sp_cap = 0;
     int options = 0;
@@ -268,7 +272,7 @@ bound_status ensure_split_cap(bound_net *net, long nnz, hipStream_t st) {
     const long cap = roundup(nnz, 4096);
     int32_t *sp;
     int8_t *sg;
-    if (!net->alloc(&sp, 3 * cap) || !net->alloc(&sg, cap))
+    if (!net->alloc(&sp, 4 * cap) || !net->alloc(&sg, cap))
         return fail(BOUND_E_NOMEM, "split scratch");
     net->sp = sp;
     net->sp_sign = sg;
@@ -376,6 +380,10 @@ bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max
               net->alloc(&net->acc_low, max_rows) &&
               net->alloc(&net->tab, (long)max_inst * (net->n_relu > 0 ? net->n_relu : 1)) &&
               net->alloc(&net->slot, (long)max_inst * (net->n_relu > 0 ? net->n_relu : 1)) &&
+              net->alloc(&net->slot_inv, (long)max_inst * (net->n_relu > 0 ? net->n_relu : 1)) &&
+              net->alloc(&net->slot_count, (long)max_inst * MAX_RELU_LAYERS) &&
+              net->alloc(&net->srow, (long)max_inst) &&
+              net->alloc(&net->gcbuf, max_save_rows * (net->max_relu_d > 0 ? net->max_relu_d : 1)) &&
               net->alloc(&net->infeas, max_inst) && net->alloc(&net->cen, (long)max_inst * net->d[0]) &&
               net->alloc(&net->rad, (long)max_inst * net->d[0]) &&
               net->alloc(&net->sbar, max_save_rows > 0 ? max_save_rows : 1) &&
@@ -432,7 +440,8 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
     const bool save = (P->flags & BOUND_SAVE_FOR_GRAD) != 0;
     const bool slack = (P->flags & BOUND_NO_SLACK) == 0;
     const int nnz = P->nnz;
-    if (nnz < 0) return fail(BOUND_E_ARG, "nnz < 0");
+    if (nnz < 0 || nnz >= (1 << 24))    // split entries are numbered exactly in FP32
+        return fail(BOUND_E_ARG, "nnz must be in [0, 2^24)");
     if (nnz > 0 && (!P->split_off || !P->split_idx || !P->split_sign))
         return fail(BOUND_E_ARG, "split arrays required when nnz > 0");
     if (P->beta && nnz == 0) return fail(BOUND_E_ARG, "beta given without splits");
@@ -471,13 +480,14 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
         if (s != BOUND_OK) return s;
     }
     int32_t *sp_inst = net->sp, *sp_layer = net->sp + net->sp_cap, *sp_j = net->sp + 2 * net->sp_cap;
+    int32_t *sp_dup = net->sp + 3 * net->sp_cap;
     const long d0 = net->d[0];
     {
     ProfScope prof_prep(net, st, "prep");
     if (used > 0) {
         HIPCHK(launch_prep_tables(net->ns, used, P->n_inst, net->n_relu, P->lo, P->hi, P->bound_of,
                                   P->alpha, net->tab, net->infeas, P->n_bounds, net->slot,
-                                  net->max_inst, st));
+                                  net->slot_inv, net->slot_count, net->srow, net->max_inst, st));
     } else {
         HIPCHK(launch_fill((float *)net->infeas, P->n_inst, 0.f, st));
     }
@@ -488,7 +498,7 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
                                         net->stop_rad, st));
         HIPCHK(launch_prep_splits(net->ns, used, P->n_inst, net->n_relu, P->lo, P->hi, P->bound_of,
                                   P->split_off, P->split_idx, P->split_sign, net->tab, net->infeas,
-                                  sp_inst, sp_layer, sp_j, P->n_bounds, sl - 1,
+                                  sp_inst, sp_layer, sp_j, sp_dup, P->n_bounds, sl - 1,
                                   smode == BOUND_STOP_RELU, sl > 0 ? net->stop_cen : nullptr,
                                   sl > 0 ? net->stop_rad : nullptr, st));
     } else if (sl > 0) {
@@ -655,6 +665,7 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
     }
     float *cur = net->buf[0], *nxt = net->buf[1];
     int32_t *sp_inst = net->sp, *sp_layer = net->sp + net->sp_cap, *sp_j = net->sp + 2 * net->sp_cap;
+    int32_t *sp_dup = net->sp + 3 * net->sp_cap;
     const int sl = net->s_stop, smode = net->s_mode;
     int m0 = 1;  // first adjoint product
     if (smode == BOUND_STOP_LINEAR) {
@@ -666,8 +677,10 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
                                       net->save + net->s_off[sl + 1], net->stop_cen, net->stop_rad,
                                       grad_lower, net->infeas, net->sbar,
                                       net->tab + net->relu_off(sl), net->n_relu,
-                                      sl + 1 < k ? cur : nullptr, grad_alpha, net->n_relu,
-                                      net->relu_off(sl), S.C, S.HW, st));
+                                      sl + 1 < k ? cur : nullptr, net->gcbuf, S.C, S.HW, st));
+        HIPCHK(launch_alpha_grad(net->s_n_inst, rows, Ds, S, sl - 1, net->n_relu, net->srow,
+                                 net->slot_count, net->slot_inv, net->tab, net->gcbuf, grad_alpha,
+                                 net->n_relu, net->relu_off(sl), st));
         if (grad_beta && net->s_nnz > 0)
             HIPCHK(launch_beta_grad_stop(net->s_nnz, rows, sl - 1, Ds, sp_inst, sp_layer, sp_j,
                                          net->sp_sign, net->save + net->s_lam_off, net->stop_cen,
@@ -695,9 +708,8 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
         ap.tab = net->tab + net->relu_off(m);
         ap.tab_ld = net->n_relu;
         ap.gout = m + 1 < k ? nxt : nullptr;
-        ap.galpha = grad_alpha;
-        ap.ga_ld = net->n_relu;
-        ap.ga_off = net->relu_off(m);
+        ap.gc = net->gcbuf;
+        ap.gbeta = grad_beta && net->s_nnz > 0 ? grad_beta : nullptr;
         ap.hw = li.L.out_h * li.L.out_w;
         ap.rpi = rows;
         {
@@ -708,6 +720,13 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
             });
             if (bs != BOUND_OK) return bs;
         }
+        {
+            ProfScope ps(net, st, "alpha_grad");
+            HIPCHK(launch_alpha_grad(net->s_n_inst, rows, net->d[m], net->ns.l[m - 1], m - 1,
+                                     net->n_relu, net->srow, net->slot_count, net->slot_inv,
+                                     net->tab, net->gcbuf, grad_alpha, net->n_relu,
+                                     net->relu_off(m), st));
+        }
         if (grad_beta && net->s_nnz > 0) {
             BetaGradLayer bl{};
             bl.kind = li.L.kind; bl.W = li.L.weight; bl.bias = li.L.bias;
@@ -716,7 +735,7 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
             bl.kh = li.L.kh; bl.kw = li.L.kw; bl.stride = li.L.stride; bl.pad = li.L.pad;
             bl.din = li.din; bl.dout = li.dout;
             ProfScope ps(net, st, "beta_grad");
-            HIPCHK(launch_beta_grad(net->s_nnz, rows, m - 1, bl, sp_inst, sp_layer, sp_j, net->sp_sign,
+            HIPCHK(launch_beta_grad(net->s_nnz, rows, m - 1, bl, sp_inst, sp_layer, sp_j, sp_dup, net->sp_sign,
                                     cur, net->sbar, net->infeas, grad_beta, st));
         }
         float *t = cur; cur = nxt; nxt = t;

@@ -65,7 +65,8 @@ __device__ inline Relax relax_of(float l, float u, float a, int k) {
 // Block (row r, layer m); each thread counts a contiguous segment, then the segment
 // bases come from a scan of the 256 counts.
 __global__ void k_prep_slots(const NetShapes ns, long n_relu, const float *lo, const float *hi,
-                             const int32_t *bound_of, int n_bounds, int per_inst, int32_t *slot) {
+                             const int32_t *bound_of, int n_bounds, int per_inst, int32_t *slot,
+                             int32_t *inv, int32_t *count) {
     __shared__ int cnt[256];
     const long r = blockIdx.x;
     const LayerShape &L = ns.l[blockIdx.y];
@@ -87,14 +88,43 @@ __global__ void k_prep_slots(const NetShapes ns, long n_relu, const float *lo, c
             cnt[t] = run;
             run += v;
         }
+        count[r * MAX_RELU_LAYERS + blockIdx.y] = run;
     }
     __syncthreads();
     int k = cnt[threadIdx.x];
     int32_t *out = slot + r * n_relu + L.off;
+    int32_t *back = inv + r * n_relu + L.off;     // slot -> internal index
     for (long j = j0; j < j1; ++j) {
         const long jn = to_cmajor(j, L.C, L.HW);
         const bool un = !(lr[jn] >= 0.f) && !(hr[jn] <= 0.f);
+        if (un) back[k] = (int32_t)j;
         out[j] = un ? k++ : -1;
+    }
+}
+
+// alpha-gradient of ReLU layer L: the adjoint product left each img's contributions
+// [G >= 0] G Lambda_bar at the compact slots of its unstable neurons (gc, row stride D);
+// one block per instance walks its slots, sums the instance's rows and stores the
+// result at the neuron's C-major index.  Slots of split neurons (w = 0) are skipped.
+__global__ void k_alpha_grad(int rows, long D, const LayerShape L, int layer, long n_relu,
+                             const int32_t *srow, const int32_t *count, const int32_t *inv,
+                             const Relax *tab, const float *gc, float *galpha, long ga_ld,
+                             long ga_off) {
+    const long inst = blockIdx.x;
+    const long r = srow[inst];
+    const int cnt = count[r * MAX_RELU_LAYERS + layer];
+    const int32_t *iv = inv + r * n_relu + L.off;
+    const Relax *tb = tab + inst * n_relu + L.off;
+    const float *g = gc + inst * rows * D;
+    float *ga = galpha + inst * ga_ld + ga_off;
+    const float *w = (const float *)tb + 3;          // the records' w components
+    for (int k = threadIdx.x; k < cnt; k += TPB) {
+        const int j = iv[k];
+        float acc = 0.f;
+        for (int q = 0; q < rows; ++q) acc += g[q * D + k];
+        if (w[4 * (long)j] <= 0.f) continue;                    // split neuron
+        const int c = j % L.C, p = j / L.C;
+        ga[(long)c * L.HW + p] = acc;
     }
 }
 
@@ -110,11 +140,14 @@ constexpr int PREP_SPAN = 2048;
 __global__ void k_prep_tables(const NetShapes ns, int used, long T, long n_relu,
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const float *alpha, Relax *tab, int32_t *infeas, long total,
-                              int n_bounds, const int32_t *slot, int per_inst) {
+                              int n_bounds, const int32_t *slot, int per_inst, int32_t *srow) {
     const long e0 = (long)blockIdx.x * PREP_SPAN;
     for (long e = e0 + threadIdx.x; e < e0 + PREP_SPAN && e < total; e += TPB) {
         const long inst = e / T, jg = e - inst * T;
-        if (jg == 0) infeas[inst] = 0;
+        if (jg == 0) {
+            infeas[inst] = 0;
+            srow[inst] = per_inst ? (int32_t)inst : (int32_t)bound_row(bound_of, inst, n_bounds);
+        }
         const int m = layer_of(ns, used, jg);
         const LayerShape &L = ns.l[m];
         const long j = jg - L.off;
@@ -131,8 +164,8 @@ __global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, 
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const int32_t *off, const int32_t *idx, const int8_t *sign,
                               Relax *tab, int32_t *infeas, int32_t *sp_inst, int32_t *sp_layer,
-                              int32_t *sp_j, int n_bounds, int stop_m, int stop_relu,
-                              float *stop_cen, float *stop_rad) {
+                              int32_t *sp_j, int32_t *sp_dup, int n_bounds, int stop_m,
+                              int stop_relu, float *stop_cen, float *stop_rad) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_inst) return;
     const long b = bound_row(bound_of, i, n_bounds);
@@ -142,20 +175,27 @@ __global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, 
         sp_inst[q] = i;
         sp_layer[q] = -1;
         sp_j[q] = 0;
+        sp_dup[q] = 0;
         if (g < 0 || g >= T) continue;  // not a layer this pass relaxes
         const int m = layer_of(ns, used, g);
         const LayerShape &L = ns.l[m];
         const long jn = g - L.off;
         float l = lo[b * n_relu + g], u = hi[b * n_relu + g];
+        int first = q;
         for (int q2 = q0; q2 < q1; ++q2) {
             if (idx[q2] != g) continue;
+            if (q2 < first) first = q2;
             if (sign[q2] > 0) l = fmaxf(l, 0.f);
             else u = fminf(u, 0.f);
         }
         if (l > u) infeas[i] = 1;
         const long j = to_internal(jn, L.C, L.HW);
-        tab[(long)i * n_relu + L.off + j] = l >= 0.f ? make_float4(1.f, 1.f, 0.f, 0.f)
-                                                     : make_float4(0.f, 0.f, 0.f, 0.f);
+        // a split neuron's record carries w = -(q + 1), q its first entry in the
+        // instance's list: the adjoint epilogue writes that entry's beta-gradient
+        const float wq = -(float)(first + 1);
+        tab[(long)i * n_relu + L.off + j] = l >= 0.f ? make_float4(1.f, 1.f, 0.f, wq)
+                                                     : make_float4(0.f, 0.f, 0.f, wq);
+        sp_dup[q] = first != q;   // a repeated entry: k_beta_grad computes it
         if (m == stop_m && stop_cen) {  // the early-stop node's box sees the clamp too
             const float a = stop_relu ? fmaxf(l, 0.f) : l, c = stop_relu ? fmaxf(u, 0.f) : u;
             stop_cen[(long)i * L.d + j] = 0.5f * (a + c);
@@ -353,13 +393,14 @@ __global__ void k_adj_init(long n_img, int rows, long d0, const float *gl, const
 
 __global__ void k_beta_grad(int nnz, int rows, int layer, const BetaGradLayer L,
                             const int32_t *sp_inst, const int32_t *sp_layer, const int32_t *sp_j,
-                            const int8_t *sign, const float *gbar_m, const float *sbar,
-                            float *gbeta) {
+                            const int32_t *sp_dup, const int8_t *sign, const float *gbar_m,
+                            const float *sbar, float *gbeta) {
     const long wv = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (wv >= (long)nnz * rows) return;
     const int q = (int)(wv / rows), r = (int)(wv - (long)q * rows);
-    if (sp_layer[q] != layer) return;
+    // first entries of a neuron get their gradient in the adjoint product's epilogue
+    if (sp_layer[q] != layer || !sp_dup[q]) return;
     const long img = (long)sp_inst[q] * rows + r;
     const float *gb = gbar_m + img * L.din;
     const long j = sp_j[q];
@@ -423,7 +464,7 @@ __global__ void k_box_conc(long img0, int rpi, long D, const float *lam, const f
 __global__ void k_adj_stop_linear(long n_img, int rows, long D, const float *lam, const float *g,
                                   const float *cen, const float *rad, const float *gl,
                                   const int32_t *infeas, float *sbar, const Relax *tab, long tab_ld,
-                                  float *gout, float *galpha, long ga_ld, long ga_off, int C, int HW) {
+                                  float *gout, float *gc, int C, int HW) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_img * D) return;
     const long img = e / D, j = e - img * D;
@@ -436,12 +477,9 @@ __global__ void k_adj_stop_linear(long n_img, int rows, long D, const float *lam
     const Relax t = tab[inst * tab_ld + j];
     // saved coefficients exist at the unstable neurons only (slot w - 1); elsewhere the
     // record has equal slopes and no intercept, so the sign of G does not matter
-    const float gv = t.w != 0.f ? g[img * D + (int)t.w - 1] : 0.f;
+    const float gv = t.w > 0.f ? g[img * D + (int)t.w - 1] : 0.f;
     if (gout) gout[e] = v * (gv >= 0.f ? t.x : t.y) + (gv < 0.f ? sb * t.z : 0.f);
-    if (t.w != 0.f && gv >= 0.f) {
-        const float c = gv * v;
-        if (c != 0.f) atomicAdd(galpha + inst * ga_ld + ga_off + to_cmajor(j, C, HW), c);
-    }
+    if (t.w > 0.f) gc[img * D + (int)t.w - 1] = gv >= 0.f ? gv * v : 0.f;   // see k_alpha_grad
 }
 
 __global__ void k_beta_grad_stop(int nnz, int rows, int layer, long D, const int32_t *sp_inst,
@@ -584,18 +622,30 @@ hipError_t launch_fill(float *p, long n, float v, hipStream_t st) {
 hipError_t launch_prep_tables(const NetShapes &ns, int used, int n_inst, long n_relu,
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const float *alpha, Relax *tab, int32_t *infeas, int n_bounds,
-                              int32_t *slot, int max_rows, hipStream_t st) {
+                              int32_t *slot, int32_t *slot_inv, int32_t *slot_count,
+                              int32_t *srow, int max_rows, hipStream_t st) {
     const long T = used > 0 ? ns.l[used - 1].off + ns.l[used - 1].d : 0;
     if (T == 0) return launch_fill((float *)infeas, n_inst, 0.f, st);  // 0.0f is all-zero bits
     // slots per bound row when the rows fit the slot table, else per instance
     const bool per_inst = bound_of == nullptr || n_bounds > max_rows;
     const int rows = per_inst ? n_inst : n_bounds;
     hipLaunchKernelGGL(k_prep_slots, dim3((unsigned)rows, (unsigned)used), dim3(256), 0, st, ns,
-                       n_relu, lo, hi, bound_of, n_bounds, per_inst ? 1 : 0, slot);
+                       n_relu, lo, hi, bound_of, n_bounds, per_inst ? 1 : 0, slot, slot_inv,
+                       slot_count);
     const long total = T * n_inst;
     hipLaunchKernelGGL(k_prep_tables, dim3(blocks_for(total, PREP_SPAN)), dim3(TPB), 0, st, ns, used, T,
                        n_relu, lo, hi, bound_of, alpha, tab, infeas, total, n_bounds, slot,
-                       per_inst ? 1 : 0);
+                       per_inst ? 1 : 0, srow);
+    return hipGetLastError();
+}
+
+hipError_t launch_alpha_grad(int n_inst, int rows, long D, const LayerShape &L, int layer,
+                             long n_relu, const int32_t *srow, const int32_t *slot_count,
+                             const int32_t *slot_inv, const Relax *tab, const float *gc,
+                             float *galpha, long ga_ld, long ga_off, hipStream_t st) {
+    if (n_inst <= 0 || D <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_alpha_grad, dim3((unsigned)n_inst), dim3(TPB), 0, st, rows, D, L, layer,
+                       n_relu, srow, slot_count, slot_inv, tab, gc, galpha, ga_ld, ga_off);
     return hipGetLastError();
 }
 
@@ -603,12 +653,12 @@ hipError_t launch_prep_splits(const NetShapes &ns, int used, int n_inst, long n_
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const int32_t *off, const int32_t *idx, const int8_t *sign,
                               Relax *tab, int32_t *infeas, int32_t *sp_inst, int32_t *sp_layer,
-                              int32_t *sp_j, int n_bounds, int stop_m, int stop_relu,
-                              float *stop_cen, float *stop_rad, hipStream_t st) {
+                              int32_t *sp_j, int32_t *sp_dup, int n_bounds, int stop_m,
+                              int stop_relu, float *stop_cen, float *stop_rad, hipStream_t st) {
     const long T = used > 0 ? ns.l[used - 1].off + ns.l[used - 1].d : 0;
     hipLaunchKernelGGL(k_prep_splits, dim3(blocks_for(n_inst, 64)), dim3(64), 0, st, ns, used, T,
                        n_inst, n_relu, lo, hi, bound_of, off, idx, sign, tab, infeas, sp_inst,
-                       sp_layer, sp_j, n_bounds, stop_m, stop_relu, stop_cen, stop_rad);
+                       sp_layer, sp_j, sp_dup, n_bounds, stop_m, stop_relu, stop_cen, stop_rad);
     return hipGetLastError();
 }
 
@@ -671,12 +721,12 @@ hipError_t launch_adj_init(long n_img, int rows, long d0, const float *gl, const
 
 hipError_t launch_beta_grad(int nnz, int rows, int layer, const BetaGradLayer &L,
                             const int32_t *sp_inst, const int32_t *sp_layer, const int32_t *sp_j,
-                            const int8_t *sign, const float *gbar_m, const float *sbar,
-                            const int32_t *, float *gbeta, hipStream_t st) {
+                            const int32_t *sp_dup, const int8_t *sign, const float *gbar_m,
+                            const float *sbar, const int32_t *, float *gbeta, hipStream_t st) {
     const long waves = (long)nnz * rows;
     if (waves == 0) return hipSuccess;
     hipLaunchKernelGGL(k_beta_grad, dim3(blocks_for(waves * 64)), dim3(TPB), 0, st, nnz, rows,
-                       layer, L, sp_inst, sp_layer, sp_j, sign, gbar_m, sbar, gbeta);
+                       layer, L, sp_inst, sp_layer, sp_j, sp_dup, sign, gbar_m, sbar, gbeta);
     return hipGetLastError();
 }
 
@@ -700,12 +750,10 @@ hipError_t launch_box_conc(long img0, long n_img, int rpi, long D, const float *
 hipError_t launch_adj_stop_linear(long n_img, int rows, long D, const float *lam, const float *g,
                                   const float *cen, const float *rad, const float *gl,
                                   const int32_t *infeas, float *sbar, const Relax *tab, long tab_ld,
-                                  float *gout, float *galpha, long ga_ld, long ga_off, int C, int HW,
-                                  hipStream_t st) {
+                                  float *gout, float *gc, int C, int HW, hipStream_t st) {
     const long total = n_img * D;
     hipLaunchKernelGGL(k_adj_stop_linear, dim3(blocks_for(total)), dim3(TPB), 0, st, n_img, rows, D,
-                       lam, g, cen, rad, gl, infeas, sbar, tab, tab_ld, gout, galpha, ga_ld, ga_off,
-                       C, HW);
+                       lam, g, cen, rad, gl, infeas, sbar, tab, tab_ld, gout, gc, C, HW);
     return hipGetLastError();
 }
 

@@ -30,9 +30,10 @@ struct GeomSet {
 };
 
 // Per-neuron relaxation record (Lemma 1) for one instance:
-// x = lower slope, y = upper slope, z = upper intercept; w = 0 for a stable (or split)
-// neuron, else k + 1 with k the neuron's slot in the compact rows of saved coefficients
-// (alpha free).  Records with w = 0 have x = y and z = 0.
+// x = lower slope, y = upper slope, z = upper intercept; w = 0 for a stable neuron,
+// -(q + 1) for a split neuron whose first entry in the instance's split list is q, and
+// k + 1 for an unstable one, k its slot in the compact rows of saved coefficients (alpha
+// free).  Records with w <= 0 have x = y and z = 0.
 typedef float4 Relax;
 
 // ----- epilogue parameter blocks -----------------------------------------------------
@@ -70,9 +71,8 @@ struct AdjParams {         // Lambda_bar_m = G_bar_m W_m^T + s_bar b_m  -> G_bar
     const Relax *tab;
     long tab_ld;
     float *gout;           // G_bar_{m+1} (nullable at the last layer)
-    float *galpha;         // [n_inst][n_relu] C-major
-    long ga_ld;
-    long ga_off;
+    float *gc;             // [img][D] compact: alpha-gradient contributions (k_alpha_grad)
+    float *gbeta;          // [nnz][rpi] beta-gradient of first split entries (nullable)
     int hw;                // H*W of layer m (C-major index)
     int rpi;
 };
@@ -143,14 +143,20 @@ hipError_t launch_fill(float *p, long n, float v, hipStream_t st);
 hipError_t launch_prep_tables(const NetShapes &ns, int n_layers_used, int n_inst,
                               long n_relu, const float *lo, const float *hi,
                               const int32_t *bound_of, const float *alpha, Relax *tab,
-                              int32_t *infeas, int n_bounds, int32_t *slot, int max_rows,
-                              hipStream_t st);
+                              int32_t *infeas, int n_bounds, int32_t *slot, int32_t *slot_inv,
+                              int32_t *slot_count, int32_t *srow, int max_rows, hipStream_t st);
+hipError_t launch_alpha_grad(int n_inst, int rows, long D, const LayerShape &L, int layer,
+                             long n_relu, const int32_t *srow, const int32_t *slot_count,
+                             const int32_t *slot_inv, const Relax *tab, const float *gc,
+                             float *galpha, long ga_ld, long ga_off, hipStream_t st);
+constexpr int MAX_RELU_LAYERS = 16;
 hipError_t launch_prep_splits(const NetShapes &ns, int n_layers_used, int n_inst, long n_relu,
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const int32_t *off, const int32_t *idx, const int8_t *sign,
                               Relax *tab, int32_t *infeas, int32_t *sp_inst,
-                              int32_t *sp_layer, int32_t *sp_j, int n_bounds, int stop_m,
-                              int stop_relu, float *stop_cen, float *stop_rad, hipStream_t st);
+                              int32_t *sp_layer, int32_t *sp_j, int32_t *sp_dup, int n_bounds,
+                              int stop_m, int stop_relu, float *stop_cen, float *stop_rad,
+                              hipStream_t st);
 hipError_t launch_prep_stop_box(int n_inst, const LayerShape &L, long n_relu, const float *lo,
                                 const float *hi, const int32_t *bound_of, int n_bounds, bool relu,
                                 float *cen, float *rad, hipStream_t st);
@@ -159,8 +165,7 @@ hipError_t launch_box_conc(long img0, long n_img, int rpi, long D, const float *
 hipError_t launch_adj_stop_linear(long n_img, int rows, long D, const float *lam, const float *g,
                                   const float *cen, const float *rad, const float *gl,
                                   const int32_t *infeas, float *sbar, const Relax *tab, long tab_ld,
-                                  float *gout, float *galpha, long ga_ld, long ga_off, int C, int HW,
-                                  hipStream_t st);
+                                  float *gout, float *gc, int C, int HW, hipStream_t st);
 hipError_t launch_beta_grad_stop(int nnz, int rows, int layer, long D, const int32_t *sp_inst,
                                  const int32_t *sp_layer, const int32_t *sp_j, const int8_t *sign,
                                  const float *lam, const float *cen, const float *rad,
@@ -218,9 +223,9 @@ struct BetaGradLayer {         // layer m, for the split-multiplier gradient
 };
 hipError_t launch_beta_grad(int nnz, int rows, int layer, const BetaGradLayer &L,
                             const int32_t *sp_inst, const int32_t *sp_layer,
-                            const int32_t *sp_j, const int8_t *sign, const float *gbar_m,
-                            const float *gl, const int32_t *infeas, float *gbeta,
-                            hipStream_t st);
+                            const int32_t *sp_j, const int32_t *sp_dup, const int8_t *sign,
+                            const float *gbar_m, const float *gl, const int32_t *infeas,
+                            float *gbeta, hipStream_t st);
 hipError_t launch_to_internal(long n_img, int C, int HW, const float *x, float *y, hipStream_t st);
 hipError_t launch_sample_minmax(long n_sub, int per_sub, long D, int C, int HW, float *z,
                                 float *lo, float *hi, long ld, bool relu, float *out, hipStream_t st);

@@ -99,7 +99,7 @@ struct EpiRelax {
         r0 += bt + off;
         r1 += fabsf(bt) + fabsf(off);
         rc.out[j] = lam;
-        if (rc.save && t.w != 0.f) rc.save[(int)t.w - 1] = g;   // unstable: compact slot
+        if (rc.save && t.w > 0.f) rc.save[(int)t.w - 1] = g;    // unstable: compact slot
     }
 };
 
@@ -132,12 +132,12 @@ struct EpiAdj {
     AdjParams p;
     static constexpr int NRED = 0;
     struct Pre { Relax t; float g; };
-    struct Row { const Relax *tb; const float *gs; float *go; float *ga; float sb; };
+    struct Row { const Relax *tb; const float *gs; float *go; float *gc; float *gb; float sb; };
     __device__ Row row(int img) const {
         const long inst = ldiv_by(img, p.rpi, 1.0f / (float)p.rpi);
         const long o = (long)img * p.D;
         return Row{p.tab + inst * p.tab_ld, p.gsave + o, p.gout ? p.gout + o : nullptr,
-                   p.galpha + inst * p.ga_ld + p.ga_off, p.sbar[img]};
+                   p.gc + o, p.gbeta ? p.gbeta + (img - inst * p.rpi) : nullptr, p.sbar[img]};
     }
     __device__ float colv(int n) const { return p.bias[n]; }
     __device__ float *red0() const { return nullptr; }
@@ -147,7 +147,7 @@ struct EpiAdj {
     // and z = 0, so the sign of G does not matter.
     __device__ Pre pre(const Row &rc, int j) const { return Pre{rc.tb[j], 0.f}; }
     __device__ void pre2(const Row &rc, Pre &q) const {
-        if (q.t.w != 0.f) q.g = rc.gs[(int)q.t.w - 1];
+        if (q.t.w > 0.f) q.g = rc.gs[(int)q.t.w - 1];
     }
     __device__ void post(const Pre &q, const Row &rc, int dpix, int n, int j, float bcol, float acc,
                          float &, float &) const {
@@ -155,10 +155,12 @@ struct EpiAdj {
         const float g = q.g;                          // G_{m+1}[img, j]
         const Relax &t = q.t;
         if (rc.go) rc.go[j] = v * (g >= 0.f ? t.x : t.y) + (g < 0.f ? rc.sb * t.z : 0.f);
-        if (t.w != 0.f && g >= 0.f) {
-            const float c = g * v;
-            if (c != 0.f) atomicAdd(rc.ga + n * p.hw + dpix, c);
-        }
+        // alpha-gradient contribution of this row at the neuron's slot (summed over the
+        // instance's rows by k_alpha_grad)
+        if (t.w > 0.f) rc.gc[(int)t.w - 1] = g >= 0.f ? g * v : 0.f;
+        // split neuron (first entry q of the instance's list): d lower / d beta_{q,r} =
+        // -sign * Lambda_bar; the active split's record has slope 1, the inactive one 0
+        if (t.w < 0.f && rc.gb) rc.gb[(long)(-(int)t.w - 1) * p.rpi] = t.x > 0.5f ? -v : v;
     }
 };
 
