@@ -69,8 +69,19 @@ def _dispatches(path: str):
     return list(out.values())
 
 
-def _match(ds, kernel: str, grid: int):
-    return [d for d in ds if _short(d["name"]) == kernel and (grid <= 0 or d["grid"] == grid)]
+def _match(ds, kernel: str, grid: int, stride: int = 1, offset: int = 0):
+    """Dispatches of one kernel and grid.  Where a step launches the same kernel and grid
+    `stride` times (different layers of one shape class), keep the `offset`-th launch of
+    each step, counting the steps back from the last dispatch."""
+    sel = [d for d in ds if _short(d["name"]) == kernel and (grid <= 0 or d["grid"] == grid)]
+    last = len(sel) - stride + offset
+    return [d for p, d in enumerate(sel) if p <= last and (last - p) % stride == 0]
+
+
+def _which(a) -> str:
+    if a.stride <= 1:
+        return ""
+    return f", launch {a.offset + 1} of the {a.stride} of this kernel and grid per step"
 
 
 def report_trace(a) -> str:
@@ -81,16 +92,16 @@ def report_trace(a) -> str:
         t[0] += d["ns"]
         t[1] += 1
     allns = sum(v[0] for v in tot.values()) or 1
-    sel = _match(ds, a.kernel, a.grid)[-a.last:]
+    sel = _match(ds, a.kernel, a.grid, a.stride, a.offset)[-a.last:]
     avg = sum(d["ns"] for d in sel) / max(len(sel), 1) / 1e6
     lines = [f"# {a.title}", "", "Command (TMPDIR=/tmp; <repo> is the repository root):", "",
              f"    {a.cmd}", "",
-             f"Dominant kernel `{a.kernel}` (grid {a.grid}): average {avg:.4f} ms over its "
+             f"Kernel `{a.kernel}` (grid {a.grid}{_which(a)}): average {avg:.4f} ms over its "
              f"last {len(sel)} dispatches (the timed steps).", "",
              "| total ms | calls | avg us | % | kernel |", "|---:|---:|---:|---:|---|"]
     for k, (ns, n) in sorted(tot.items(), key=lambda kv: -kv[1][0])[: a.top]:
         lines.append(f"| {ns / 1e6:.2f} | {n} | {ns / n / 1e3:.1f} | {100 * ns / allns:.1f} | `{k[:90]}` |")
-    lines += ["", f"<!-- trace: {json.dumps({'kernel': a.kernel, 'grid': a.grid, 'avg_ms': avg, 'n': len(sel)})} -->"]
+    lines += ["", f"<!-- trace: {json.dumps({'kernel': a.kernel, 'grid': a.grid, 'stride': a.stride, 'offset': a.offset, 'avg_ms': avg, 'n': len(sel)})} -->"]
     return "\n".join(lines) + "\n"
 
 
@@ -106,11 +117,13 @@ def report_traffic(a) -> str:
 
     fc, wc = calib(fd), calib(wd)
     fs, ws = a.copy_bytes / fc, a.copy_bytes / wc
-    fsel, wsel = _match(fd, a.kernel, a.grid), _match(wd, a.kernel, a.grid)
+    fsel = _match(fd, a.kernel, a.grid, a.stride, a.offset)
+    wsel = _match(wd, a.kernel, a.grid, a.stride, a.offset)
     if not fsel or not wsel:
         raise SystemExit(f"kernel {a.kernel!r} grid {a.grid} not found")
     fb, wb = fsel[-1]["value"] * 1024.0, wsel[-1]["value"] * 1024.0
-    rec = {"label": a.label, "kernel": a.kernel, "grid": a.grid, "fetch_bytes": fb * fs,
+    rec = {"label": a.label, "kernel": a.kernel, "grid": a.grid, "stride": a.stride,
+           "offset": a.offset, "fetch_bytes": fb * fs,
            "write_bytes": wb * ws, "fetch_scale": fs, "write_scale": ws,
            "bytes": fb * fs + wb * ws, "src_sha256": source_hash()}
     lines = [f"# {a.title}", "", "Commands (one counter per run; TMPDIR=/tmp; <repo> is the "
@@ -119,7 +132,7 @@ def report_traffic(a) -> str:
     lines += ["", f"Calibration: the {a.copy_bytes / 2**30:.0f} GiB device copy in the same run reads "
               f"FETCH_SIZE = {fc / 2**30:.3f} GiB and WRITE_SIZE = {wc / 2**30:.3f} GiB, so the "
               f"counters are scaled by {fs:.3f} (fetch) and {ws:.3f} (write).", "",
-              f"Kernel `{a.kernel}` (grid {a.grid}, `{a.label}`), last dispatch:", "",
+              f"Kernel `{a.kernel}` (grid {a.grid}{_which(a)}, `{a.label}`), last dispatch:", "",
               "| counter | raw GB | scaled GB |", "|---|---:|---:|",
               f"| FETCH_SIZE | {fb / 1e9:.3f} | {fb * fs / 1e9:.3f} |",
               f"| WRITE_SIZE | {wb / 1e9:.3f} | {wb * ws / 1e9:.3f} |",
@@ -158,6 +171,11 @@ def main(argv=None):
     t.add_argument("--title", required=True)
     t.add_argument("--cmd", required=True)
     r = sub.add_parser("traffic")
+    for q in (t, r):
+        q.add_argument("--stride", type=int, default=1,
+                       help="launches of this kernel and grid per step")
+        q.add_argument("--offset", type=int, default=0,
+                       help="which of them (0-based, in launch order)")
     r.add_argument("--fetch", required=True)
     r.add_argument("--write", required=True)
     r.add_argument("--kernel", required=True)

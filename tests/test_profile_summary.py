@@ -34,6 +34,7 @@ def test_traffic_scaling_and_staleness(tmp_path):
     a.fetch, a.write, a.kernel, a.grid, a.label = str(fetch), str(write), \
         "void k_conv<EpiRelax, 16, 16, true>", 64, "bwd_relax_L2"
     a.copy_bytes, a.title, a.cmd = float(2**30), "t", ["c"]
+    a.stride, a.offset = 1, 0
     out.write_text(RS.report_traffic(a))
     rec = RS.read_traffic(str(out), "bwd_relax_L2")
     assert rec is not None
@@ -43,6 +44,20 @@ def test_traffic_scaling_and_staleness(tmp_path):
     txt = out.read_text().replace(RS.source_hash(), "0" * 64)   # other kernel sources
     out.write_text(txt)
     assert RS.read_traffic(str(out), "bwd_relax_L2") is None
+
+
+def test_match_picks_one_launch_per_step():
+    # two steps, each launching the same kernel and grid for two layers (A, B), after
+    # tuning launches of the same kernel; the selection is aligned to the last dispatch
+    k = "void bp::(anonymous namespace)::k_gemm<bp::dev::EpiAdj, 32, 256, 32, 4, 1, false, true>(bp::GeomSet, x)"
+    ds = [{"name": k, "grid": 8, "ns": n, "value": 0.0}
+          for n in (7, 7, 7, 1, 2, 3, 4)]       # tuning x3, then A1 B1 A2 B2
+    first = RS._match(ds, "void k_gemm<EpiAdj, 32, 256, 32, 4, 1, false, true>", 8, 2, 0)
+    second = RS._match(ds, "void k_gemm<EpiAdj, 32, 256, 32, 4, 1, false, true>", 8, 2, 1)
+    assert [d["ns"] for d in first][-2:] == [1, 3]
+    assert [d["ns"] for d in second][-2:] == [2, 4]
+    assert [d["ns"] for d in RS._match(ds, "void k_gemm<EpiAdj, 32, 256, 32, 4, 1, false, true>", 8)] \
+        == [7, 7, 7, 1, 2, 3, 4]
 
 
 def test_committed_traffic_summaries_parse():
