@@ -202,6 +202,7 @@ bound_status build_geoms(bound_net *net, hipStream_t st) {
             HIPCHK(launch_pack_T(L.weight, 0, L.in_c, L.in_h, L.in_w, L.out_c, 1, 1, 1, 1, 1, 0, 0, 0,
                                  0, 0, 1, 1, t.N, t.K, t.Kp, (int)NpT, bt, st));
             t.Bt = bt;
+            set_recips(t);
             li.gT.g[0] = t; li.gT.n = 1;
 
             Geom f{};
@@ -214,6 +215,7 @@ bound_status build_geoms(bound_net *net, hipStream_t st) {
             HIPCHK(launch_pack_F(L.weight, 0, L.in_c, L.in_h, L.in_w, L.out_c, 1, 1, f.N, f.K, f.Kp,
                                  (int)NpF, bf, st));
             f.Bt = bf;
+            set_recips(f);
             li.gF.g[0] = f; li.gF.n = 1;
         } else {
             // forward convolution (adjoint)
@@ -228,6 +230,7 @@ bound_status build_geoms(bound_net *net, hipStream_t st) {
             HIPCHK(launch_pack_F(L.weight, 1, L.in_c, L.in_h, L.in_w, L.out_c, L.kh, L.kw, f.N, f.K,
                                  f.Kp, (int)NpF, bf, st));
             f.Bt = bf;
+            set_recips(f);
             li.gF.g[0] = f; li.gF.n = 1;
             // transposed convolution, one stride-1 implicit GEMM per output phase
             const int s = L.stride;
@@ -254,6 +257,7 @@ bound_status build_geoms(bound_net *net, hipStream_t st) {
                                          L.out_w, L.kh, L.kw, s, L.pad, py, px, ky0, kx0, Ty, Tx,
                                          t.N, t.K, t.Kp, (int)NpT, bt, st));
                     t.Bt = bt;
+                    set_recips(t);
                     li.gT.g[np++] = t;
                 }
             }
@@ -587,6 +591,7 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             rp.mag = net->acc_mag;
             rp.img0 = img0;
             rp.rpi = rpi;
+            rp.rrpi = 1.0f / (float)rpi;
             {
                 ProfScope ps(net, st, lbl("bwd_relax_L%d", m));
                 const GeomSet &gs = net->layers[m - 1].gT;
@@ -618,7 +623,7 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             cp.emit = conc ? nullptr : out->coeff + img0 * d0;
             cp.chan = sl > 0 ? SL->C : net->C0;
             cp.hw = sl > 0 ? SL->HW : net->HW0;
-            cp.img0 = img0; cp.rpi = rpi;
+            cp.img0 = img0; cp.rpi = rpi; cp.rrpi = 1.0f / (float)rpi;
             ProfScope ps(net, st, lbl("bwd_conc_L%d", conc_m));
             const GeomSet &gs = net->layers[conc_m - 1].gT;
             const float *A = cur;
@@ -712,6 +717,7 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
         ap.gbeta = grad_beta && net->s_nnz > 0 ? grad_beta : nullptr;
         ap.hw = li.L.out_h * li.L.out_w;
         ap.rpi = rows;
+        ap.rrpi = 1.0f / (float)rows;
         {
             ProfScope ps(net, st, lbl("adj_L%d", m));
             const float *A = cur;

@@ -21,8 +21,22 @@ struct Geom {
     int kh, kw, stride, pad_y, pad_x;
     int K, N, Kp;
     int DH, DW, ostr, oy0, ox0;
+    float rOW, rM;             // fl(1 / OW), fl(1 / (OH * OW)) for the quotients of qdiv
+    float rC, rKW;             // fl(1 / C), fl(1 / kw)
+    double rMd;                // 1 / (OH * OW) in FP64 for row indices beyond 2^21
     const float *Bt;
 };
+
+// Reciprocals of a geometry's divisors, taken once on the host (the same correctly
+// rounded FP32 quotients a kernel would form).
+inline void set_recips(Geom &g) {
+    const int m = g.OH * g.OW > 0 ? g.OH * g.OW : 1;
+    g.rOW = 1.0f / (float)(g.OW > 0 ? g.OW : 1);
+    g.rM = 1.0f / (float)m;
+    g.rC = 1.0f / (float)(g.C > 0 ? g.C : 1);
+    g.rKW = 1.0f / (float)(g.kw > 0 ? g.kw : 1);
+    g.rMd = 1.0 / (double)m;
+}
 
 struct GeomSet {
     Geom g[4];
@@ -49,6 +63,7 @@ struct RelaxParams {       // G_m = Lambda_m W_m  ->  Lambda_{m-1} = relax(G_m)
     float *s, *mag;        // per-img offset accumulator and |term| accumulator
     long img0;             // global img index of local img 0
     int rpi;               // imgs per instance
+    float rrpi;            // fl(1 / rpi)
 };
 
 struct ConcParams {        // G_1 = Lambda_1 W_1  ->  concretise over the box
@@ -60,6 +75,7 @@ struct ConcParams {        // G_1 = Lambda_1 W_1  ->  concretise over the box
     int chan, hw;          // input shape for the C-major index
     long img0;
     int rpi;
+    float rrpi;
 };
 
 struct AdjParams {         // Lambda_bar_m = G_bar_m W_m^T + s_bar b_m  -> G_bar_{m+1}
@@ -75,6 +91,7 @@ struct AdjParams {         // Lambda_bar_m = G_bar_m W_m^T + s_bar b_m  -> G_bar
     float *gbeta;          // [nnz][rpi] beta-gradient of first split entries (nullable)
     int hw;                // H*W of layer m (C-major index)
     int rpi;
+    float rrpi;
 };
 
 struct FwdParams {         // z_m = W_m h_{m-1} + b_m for sample rows

@@ -32,6 +32,8 @@ struct ConvTile {
     int KB;        // padded k per chunk (multiple of 16)
     int WS;        // LDS weight row stride
     int in_floats; // G * IH * IW * CS
+    // fl(1 / d) of the divisors the kernels split indices by (qdiv), set on the host
+    float rTY, rCC, rKW, rTP, rIH, rIW, rPin, rPw, rC4, rTK, rKB;
 };
 
 // Stage the input tile (channels [c0, c0+CC)) of images img0.. into LDS, zero outside.
@@ -43,9 +45,9 @@ __device__ inline void stage_input(float *In, const ConvTile &ct, const Geom &g,
         const int c4n = ct.CC >> 2;
         const int total = ct.G * ct.IH * ct.IW * c4n;
         for (int e = tid; e < total; e += 256) {
-            const int c4 = e % c4n, pix = e / c4n;
-            const int ix = pix % ct.IW, t2 = pix / ct.IW;
-            const int iy = t2 % ct.IH, gi = t2 / ct.IH;
+            const int pix = qdiv(e, ct.rC4), c4 = e - pix * c4n;
+            const int t2 = qdiv(pix, ct.rIW), ix = pix - t2 * ct.IW;
+            const int gi = qdiv(t2, ct.rIH), iy = t2 - gi * ct.IH;
             const long img = img0 + gi;
             const int y = iy0 + iy, x = ix0 + ix;
             float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -56,8 +58,8 @@ __device__ inline void stage_input(float *In, const ConvTile &ct, const Geom &g,
     } else {  // C < 4: one chunk, channels padded with zeros up to CS = 4
         const int total = ct.G * ct.IH * ct.IW;
         for (int e = tid; e < total; e += 256) {
-            const int ix = e % ct.IW, t2 = e / ct.IW;
-            const int iy = t2 % ct.IH, gi = t2 / ct.IH;
+            const int t2 = qdiv(e, ct.rIW), ix = e - t2 * ct.IW;
+            const int gi = qdiv(t2, ct.rIH), iy = t2 - gi * ct.IH;
             const long img = img0 + gi;
             const int y = iy0 + iy, x = ix0 + ix;
             float v[4] = {0.f, 0.f, 0.f, 0.f};
@@ -76,10 +78,10 @@ __device__ inline void stage_weights(float *Wl, const ConvTile &ct, const Geom &
     const int total = BN * ct.KB;
     const int TC = ct.T * ct.CC;
     for (int e = threadIdx.x; e < total; e += 256) {
-        const int n = e / ct.KB, k = e - n * ct.KB;
+        const int n = qdiv(e, ct.rKB), k = e - n * ct.KB;
         float v = 0.f;
         if (k < TC) {
-            const int t = k / ct.CC, c = k - t * ct.CC;
+            const int t = qdiv(k, ct.rCC), c = k - t * ct.CC;
             v = g.Bt[(long)(n0 + n) * g.Kp + t * g.C + c0 + c];
         }
         Wl[n * ct.WS + k] = v;
@@ -94,8 +96,8 @@ constexpr int MAX_IN4 = 8, MAX_W4 = 6;
 // the row / column of each visit advance incrementally (one division per thread).
 struct Walk {
     int r, p, dr, dp, P;
-    __device__ Walk(int P_) : P(P_) {
-        r = qdiv(threadIdx.x, 1.0f / (float)P);
+    __device__ Walk(int P_, float rP) : P(P_) {
+        r = qdiv(threadIdx.x, rP);
         p = threadIdx.x - r * P;
         dr = 256 / P;
         dp = 256 - dr * P;
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     const TileIdx ti = xcd_tile(gs.g[0].N / BN, gs.n);
     const Geom &g = gs.g[ti.z];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const long grp = ldiv_by(ti.x, ct.tiles_y, 1.0f / (float)ct.tiles_y);
+    const long grp = ldiv_by(ti.x, ct.tiles_y, ct.rTY);
     const int band = (int)(ti.x - grp * ct.tiles_y);
     const long img0 = grp * ct.G;
     if (img0 >= n_img) return;
@@ -140,8 +142,8 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     for (int k = tid; k < ct.KB; k += 256) {
         int o = 0;
         if (k < TC) {
-            const int t = qdiv(k, 1.0f / (float)ct.CC), c = k - t * ct.CC;
-            const int ty = qdiv(t, 1.0f / (float)g.kw), tx = t - ty * g.kw;
+            const int t = qdiv(k, ct.rCC), c = k - t * ct.CC;
+            const int ty = qdiv(t, ct.rKW), tx = t - ty * g.kw;
             o = (ty * ct.IW + tx) * ct.CS + c;
         }
         koff[k] = o;
@@ -152,8 +154,8 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
         const int lr = wave * 64 + i * MF + MM::idx(lane);
-        const int gi = qdiv(lr, 1.0f / (float)tile_px), q = lr - gi * tile_px;
-        const int py = qdiv(q, 1.0f / (float)g.OW), px = q - py * g.OW;
+        const int gi = qdiv(lr, ct.rTP), q = lr - gi * tile_px;
+        const int py = qdiv(q, g.rOW), px = q - py * g.OW;
         abase[i] = ((gi * ct.IH + py * g.stride) * ct.IW + px * g.stride) * ct.CS;
     }
     acc_t acc[FM][FN];
@@ -175,13 +177,13 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     const float *Bb = g.Bt + (long)n0 * g.Kp;
     int gin[MAX_IN4], lin[MAX_IN4], gw[MAX_W4], lw[MAX_W4];
     if (VEC) {
-        Walk w(Pin);
+        Walk w(Pin, ct.rPin);
 #pragma unroll
         for (int i = 0; i < MAX_IN4; ++i) {
             gin[i] = -1;
             lin[i] = -1;
             if (w.r < Rin) {
-                const int gi = qdiv(w.r, 1.0f / (float)ct.IH), iy = w.r - gi * ct.IH;
+                const int gi = qdiv(w.r, ct.rIH), iy = w.r - gi * ct.IH;
                 const int ix = w.p >> c4s, c4 = w.p & ((1 << c4s) - 1);
                 const int y = iy0 + iy, x = ix0 + ix;
                 lin[i] = (w.r * ct.IW + ix) * ct.CS + 4 * c4;
@@ -190,7 +192,7 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
             }
             w.next();
         }
-        Walk ww(Pw);
+        Walk ww(Pw, ct.rPw);
 #pragma unroll
         for (int i = 0; i < MAX_W4; ++i) {
             gw[i] = -1;
@@ -282,12 +284,12 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
         ncol[j] = n0 + j * MF + MM::col(lane);
         bcol[j] = ncol[j] < g.N ? epi.colv(ncol[j]) : 0.f;
     }
-    const float rTP = 1.0f / (float)tile_px;
+    const float rTP = ct.rTP;
     const int gfirst = qdiv(wave * 64, rTP), glast = qdiv(wave * 64 + 63, rTP);
     const bool uniform = gfirst == glast && img0 + gfirst < n_img;
     // Local row lr < 256 -> (image of the block, pixel); with OW a multiple of 4 a group
     // of four consecutive rows is four neighbouring pixels of one output row.
-    const float rOW = 1.0f / (float)g.OW;
+    const float rOW = g.rOW;
     const bool quad = g.OW % 4 == 0;
     auto rowfn4 = [&](int i, int vg, int (&img)[4], int (&dp)[4]) -> bool {
         const int lr0 = wave * 64 + i * MF + MM::row(4 * vg, lane);
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvT
     const TileIdx ti = xcd_tile(1, gs.n);
     const Geom &g = gs.g[ti.z];
     const int tid = threadIdx.x;
-    const long grp = ti.x / ct.tiles_y;
+    const long grp = ldiv_by(ti.x, ct.tiles_y, ct.rTY);
     const int band = (int)(ti.x - grp * ct.tiles_y);
     const long img0 = grp * ct.G;
     if (img0 >= n_img) return;
@@ -332,18 +334,18 @@ __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvT
     const int TK = ct.T * g.C;
     stage_input<true>(In, ct, g, X, img0, n_img, oyb * g.stride - g.pad_y, -g.pad_x, 0);
     for (int e = tid; e < NMAX * TK; e += 256) {
-        const int n = e / TK, k = e - n * TK;
+        const int n = qdiv(e, ct.rTK), k = e - n * TK;
         Wl[e] = n < g.N ? g.Bt[(long)n * g.Kp + k] : 0.f;
     }
     __syncthreads();
-    const int gi = tid / tile_px, q = tid - gi * tile_px;
-    const int py = q / g.OW, px = q - py * g.OW;
+    const int gi = qdiv(tid, ct.rTP), q = tid - gi * tile_px;
+    const int py = qdiv(q, g.rOW), px = q - py * g.OW;
     const int base = ((gi * ct.IH + py * g.stride) * ct.IW + px * g.stride) * ct.CS;
     float acc[NMAX];
 #pragma unroll
     for (int n = 0; n < NMAX; ++n) acc[n] = 0.f;
-    for (int t = 0; t < ct.T; ++t) {
-        const int ty = t / g.kw, tx = t - ty * g.kw;
+    for (int ty = 0, t = 0; ty < g.kh; ++ty)
+    for (int tx = 0; tx < g.kw; ++tx, ++t) {
         const float *a = In + base + (ty * ct.IW + tx) * ct.CS;
         const float *w = Wl + t * g.C;
         for (int c = 0; c < g.C; c += 4) {
@@ -378,7 +380,7 @@ __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvT
         // a wave's 64 pixels lie in one image whenever an image has >= 64 pixels
         const int lane = tid & 63;
         const int wave = tid >> 6;
-        const int gf = (wave * 64) / tile_px, gl = (wave * 64 + 63) / tile_px;
+        const int gf = qdiv(wave * 64, ct.rTP), gl = qdiv(wave * 64 + 63, ct.rTP);
         if (gf == gl) {
             if (img0 + gf < n_img) reduce_wave_atomic(r0, r1, img0 + gf, lane, epi.red0(), epi.red1());
         } else {
@@ -413,6 +415,23 @@ bool plan_tile(const Geom &g, ConvTile &ct) {
     ct.IW = (g.OW - 1) * g.stride + g.kw;
     ct.T = g.kh * g.kw;
     return true;
+}
+
+float recip(int d) { return 1.0f / (float)(d > 0 ? d : 1); }
+
+// Reciprocals of the tile's divisors for qdiv (after plan_tile / plan_chunk).
+void set_tile_recips(const Geom &g, ConvTile &ct) {
+    ct.rTY = recip(ct.tiles_y);
+    ct.rCC = recip(ct.CC);
+    ct.rKW = recip(g.kw);
+    ct.rTP = recip(ct.TR * g.OW);
+    ct.rIH = recip(ct.IH);
+    ct.rIW = recip(ct.IW);
+    ct.rPin = recip(ct.CC >= 4 ? ct.IW * (ct.CC >> 2) : ct.IW);
+    ct.rPw = recip(ct.KB >> 2);
+    ct.rC4 = recip(ct.CC >> 2);
+    ct.rTK = recip(ct.T * g.C);
+    ct.rKB = recip(ct.KB);
 }
 
 bool same_shape(const GeomSet &gs) {
@@ -503,6 +522,7 @@ hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &
         ct.in_floats = ct.G * ct.IH * ct.IW * ct.CS;
         const size_t lds = ((size_t)ct.in_floats + 4 * (size_t)ct.T * g.C) * 4;
         if (lds > LDS_BUDGET) return hipSuccess;
+        set_tile_recips(g, ct);
         const dim3 grid((unsigned)(groups * ct.tiles_y * gs.n));   // xcd_tile order
         if (g.N == 3) {   // RGB input layers: no idle fourth output
             static const hipError_t ok3 = allow_lds(k_conv_valu<Epi, 3>);
@@ -521,6 +541,7 @@ hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &
     const int KPL = BN == 16 ? Mma<16>::KPL : Mma<32>::KPL;
     const size_t lds = plan_chunk(g, BN, KPL, ct, want_cc);
     if (!lds) return hipSuccess;
+    set_tile_recips(g, ct);
     *used = true;
     if (BN == 16) return launch_mfma<Epi, 16, 16>(gs, ct, lds, X, n_img, epi, st);
     if (BN == 32) return launch_mfma<Epi, 32, 32>(gs, ct, lds, X, n_img, epi, st);

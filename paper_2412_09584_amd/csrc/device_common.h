@@ -68,6 +68,17 @@ __device__ inline int qdiv(int n, float rd) { return (int)(((float)n + 0.5f) * r
 __device__ inline long ldiv_by(long n, int d, float rd) {
     return n < (1L << 21) ? (long)qdiv((int)n, rd) : n / d;
 }
+// The same in FP64 with rd = fl64(1 / d): exact for 0 <= n < 2^50 by the argument above
+// with 2^-52 in place of 2^-23.
+__device__ inline long ldiv64(long n, double rd) { return (long)(((double)n + 0.5) * rd); }
+
+// Element i of one img's row segment starting at base.  Every epilogue offset stays inside
+// such a segment (i * sizeof(T) < 2^32, layer widths are validated on the host), so the
+// byte offset is formed in 32 bits; with a wave-uniform base the load or store then
+// takes the scalar-base address form and needs no 64-bit address arithmetic per element.
+template <class T> __device__ inline T &at(T *base, int i) {
+    return *(T *)((const char *)base + (unsigned)i * (unsigned)sizeof(T));
+}
 
 // ---------------------------------------------------------------------- epilogues
 // Each epilogue splits its per-element work into pre() -- the global loads it needs
@@ -82,14 +93,14 @@ struct EpiRelax {
     using Pre = Relax;
     struct Row { const Relax *tb; float *out, *save; };
     __device__ Row row(int img) const {
-        const long inst = ldiv_by(p.img0 + img, p.rpi, 1.0f / (float)p.rpi);
+        const long inst = ldiv_by(p.img0 + img, p.rpi, p.rrpi);
         const long o = (long)img * p.D;
         return Row{p.tab + inst * p.tab_ld, p.out + o, p.save ? p.save + o : nullptr};
     }
     __device__ float colv(int n) const { return p.bias[n % p.chan]; }
     __device__ float *red0() const { return p.s; }
     __device__ float *red1() const { return p.mag; }
-    __device__ Pre pre(const Row &rc, int j) const { return rc.tb[j]; }
+    __device__ Pre pre(const Row &rc, int j) const { return at(rc.tb, j); }
     __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &t, const Row &rc, int, int, int j, float bcol, float g,
                          float &r0, float &r1) const {
@@ -98,8 +109,8 @@ struct EpiRelax {
         const float bt = lam * bcol;
         r0 += bt + off;
         r1 += fabsf(bt) + fabsf(off);
-        rc.out[j] = lam;
-        if (rc.save && t.w > 0.f) rc.save[(int)t.w - 1] = g;    // unstable: compact slot
+        at(rc.out, j) = lam;
+        if (rc.save && t.w > 0.f) at(rc.save, (int)t.w - 1) = g;    // unstable: compact slot
     }
 };
 
@@ -109,7 +120,7 @@ struct EpiConc {
     using Pre = float2;
     struct Row { const float *cen, *rad; float *save, *emit; };
     __device__ Row row(int img) const {
-        const long inst = ldiv_by(p.img0 + img, p.rpi, 1.0f / (float)p.rpi);
+        const long inst = ldiv_by(p.img0 + img, p.rpi, p.rrpi);
         const long o = (long)img * p.D;
         return Row{p.cen + inst * p.D, p.rad + inst * p.D, p.save ? p.save + o : nullptr,
                    p.emit ? p.emit + o : nullptr};
@@ -117,14 +128,14 @@ struct EpiConc {
     __device__ float colv(int) const { return 0.f; }
     __device__ float *red0() const { return p.low; }
     __device__ float *red1() const { return p.mag; }
-    __device__ Pre pre(const Row &rc, int j) const { return make_float2(rc.cen[j], rc.rad[j]); }
+    __device__ Pre pre(const Row &rc, int j) const { return make_float2(at(rc.cen, j), at(rc.rad, j)); }
     __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &cr, const Row &rc, int dpix, int n, int j, float, float g,
                          float &r0, float &r1) const {
         r0 += g * cr.x - fabsf(g) * cr.y;
         r1 += fabsf(g) * (fabsf(cr.x) + cr.y);
-        if (rc.save) rc.save[j] = g;
-        if (rc.emit) rc.emit[n * p.hw + dpix] = g;
+        if (rc.save) at(rc.save, j) = g;
+        if (rc.emit) at(rc.emit, n * p.hw + dpix) = g;
     }
 };
 
@@ -134,7 +145,7 @@ struct EpiAdj {
     struct Pre { Relax t; float g; };
     struct Row { const Relax *tb; const float *gs; float *go; float *gc; float *gb; float sb; };
     __device__ Row row(int img) const {
-        const long inst = ldiv_by(img, p.rpi, 1.0f / (float)p.rpi);
+        const long inst = ldiv_by(img, p.rpi, p.rrpi);
         const long o = (long)img * p.D;
         return Row{p.tab + inst * p.tab_ld, p.gsave + o, p.gout ? p.gout + o : nullptr,
                    p.gc + o, p.gbeta ? p.gbeta + (img - inst * p.rpi) : nullptr, p.sbar[img]};
@@ -145,19 +156,19 @@ struct EpiAdj {
     // G is saved at the unstable neurons only (slot w - 1), a load that depends on the
     // record: pre() fetches the record, pre2() the saved coefficient.  Elsewhere x = y
     // and z = 0, so the sign of G does not matter.
-    __device__ Pre pre(const Row &rc, int j) const { return Pre{rc.tb[j], 0.f}; }
+    __device__ Pre pre(const Row &rc, int j) const { return Pre{at(rc.tb, j), 0.f}; }
     __device__ void pre2(const Row &rc, Pre &q) const {
-        if (q.t.w > 0.f) q.g = rc.gs[(int)q.t.w - 1];
+        if (q.t.w > 0.f) q.g = at(rc.gs, (int)q.t.w - 1);
     }
     __device__ void post(const Pre &q, const Row &rc, int dpix, int n, int j, float bcol, float acc,
                          float &, float &) const {
         const float v = acc + rc.sb * bcol;           // Lambda_bar_m[img, j]
         const float g = q.g;                          // G_{m+1}[img, j]
         const Relax &t = q.t;
-        if (rc.go) rc.go[j] = v * (g >= 0.f ? t.x : t.y) + (g < 0.f ? rc.sb * t.z : 0.f);
+        if (rc.go) at(rc.go, j) = v * (g >= 0.f ? t.x : t.y) + (g < 0.f ? rc.sb * t.z : 0.f);
         // alpha-gradient contribution of this row at the neuron's slot (summed over the
         // instance's rows by k_alpha_grad)
-        if (t.w > 0.f) rc.gc[(int)t.w - 1] = g >= 0.f ? g * v : 0.f;
+        if (t.w > 0.f) at(rc.gc, (int)t.w - 1) = g >= 0.f ? g * v : 0.f;
         // split neuron (first entry q of the instance's list): d lower / d beta_{q,r} =
         // -sign * Lambda_bar; the active split's record has slope 1, the inactive one 0
         if (t.w < 0.f && rc.gb) rc.gb[(long)(-(int)t.w - 1) * p.rpi] = t.x > 0.5f ? -v : v;
@@ -178,7 +189,7 @@ struct EpiFwd {
     __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &, const Row &rc, int, int, int j, float bcol, float acc,
                          float &, float &) const {
-        rc.out[j] = acc + bcol;
+        at(rc.out, j) = acc + bcol;
     }
 };
 
@@ -233,7 +244,7 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
         // coefficients never alias the outputs), so about one memory latency is exposed
         // per tile rather than one or two per group -- when three groups' loads fit in
         // about 64 registers (else two stages, or none).
-        rw = epi.row(uimg);
+        rw = epi.row(__builtin_amdgcn_readfirstlane(uimg));
         constexpr int NG = FM * (NACC / 4);
         constexpr int GREG = FN * 4 * (int)sizeof(typename Epi::Pre) / 4;
         constexpr int DEPTH = 3 * GREG <= 64 ? 2 : (2 * GREG <= 48 ? 1 : 0);

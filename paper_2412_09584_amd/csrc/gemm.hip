@@ -61,8 +61,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
 
     if (!DENSE) {
         for (int k = tid; k < K; k += 256) {
-            const int tap = k / g.C, c = k - tap * g.C;
-            const int ky = tap / g.kw, kx = tap - ky * g.kw;
+            const int tap = qdiv(k, g.rC), c = k - tap * g.C;
+            const int ky = qdiv(tap, g.rKW), kx = tap - ky * g.kw;
             kdec[k] = make_int2((ky * g.W + kx) * g.C + c, (ky << 16) | kx);
         }
         // visible to every thread after the first barrier of the k loop
@@ -73,9 +73,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
     const float *abase[APT];
     int aby[APT], abx[APT], akq[APT], arow[APT];
     bool aok[APT];
-    const long bimg = DENSE ? m0 : m0 / Mimg;
+    const long bimg = DENSE ? m0 : ldiv64(m0, g.rMd);
     const int bp0 = (int)(m0 - bimg * Mimg);
-    const float rMb = 1.0f / (float)Mimg, rOWb = 1.0f / (float)g.OW;
+    const float rMb = g.rM, rOWb = g.rOW;
 #pragma unroll
     for (int i = 0; i < APT; ++i) {
         const int f = tid + 256 * i;
@@ -218,12 +218,12 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
     // Row m = wrow0 + off (off < TM) is decomposed from the wave's first row, so only
     // small quotients (qdiv) are needed per row group.  With Mimg and OW multiples of 4
     // a group of four consecutive rows is four neighbouring pixels of one output row.
-    const long imgw = wrow0 / Mimg;
+    const long imgw = DENSE ? wrow0 : ldiv64(wrow0, g.rMd);
     const int pw = (int)(wrow0 - imgw * Mimg);
     // every row of the wave's tile exists and belongs to img imgw (the usual case for
     // convolutions): the fast epilogue applies
     const bool uniform = wrow0 + TM <= M && pw + TM <= Mimg;
-    const float rM = 1.0f / (float)Mimg, rOW = 1.0f / (float)g.OW;
+    const float rM = g.rM, rOW = g.rOW;
     const bool quad = (Mimg % 4 == 0) && (g.OW % 4 == 0);
     auto rowfn4 = [&](int i, int vg, int (&img)[4], int (&dp)[4]) -> bool {
         const int off = i * MF + MM::row(4 * vg, lane);
