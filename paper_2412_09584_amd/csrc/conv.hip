@@ -12,7 +12,8 @@
 //
 // k_conv_valu covers products with at most 4 output channels (the first layer's
 // transposed convolution back to a 3-channel input), where a 16-wide MFMA tile would
-// waste most of its work: one thread per output pixel, plain FP32 FMAs from LDS.
+// waste most of its work: one thread per output pixel, plain FP32 FMAs of LDS inputs
+// and scalar-loaded weights.
 #include "device_common.h"
 
 namespace bp {
@@ -112,7 +113,7 @@ struct Walk {
     }
 };
 
-template <class Epi, int MF, int BN, bool VEC>
+template <class Epi, int MF, int BN, bool VEC, int NIN, int NW>
 __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile ct,
                                               const float *__restrict__ X, const long n_img,
                                               const Epi epi) {
@@ -175,11 +176,11 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     const int Pw = ct.KB >> 2;                         // weight grid [BN][KB/4]
     const float *Xb = X + img0 * (long)g.H * g.W * g.C;
     const float *Bb = g.Bt + (long)n0 * g.Kp;
-    int gin[MAX_IN4], lin[MAX_IN4], gw[MAX_W4], lw[MAX_W4];
+    int gin[NIN], lin[NIN], gw[NW], lw[NW];
     if (VEC) {
         Walk w(Pin, ct.rPin);
 #pragma unroll
-        for (int i = 0; i < MAX_IN4; ++i) {
+        for (int i = 0; i < NIN; ++i) {
             gin[i] = -1;
             lin[i] = -1;
             if (w.r < Rin) {
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
         }
         Walk ww(Pw, ct.rPw);
 #pragma unroll
-        for (int i = 0; i < MAX_W4; ++i) {
+        for (int i = 0; i < NW; ++i) {
             gw[i] = -1;
             lw[i] = -1;
             const int k = ww.p << 2;
@@ -205,21 +206,21 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
             ww.next();
         }
     }
-    float4 rin[MAX_IN4], rw[MAX_W4];
+    float4 rin[NIN], rw[NW];
     auto load_chunk = [&](int c0) {
 #pragma unroll
-        for (int i = 0; i < MAX_IN4; ++i)
+        for (int i = 0; i < NIN; ++i)
             rin[i] = gin[i] >= 0 ? *(const float4 *)(Xb + gin[i] + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-        for (int i = 0; i < MAX_W4; ++i)
+        for (int i = 0; i < NW; ++i)
             rw[i] = gw[i] >= 0 ? *(const float4 *)(Bb + gw[i] + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
     };
     auto store_chunk = [&]() {
 #pragma unroll
-        for (int i = 0; i < MAX_IN4; ++i)
+        for (int i = 0; i < NIN; ++i)
             if (lin[i] >= 0) *(float4 *)(In + lin[i]) = rin[i];
 #pragma unroll
-        for (int i = 0; i < MAX_W4; ++i)
+        for (int i = 0; i < NW; ++i)
             if (lw[i] >= 0) *(float4 *)(Wl + lw[i]) = rw[i];
     };
 
@@ -319,9 +320,12 @@ template <class Epi, int NMAX>
 __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvTile ct,
                                                    const float *__restrict__ X, const long n_img,
                                                    const Epi epi) {
+    // The weights are read at block-uniform addresses through the constant address
+    // space, so they arrive by scalar loads into SGPRs and feed the FMAs directly; only
+    // the input tile goes through LDS.
+    using cfloat = const __attribute__((address_space(4))) float;
     extern __shared__ __attribute__((aligned(16))) float smem[];
     float *In = smem;
-    float *Wl = smem + ct.in_floats;  // [NMAX][T*C]
     const TileIdx ti = xcd_tile(1, gs.n);
     const Geom &g = gs.g[ti.z];
     const int tid = threadIdx.x;
@@ -331,32 +335,53 @@ __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvT
     if (img0 >= n_img) return;
     const int oyb = band * ct.TR;
     const int tile_px = ct.TR * g.OW;
-    const int TK = ct.T * g.C;
     stage_input<true>(In, ct, g, X, img0, n_img, oyb * g.stride - g.pad_y, -g.pad_x, 0);
-    for (int e = tid; e < NMAX * TK; e += 256) {
-        const int n = qdiv(e, ct.rTK), k = e - n * TK;
-        Wl[e] = n < g.N ? g.Bt[(long)n * g.Kp + k] : 0.f;
-    }
     __syncthreads();
     const int gi = qdiv(tid, ct.rTP), q = tid - gi * tile_px;
     const int py = qdiv(q, g.rOW), px = q - py * g.OW;
     const int base = ((gi * ct.IH + py * g.stride) * ct.IW + px * g.stride) * ct.CS;
+    cfloat *Wg = (cfloat *)g.Bt;
+    const int C = g.C, Kp = g.Kp, N = g.N;
+    // weight row of output n (rows past N repeat the last one; their sums are unused)
+    long wrow[NMAX];
+#pragma unroll
+    for (int n = 0; n < NMAX; ++n) wrow[n] = (long)(n < N ? n : N - 1) * Kp;
     float acc[NMAX];
 #pragma unroll
     for (int n = 0; n < NMAX; ++n) acc[n] = 0.f;
     for (int ty = 0, t = 0; ty < g.kh; ++ty)
     for (int tx = 0; tx < g.kw; ++tx, ++t) {
         const float *a = In + base + (ty * ct.IW + tx) * ct.CS;
-        const float *w = Wl + t * g.C;
-        for (int c = 0; c < g.C; c += 4) {
+        cfloat *w = Wg + t * C;
+        int c = 0;
+        for (; c + 16 <= C; c += 16) {     // 16 channels: the weights in one batch of loads
+            float wv[NMAX][16];
+#pragma unroll
+            for (int n = 0; n < NMAX; ++n)
+#pragma unroll
+                for (int u = 0; u < 16; ++u) wv[n][u] = w[wrow[n] + c + u];
+            float4 av[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) av[u] = *(const float4 *)(a + c + 4 * u);
+#pragma unroll
+            for (int n = 0; n < NMAX; ++n)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    acc[n] = fmaf(av[u].x, wv[n][4 * u], acc[n]);
+                    acc[n] = fmaf(av[u].y, wv[n][4 * u + 1], acc[n]);
+                    acc[n] = fmaf(av[u].z, wv[n][4 * u + 2], acc[n]);
+                    acc[n] = fmaf(av[u].w, wv[n][4 * u + 3], acc[n]);
+                }
+        }
+        for (; c < C; c += 4) {
             const float4 av = *(const float4 *)(a + c);
 #pragma unroll
             for (int n = 0; n < NMAX; ++n) {
-                const float4 wv = *(const float4 *)(w + n * TK + c);
-                acc[n] = fmaf(av.x, wv.x, acc[n]);
-                acc[n] = fmaf(av.y, wv.y, acc[n]);
-                acc[n] = fmaf(av.z, wv.z, acc[n]);
-                acc[n] = fmaf(av.w, wv.w, acc[n]);
+                cfloat *wn = w + wrow[n] + c;
+                acc[n] = fmaf(av.x, wn[0], acc[n]);
+                acc[n] = fmaf(av.y, wn[1], acc[n]);
+                acc[n] = fmaf(av.z, wn[2], acc[n]);
+                acc[n] = fmaf(av.w, wn[3], acc[n]);
             }
         }
     }
@@ -481,21 +506,35 @@ template <class K> hipError_t allow_lds(K kern) {
                                LDS_BUDGET);
 }
 
+// Register prefetch slots of a launch: a small set when the tile needs no more, which
+// keeps the kernel's register count (and so its occupancy) down.
+constexpr int SMALL_IN4 = 5, SMALL_W4 = 2;
+
+template <class Epi, int MF, int BN, int NIN, int NW>
+hipError_t launch_slots(const GeomSet &gs, const ConvTile &ct, size_t lds, const float *X,
+                        long n_img, const Epi &epi, hipStream_t st, dim3 grid) {
+    if (gs.g[0].C % 4 == 0) {
+        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, true, NIN, NW>);
+        if (ok != hipSuccess) return ok;
+        hipLaunchKernelGGL((k_conv<Epi, MF, BN, true, NIN, NW>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+    } else {
+        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, false, NIN, NW>);
+        if (ok != hipSuccess) return ok;
+        hipLaunchKernelGGL((k_conv<Epi, MF, BN, false, NIN, NW>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+    }
+    return hipGetLastError();
+}
+
 template <class Epi, int MF, int BN>
 hipError_t launch_mfma(const GeomSet &gs, const ConvTile &ct, size_t lds, const float *X, long n_img,
                        const Epi &epi, hipStream_t st) {
     const long groups = (n_img + ct.G - 1) / ct.G;
     const dim3 grid((unsigned)(groups * ct.tiles_y * (gs.g[0].N / BN) * gs.n));   // xcd_tile order
-    if (gs.g[0].C % 4 == 0) {
-        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, true>);
-        if (ok != hipSuccess) return ok;
-        hipLaunchKernelGGL((k_conv<Epi, MF, BN, true>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
-    } else {
-        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, false>);
-        if (ok != hipSuccess) return ok;
-        hipLaunchKernelGGL((k_conv<Epi, MF, BN, false>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
-    }
-    return hipGetLastError();
+    const bool small = gs.g[0].C % 4 == 0 &&
+                       (size_t)ct.G * ct.IH * ct.IW * (ct.CC / 4) <= 256 * SMALL_IN4 &&
+                       (size_t)BN * (ct.KB / 4) <= 256 * SMALL_W4;
+    if (small) return launch_slots<Epi, MF, BN, SMALL_IN4, SMALL_W4>(gs, ct, lds, X, n_img, epi, st, grid);
+    return launch_slots<Epi, MF, BN, MAX_IN4, MAX_W4>(gs, ct, lds, X, n_img, epi, st, grid);
 }
 
 int bn_for(int N) {
@@ -520,7 +559,7 @@ hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &
         ct.CC = g.C;
         ct.CS = g.C + 4;
         ct.in_floats = ct.G * ct.IH * ct.IW * ct.CS;
-        const size_t lds = ((size_t)ct.in_floats + 4 * (size_t)ct.T * g.C) * 4;
+        const size_t lds = (size_t)ct.in_floats * 4;
         if (lds > LDS_BUDGET) return hipSuccess;
         set_tile_recips(g, ct);
         const dim3 grid((unsigned)(groups * ct.tiles_y * gs.n));   // xcd_tile order
