@@ -218,8 +218,11 @@ bound_status bound_adam(int64_t n, float *param, const float *grad, float *m, fl
 
 /* Kernel selection: BOUND_OPT_GEMM_ONLY runs every product as an implicit GEMM (the
  * LDS-tiled direct-convolution kernels are otherwise used where the layer geometry fits
- * them).  Both compute the same bound; the option exists to test and compare them. */
-enum { BOUND_OPT_GEMM_ONLY = 1 };
+ * them).  BOUND_OPT_DIRECT_DMA makes the direct-convolution kernels of products that
+ * bound_autotune has not planned stage their tiles by LDS DMA instead of through
+ * registers.  All variants compute the same bound; the options exist to test and
+ * compare them. */
+enum { BOUND_OPT_GEMM_ONLY = 1, BOUND_OPT_DIRECT_DMA = 2 };
 bound_status bound_set_options(bound_net *net, int32_t options);
 
 /* Kernel autotuning: runs the given pass (and, if grad_lower is not NULL and the pass

@@ -144,7 +144,10 @@ bound_status run_product(bound_net *net, hipStream_t st, int key, const GeomSet 
             p.path = 2;
         } else {
             auto it = net->plans.find(key);
-            if (it != net->plans.end()) p = it->second;
+            if (it != net->plans.end())
+                p = it->second;
+            else if (net->options & BOUND_OPT_DIRECT_DMA)
+                p.cfg = 1;
         }
         HIPCHK(launch(p));
         return BOUND_OK;
@@ -858,7 +861,8 @@ int32_t bound_autotune_report(const bound_net *net, char *buf, int32_t cap) {
 }
 
 bound_status bound_set_options(bound_net *net, int32_t options) {
-    if (!net || (options & ~BOUND_OPT_GEMM_ONLY)) return fail(BOUND_E_ARG, "bound_set_options: bad arguments");
+    if (!net || (options & ~(BOUND_OPT_GEMM_ONLY | BOUND_OPT_DIRECT_DMA)))
+        return fail(BOUND_E_ARG, "bound_set_options: bad arguments");
     net->options = options;
     return BOUND_OK;
 }

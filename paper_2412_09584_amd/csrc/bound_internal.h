@@ -132,17 +132,17 @@ hipError_t gemm_adj_cfg(const GeomSet &gs, const float *A, long n_img, const Adj
 hipError_t gemm_fwd_cfg(const GeomSet &gs, const float *A, long n_img, const FwdParams &p,
                         hipStream_t st, int cfg);
 int gemm_candidates(const GeomSet &gs, int *cfgs, int cap);
-// conv.hip: direct convolution (cc = 0: largest chunk that fits); *used = false when the
-// geometry does not fit
+// conv.hip: direct convolution (cc = 0: largest chunk that fits; mode 1: tiles staged by
+// LDS DMA, else through registers); *used = false when the geometry does not fit
 hipError_t direct_relax(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
-                        hipStream_t st, int cc, bool *used);
+                        hipStream_t st, int cc, int mode, bool *used);
 hipError_t direct_conc(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,
-                       hipStream_t st, int cc, bool *used);
+                       hipStream_t st, int cc, int mode, bool *used);
 hipError_t direct_adj(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
-                      hipStream_t st, int cc, bool *used);
+                      hipStream_t st, int cc, int mode, bool *used);
 hipError_t direct_fwd(const GeomSet &gs, const float *A, long n_img, const FwdParams &p,
-                      hipStream_t st, int cc, bool *used);
-int direct_candidates(const GeomSet &gs, int *cc, int cap);
+                      hipStream_t st, int cc, int mode, bool *used);
+int direct_candidates(const GeomSet &gs, int *cc, int *mode, int cap);
 
 // ----- auxiliary kernels (aux.hip) ---------------------------------------------------
 struct LayerShape {        // output shape of a ReLU layer (for index maps)

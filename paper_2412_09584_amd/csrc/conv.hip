@@ -34,7 +34,7 @@ struct ConvTile {
     int WS;        // LDS weight row stride
     int in_floats; // G * IH * IW * CS
     // fl(1 / d) of the divisors the kernels split indices by (qdiv), set on the host
-    float rTY, rCC, rKW, rTP, rIH, rIW, rPin, rPw, rC4, rTK, rKB;
+    float rTY, rCC, rKW, rTP, rIH, rIW, rPin, rPw, rC4, rTK, rKB, rSPP, rSPR;
 };
 
 // Stage the input tile (channels [c0, c0+CC)) of images img0.. into LDS, zero outside.
@@ -92,6 +92,19 @@ __device__ inline void stage_weights(float *Wl, const ConvTile &ct, const Geom &
 // Register prefetch capacity per thread (float4s) for the next chunk's input tile and
 // weights; plan_chunk keeps every tile within it.
 constexpr int MAX_IN4 = 8, MAX_W4 = 6;
+// DMA staging: slots per thread (input, weights), one offset register each
+constexpr int DMA_IN4 = 12, DMA_W4 = 6;
+// dword 3 of a raw buffer resource (32-bit data format; no swizzle, no index stride)
+constexpr int BUF_FLAGS = 0x00020000;
+
+// 16 bytes per lane from base + voff (bytes) into LDS at lds + 16 * lane (lds uniform
+// across the wave); offsets at or past nbytes read nothing.
+__device__ inline void lds_dma16(const float *base, int nbytes, float *lds, int voff) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nbytes, BUF_FLAGS);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void *)lds, 16,
+                                             voff, 0, 0, 0);
+}
 
 // Element walk over a [rows][P] float4 grid: thread tid visits e = tid, tid + 256, ...;
 // the row / column of each visit advance incrementally (one division per thread).
@@ -113,7 +126,7 @@ struct Walk {
     }
 };
 
-template <class Epi, int MF, int BN, bool VEC, int NIN, int NW>
+template <class Epi, int MF, int BN, bool VEC, int NIN, int NW, bool DMA>
 __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile ct,
                                               const float *__restrict__ X, const long n_img,
                                               const Epi epi) {
@@ -171,13 +184,55 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     // The tile position of each staged float4 is the same for every chunk; only the
     // channel offset c0 changes, so global and LDS offsets are computed once here
     // (global offsets relative to the block's first image; -1 marks zero padding).
+    //
+    // DMA: the chunk goes from global memory straight into LDS (buffer loads with the
+    // LDS destination, 16 bytes per lane at consecutive LDS addresses), so no staging
+    // registers are held across the k-loop.  LDS float4 slot s = i * 256 + tid of the
+    // input tile (pixel, channel quad incl. the row padding) and of the weight tile
+    // (output, k quad incl. padding) is fetched by that thread; slots that are always
+    // zero (spatial padding, k past the chunk) are written once, the padding columns
+    // never, and slots past the last image of a partial group read out of range of the
+    // buffer (no access) and feed only rows the epilogue drops.
     const int c4s = VEC ? ct.lcc - 2 : 0;             // log2(CC / 4)
     const int Pin = ct.IW << c4s, Rin = ct.G * ct.IH;  // input grid [G*IH][IW*CC/4]
     const int Pw = ct.KB >> 2;                         // weight grid [BN][KB/4]
     const float *Xb = X + img0 * (long)g.H * g.W * g.C;
     const float *Bb = g.Bt + (long)n0 * g.Kp;
     int gin[NIN], lin[NIN], gw[NW], lw[NW];
-    if (VEC) {
+    if (VEC && DMA) {
+        const int spp = ct.CS >> 2, S_in = ct.in_floats >> 2;
+#pragma unroll
+        for (int i = 0; i < NIN; ++i) {
+            const int sl = i * 256 + tid;
+            int o = -2;
+            if (sl < S_in) {
+                o = -1;
+                const int pix = qdiv(sl, ct.rSPP), c4 = sl - pix * spp;
+                const int row = qdiv(pix, ct.rIW), ix = pix - row * ct.IW;
+                const int gi = qdiv(row, ct.rIH), iy = row - gi * ct.IH;
+                const int y = iy0 + iy, x = ix0 + ix;
+                if (c4 < (ct.CC >> 2) && (unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W)
+                    o = (((gi * g.H + y) * g.W + x) * g.C + 4 * c4) * 4;
+                else if (c4 == (ct.CC >> 2))
+                    o = -2;                           // row padding: never read
+            }
+            gin[i] = o;
+            if (o == -1) *(float4 *)(In + 4 * sl) = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        const int spr = ct.WS >> 2, S_w = BN * spr;
+#pragma unroll
+        for (int i = 0; i < NW; ++i) {
+            const int sl = i * 256 + tid;
+            int o = -2;
+            if (sl < S_w) {
+                const int n = qdiv(sl, ct.rSPR), k4 = sl - n * spr, k = 4 * k4;
+                if (k4 < (ct.KB >> 2))
+                    o = k < TC ? (n * g.Kp + (k >> ct.lcc) * g.C + (k & (ct.CC - 1))) * 4 : -1;
+            }
+            gw[i] = o;
+            if (o == -1) *(float4 *)(Wl + 4 * sl) = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    } else if (VEC) {
         Walk w(Pin, ct.rPin);
 #pragma unroll
         for (int i = 0; i < NIN; ++i) {
@@ -206,8 +261,9 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
             ww.next();
         }
     }
-    float4 rin[NIN], rw[NW];
+    float4 rin[DMA ? 1 : NIN], rw[DMA ? 1 : NW];
     auto load_chunk = [&](int c0) {
+        if (DMA) return;
 #pragma unroll
         for (int i = 0; i < NIN; ++i)
             rin[i] = gin[i] >= 0 ? *(const float4 *)(Xb + gin[i] + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -216,6 +272,7 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
             rw[i] = gw[i] >= 0 ? *(const float4 *)(Bb + gw[i] + c0) : make_float4(0.f, 0.f, 0.f, 0.f);
     };
     auto store_chunk = [&]() {
+        if (DMA) return;
 #pragma unroll
         for (int i = 0; i < NIN; ++i)
             if (lin[i] >= 0) *(float4 *)(In + lin[i]) = rin[i];
@@ -223,9 +280,25 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
         for (int i = 0; i < NW; ++i)
             if (lw[i] >= 0) *(float4 *)(Wl + lw[i]) = rw[i];
     };
+    // buffer extents: the block's image group (clipped to the images that exist) and
+    // its weight rows
+    const long nvg = n_img - img0 < ct.G ? n_img - img0 : ct.G;
+    const int xbytes = (int)(nvg * g.H * g.W * g.C * 4), wbytes = BN * g.Kp * 4;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    auto dma_chunk = [&](int c0) {
+#pragma unroll
+        for (int i = 0; i < NIN; ++i)
+            if (gin[i] >= 0) lds_dma16(Xb, xbytes, In + (i * 256 + wv * 64) * 4, gin[i] + 4 * c0);
+#pragma unroll
+        for (int i = 0; i < NW; ++i)
+            if (gw[i] >= 0) lds_dma16(Bb, wbytes, Wl + (i * 256 + wv * 64) * 4, gw[i] + 4 * c0);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    };
 
     const int kgrp = MM::grp(lane) * KPL;   // this lane's first k inside a 16-wide k block
-    if (VEC) {
+    if (VEC && DMA) {
+        dma_chunk(0);
+    } else if (VEC) {
         load_chunk(0);
         store_chunk();
     } else {
@@ -235,7 +308,7 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     __syncthreads();
     for (int ch = 0; ch < ct.nchunk; ++ch) {
         const bool more = VEC && ch + 1 < ct.nchunk;
-        if (more) load_chunk((ch + 1) * ct.CC);      // in flight during this chunk's MFMAs
+        if (more && !DMA) load_chunk((ch + 1) * ct.CC);      // in flight during this chunk's MFMAs
         for (int kb = 0; kb < ct.KB; kb += 16) {
             const int k = kb + kgrp;
             float af[FM][KPL], bf[FN][KPL];
@@ -272,7 +345,10 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
         }
         if (more) {
             __syncthreads();
-            store_chunk();
+            if (DMA)
+                dma_chunk((ch + 1) * ct.CC);
+            else
+                store_chunk();
             __syncthreads();
         }
     }
@@ -311,8 +387,8 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
         }
         return quad;
     };
-    tile_epilogue<Epi, MF, FM, FN>(epi, acc, ncol, bcol, g.N, rowfn4, lane, uniform && quad,
-                                   (int)(img0 + gfirst));
+    tile_epilogue<Epi, MF, FM, FN, true>(epi, acc, ncol, bcol, g.N, rowfn4, lane, uniform && quad,
+                                         (int)(img0 + gfirst));
 }
 
 // One thread per output pixel, up to NMAX output channels, VALU FMAs from LDS.
@@ -457,6 +533,8 @@ void set_tile_recips(const Geom &g, ConvTile &ct) {
     ct.rC4 = recip(ct.CC >> 2);
     ct.rTK = recip(ct.T * g.C);
     ct.rKB = recip(ct.KB);
+    ct.rSPP = recip(ct.CS >> 2);
+    ct.rSPR = recip(ct.WS >> 2);
 }
 
 bool same_shape(const GeomSet &gs) {
@@ -469,7 +547,7 @@ bool same_shape(const GeomSet &gs) {
 
 // Choose the channel chunk for the MFMA kernel (want = 0: the largest that fits, else
 // exactly want); returns LDS bytes or 0 if nothing fits.
-size_t plan_chunk(const Geom &g, int BN, int KPL, ConvTile &ct, int want = 0) {
+size_t plan_chunk(const Geom &g, int BN, int KPL, ConvTile &ct, int want = 0, bool dma = false) {
     if (g.C < 4) {
         ct.CC = g.C;
         ct.lcc = 0;
@@ -483,8 +561,11 @@ size_t plan_chunk(const Geom &g, int BN, int KPL, ConvTile &ct, int want = 0) {
             const size_t in = (size_t)ct.G * ct.IH * ct.IW * cs;
             const int kb = ((ct.T * cc + 15) / 16) * 16;
             const size_t w = (size_t)BN * (kb + 4);
-            const bool regs = (size_t)ct.G * ct.IH * ct.IW * (cc / 4) <= 256 * MAX_IN4 &&
-                              (size_t)BN * (kb / 4) <= 256 * MAX_W4;
+            const bool regs =
+                dma ? in / 4 <= 256 * DMA_IN4 && w / 4 <= 256 * DMA_W4 &&
+                          (size_t)ct.G * g.H * g.W * g.C * 4 < 0x7fffffffUL
+                    : (size_t)ct.G * ct.IH * ct.IW * (cc / 4) <= 256 * MAX_IN4 &&
+                          (size_t)BN * (kb / 4) <= 256 * MAX_W4;
             if (regs && (in + w + kb) * 4 <= LDS_BUDGET) { best = cc; break; }
         }
         if (!best) return 0;
@@ -514,22 +595,28 @@ template <class Epi, int MF, int BN, int NIN, int NW>
 hipError_t launch_slots(const GeomSet &gs, const ConvTile &ct, size_t lds, const float *X,
                         long n_img, const Epi &epi, hipStream_t st, dim3 grid) {
     if (gs.g[0].C % 4 == 0) {
-        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, true, NIN, NW>);
+        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, true, NIN, NW, false>);
         if (ok != hipSuccess) return ok;
-        hipLaunchKernelGGL((k_conv<Epi, MF, BN, true, NIN, NW>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+        hipLaunchKernelGGL((k_conv<Epi, MF, BN, true, NIN, NW, false>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
     } else {
-        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, false, NIN, NW>);
+        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, false, NIN, NW, false>);
         if (ok != hipSuccess) return ok;
-        hipLaunchKernelGGL((k_conv<Epi, MF, BN, false, NIN, NW>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+        hipLaunchKernelGGL((k_conv<Epi, MF, BN, false, NIN, NW, false>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
     }
     return hipGetLastError();
 }
 
 template <class Epi, int MF, int BN>
 hipError_t launch_mfma(const GeomSet &gs, const ConvTile &ct, size_t lds, const float *X, long n_img,
-                       const Epi &epi, hipStream_t st) {
+                       const Epi &epi, hipStream_t st, bool dma) {
     const long groups = (n_img + ct.G - 1) / ct.G;
     const dim3 grid((unsigned)(groups * ct.tiles_y * (gs.g[0].N / BN) * gs.n));   // xcd_tile order
+    if (dma) {   // planned only with C % 4 == 0
+        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, true, DMA_IN4, DMA_W4, true>);
+        if (ok != hipSuccess) return ok;
+        hipLaunchKernelGGL((k_conv<Epi, MF, BN, true, DMA_IN4, DMA_W4, true>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+        return hipGetLastError();
+    }
     const bool small = gs.g[0].C % 4 == 0 &&
                        (size_t)ct.G * ct.IH * ct.IW * (ct.CC / 4) <= 256 * SMALL_IN4 &&
                        (size_t)BN * (ct.KB / 4) <= 256 * SMALL_W4;
@@ -546,7 +633,7 @@ int bn_for(int N) {
 
 template <class Epi>
 hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &epi, hipStream_t st,
-                      int want_cc, bool *used) {
+                      int want_cc, int mode, bool *used) {
     *used = false;
     const Geom &g = gs.g[0];
     if (g.H == 1 && g.W == 1 && g.kh == 1 && g.kw == 1) return hipSuccess;  // dense: GEMM
@@ -578,36 +665,37 @@ hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &
     const int BN = bn_for(g.N);
     if (!BN) return hipSuccess;
     const int KPL = BN == 16 ? Mma<16>::KPL : Mma<32>::KPL;
-    const size_t lds = plan_chunk(g, BN, KPL, ct, want_cc);
+    const bool dma = mode == 1 && g.C % 4 == 0;
+    const size_t lds = plan_chunk(g, BN, KPL, ct, want_cc, dma);
     if (!lds) return hipSuccess;
     set_tile_recips(g, ct);
     *used = true;
-    if (BN == 16) return launch_mfma<Epi, 16, 16>(gs, ct, lds, X, n_img, epi, st);
-    if (BN == 32) return launch_mfma<Epi, 32, 32>(gs, ct, lds, X, n_img, epi, st);
-    return launch_mfma<Epi, 32, 64>(gs, ct, lds, X, n_img, epi, st);
+    if (BN == 16) return launch_mfma<Epi, 16, 16>(gs, ct, lds, X, n_img, epi, st, dma);
+    if (BN == 32) return launch_mfma<Epi, 32, 32>(gs, ct, lds, X, n_img, epi, st, dma);
+    return launch_mfma<Epi, 32, 64>(gs, ct, lds, X, n_img, epi, st, dma);
 }
 
 }  // namespace
 
 hipError_t direct_relax(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
-                        hipStream_t st, int cc, bool *used) {
-    return try_direct(gs, A, n_img, EpiRelax{p}, st, cc, used);
+                        hipStream_t st, int cc, int mode, bool *used) {
+    return try_direct(gs, A, n_img, EpiRelax{p}, st, cc, mode, used);
 }
 hipError_t direct_conc(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,
-                       hipStream_t st, int cc, bool *used) {
-    return try_direct(gs, A, n_img, EpiConc{p}, st, cc, used);
+                        hipStream_t st, int cc, int mode, bool *used) {
+    return try_direct(gs, A, n_img, EpiConc{p}, st, cc, mode, used);
 }
 hipError_t direct_adj(const GeomSet &gs, const float *A, long n_img, const AdjParams &p,
-                      hipStream_t st, int cc, bool *used) {
-    return try_direct(gs, A, n_img, EpiAdj{p}, st, cc, used);
+                        hipStream_t st, int cc, int mode, bool *used) {
+    return try_direct(gs, A, n_img, EpiAdj{p}, st, cc, mode, used);
 }
 
 hipError_t direct_fwd(const GeomSet &gs, const float *A, long n_img, const FwdParams &p,
-                      hipStream_t st, int cc, bool *used) {
-    return try_direct(gs, A, n_img, EpiFwd{p}, st, cc, used);
+                        hipStream_t st, int cc, int mode, bool *used) {
+    return try_direct(gs, A, n_img, EpiFwd{p}, st, cc, mode, used);
 }
 
-int direct_candidates(const GeomSet &gs, int *cc, int cap) {
+int direct_candidates(const GeomSet &gs, int *cc, int *mode, int cap) {
     const Geom &g = gs.g[0];
     if (g.H == 1 && g.W == 1 && g.kh == 1 && g.kw == 1) return 0;
     if (!same_shape(gs)) return 0;
@@ -616,6 +704,7 @@ int direct_candidates(const GeomSet &gs, int *cc, int cap) {
     if (g.N <= 4) {
         if (g.C % 4 != 0) return 0;
         cc[0] = 0;
+        mode[0] = -1;
         return cap > 0 ? 1 : 0;
     }
     const int BN = bn_for(g.N);
@@ -624,12 +713,20 @@ int direct_candidates(const GeomSet &gs, int *cc, int cap) {
     if (g.C < 4) {
         if (!plan_chunk(g, BN, KPL, ct)) return 0;
         cc[0] = 0;
+        mode[0] = -1;
         return cap > 0 ? 1 : 0;
     }
+    // each channel chunk with register staging (mode -1) and with LDS DMA staging (1)
     int n = 0;
-    for (int c = 64; c >= KPL && n < cap; c >>= 1) {
-        ConvTile t = ct;
-        if (g.C % c == 0 && plan_chunk(g, BN, KPL, t, c)) cc[n++] = c;
+    for (int c = 64; c >= KPL; c >>= 1) {
+        for (int m = -1; m <= 1 && n < cap; m += 2) {
+            ConvTile t = ct;
+            if (g.C % c == 0 && plan_chunk(g, BN, KPL, t, c, m == 1)) {
+                cc[n] = c;
+                mode[n] = m;
+                ++n;
+            }
+        }
     }
     return n;
 }

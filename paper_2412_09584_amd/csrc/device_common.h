@@ -109,6 +109,9 @@ struct EpiRelax {
         const float bt = lam * bcol;
         r0 += bt + off;
         r1 += fabsf(bt) + fabsf(off);
+        // the sums are formed in order; without this the compiler defers them past the
+        // tile's stores and keeps every lam and offset of the tile live in registers
+        asm volatile("" : "+v"(r0), "+v"(r1));
         at(rc.out, j) = lam;
         if (rc.save && t.w > 0.f) at(rc.save, (int)t.w - 1) = g;    // unstable: compact slot
     }
@@ -134,6 +137,7 @@ struct EpiConc {
                          float &r0, float &r1) const {
         r0 += g * cr.x - fabsf(g) * cr.y;
         r1 += fabsf(g) * (fabsf(cr.x) + cr.y);
+        asm volatile("" : "+v"(r0), "+v"(r1));   // in order, as in EpiRelax
         if (rc.save) at(rc.save, j) = g;
         if (rc.emit) at(rc.emit, n * p.hw + dpix) = g;
     }
@@ -230,7 +234,7 @@ __device__ inline void reduce_wave_atomic(float u0, float u1, long img, int lane
 // FAST: every row of the wave lies in img uimg and every column is in range (the
 // common case of a convolution tile), so the pointers are resolved once per wave, no
 // element is masked and the row sums collapse into one atomic pair per wave.
-template <bool FAST, class Epi, int MF, int FM, int FN, class Acc, class RowFn>
+template <bool FAST, bool LEAN, class Epi, int MF, int FM, int FN, class Acc, class RowFn>
 __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], const int (&ncol)[FN],
                                           const float (&bcol)[FN], int N, const RowFn &rowfn4,
                                           int lane, int uimg) {
@@ -304,6 +308,35 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
         if (NR > 0) reduce_wave_atomic(u0, u1, uimg, lane, epi.red0(), epi.red1());
         return;
     }
+    if (LEAN) {
+        // one element at a time: the rare tiles of a convolution that straddle images
+        // or the end of the batch; few registers, so the common path keeps its occupancy
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+#pragma unroll
+            for (int vg = 0; vg < NACC / 4; ++vg) {
+                int img[4], dp[4];
+                rowfn4(i, vg, img, dp);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float r0 = 0.f, r1 = 0.f;
+                    if (img[q] >= 0) {
+                        const typename Epi::Row rc = epi.row(img[q]);
+#pragma unroll
+                        for (int j = 0; j < FN; ++j)
+                            if (ncol[j] < N) {
+                                typename Epi::Pre pr = epi.pre(rc, dp[q] * N + ncol[j]);
+                                epi.pre2(rc, pr);
+                                epi.post(pr, rc, dp[q], ncol[j], dp[q] * N + ncol[j], bcol[j],
+                                         acc[i][j][vg * 4 + q], r0, r1);
+                            }
+                    }
+                    if (NR > 0) reduce_row_atomic<MF>(r0, r1, img[q], lane, epi.red0(), epi.red1());
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < FM; ++i) {
 #pragma unroll
@@ -353,14 +386,16 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
 }
 
 // fast: see tile_epilogue_impl (wave-uniform).
-template <class Epi, int MF, int FM, int FN, class Acc, class RowFn>
+// LEAN: the other tiles take the one-element-at-a-time path (convolution tiles, where
+// they are rare) instead of the batched one (dense products, where every tile is such).
+template <class Epi, int MF, int FM, int FN, bool LEAN = false, class Acc, class RowFn>
 __device__ inline void tile_epilogue(const Epi &epi, Acc (&acc)[FM][FN], const int (&ncol)[FN],
                                      const float (&bcol)[FN], int N, const RowFn &rowfn4, int lane,
                                      bool fast, int uimg) {
     if (fast)
-        tile_epilogue_impl<true, Epi, MF, FM, FN>(epi, acc, ncol, bcol, N, rowfn4, lane, uimg);
+        tile_epilogue_impl<true, false, Epi, MF, FM, FN>(epi, acc, ncol, bcol, N, rowfn4, lane, uimg);
     else
-        tile_epilogue_impl<false, Epi, MF, FM, FN>(epi, acc, ncol, bcol, N, rowfn4, lane, -1);
+        tile_epilogue_impl<false, LEAN, Epi, MF, FM, FN>(epi, acc, ncol, bcol, N, rowfn4, lane, -1);
 }
 
 }  // namespace dev

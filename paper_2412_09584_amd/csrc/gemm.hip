@@ -261,8 +261,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
         return false;
     };
     const bool fast = !DENSE && uniform && quad && n0 + BN <= g.N;
-    tile_epilogue<Epi, MF, FM, FN>(epi, acc, ncol, bcol, g.N, rowfn4, lane, fast,
-                                   fast ? (int)imgw : -1);
+    tile_epilogue<Epi, MF, FM, FN, !DENSE>(epi, acc, ncol, bcol, g.N, rowfn4, lane, fast,
+                                           fast ? (int)imgw : -1);
 }
 
 // ---------------------------------------------------------------------- dispatch
@@ -353,11 +353,11 @@ hipError_t gemm_fwd_cfg(const GeomSet &gs, const float *A, long n_img, const Fwd
 
 int plan_candidates(const GeomSet &gs, Plan *out, int cap) {
     int n = 0;
-    int cc[kMaxCandidates];
-    const int nd = direct_candidates(gs, cc, kMaxCandidates);
+    int cc[kMaxCandidates], mode[kMaxCandidates];
+    const int nd = direct_candidates(gs, cc, mode, kMaxCandidates);
     for (int i = 0; i < nd && n < cap; ++i) {
         out[n].path = 1;
-        out[n].cfg = -1;
+        out[n].cfg = mode[i];
         out[n].cc = cc[i];
         ++n;
     }
@@ -377,7 +377,8 @@ int plan_candidates(const GeomSet &gs, Plan *out, int cap) {
                     hipStream_t st, const Plan &plan) {                                      \
         if (plan.path != 2) {                                                                \
             bool used = false;                                                               \
-            const hipError_t e = DIRECT(gs, A, n_img, p, st, plan.path == 1 ? plan.cc : 0, &used); \
+            const hipError_t e = DIRECT(gs, A, n_img, p, st, plan.path == 1 ? plan.cc : 0,      \
+                                        plan.cfg, &used);                                     \
             if (used || e != hipSuccess) return e;                                           \
         }                                                                                    \
         return CFG(gs, A, n_img, p, st, plan.path == 2 ? plan.cfg : -1);                     \

@@ -164,7 +164,7 @@ def _cached_crown(key, net, x_lo, x_hi):
     return _ORACLE_CACHE[key]
 
 
-@pytest.mark.parametrize("path", ["auto", "gemm"])
+@pytest.mark.parametrize("path", ["auto", "gemm", "dma"])
 @pytest.mark.parametrize("gi", range(len(CNN_GEOMS)))
 def test_cnn_small_end_to_end(mod, gi, path):
     N, B = mod
@@ -176,6 +176,8 @@ def test_cnn_small_end_to_end(mod, gi, path):
     bn = N.BoundNet(net, n, 1 << 16)
     if path == "gemm":
         B.bound_set_options(bn.handle, B.BOUND_OPT_GEMM_ONLY)
+    elif path == "dma":
+        B.bound_set_options(bn.handle, B.BOUND_OPT_DIRECT_DMA)
     glo, ghi = bn.crown_bounds(x_lo, x_hi)
     gl, gu = bn.spec_bounds(C, glo, ghi, x_lo, x_hi)
     L = len(net)
@@ -260,7 +262,7 @@ def _oracle_unit(net, C, lo_row, hi_row, x_lo, x_hi, alpha_row, sp, q0, q1, beta
     return low, np.concatenate(ga), gb
 
 
-@pytest.mark.parametrize("kind", ["mlp", "cnn", "cnn_direct", "cnn_direct_gemm"])
+@pytest.mark.parametrize("kind", ["mlp", "cnn", "cnn_direct", "cnn_direct_gemm", "cnn_direct_dma"])
 def test_alpha_beta_pass_and_grad(mod, kind):
     N, B = mod
     if kind == "mlp":
@@ -286,6 +288,8 @@ def test_alpha_beta_pass_and_grad(mod, kind):
     bn = N.BoundNet(net, n, 4096, 4096)
     if kind.endswith("_gemm"):
         B.bound_set_options(bn.handle, B.BOUND_OPT_GEMM_ONLY)
+    elif kind.endswith("_dma"):
+        B.bound_set_options(bn.handle, B.BOUND_OPT_DIRECT_DMA)
     spd = N.splits_to_device(sp)
     gl, _ = bn.spec_bounds(Cs, dev(f32(lo)), dev(f32(hi)), x_lo[root_of], x_hi[root_of],
                            alpha=dev(alpha), bound_of=dev(root_of, torch.int32), splits=spd,
@@ -531,7 +535,8 @@ def test_ragged_batch_one_launch_vs_chunked(mod, golden_cnn):
 
 
 def test_direct_and_gemm_paths_agree_full_size(mod, golden_cnn):
-    """The 4096-subdomain pass + gradient through both kernel paths (same inputs)."""
+    """The 4096-subdomain pass + gradient through the kernel paths (direct convolution with
+    register or LDS DMA staging, implicit GEMM) on the same inputs."""
     N, B = mod
     w = W.cnn_cifar(1)
     lo = f32(golden_cnn["lo"])[None]
@@ -544,7 +549,7 @@ def test_direct_and_gemm_paths_agree_full_size(mod, golden_cnn):
     beta = dev(W.random_beta(sp.nnz, 9, 7))
     bn = N.BoundNet(w.net, n, n * 9, n * 9)
     out = []
-    for opt in (0, B.BOUND_OPT_GEMM_ONLY):
+    for opt in (0, B.BOUND_OPT_GEMM_ONLY, B.BOUND_OPT_DIRECT_DMA):
         B.bound_set_options(bn.handle, opt)
         gl, _ = bn.spec_bounds(np.repeat(w.spec, n, 0), dev(lo), dev(hi), np.repeat(w.x_lo, n, 0),
                                np.repeat(w.x_hi, n, 0), alpha=alpha, bound_of=dev(root_of, torch.int32),
@@ -562,6 +567,13 @@ def test_direct_and_gemm_paths_agree_full_size(mod, golden_cnn):
     sb = max(np.max(np.abs(out[1][2])), 1e-30)
     print(f"alpha-grad entries off by >1e-5: {np.mean(da > 1e-5 * sa):.2e}; "
           f"beta-grad: {np.mean(db > 1e-5 * sb):.2e}; worst {np.max(da / sa):.2e} / {np.max(db) / sb:.2e}")
+    assert np.mean(da > 1e-5 * sa) <= 1e-4 and np.max(da / sa) <= 1e-3
+    assert np.mean(db > 1e-5 * sb) <= 1e-3 and np.max(db) / sb <= 1e-3
+    # tiles staged by LDS DMA: the same products (the channel chunking, and with it the
+    # summation order, may differ), same criteria against the register-staged kernels
+    close(out[2][0], out[0][0], rel=1e-5, what="lower dma vs registers")
+    da = np.abs(out[2][1] - out[0][1])
+    db = np.abs(out[2][2] - out[0][2])
     assert np.mean(da > 1e-5 * sa) <= 1e-4 and np.max(da / sa) <= 1e-3
     assert np.mean(db > 1e-5 * sb) <= 1e-3 and np.max(db) / sb <= 1e-3
 
