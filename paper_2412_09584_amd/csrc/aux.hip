@@ -133,31 +133,86 @@ __global__ void k_fill(float *p, long n, float v) {
     if (i < n) p[i] = v;
 }
 
-// A block writes PREP_SPAN consecutive records (internal order): the C-major reads of
-// alpha / lo / hi then revisit the same cache lines within one block, on one XCD.
-constexpr int PREP_SPAN = 2048;
+// Relaxation records of one instance: a block covers a tile of one ReLU layer -- P
+// pixels x all C channels of a convolutional layer (C <= PREP_TILE), or PREP_TILE
+// consecutive neurons of a dense one -- and moves the bounds and alpha, stored C-major,
+// into the records, stored pixel-major, through LDS: both the reads and the 16-byte
+// record writes are contiguous across the block.  Layers with more channels than a tile
+// take one pixel's channels per block with direct (strided) reads.
+constexpr int PREP_TILE = 1024;
 
-__global__ void k_prep_tables(const NetShapes ns, int used, long T, long n_relu,
-                              const float *lo, const float *hi, const int32_t *bound_of,
-                              const float *alpha, Relax *tab, int32_t *infeas, long total,
-                              int n_bounds, const int32_t *slot, int per_inst, int32_t *srow) {
-    const long e0 = (long)blockIdx.x * PREP_SPAN;
-    for (long e = e0 + threadIdx.x; e < e0 + PREP_SPAN && e < total; e += TPB) {
-        const long inst = e / T, jg = e - inst * T;
-        if (jg == 0) {
-            infeas[inst] = 0;
-            srow[inst] = per_inst ? (int32_t)inst : (int32_t)bound_row(bound_of, inst, n_bounds);
-        }
-        const int m = layer_of(ns, used, jg);
-        const LayerShape &L = ns.l[m];
-        const long j = jg - L.off;
-        const long jn = to_cmajor(j, L.C, L.HW);
-        const long b = bound_row(bound_of, inst, n_bounds);
-        const float l = lo[b * n_relu + L.off + jn], u = hi[b * n_relu + L.off + jn];
-        const float a = alpha ? alpha[inst * n_relu + L.off + jn] : (u >= -l ? 1.f : 0.f);
-        const int k = slot[(per_inst ? inst : b) * n_relu + L.off + j];
-        tab[inst * n_relu + L.off + j] = relax_of(l, u, a, k);
+__device__ inline int prep_tiles(const LayerShape &L) {
+    if (L.HW == 1) return (int)((L.d + PREP_TILE - 1) / PREP_TILE);
+    if (L.C > PREP_TILE) return L.HW * ((L.C + PREP_TILE - 1) / PREP_TILE);
+    const int P = PREP_TILE / L.C;
+    return (L.HW + P - 1) / P;
+}
+
+__global__ __launch_bounds__(256) void k_prep_tables(const NetShapes ns, int used, long n_relu,
+                                                     const float *lo, const float *hi,
+                                                     const int32_t *bound_of, const float *alpha,
+                                                     Relax *tab, int32_t *infeas, int n_bounds,
+                                                     const int32_t *slot, int per_inst,
+                                                     int32_t *srow) {
+    __shared__ float sh[3 * PREP_TILE];
+    const long inst = blockIdx.x;   // consecutive blocks: other instances, same bounds rows
+    int t = blockIdx.y, m = 0;
+    for (; m < used; ++m) {
+        const int nt = prep_tiles(ns.l[m]);
+        if (t < nt) break;
+        t -= nt;
     }
+    if (m >= used) return;
+    const LayerShape &L = ns.l[m];
+    const long b = bound_row(bound_of, inst, n_bounds);
+    if (blockIdx.y == 0 && threadIdx.x == 0) {
+        infeas[inst] = 0;
+        srow[inst] = per_inst ? (int32_t)inst : (int32_t)b;
+    }
+    const float *lr = lo + b * n_relu + L.off, *hr = hi + b * n_relu + L.off;
+    const float *ar = alpha ? alpha + inst * n_relu + L.off : nullptr;
+    const int32_t *kr = slot + (per_inst ? inst : b) * n_relu + L.off;
+    Relax *tr = tab + inst * n_relu + L.off;
+    auto record = [&](long j, float l, float u, float a) {
+        if (!ar) a = u >= -l ? 1.f : 0.f;
+        tr[j] = relax_of(l, u, a, kr[j]);
+    };
+    if (L.HW == 1) {                        // dense: the two orders coincide
+        const long j0 = (long)t * PREP_TILE;
+        for (int e = threadIdx.x; e < PREP_TILE; e += 256) {
+            const long j = j0 + e;
+            if (j < L.d) record(j, lr[j], hr[j], ar ? ar[j] : 0.f);
+        }
+        return;
+    }
+    if (L.C > PREP_TILE) {                  // one pixel, a chunk of its channels
+        const int nch = (L.C + PREP_TILE - 1) / PREP_TILE;
+        const int p = t / nch, c0 = (t - p * nch) * PREP_TILE;
+        for (int e = threadIdx.x; e < PREP_TILE && c0 + e < L.C; e += 256) {
+            const long jn = (long)(c0 + e) * L.HW + p;
+            record((long)p * L.C + c0 + e, lr[jn], hr[jn], ar ? ar[jn] : 0.f);
+        }
+        return;
+    }
+    const int C = L.C, P = PREP_TILE / C, p0 = t * P;
+    const int np = L.HW - p0 < P ? L.HW - p0 : P;     // pixels of this tile
+    const float rP = 1.0f / (float)P;
+    // C-major reads: e -> (c, pixel p0 + q), contiguous in q
+    for (int e = threadIdx.x; e < C * P; e += 256) {
+        // e / P through one FP32 multiply by fl(1 / P): exact for e < 2^21
+        const int c = (int)(((float)e + 0.5f) * rP), q = e - c * P;
+        if (q < np) {
+            const long jn = (long)c * L.HW + p0 + q;
+            const int s = q * C + c;
+            sh[s] = lr[jn];
+            sh[PREP_TILE + s] = hr[jn];
+            sh[2 * PREP_TILE + s] = ar ? ar[jn] : 0.f;
+        }
+    }
+    __syncthreads();
+    // pixel-major writes: record p0 * C + e
+    for (int e = threadIdx.x; e < np * C; e += 256)
+        record((long)p0 * C + e, sh[e], sh[PREP_TILE + e], sh[2 * PREP_TILE + e]);
 }
 
 __global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, long n_relu,
@@ -632,9 +687,16 @@ hipError_t launch_prep_tables(const NetShapes &ns, int used, int n_inst, long n_
     hipLaunchKernelGGL(k_prep_slots, dim3((unsigned)rows, (unsigned)used), dim3(256), 0, st, ns,
                        n_relu, lo, hi, bound_of, n_bounds, per_inst ? 1 : 0, slot, slot_inv,
                        slot_count);
-    const long total = T * n_inst;
-    hipLaunchKernelGGL(k_prep_tables, dim3(blocks_for(total, PREP_SPAN)), dim3(TPB), 0, st, ns, used, T,
-                       n_relu, lo, hi, bound_of, alpha, tab, infeas, total, n_bounds, slot,
+    long tiles = 0;
+    for (int m = 0; m < used; ++m) {
+        const LayerShape &L = ns.l[m];
+        tiles += L.HW == 1 ? (L.d + PREP_TILE - 1) / PREP_TILE
+                 : L.C > PREP_TILE ? (long)L.HW * ((L.C + PREP_TILE - 1) / PREP_TILE)
+                                   : (L.HW + PREP_TILE / L.C - 1) / (PREP_TILE / L.C);
+    }
+    if (tiles > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_prep_tables, dim3((unsigned)n_inst, (unsigned)tiles), dim3(256), 0, st, ns,
+                       used, n_relu, lo, hi, bound_of, alpha, tab, infeas, n_bounds, slot,
                        per_inst ? 1 : 0, srow);
     return hipGetLastError();
 }
