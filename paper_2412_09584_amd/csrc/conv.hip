@@ -94,6 +94,10 @@ __device__ inline void stage_weights(float *Wl, const ConvTile &ct, const Geom &
 constexpr int MAX_IN4 = 8, MAX_W4 = 6;
 // DMA staging: slots per thread (input, weights), one offset register each
 constexpr int DMA_IN4 = 12, DMA_W4 = 6;
+// ... and a smaller set for tiles that need no more (fewer set-up instructions)
+constexpr int DMA_SMALL_IN4 = 8, DMA_SMALL_W4 = 4;
+// input slots of the narrow-output VALU kernel's DMA staging
+constexpr int VALU_DMA_IN4 = 8;
 // dword 3 of a raw buffer resource (32-bit data format; no swizzle, no index stride)
 constexpr int BUF_FLAGS = 0x00020000;
 
@@ -392,7 +396,35 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
 }
 
 // One thread per output pixel, up to NMAX output channels, VALU FMAs from LDS.
-template <class Epi, int NMAX>
+// Input tile of all C channels (CC = C, C % 4 == 0) by LDS DMA in one pass: slot
+// s = i * 256 + tid as in k_conv; spatial padding is written as zeros, the row padding
+// column not at all; images past the batch read nothing (their pixels are dropped).
+template <int NIN>
+__device__ inline void dma_input_tile(float *In, const ConvTile &ct, const Geom &g, const float *Xb,
+                                      int xbytes, int iy0, int ix0) {
+    const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int spp = ct.CS >> 2, S_in = ct.in_floats >> 2, c4n = ct.CC >> 2;
+#pragma unroll
+    for (int i = 0; i < NIN; ++i) {
+        const int sl = i * 256 + tid;
+        if (sl < S_in) {
+            const int pix = qdiv(sl, ct.rSPP), c4 = sl - pix * spp;
+            const int row = qdiv(pix, ct.rIW), ix = pix - row * ct.IW;
+            const int gi = qdiv(row, ct.rIH), iy = row - gi * ct.IH;
+            const int y = iy0 + iy, x = ix0 + ix;
+            if (c4 < c4n) {
+                if ((unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W)
+                    lds_dma16(Xb, xbytes, In + (i * 256 + wv * 64) * 4,
+                              (((gi * g.H + y) * g.W + x) * g.C + 4 * c4) * 4);
+                else
+                    *(float4 *)(In + 4 * sl) = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+    }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+template <class Epi, int NMAX, bool DMA>
 __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvTile ct,
                                                    const float *__restrict__ X, const long n_img,
                                                    const Epi epi) {
@@ -411,7 +443,14 @@ __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvT
     if (img0 >= n_img) return;
     const int oyb = band * ct.TR;
     const int tile_px = ct.TR * g.OW;
-    stage_input<true>(In, ct, g, X, img0, n_img, oyb * g.stride - g.pad_y, -g.pad_x, 0);
+    if (DMA) {
+        const long nvg = n_img - img0 < ct.G ? n_img - img0 : ct.G;
+        dma_input_tile<VALU_DMA_IN4>(In, ct, g, X + img0 * (long)g.H * g.W * g.C,
+                                     (int)(nvg * g.H * g.W * g.C * 4), oyb * g.stride - g.pad_y,
+                                     -g.pad_x);
+    } else {
+        stage_input<true>(In, ct, g, X, img0, n_img, oyb * g.stride - g.pad_y, -g.pad_x, 0);
+    }
     __syncthreads();
     const int gi = qdiv(tid, ct.rTP), q = tid - gi * tile_px;
     const int py = qdiv(q, g.rOW), px = q - py * g.OW;
@@ -612,9 +651,20 @@ hipError_t launch_mfma(const GeomSet &gs, const ConvTile &ct, size_t lds, const 
     const long groups = (n_img + ct.G - 1) / ct.G;
     const dim3 grid((unsigned)(groups * ct.tiles_y * (gs.g[0].N / BN) * gs.n));   // xcd_tile order
     if (dma) {   // planned only with C % 4 == 0
-        static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, true, DMA_IN4, DMA_W4, true>);
-        if (ok != hipSuccess) return ok;
-        hipLaunchKernelGGL((k_conv<Epi, MF, BN, true, DMA_IN4, DMA_W4, true>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+        const bool dsmall = ct.in_floats / 4 <= 256 * DMA_SMALL_IN4 &&
+                            BN * ct.WS / 4 <= 256 * DMA_SMALL_W4;
+        if (dsmall) {
+            static const hipError_t ok =
+                allow_lds(k_conv<Epi, MF, BN, true, DMA_SMALL_IN4, DMA_SMALL_W4, true>);
+            if (ok != hipSuccess) return ok;
+            hipLaunchKernelGGL((k_conv<Epi, MF, BN, true, DMA_SMALL_IN4, DMA_SMALL_W4, true>), grid,
+                               dim3(256), lds, st, gs, ct, X, n_img, epi);
+        } else {
+            static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, true, DMA_IN4, DMA_W4, true>);
+            if (ok != hipSuccess) return ok;
+            hipLaunchKernelGGL((k_conv<Epi, MF, BN, true, DMA_IN4, DMA_W4, true>), grid, dim3(256),
+                               lds, st, gs, ct, X, n_img, epi);
+        }
         return hipGetLastError();
     }
     const bool small = gs.g[0].C % 4 == 0 &&
@@ -650,14 +700,25 @@ hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &
         if (lds > LDS_BUDGET) return hipSuccess;
         set_tile_recips(g, ct);
         const dim3 grid((unsigned)(groups * ct.tiles_y * gs.n));   // xcd_tile order
-        if (g.N == 3) {   // RGB input layers: no idle fourth output
-            static const hipError_t ok3 = allow_lds(k_conv_valu<Epi, 3>);
-            if (ok3 != hipSuccess) return ok3;
-            hipLaunchKernelGGL((k_conv_valu<Epi, 3>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
-        } else {
-            static const hipError_t ok = allow_lds(k_conv_valu<Epi, 4>);
+        // DMA staging when asked for and the tile fits its slots (int offsets inside a group)
+        const bool dma = mode == 1 && ct.in_floats / 4 <= 256 * VALU_DMA_IN4 &&
+                         (size_t)ct.G * g.H * g.W * g.C * 4 < 0x7fffffffUL;
+        if (g.N == 3 && dma) {   // RGB input layers: no idle fourth output
+            static const hipError_t ok = allow_lds(k_conv_valu<Epi, 3, true>);
             if (ok != hipSuccess) return ok;
-            hipLaunchKernelGGL((k_conv_valu<Epi, 4>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+            hipLaunchKernelGGL((k_conv_valu<Epi, 3, true>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+        } else if (g.N == 3) {
+            static const hipError_t ok = allow_lds(k_conv_valu<Epi, 3, false>);
+            if (ok != hipSuccess) return ok;
+            hipLaunchKernelGGL((k_conv_valu<Epi, 3, false>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+        } else if (dma) {
+            static const hipError_t ok = allow_lds(k_conv_valu<Epi, 4, true>);
+            if (ok != hipSuccess) return ok;
+            hipLaunchKernelGGL((k_conv_valu<Epi, 4, true>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
+        } else {
+            static const hipError_t ok = allow_lds(k_conv_valu<Epi, 4, false>);
+            if (ok != hipSuccess) return ok;
+            hipLaunchKernelGGL((k_conv_valu<Epi, 4, false>), grid, dim3(256), lds, st, gs, ct, X, n_img, epi);
         }
         *used = true;
         return hipGetLastError();
@@ -703,9 +764,12 @@ int direct_candidates(const GeomSet &gs, int *cc, int *mode, int cap) {
     if (!plan_tile(g, ct)) return 0;
     if (g.N <= 4) {
         if (g.C % 4 != 0) return 0;
-        cc[0] = 0;
-        mode[0] = -1;
-        return cap > 0 ? 1 : 0;
+        int n = 0;
+        for (int m = -1; m <= 1 && n < cap; m += 2) {
+            cc[n] = 0;
+            mode[n++] = m;
+        }
+        return n;
     }
     const int BN = bn_for(g.N);
     if (!BN) return 0;
