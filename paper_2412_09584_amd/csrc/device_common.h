@@ -251,7 +251,7 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
         rw = epi.row(__builtin_amdgcn_readfirstlane(uimg));
         constexpr int NG = FM * (NACC / 4);
         constexpr int GREG = FN * 4 * (int)sizeof(typename Epi::Pre) / 4;
-        constexpr int DEPTH = 3 * GREG <= 64 ? 2 : (2 * GREG <= 48 ? 1 : 0);
+        constexpr int DEPTH = 2 * GREG <= 48 ? 1 : 0;
         using PreG = typename Epi::Pre[FN][4];
         auto load1 = [&](int g, int (&dp)[4], PreG &pre) {
             int img[4];
