@@ -110,7 +110,7 @@ struct Plan {
     int cfg = -1;
     int cc = 0;
 };
-constexpr int kMaxCandidates = 16;
+constexpr int kMaxCandidates = 24;
 
 hipError_t gemm_relax(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
                       hipStream_t st, const Plan &plan);

@@ -299,8 +299,10 @@ hipError_t launch_cfg(const GeomSet &gs, const float *A, long n_img, const Epi &
 // Tile configurations: {MFMA size, BM, BN, wave grid}.
 //   0: 32x32 MFMA, 128x128, 2x2   1: 32, 128x64, 2x2    2: 32, 256x32, 4x1
 //   3: 16x16 MFMA, 256x16, 4x1    4: 32, 256x64, 4x1    5: 32, 256x128, 4x1
-constexpr int kGemmCfgs = 6;
-const int kCfgBN[kGemmCfgs] = {128, 64, 32, 16, 64, 128};
+//   6: 32, 128x32, 4x1 (one 32x32 tile per wave: fewest registers)
+//   7: 16x16 MFMA, 128x32, 2x2    8: 32, 128x64, 4x1
+constexpr int kGemmCfgs = 9;
+const int kCfgBN[kGemmCfgs] = {128, 64, 32, 16, 64, 128, 32, 32, 64};
 
 int default_cfg(int N) {
     if (N >= 128) return 0;
@@ -319,6 +321,9 @@ hipError_t dispatch(const GeomSet &gs, const float *A, long n_img, const Epi &ep
     case 2: return launch_cfg<Epi, 32, 256, 32, 4, 1>(gs, A, n_img, epi, st);
     case 3: return launch_cfg<Epi, 16, 256, 16, 4, 1>(gs, A, n_img, epi, st);
     case 4: return launch_cfg<Epi, 32, 256, 64, 4, 1>(gs, A, n_img, epi, st);
+    case 6: return launch_cfg<Epi, 32, 128, 32, 4, 1>(gs, A, n_img, epi, st);
+    case 7: return launch_cfg<Epi, 16, 128, 32, 2, 2>(gs, A, n_img, epi, st);
+    case 8: return launch_cfg<Epi, 32, 128, 64, 4, 1>(gs, A, n_img, epi, st);
     default: return launch_cfg<Epi, 32, 256, 128, 4, 1>(gs, A, n_img, epi, st);
     }
 }
