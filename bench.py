@@ -56,6 +56,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the kernel autotuner")
+    ap.add_argument("--plans", default=None,
+                    help="JSON line of an earlier run: reuse its tuned kernel plans (its "
+                         "'autotune' field) instead of tuning, so that profiler runs time the "
+                         "same kernels")
     ap.add_argument("--bab-iters", type=int, default=10,
                     help="iterations of the branch-and-bound planning loop timed after the "
                          "main measurement (0: skip)")
@@ -126,7 +130,15 @@ def main():
         B.bound_adam(beta, gb, mb, vb, t, lr, grad_scale=-1.0, clip_lo=0.0, stream=stream)
 
     tune_log = None
-    if not args.no_tune:
+    pinned = None
+    if args.plans:
+        with open(args.plans) as f:
+            pinned = json.loads(f.read().strip().splitlines()[-1])["autotune"]
+        for key, plan in pinned.items():
+            path, cfg, cc = plan.split()[:3]
+            B.bound_set_plan(bn.handle, key[0], int(key[1:]), 1 if path == "direct" else 2,
+                             int(cfg.split("=")[1]), int(cc.split("=")[1]))
+    elif not args.no_tune:
         tune_log = B.bound_autotune(bn.handle, n, R, L, grad_lower=ones, spec=C, lo=lo, hi=hi,
                                     n_bounds=args.roots, bound_of=bof, alpha=alpha,
                                     split_off=spd["off"], split_idx=spd["idx"],
@@ -254,7 +266,7 @@ def main():
                       "subdomains": n, "rows": R, "split_nnz": sp.nnz, "parallelism": "none"},
            "tflops_step": tflops, "flop_per_subdomain": flop_unit, "wall_s": wall,
            "plain": plain, "roofline": roofline, "kernel_ms_per_step": breakdown,
-           "autotune": _tuned(tune_log), "bab_loop": bab,
+           "autotune": _tuned(tune_log) if pinned is None else pinned, "bab_loop": bab,
            "cpu_baseline": cpu}
     print(json.dumps(rec))
 

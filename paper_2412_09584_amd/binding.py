@@ -21,7 +21,7 @@ BOUND_OPT_DIRECT_DMA = 2
 BOUND_STOP_RELU, BOUND_STOP_LINEAR = 1, 2
 
 EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "bound_grad",
-            "bound_adam", "bound_sample_bounds", "bound_autotune", "bound_autotune_report", "bound_set_options",
+            "bound_adam", "bound_sample_bounds", "bound_autotune", "bound_autotune_report", "bound_set_options", "bound_set_plan",
             "bound_profile", "bound_profile_read", "bound_destroy",
             "bound_bab_init", "bound_bab_pick_out", "bound_bab_samples", "bound_bab_search_summary",
             "bound_bab_split", "bound_bab_update_best", "bound_bab_prune", "bound_bab_destroy",
@@ -84,6 +84,8 @@ def lib():
         L.bound_autotune_report.argtypes = [_p, ctypes.c_char_p, ctypes.c_int32]
         L.bound_autotune_report.restype = ctypes.c_int32
         L.bound_set_options.argtypes = [_p, ctypes.c_int32]
+        L.bound_set_plan.argtypes = [_p, ctypes.c_char, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32]
         L.bound_profile.argtypes = [_p, ctypes.c_int32]
         L.bound_profile_read.argtypes = [_p, ctypes.c_int32, ctypes.c_char_p,
                                          ctypes.POINTER(ctypes.c_double),
@@ -230,6 +232,11 @@ def bound_adam(param, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8, grad_sca
 
 def bound_set_options(handle, options):
     _check(lib().bound_set_options(handle, int(options)))
+
+
+def bound_set_plan(handle, product, layer, path, cfg, cc):
+    _check(lib().bound_set_plan(handle, str(product).encode()[:1], int(layer), int(path), int(cfg),
+                                int(cc)))
 
 
 def bound_profile(handle, enable=True):

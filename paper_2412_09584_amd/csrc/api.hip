@@ -867,6 +867,20 @@ bound_status bound_set_options(bound_net *net, int32_t options) {
     return BOUND_OK;
 }
 
+bound_status bound_set_plan(bound_net *net, char product, int32_t layer, int32_t path,
+                            int32_t cfg, int32_t cc) {
+    if (!net || (product != 'R' && product != 'C' && product != 'A' && product != 'F') ||
+        layer < 1 || layer > net->n_layers || path < 0 || path > 2 || cfg < -1 || cfg > 15 ||
+        cc < 0 || cc > 1024)
+        return fail(BOUND_E_ARG, "bound_set_plan: bad arguments");
+    Plan p;
+    p.path = path;
+    p.cfg = cfg;
+    p.cc = cc;
+    net->plans[pkey(product, layer)] = p;
+    return BOUND_OK;
+}
+
 bound_status bound_profile(bound_net *net, int32_t enable) {
     if (!net) return fail(BOUND_E_ARG, "bound_profile: null net");
     net->prof = enable != 0;

@@ -446,6 +446,28 @@ __global__ void k_adj_init(long n_img, int rows, long d0, const float *gl, const
     gbar[e] = w * (cen[inst * d0 + j] - sg * rad[inst * d0 + j]);
 }
 
+// The same, four consecutive inputs per thread (d0 % 4 == 0): 16-byte loads and stores.
+__global__ void k_adj_init4(long n_img, int rows, long d0, const float *gl, const float *g1,
+                            const float *cen, const float *rad, const int32_t *infeas,
+                            float *gbar, float *sbar) {
+    const long e4 = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long q = d0 >> 2;
+    if (e4 >= n_img * q) return;
+    const long img = e4 / q, j = (e4 - img * q) * 4;
+    const long inst = img / rows;
+    const float w = infeas[inst] ? 0.f : gl[img];
+    if (j == 0) sbar[img] = w;
+    const float4 g = *(const float4 *)(g1 + img * d0 + j);
+    const float4 c = *(const float4 *)(cen + inst * d0 + j);
+    const float4 r = *(const float4 *)(rad + inst * d0 + j);
+    auto one = [&](float gv, float cv, float rv) {
+        const float sg = gv > 0.f ? 1.f : (gv < 0.f ? -1.f : 0.f);
+        return w * (cv - sg * rv);
+    };
+    *(float4 *)(gbar + img * d0 + j) =
+        make_float4(one(g.x, c.x, r.x), one(g.y, c.y, r.y), one(g.z, c.z, r.z), one(g.w, c.w, r.w));
+}
+
 __global__ void k_beta_grad(int nnz, int rows, int layer, const BetaGradLayer L,
                             const int32_t *sp_inst, const int32_t *sp_layer, const int32_t *sp_j,
                             const int32_t *sp_dup, const int8_t *sign, const float *gbar_m,
@@ -776,8 +798,13 @@ hipError_t launch_adj_init(long n_img, int rows, long d0, const float *gl, const
                            const float *cen, const float *rad, const int32_t *infeas, float *gbar,
                            float *sbar, hipStream_t st) {
     const long total = n_img * d0;
-    hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(total)), dim3(TPB), 0, st, n_img, rows, d0, gl,
-                       g1, cen, rad, infeas, gbar, sbar);
+    const bool al16 = (((uintptr_t)g1 | (uintptr_t)cen | (uintptr_t)rad | (uintptr_t)gbar) & 15) == 0;
+    if (d0 % 4 == 0 && al16)
+        hipLaunchKernelGGL(k_adj_init4, dim3(blocks_for(total / 4)), dim3(TPB), 0, st, n_img, rows,
+                           d0, gl, g1, cen, rad, infeas, gbar, sbar);
+    else
+        hipLaunchKernelGGL(k_adj_init, dim3(blocks_for(total)), dim3(TPB), 0, st, n_img, rows, d0,
+                           gl, g1, cen, rad, infeas, gbar, sbar);
     return hipGetLastError();
 }
 

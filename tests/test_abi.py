@@ -53,6 +53,8 @@ def test_error_paths_without_device(L):
     layer = B.BoundLayer(B.BOUND_LINEAR, 4, 1, 1, 3, 1, 1, 1, 1, 1, 0, None, None)
     assert L.bound_init(ctypes.byref(layer), 1, 1, 16, 32, None, ctypes.byref(out)) == B.BOUND_E_ARG
     assert "max_save_rows" in B.bound_last_error()
+    assert L.bound_set_plan(None, b"R", 1, 1, -1, 0) == B.BOUND_E_ARG
+    assert "bound_set_plan" in B.bound_last_error()
 
 
 def test_bab_error_paths_without_device(L):
