@@ -687,8 +687,9 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
                                       net->tab + net->relu_off(sl), net->n_relu,
                                       sl + 1 < k ? cur : nullptr, net->gcbuf, S.C, S.HW, st));
         HIPCHK(launch_alpha_grad(net->s_n_inst, rows, Ds, S, sl - 1, net->n_relu, net->srow,
-                                 net->slot_count, net->slot_inv, net->tab, net->gcbuf, grad_alpha,
-                                 net->n_relu, net->relu_off(sl), st));
+                                 net->slot_count, net->slot_inv, net->gcbuf, grad_alpha,
+                                 net->n_relu, net->relu_off(sl), (int)net->s_nnz, sp_inst, sp_layer,
+                                 sp_j, st));
         if (grad_beta && net->s_nnz > 0)
             HIPCHK(launch_beta_grad_stop(net->s_nnz, rows, sl - 1, Ds, sp_inst, sp_layer, sp_j,
                                          net->sp_sign, net->save + net->s_lam_off, net->stop_cen,
@@ -733,8 +734,8 @@ bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alp
             ProfScope ps(net, st, "alpha_grad");
             HIPCHK(launch_alpha_grad(net->s_n_inst, rows, net->d[m], net->ns.l[m - 1], m - 1,
                                      net->n_relu, net->srow, net->slot_count, net->slot_inv,
-                                     net->tab, net->gcbuf, grad_alpha, net->n_relu,
-                                     net->relu_off(m), st));
+                                     net->gcbuf, grad_alpha, net->n_relu, net->relu_off(m),
+                                     (int)net->s_nnz, sp_inst, sp_layer, sp_j, st));
         }
         if (grad_beta && net->s_nnz > 0) {
             BetaGradLayer bl{};

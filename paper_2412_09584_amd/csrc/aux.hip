@@ -108,24 +108,33 @@ __global__ void k_prep_slots(const NetShapes ns, long n_relu, const float *lo, c
 // result at the neuron's C-major index.  Slots of split neurons (w = 0) are skipped.
 __global__ void k_alpha_grad(int rows, long D, const LayerShape L, int layer, long n_relu,
                              const int32_t *srow, const int32_t *count, const int32_t *inv,
-                             const Relax *tab, const float *gc, float *galpha, long ga_ld,
-                             long ga_off) {
+                             const float *gc, float *galpha, long ga_ld, long ga_off) {
     const long inst = blockIdx.x;
     const long r = srow[inst];
     const int cnt = count[r * MAX_RELU_LAYERS + layer];
     const int32_t *iv = inv + r * n_relu + L.off;
-    const Relax *tb = tab + inst * n_relu + L.off;
     const float *g = gc + inst * rows * D;
     float *ga = galpha + inst * ga_ld + ga_off;
-    const float *w = (const float *)tb + 3;          // the records' w components
     for (int k = threadIdx.x; k < cnt; k += TPB) {
         const int j = iv[k];
         float acc = 0.f;
         for (int q = 0; q < rows; ++q) acc += g[q * D + k];
-        if (w[4 * (long)j] <= 0.f) continue;                    // split neuron
+        // a split neuron's slot holds no contribution of this pass: its entry is
+        // overwritten with 0 by k_alpha_split_zero (no per-slot record read here)
         const int c = j % L.C, p = j / L.C;
         ga[(long)c * L.HW + p] = acc;
     }
+}
+
+// The alpha-gradient of a split neuron is 0 (its relaxation has no alpha): one thread per
+// split entry of the layer.
+__global__ void k_alpha_split_zero(int nnz, int layer, const LayerShape L, const int32_t *sp_inst,
+                                   const int32_t *sp_layer, const int32_t *sp_j, float *galpha,
+                                   long ga_ld, long ga_off) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nnz || sp_layer[q] != layer) return;
+    const int j = sp_j[q], c = j % L.C, p = j / L.C;
+    galpha[(long)sp_inst[q] * ga_ld + ga_off + (long)c * L.HW + p] = 0.f;
 }
 
 __global__ void k_fill(float *p, long n, float v) {
@@ -725,11 +734,15 @@ hipError_t launch_prep_tables(const NetShapes &ns, int used, int n_inst, long n_
 
 hipError_t launch_alpha_grad(int n_inst, int rows, long D, const LayerShape &L, int layer,
                              long n_relu, const int32_t *srow, const int32_t *slot_count,
-                             const int32_t *slot_inv, const Relax *tab, const float *gc,
-                             float *galpha, long ga_ld, long ga_off, hipStream_t st) {
+                             const int32_t *slot_inv, const float *gc, float *galpha, long ga_ld,
+                             long ga_off, int nnz, const int32_t *sp_inst, const int32_t *sp_layer,
+                             const int32_t *sp_j, hipStream_t st) {
     if (n_inst <= 0 || D <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_alpha_grad, dim3((unsigned)n_inst), dim3(TPB), 0, st, rows, D, L, layer,
-                       n_relu, srow, slot_count, slot_inv, tab, gc, galpha, ga_ld, ga_off);
+                       n_relu, srow, slot_count, slot_inv, gc, galpha, ga_ld, ga_off);
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_alpha_split_zero, dim3(blocks_for(nnz)), dim3(TPB), 0, st, nnz, layer, L,
+                           sp_inst, sp_layer, sp_j, galpha, ga_ld, ga_off);
     return hipGetLastError();
 }
 

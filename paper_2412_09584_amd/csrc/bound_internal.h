@@ -162,10 +162,13 @@ hipError_t launch_prep_tables(const NetShapes &ns, int n_layers_used, int n_inst
                               const int32_t *bound_of, const float *alpha, Relax *tab,
                               int32_t *infeas, int n_bounds, int32_t *slot, int32_t *slot_inv,
                               int32_t *slot_count, int32_t *srow, int max_rows, hipStream_t st);
+// alpha-gradient of one layer from the compact per-row contributions gc (sum over an
+// instance's rows per slot, written C-major), then 0 at the layer's split neurons
 hipError_t launch_alpha_grad(int n_inst, int rows, long D, const LayerShape &L, int layer,
                              long n_relu, const int32_t *srow, const int32_t *slot_count,
-                             const int32_t *slot_inv, const Relax *tab, const float *gc,
-                             float *galpha, long ga_ld, long ga_off, hipStream_t st);
+                             const int32_t *slot_inv, const float *gc, float *galpha, long ga_ld,
+                             long ga_off, int nnz, const int32_t *sp_inst, const int32_t *sp_layer,
+                             const int32_t *sp_j, hipStream_t st);
 constexpr int MAX_RELU_LAYERS = 16;
 hipError_t launch_prep_splits(const NetShapes &ns, int n_layers_used, int n_inst, long n_relu,
                               const float *lo, const float *hi, const int32_t *bound_of,
