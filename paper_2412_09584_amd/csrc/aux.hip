@@ -184,7 +184,10 @@ __global__ __launch_bounds__(256) void k_prep_tables(const NetShapes ns, int use
     Relax *tr = tab + inst * n_relu + L.off;
     auto record = [&](long j, float l, float u, float a) {
         if (!ar) a = u >= -l ? 1.f : 0.f;
-        tr[j] = relax_of(l, u, a, kr[j]);
+        const Relax r = relax_of(l, u, a, kr[j]);
+        // streaming store: the table is far larger than the caches and read back later
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        __builtin_nontemporal_store((f4){r.x, r.y, r.z, r.w}, (f4 *)(tr + j));
     };
     if (L.HW == 1) {                        // dense: the two orders coincide
         const long j0 = (long)t * PREP_TILE;
