@@ -110,7 +110,7 @@ struct Plan {
     int cfg = -1;
     int cc = 0;
 };
-constexpr int kMaxCandidates = 24;
+constexpr int kMaxCandidates = 32;
 
 hipError_t gemm_relax(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
                       hipStream_t st, const Plan &plan);
@@ -132,8 +132,9 @@ hipError_t gemm_adj_cfg(const GeomSet &gs, const float *A, long n_img, const Adj
 hipError_t gemm_fwd_cfg(const GeomSet &gs, const float *A, long n_img, const FwdParams &p,
                         hipStream_t st, int cfg);
 int gemm_candidates(const GeomSet &gs, int *cfgs, int cap);
-// conv.hip: direct convolution (cc = 0: largest chunk that fits; mode 1: tiles staged by
-// LDS DMA, else through registers); *used = false when the geometry does not fit
+// conv.hip: direct convolution (cc = 0: largest chunk that fits; mode 1 or 3: tiles staged
+// by LDS DMA, else through registers; mode 2 or 3: 16x16 MFMA tiles for 32 output
+// channels); *used = false when the geometry does not fit
 hipError_t direct_relax(const GeomSet &gs, const float *A, long n_img, const RelaxParams &p,
                         hipStream_t st, int cc, int mode, bool *used);
 hipError_t direct_conc(const GeomSet &gs, const float *A, long n_img, const ConcParams &p,

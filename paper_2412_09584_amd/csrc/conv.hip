@@ -725,13 +725,16 @@ hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &
     }
     const int BN = bn_for(g.N);
     if (!BN) return hipSuccess;
-    const int KPL = BN == 16 ? Mma<16>::KPL : Mma<32>::KPL;
-    const bool dma = mode == 1 && g.C % 4 == 0;
+    // mode: bit 0 (1, 3) LDS DMA staging, bit 1 (2, 3) 16x16 MFMA tiles for 32 outputs
+    const bool mf16 = BN == 32 && (mode == 2 || mode == 3);
+    const int KPL = BN == 16 || mf16 ? Mma<16>::KPL : Mma<32>::KPL;
+    const bool dma = (mode == 1 || mode == 3) && g.C % 4 == 0;
     const size_t lds = plan_chunk(g, BN, KPL, ct, want_cc, dma);
     if (!lds) return hipSuccess;
     set_tile_recips(g, ct);
     *used = true;
     if (BN == 16) return launch_mfma<Epi, 16, 16>(gs, ct, lds, X, n_img, epi, st, dma);
+    if (BN == 32 && mf16) return launch_mfma<Epi, 16, 32>(gs, ct, lds, X, n_img, epi, st, dma);
     if (BN == 32) return launch_mfma<Epi, 32, 32>(gs, ct, lds, X, n_img, epi, st, dma);
     return launch_mfma<Epi, 32, 64>(gs, ct, lds, X, n_img, epi, st, dma);
 }
@@ -780,12 +783,17 @@ int direct_candidates(const GeomSet &gs, int *cc, int *mode, int cap) {
         mode[0] = -1;
         return cap > 0 ? 1 : 0;
     }
-    // each channel chunk with register staging (mode -1) and with LDS DMA staging (1)
+    // each channel chunk with register staging (mode -1) and with LDS DMA staging (1);
+    // 32-output products also with 16x16 MFMA tiles (modes 2, 3), which allow chunks of
+    // 4 channels
     int n = 0;
-    for (int c = 64; c >= KPL; c >>= 1) {
-        for (int m = -1; m <= 1 && n < cap; m += 2) {
+    const int modes[4] = {-1, 1, 2, 3};
+    for (int c = 64; c >= 4; c >>= 1) {
+        for (int mi = 0; mi < (BN == 32 ? 4 : 2) && n < cap; ++mi) {
+            const int m = modes[mi];
+            const int kpl = m >= 2 ? Mma<16>::KPL : KPL;
             ConvTile t = ct;
-            if (g.C % c == 0 && plan_chunk(g, BN, KPL, t, c, m == 1)) {
+            if (c >= kpl && g.C % c == 0 && plan_chunk(g, BN, kpl, t, c, m == 1 || m == 3)) {
                 cc[n] = c;
                 mode[n] = m;
                 ++n;

@@ -790,3 +790,50 @@ def test_sample_bounds_and_early_stop_over_them(mod, kind):
         for i in range(n_sub):
             b = list(zip(O.per_layer(net, e_lo[i]), O.per_layer(net, e_hi[i])))
             close(np_(gl)[i], O.spec_lower_early_stop(net, L, C[i], b, L - 1, mode), what=f"{mode} {i}")
+
+
+@pytest.mark.parametrize("gi", [0, 1])
+def test_every_direct_variant_keeps_the_bound(mod, gi):
+    """Every direct-convolution variant pinned on every product (staging through
+    registers or by LDS DMA, 32x32 or 16x16 MFMA tiles, largest or 4-channel chunks)
+    gives the bound and gradient of the default plans (which the oracle tests pin)."""
+    N, B = mod
+    net = tiny_cnn(seed=170 + gi, **CNN_GEOMS[gi])
+    n_roots, per_root = 2, 5
+    x0 = W.uniform_inputs(n_roots, W.in_dim(net), 171)
+    x_lo, x_hi = W.linf_box(x0, 0.05)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    n = n_roots * per_root
+    root_of = np.repeat(np.arange(n_roots), per_root).astype(np.int32)
+    L = len(net)
+
+    def run(pin, fixed=None):
+        bn = N.BoundNet(net, n, 4096, 4096)
+        if pin is not None:
+            for m in range(1, L + 1):
+                for prod in "RCA":
+                    B.bound_set_plan(bn.handle, prod, m, 1, pin[0], pin[1])
+        glo, ghi = bn.crown_bounds(x_lo[root_of], x_hi[root_of])
+        out = [np_(glo)]
+        if fixed is None:          # the reference run fixes bounds, splits, alpha, beta
+            lo_np, hi_np = np_(glo), np_(ghi)
+            sp = _random_splits(net, lo_np.astype(np.float64), hi_np.astype(np.float64), n, 172,
+                                np.arange(n, dtype=np.int32))
+            fixed = (glo, ghi, sp, dev(W.random_alpha(n, lo_np.shape[1], 173)),
+                     dev(W.random_beta(sp.nnz, C.shape[1], 174)))
+        flo, fhi, sp, alpha, beta = fixed
+        gl, _ = bn.spec_bounds(C[root_of], flo, fhi, x_lo[root_of], x_hi[root_of], alpha=alpha,
+                               splits=N.splits_to_device(sp), beta=beta, both=False, save=True)
+        ga, gb = bn.grad(torch.ones(n, C.shape[1], device="cuda"), sp.nnz)
+        return out + [np_(gl), np_(ga), np_(gb)], fixed
+
+    ref, fixed = run(None)
+    for pin in [(-1, 0), (1, 0), (2, 0), (3, 0), (2, 4), (3, 4)]:
+        got, _ = run(pin, fixed)
+        close(got[0], ref[0], rel=1e-5, what=f"intermediate bounds {pin}")
+        close(got[1], ref[1], rel=1e-5, what=f"lower {pin}")
+        sa = np.max(np.abs(ref[2]), axis=1, keepdims=True) + 1e-30
+        assert np.max(np.abs(got[2] - ref[2]) / sa) <= 1e-3, f"grad alpha {pin}"
+        assert np.mean(np.abs(got[2] - ref[2]) > 1e-5 * sa) <= 1e-2, f"grad alpha {pin}"
+        sb = np.max(np.abs(ref[3])) + 1e-30
+        assert np.max(np.abs(got[3] - ref[3])) <= 1e-3 * sb, f"grad beta {pin}"
