@@ -596,7 +596,7 @@ size_t plan_chunk(const Geom &g, int BN, int KPL, ConvTile &ct, int want = 0, bo
         int best = 0;
         for (int cc = 64; cc >= KPL; cc >>= 1) {
             if (g.C % cc || (want && cc != want)) continue;
-            const int cs = cc + 4;
+            const int cs = dma ? cc : cc + 4;   // DMA tiles unpadded (more blocks per CU)
             const size_t in = (size_t)ct.G * ct.IH * ct.IW * cs;
             const int kb = ((ct.T * cc + 15) / 16) * 16;
             const size_t w = (size_t)BN * (kb + 4);
@@ -610,7 +610,7 @@ size_t plan_chunk(const Geom &g, int BN, int KPL, ConvTile &ct, int want = 0, bo
         if (!best) return 0;
         ct.CC = best;
         ct.lcc = __builtin_ctz(best);
-        ct.CS = best + 4;
+        ct.CS = dma ? best : best + 4;
         ct.nchunk = g.C / best;
     }
     ct.KB = ((ct.T * ct.CC + 15) / 16) * 16;
