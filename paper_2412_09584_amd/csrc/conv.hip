@@ -694,14 +694,14 @@ hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &
     if (groups * ct.tiles_y * (g.N / 4 + 1) * gs.n > 0x7fffffffL) return hipSuccess;
     if (g.N <= 4 && g.C % 4 == 0) {      // narrow output: VALU kernel
         ct.CC = g.C;
-        ct.CS = g.C + 4;
+        ct.CS = mode == 3 ? g.C : g.C + 4;   // mode 3: DMA into unpadded rows
         ct.in_floats = ct.G * ct.IH * ct.IW * ct.CS;
         const size_t lds = (size_t)ct.in_floats * 4;
         if (lds > LDS_BUDGET) return hipSuccess;
         set_tile_recips(g, ct);
         const dim3 grid((unsigned)(groups * ct.tiles_y * gs.n));   // xcd_tile order
         // DMA staging when asked for and the tile fits its slots (int offsets inside a group)
-        const bool dma = mode == 1 && ct.in_floats / 4 <= 256 * VALU_DMA_IN4 &&
+        const bool dma = (mode == 1 || mode == 3) && ct.in_floats / 4 <= 256 * VALU_DMA_IN4 &&
                          (size_t)ct.G * g.H * g.W * g.C * 4 < 0x7fffffffUL;
         if (g.N == 3 && dma) {   // RGB input layers: no idle fourth output
             static const hipError_t ok = allow_lds(k_conv_valu<Epi, 3, true>);
@@ -768,7 +768,7 @@ int direct_candidates(const GeomSet &gs, int *cc, int *mode, int cap) {
     if (g.N <= 4) {
         if (g.C % 4 != 0) return 0;
         int n = 0;
-        for (int m = -1; m <= 1 && n < cap; m += 2) {
+        for (int m = -1; m <= 3 && n < cap; m += 2) {   // registers, DMA, DMA unpadded
             cc[n] = 0;
             mode[n++] = m;
         }
