@@ -192,11 +192,12 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     // DMA: the chunk goes from global memory straight into LDS (buffer loads with the
     // LDS destination, 16 bytes per lane at consecutive LDS addresses), so no staging
     // registers are held across the k-loop.  LDS float4 slot s = i * 256 + tid of the
-    // input tile (pixel, channel quad incl. the row padding) and of the weight tile
-    // (output, k quad incl. padding) is fetched by that thread; slots that are always
-    // zero (spatial padding, k past the chunk) are written once, the padding columns
-    // never, and slots past the last image of a partial group read out of range of the
-    // buffer (no access) and feed only rows the epilogue drops.
+    // input tile (pixel, channel quad; the rows are unpadded, which keeps the tile small
+    // enough for one more block per CU) and of the weight tile (output, k quad incl.
+    // padding) is fetched by that thread; slots that are always zero (spatial padding, k
+    // past the chunk) are written once, padding columns never, and slots past the last
+    // image of a partial group read out of range of the buffer (no access) and feed only
+    // rows the epilogue drops.
     const int c4s = VEC ? ct.lcc - 2 : 0;             // log2(CC / 4)
     const int Pin = ct.IW << c4s, Rin = ct.G * ct.IH;  // input grid [G*IH][IW*CC/4]
     const int Pw = ct.KB >> 2;                         // weight grid [BN][KB/4]
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
                 if (c4 < (ct.CC >> 2) && (unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W)
                     o = (((gi * g.H + y) * g.W + x) * g.C + 4 * c4) * 4;
                 else if (c4 == (ct.CC >> 2))
-                    o = -2;                           // row padding: never read
+                    o = -2;                           // row padding (if any): never read
             }
             gin[i] = o;
             if (o == -1) *(float4 *)(In + 4 * sl) = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -397,8 +398,9 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
 
 // One thread per output pixel, up to NMAX output channels, VALU FMAs from LDS.
 // Input tile of all C channels (CC = C, C % 4 == 0) by LDS DMA in one pass: slot
-// s = i * 256 + tid as in k_conv; spatial padding is written as zeros, the row padding
-// column not at all; images past the batch read nothing (their pixels are dropped).
+// s = i * 256 + tid as in k_conv; spatial padding is written as zeros, a row padding
+// column (when the rows are padded) not at all; images past the batch read nothing
+// (their pixels are dropped).
 template <int NIN>
 __device__ inline void dma_input_tile(float *In, const ConvTile &ct, const Geom &g, const float *Xb,
                                       int xbytes, int iy0, int ix0) {
