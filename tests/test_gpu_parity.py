@@ -332,14 +332,15 @@ def test_infeasible_split_gives_inf(mod):
     assert np.all(np_(ga)[0] == 0)
 
 
-def test_adam_kernel(mod):
+@pytest.mark.parametrize("n", [1000, 1001])  # and a length that is not a multiple of four
+def test_adam_kernel(mod, n):
     N, B = mod
     rng = np.random.default_rng(71)
-    p0 = rng.uniform(0, 1, 1000)
-    p, m, v = dev(p0), torch.zeros(1000, device="cuda"), torch.zeros(1000, device="cuda")
-    op, om, ov = p0.astype(np.float32).astype(np.float64), np.zeros(1000), np.zeros(1000)
+    p0 = rng.uniform(0, 1, n)
+    p, m, v = dev(p0), torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    op, om, ov = p0.astype(np.float32).astype(np.float64), np.zeros(n), np.zeros(n)
     for t in range(1, 6):
-        g = rng.normal(size=1000)
+        g = rng.normal(size=n)
         B.bound_adam(p, dev(g), m, v, t, 0.1, grad_scale=-1.0, clip_lo=0.0, clip_hi=1.0)
         op, om, ov = O.adam_step(op, -g.astype(np.float32).astype(np.float64), om, ov, t, 0.1,
                                  lo=0.0, hi=1.0)
