@@ -149,6 +149,7 @@ __global__ void k_fill(float *p, long n, float v) {
 // record writes are contiguous across the block.  Layers with more channels than a tile
 // take one pixel's channels per block with direct (strided) reads.
 constexpr int PREP_TILE = 1024;
+constexpr int PREP_SH = PREP_TILE + PREP_TILE / 8;  // room for one pad per pixel when C >= 8
 
 __device__ inline int prep_tiles(const LayerShape &L) {
     if (L.HW == 1) return (int)((L.d + PREP_TILE - 1) / PREP_TILE);
@@ -162,10 +163,13 @@ __global__ __launch_bounds__(256) void k_prep_tables(const NetShapes ns, int use
                                                      const int32_t *bound_of, const float *alpha,
                                                      Relax *tab, int32_t *infeas, int n_bounds,
                                                      const int32_t *slot, int per_inst,
-                                                     int32_t *srow) {
-    __shared__ float sh[3 * PREP_TILE];
-    const long inst = blockIdx.x;   // consecutive blocks: other instances, same bounds rows
-    int t = blockIdx.y, m = 0;
+                                                     int32_t *srow, int tiles) {
+    __shared__ float sh[3 * PREP_SH];
+    // consecutive blocks take consecutive tiles of one instance, so the blocks in flight
+    // write one contiguous stretch of the record table (and share one bounds row)
+    const long inst = blockIdx.x / (unsigned)tiles;
+    const int t0 = (int)(blockIdx.x - inst * tiles);
+    int t = t0, m = 0;
     for (; m < used; ++m) {
         const int nt = prep_tiles(ns.l[m]);
         if (t < nt) break;
@@ -174,7 +178,7 @@ __global__ __launch_bounds__(256) void k_prep_tables(const NetShapes ns, int use
     if (m >= used) return;
     const LayerShape &L = ns.l[m];
     const long b = bound_row(bound_of, inst, n_bounds);
-    if (blockIdx.y == 0 && threadIdx.x == 0) {
+    if (t0 == 0 && threadIdx.x == 0) {
         infeas[inst] = 0;
         srow[inst] = per_inst ? (int32_t)inst : (int32_t)b;
     }
@@ -182,9 +186,9 @@ __global__ __launch_bounds__(256) void k_prep_tables(const NetShapes ns, int use
     const float *ar = alpha ? alpha + inst * n_relu + L.off : nullptr;
     const int32_t *kr = slot + (per_inst ? inst : b) * n_relu + L.off;
     Relax *tr = tab + inst * n_relu + L.off;
-    auto record = [&](long j, float l, float u, float a) {
+    auto record = [&](long j, float l, float u, float a, int32_t k) {
         if (!ar) a = u >= -l ? 1.f : 0.f;
-        const Relax r = relax_of(l, u, a, kr[j]);
+        const Relax r = relax_of(l, u, a, k);
         // streaming store: the table is far larger than the caches and read back later
         typedef float f4 __attribute__((ext_vector_type(4)));
         __builtin_nontemporal_store((f4){r.x, r.y, r.z, r.w}, (f4 *)(tr + j));
@@ -193,7 +197,7 @@ __global__ __launch_bounds__(256) void k_prep_tables(const NetShapes ns, int use
         const long j0 = (long)t * PREP_TILE;
         for (int e = threadIdx.x; e < PREP_TILE; e += 256) {
             const long j = j0 + e;
-            if (j < L.d) record(j, lr[j], hr[j], ar ? ar[j] : 0.f);
+            if (j < L.d) record(j, lr[j], hr[j], ar ? ar[j] : 0.f, kr[j]);
         }
         return;
     }
@@ -202,29 +206,56 @@ __global__ __launch_bounds__(256) void k_prep_tables(const NetShapes ns, int use
         const int p = t / nch, c0 = (t - p * nch) * PREP_TILE;
         for (int e = threadIdx.x; e < PREP_TILE && c0 + e < L.C; e += 256) {
             const long jn = (long)(c0 + e) * L.HW + p;
-            record((long)p * L.C + c0 + e, lr[jn], hr[jn], ar ? ar[jn] : 0.f);
+            record((long)p * L.C + c0 + e, lr[jn], hr[jn], ar ? ar[jn] : 0.f, kr[(long)p * L.C + c0 + e]);
         }
         return;
     }
     const int C = L.C, P = PREP_TILE / C, p0 = t * P;
     const int np = L.HW - p0 < P ? L.HW - p0 : P;     // pixels of this tile
-    const float rP = 1.0f / (float)P;
-    // C-major reads: e -> (c, pixel p0 + q), contiguous in q
-    for (int e = threadIdx.x; e < C * P; e += 256) {
+    const int CS = C >= 8 ? C + 1 : C;                // LDS pixel stride, odd when padded
+    const float rP = 1.0f / (float)P, rC = 1.0f / (float)C;
+    constexpr int PER = PREP_TILE / 256;
+    // C-major reads: e -> (c, pixel p0 + q), contiguous in q; all of a thread's loads are
+    // issued before the first LDS store
+    float vl[PER], vh[PER], va[PER];
+    int vs[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
         // e / P through one FP32 multiply by fl(1 / P): exact for e < 2^21
         const int c = (int)(((float)e + 0.5f) * rP), q = e - c * P;
-        if (q < np) {
+        vs[k] = -1;
+        if (e < C * P && q < np) {
             const long jn = (long)c * L.HW + p0 + q;
-            const int s = q * C + c;
-            sh[s] = lr[jn];
-            sh[PREP_TILE + s] = hr[jn];
-            sh[2 * PREP_TILE + s] = ar ? ar[jn] : 0.f;
+            vs[k] = q * CS + c;
+            vl[k] = lr[jn];
+            vh[k] = hr[jn];
+            va[k] = ar ? ar[jn] : 0.f;
         }
     }
+#pragma unroll
+    for (int k = 0; k < PER; ++k)
+        if (vs[k] >= 0) {
+            sh[vs[k]] = vl[k];
+            sh[PREP_SH + vs[k]] = vh[k];
+            sh[2 * PREP_SH + vs[k]] = va[k];
+        }
     __syncthreads();
-    // pixel-major writes: record p0 * C + e
-    for (int e = threadIdx.x; e < np * C; e += 256)
-        record((long)p0 * C + e, sh[e], sh[PREP_TILE + e], sh[2 * PREP_TILE + e]);
+    // pixel-major writes: record p0 * C + e, slot entries loaded first
+    int ks[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
+        ks[k] = e < np * C ? kr[(long)p0 * C + e] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
+        if (e < np * C) {
+            const int q = (int)(((float)e + 0.5f) * rC), o = e + q * (CS - C);
+            record((long)p0 * C + e, sh[o], sh[PREP_SH + o], sh[2 * PREP_SH + o], ks[k]);
+        }
+    }
 }
 
 __global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, long n_relu,
@@ -728,10 +759,10 @@ hipError_t launch_prep_tables(const NetShapes &ns, int used, int n_inst, long n_
                  : L.C > PREP_TILE ? (long)L.HW * ((L.C + PREP_TILE - 1) / PREP_TILE)
                                    : (L.HW + PREP_TILE / L.C - 1) / (PREP_TILE / L.C);
     }
-    if (tiles > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_prep_tables, dim3((unsigned)n_inst, (unsigned)tiles), dim3(256), 0, st, ns,
+    if (tiles * n_inst > 0x7fffffffL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_prep_tables, dim3((unsigned)(tiles * n_inst)), dim3(256), 0, st, ns,
                        used, n_relu, lo, hi, bound_of, alpha, tab, infeas, n_bounds, slot,
-                       per_inst ? 1 : 0, srow);
+                       per_inst ? 1 : 0, srow, (int)tiles);
     return hipGetLastError();
 }
 
