@@ -118,7 +118,16 @@ __global__ void k_alpha_grad(int rows, long D, const LayerShape L, int layer, lo
     for (int k = threadIdx.x; k < cnt; k += TPB) {
         const int j = iv[k];
         float acc = 0.f;
-        for (int q = 0; q < rows; ++q) acc += g[q * D + k];
+        int q = 0;
+        // eight rows' loads in flight at once; the sum keeps the row order
+        for (; q + 8 <= rows; q += 8) {
+            float a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = g[(q + u) * D + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += a[u];
+        }
+        for (; q < rows; ++q) acc += g[q * D + k];
         // a split neuron's slot holds no contribution of this pass: its entry is
         // overwritten with 0 by k_alpha_split_zero (no per-slot record read here)
         const int c = j % L.C, p = j / L.C;
@@ -498,11 +507,14 @@ __global__ void k_adj_init4(long n_img, int rows, long d0, const float *gl, cons
     if (e4 >= n_img * q) return;
     const long img = e4 / q, j = (e4 - img * q) * 4;
     const long inst = img / rows;
-    const float w = infeas[inst] ? 0.f : gl[img];
-    if (j == 0) sbar[img] = w;
+    // every load issued before the first use
+    const int bad = infeas[inst];
+    const float glv = gl[img];
     const float4 g = *(const float4 *)(g1 + img * d0 + j);
     const float4 c = *(const float4 *)(cen + inst * d0 + j);
     const float4 r = *(const float4 *)(rad + inst * d0 + j);
+    const float w = bad ? 0.f : glv;
+    if (j == 0) sbar[img] = w;
     auto one = [&](float gv, float cv, float rv) {
         const float sg = gv > 0.f ? 1.f : (gv < 0.f ? -1.f : 0.f);
         return w * (cv - sg * rv);
