@@ -151,6 +151,12 @@ __global__ void k_fill(float *p, long n, float v) {
     if (i < n) p[i] = v;
 }
 
+// Four values per thread through 16-byte stores (16-byte aligned p, n4 = n / 4).
+__global__ void k_fill4(float4 *p, long n4, float v) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n4) p[i] = make_float4(v, v, v, v);
+}
+
 // Relaxation records of one instance: a block covers a tile of one ReLU layer -- P
 // pixels x all C channels of a convolutional layer (C <= PREP_TILE), or PREP_TILE
 // consecutive neurons of a dense one -- and moves the bounds and alpha, stored C-major,
@@ -502,11 +508,12 @@ __global__ void k_adj_init(long n_img, int rows, long d0, const float *gl, const
 __global__ void k_adj_init4(long n_img, int rows, long d0, const float *gl, const float *g1,
                             const float *cen, const float *rad, const int32_t *infeas,
                             float *gbar, float *sbar) {
-    const long e4 = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long q = d0 >> 2;
-    if (e4 >= n_img * q) return;
-    const long img = e4 / q, j = (e4 - img * q) * 4;
-    const long inst = img / rows;
+    // 32-bit quotients: the launch keeps n_img * d0 / 4 below 2^31
+    const unsigned e4 = blockIdx.x * blockDim.x + threadIdx.x;
+    const unsigned q = (unsigned)(d0 >> 2);
+    if (e4 >= (unsigned)n_img * q) return;
+    const long img = e4 / q, j = (long)(e4 - (unsigned)img * q) * 4;
+    const long inst = (unsigned)img / (unsigned)rows;
     // every load issued before the first use
     const int bad = infeas[inst];
     const float glv = gl[img];
@@ -747,7 +754,10 @@ __global__ void k_pack_F(const float *W, int kind, int ci, int hwin, int kh, int
 
 hipError_t launch_fill(float *p, long n, float v, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(TPB), 0, st, p, n, v);
+    if (n % 4 == 0 && ((uintptr_t)p & 15) == 0)
+        hipLaunchKernelGGL(k_fill4, dim3(blocks_for(n / 4)), dim3(TPB), 0, st, (float4 *)p, n / 4, v);
+    else
+        hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(TPB), 0, st, p, n, v);
     return hipGetLastError();
 }
 
@@ -858,7 +868,7 @@ hipError_t launch_adj_init(long n_img, int rows, long d0, const float *gl, const
                            float *sbar, hipStream_t st) {
     const long total = n_img * d0;
     const bool al16 = (((uintptr_t)g1 | (uintptr_t)cen | (uintptr_t)rad | (uintptr_t)gbar) & 15) == 0;
-    if (d0 % 4 == 0 && al16)
+    if (d0 % 4 == 0 && al16 && total / 4 < 0x7fffffffL)
         hipLaunchKernelGGL(k_adj_init4, dim3(blocks_for(total / 4)), dim3(TPB), 0, st, n_img, rows,
                            d0, gl, g1, cen, rad, infeas, gbar, sbar);
     else
