@@ -673,12 +673,13 @@ __global__ void k_adam(long n, float *p, const float *g, float *m, float *v, flo
                        float bc1, float bc2s, float lr, float eps, float gs, float lo, float hi) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const float pi = p[i];   // loaded with the others, ahead of the moment stores
     const float gr = gs * g[i];
     const float mi = b1 * m[i] + (1.f - b1) * gr;
     const float vi = b2 * v[i] + (1.f - b2) * gr * gr;
     m[i] = mi;
     v[i] = vi;
-    float x = p[i] - (lr / bc1) * mi / (sqrtf(vi) / bc2s + eps);
+    float x = pi - (lr / bc1) * mi / (sqrtf(vi) / bc2s + eps);
     x = fminf(fmaxf(x, lo), hi);
     p[i] = x;
 }
