@@ -74,10 +74,34 @@ __global__ void k_prep_slots(const NetShapes ns, long n_relu, const float *lo, c
     const float *lr = lo + b * n_relu + L.off, *hr = hi + b * n_relu + L.off;
     const long seg = (L.d + 255) / 256, j0 = threadIdx.x * seg;
     const long j1 = j0 + seg < L.d ? j0 + seg : L.d;
+    // unstable flags of n <= 64 neurons from internal index (channel cc, pixel pp) on,
+    // which advances; eight neurons' loads are issued at a time
+    auto flags = [&](int n, int &cc, long &pp) -> uint64_t {
+        uint64_t f = 0;
+        for (int u0 = 0; u0 < n; u0 += 8) {
+            float a[8], h[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool ok = u0 + u < n;
+                const long jn = ok ? (long)cc * L.HW + pp : 0;   // index 0 stands in past the end
+                a[u] = lr[jn];
+                h[u] = hr[jn];
+                if (ok && ++cc == L.C) { cc = 0; ++pp; }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (u0 + u < n && !(a[u] >= 0.f) && !(h[u] <= 0.f)) f |= 1ull << (u0 + u);
+        }
+        return f;
+    };
+    const int cs = j0 < L.d ? (int)(j0 % L.C) : 0;
+    const long ps = j0 < L.d ? j0 / L.C : 0;
     int c = 0;
-    for (long j = j0; j < j1; ++j) {
-        const long jn = to_cmajor(j, L.C, L.HW);
-        c += (!(lr[jn] >= 0.f) && !(hr[jn] <= 0.f)) ? 1 : 0;
+    {
+        int cc = cs;
+        long pp = ps;
+        for (long ja = j0; ja < j1; ja += 64)
+            c += __popcll(flags(j1 - ja < 64 ? (int)(j1 - ja) : 64, cc, pp));
     }
     cnt[threadIdx.x] = c;
     __syncthreads();
@@ -94,11 +118,16 @@ __global__ void k_prep_slots(const NetShapes ns, long n_relu, const float *lo, c
     int k = cnt[threadIdx.x];
     int32_t *out = slot + r * n_relu + L.off;
     int32_t *back = inv + r * n_relu + L.off;     // slot -> internal index
-    for (long j = j0; j < j1; ++j) {
-        const long jn = to_cmajor(j, L.C, L.HW);
-        const bool un = !(lr[jn] >= 0.f) && !(hr[jn] <= 0.f);
-        if (un) back[k] = (int32_t)j;
-        out[j] = un ? k++ : -1;
+    int cc = cs;
+    long pp = ps;
+    for (long ja = j0; ja < j1; ja += 64) {
+        const int n = j1 - ja < 64 ? (int)(j1 - ja) : 64;
+        const uint64_t f = flags(n, cc, pp);
+        for (int u = 0; u < n; ++u) {
+            const bool un = (f >> u) & 1;
+            if (un) back[k] = (int32_t)(ja + u);
+            out[ja + u] = un ? k++ : -1;
+        }
     }
 }
 
