@@ -262,11 +262,16 @@ def _oracle_unit(net, C, lo_row, hi_row, x_lo, x_hi, alpha_row, sp, q0, q1, beta
     return low, np.concatenate(ga), gb
 
 
-@pytest.mark.parametrize("kind", ["mlp", "cnn", "cnn_direct", "cnn_direct_gemm", "cnn_direct_dma"])
+@pytest.mark.parametrize("kind", ["mlp", "mlp_wide", "cnn", "cnn_direct", "cnn_direct_gemm",
+                                  "cnn_direct_dma"])
 def test_alpha_beta_pass_and_grad(mod, kind):
     N, B = mod
     if kind == "mlp":
         net = W.mlp([30, 24, 24, 24, 6], seed=51)
+    elif kind == "mlp_wide":
+        # a ReLU layer wider than 256 x 64 neurons: each thread of the slot numbering
+        # walks more than one 64-neuron flag mask
+        net = W.mlp([10, 17000, 6], seed=58)
     elif kind == "cnn":
         net = tiny_cnn(seed=52)
     else:
