@@ -367,12 +367,15 @@ __global__ void k_prep_stop_box(long total, LayerShape L, long n_relu, const flo
     rad[e] = 0.5f * (u - l);
 }
 
+// I: the index type, 32-bit unsigned whenever the launch has fewer than 2^31 elements
+// (cheaper quotients), else long.
+template <class I>
 __global__ void k_prep_box(long total, long d0, int C0, int HW0, const float *x_lo,
                            const float *x_hi, float *cen, float *rad) {
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= total) return;
-    const long inst = e / d0, j = e - inst * d0;
-    const long jn = to_cmajor(j, C0, HW0);
+    const I e = (I)blockIdx.x * (I)blockDim.x + (I)threadIdx.x;
+    if ((long)e >= total) return;
+    const I inst = e / (I)d0, j = e - inst * (I)d0;
+    const long jn = (long)(j % (I)C0) * HW0 + (long)(j / (I)C0);
     const float a = x_lo[inst * d0 + jn], b = x_hi[inst * d0 + jn];
     cen[e] = 0.5f * (a + b);
     rad[e] = 0.5f * (b - a);
@@ -848,8 +851,12 @@ hipError_t launch_prep_splits(const NetShapes &ns, int used, int n_inst, long n_
 hipError_t launch_prep_box(int n_inst, int C0, int HW0, const float *x_lo, const float *x_hi,
                            float *cen, float *rad, hipStream_t st) {
     const long d0 = (long)C0 * HW0, total = d0 * n_inst;
-    hipLaunchKernelGGL(k_prep_box, dim3(blocks_for(total)), dim3(TPB), 0, st, total, d0, C0, HW0,
-                       x_lo, x_hi, cen, rad);
+    if (total < 0x7fffffffL)
+        hipLaunchKernelGGL(k_prep_box<unsigned>, dim3(blocks_for(total)), dim3(TPB), 0, st, total,
+                           d0, C0, HW0, x_lo, x_hi, cen, rad);
+    else
+        hipLaunchKernelGGL(k_prep_box<long>, dim3(blocks_for(total)), dim3(TPB), 0, st, total, d0,
+                           C0, HW0, x_lo, x_hi, cen, rad);
     return hipGetLastError();
 }
 
