@@ -314,6 +314,52 @@ def test_alpha_beta_pass_and_grad(mod, kind):
             assert np.max(np.abs(gb[q0:q1] - ogb)) <= 1e-4 * max(sb, scale), f"grad beta {i}"
 
 
+@pytest.mark.parametrize("kind", ["mlp", "cnn"])
+def test_repeated_split_entries_bound_and_grad(mod, kind):
+    """A neuron split twice with the same sign: each entry has its own beta; the bound and
+    both entries' beta-gradients match the oracle (the later entry's gradient is the one
+    the separate beta-gradient kernel computes)."""
+    N, B = mod
+    net = W.mlp([30, 24, 24, 24, 6], seed=141) if kind == "mlp" else tiny_cnn(seed=142)
+    n_roots, per_root = 2, 3
+    x0 = W.uniform_inputs(n_roots, W.in_dim(net), 143)
+    x_lo, x_hi = W.linf_box(x0, 0.05)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    ob = oracle_bounds(net, x_lo, x_hi)
+    lo, hi = flat(ob)
+    lo, hi = f32(lo).astype(np.float64), f32(hi).astype(np.float64)
+    n = n_roots * per_root
+    root_of = np.repeat(np.arange(n_roots), per_root).astype(np.int32)
+    base = _random_splits(net, lo, hi, n, 144, root_of)
+    off, neu, sg = [0], [], []
+    for i in range(n):          # every subdomain repeats its first entry at the end
+        q0, q1 = base.off[i], base.off[i + 1]
+        neu += list(base.neuron[q0:q1]) + [base.neuron[q0]]
+        sg += list(base.sign[q0:q1]) + [base.sign[q0]]
+        off.append(len(neu))
+    sp = W.Splits(np.array(off, np.int32), np.array(neu, np.int32), np.array(sg, np.int8))
+    n_relu = lo.shape[1]
+    alpha = W.random_alpha(n, n_relu, 145)
+    beta = W.random_beta(sp.nnz, C.shape[1], 146)
+    bn = N.BoundNet(net, n, 4096, 4096)
+    gl, _ = bn.spec_bounds(C[root_of], dev(f32(lo)), dev(f32(hi)), x_lo[root_of], x_hi[root_of],
+                           alpha=dev(alpha), bound_of=dev(root_of, torch.int32),
+                           splits=N.splits_to_device(sp), beta=dev(beta), both=False, save=True)
+    ga, gb = bn.grad(torch.ones(n, C.shape[1], device="cuda"), sp.nnz)
+    ga, gb = np_(ga), np_(gb)
+    for i in range(n):
+        r = root_of[i]
+        q0, q1 = sp.off[i], sp.off[i + 1]
+        low, oga, ogb = _oracle_unit(net, C[r], lo[r], hi[r], x_lo[r], x_hi[r], alpha[i], sp, q0,
+                                     q1, beta.astype(np.float64))
+        close(np_(gl)[i], low, what=f"lower {i}")
+        scale = max(np.max(np.abs(oga)), 1e-30)
+        assert np.max(np.abs(ga[i] - oga)) <= 1e-4 * scale, f"grad alpha {i}"
+        sb = max(np.max(np.abs(ogb)), scale, 1e-30)
+        assert np.max(np.abs(gb[q0:q1] - ogb)) <= 1e-4 * sb, f"grad beta {i}"
+        assert np.array_equal(ogb[0], ogb[-1])      # the oracle gives both entries one gradient
+
+
 def test_infeasible_split_gives_inf(mod):
     N, B = mod
     net = W.mlp([10, 12, 12, 3], seed=61)
