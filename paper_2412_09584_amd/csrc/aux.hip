@@ -566,45 +566,47 @@ __global__ void k_beta_grad(int nnz, int rows, int layer, const BetaGradLayer L,
                             const int32_t *sp_inst, const int32_t *sp_layer, const int32_t *sp_j,
                             const int32_t *sp_dup, const int8_t *sign, const float *gbar_m,
                             const float *sbar, float *gbeta) {
-    const long wv = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    // one wave per split entry, its rows in turn: most entries leave at once
+    const long q = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
-    if (wv >= (long)nnz * rows) return;
-    const int q = (int)(wv / rows), r = (int)(wv - (long)q * rows);
+    if (q >= nnz) return;
     // first entries of a neuron get their gradient in the adjoint product's epilogue
     if (sp_layer[q] != layer || !sp_dup[q]) return;
-    const long img = (long)sp_inst[q] * rows + r;
-    const float *gb = gbar_m + img * L.din;
-    const long j = sp_j[q];
-    float acc = 0.f;
-    int bidx;
-    if (L.kind == 0) {
-        const int hwin = L.hi_ * L.wi;
-        const float *wrow = L.W + j * L.din;
-        for (long k = lane; k < L.din; k += 64) {
-            const long pix = k / L.ci;
-            const int c = (int)(k - pix * L.ci);
-            acc += gb[k] * wrow[(long)c * hwin + pix];
+    for (int r = 0; r < rows; ++r) {
+        const long img = (long)sp_inst[q] * rows + r;
+        const float *gb = gbar_m + img * L.din;
+        const long j = sp_j[q];
+        float acc = 0.f;
+        int bidx;
+        if (L.kind == 0) {
+            const int hwin = L.hi_ * L.wi;
+            const float *wrow = L.W + j * L.din;
+            for (long k = lane; k < L.din; k += 64) {
+                const long pix = k / L.ci;
+                const int c = (int)(k - pix * L.ci);
+                acc += gb[k] * wrow[(long)c * hwin + pix];
+            }
+            bidx = (int)j;
+        } else {
+            const long pix = j / L.co;
+            const int co = (int)(j - pix * L.co);
+            const int oy = (int)(pix / L.wo), ox = (int)(pix - (long)oy * L.wo);
+            const int taps = L.kh * L.kw * L.ci;
+            for (int t = lane; t < taps; t += 64) {
+                const int ci = t % L.ci, kk = t / L.ci;
+                const int ky = kk / L.kw, kx = kk - ky * L.kw;
+                const int y = oy * L.stride - L.pad + ky, x = ox * L.stride - L.pad + kx;
+                if (y < 0 || y >= L.hi_ || x < 0 || x >= L.wi) continue;
+                acc += gb[((long)y * L.wi + x) * L.ci + ci] *
+                       L.W[(((long)co * L.ci + ci) * L.kh + ky) * L.kw + kx];
+            }
+            bidx = co;
         }
-        bidx = (int)j;
-    } else {
-        const long pix = j / L.co;
-        const int co = (int)(j - pix * L.co);
-        const int oy = (int)(pix / L.wo), ox = (int)(pix - (long)oy * L.wo);
-        const int taps = L.kh * L.kw * L.ci;
-        for (int t = lane; t < taps; t += 64) {
-            const int ci = t % L.ci, kk = t / L.ci;
-            const int ky = kk / L.kw, kx = kk - ky * L.kw;
-            const int y = oy * L.stride - L.pad + ky, x = ox * L.stride - L.pad + kx;
-            if (y < 0 || y >= L.hi_ || x < 0 || x >= L.wi) continue;
-            acc += gb[((long)y * L.wi + x) * L.ci + ci] *
-                   L.W[(((long)co * L.ci + ci) * L.kh + ky) * L.kw + kx];
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            const float lam_bar = acc + sbar[img] * L.bias[bidx];
+            gbeta[q * rows + r] = -(float)sign[q] * lam_bar;
         }
-        bidx = co;
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) {
-        const float lam_bar = acc + sbar[img] * L.bias[bidx];
-        gbeta[(long)q * rows + r] = -(float)sign[q] * lam_bar;
     }
 }
 
@@ -918,8 +920,8 @@ hipError_t launch_beta_grad(int nnz, int rows, int layer, const BetaGradLayer &L
                             const int32_t *sp_inst, const int32_t *sp_layer, const int32_t *sp_j,
                             const int32_t *sp_dup, const int8_t *sign, const float *gbar_m,
                             const float *sbar, const int32_t *, float *gbeta, hipStream_t st) {
-    const long waves = (long)nnz * rows;
-    if (waves == 0) return hipSuccess;
+    const long waves = nnz;
+    if (waves == 0 || rows == 0) return hipSuccess;
     hipLaunchKernelGGL(k_beta_grad, dim3(blocks_for(waves * 64)), dim3(TPB), 0, st, nnz, rows,
                        layer, L, sp_inst, sp_layer, sp_j, sp_dup, sign, gbar_m, sbar, gbeta);
     return hipGetLastError();
