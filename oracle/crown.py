@@ -26,10 +26,14 @@ Readings where the text is silent or garbled (each is listed in the design notes
   * beta: a split sigma*z_j >= 0 clamps l or u, and its Lagrange multiplier beta >= 0
     adds -beta*sigma to the coefficient of z_j (weak duality keeps the bound sound).
   * Intermediate bounds use the adaptive slope alpha_j = 1 if u_j >= -l_j else 0 and
-    stay frozen while alpha / beta are optimised.
+    stay frozen while alpha / beta are optimised.  The paper allows any slope in [0, 1];
+    the rule is pinned as the choice in {0, 1} with the smaller relaxed area.
   * FP32 soundness slack: every bound moves outward by KAPPA * 2^-24 * M, where M sums
-    the magnitudes of every term of the final dot products.  Parity unpinned (the value
-    of KAPPA is a convention); the raw bound is pinned.
+    the magnitudes of every term of the final dot products; at a split neuron the
+    coefficient that multiplies the bias is the relaxed one with the beta term already
+    added, |(Lambda - beta sigma) b|.  KAPPA = 64 is a convention, pinned as a margin:
+    an FP32 evaluation of the same bound stays within KAPPA / 4 units of 2^-24 M of
+    the FP64 raw bound on the test networks.  The raw bound is pinned exactly.
   * Gradient (adjoint) of the raw lower bound w.r.t. alpha and beta: reverse mode of
     backward() + concretize(), with intermediate bounds held fixed.
   * Adam with PyTorch's default moments, followed by projection of alpha to [0, 1] and

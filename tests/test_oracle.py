@@ -19,6 +19,10 @@ not by re-typing the oracle's own formula.
   * The adjoint against central finite differences (h = 1e-6).
   * Adam against torch.optim.Adam.
   * CROWN with alpha = 0 is never looser than interval bounds on one hidden layer.
+  * The default slope rule picks, of alpha in {0, 1}, the one with the smaller relaxed
+    area (numerical integration over [l, u]).
+  * The FP32 rounding allowance: an FP32 evaluation of the same bound stays within
+    KAPPA / 4 units of 2^-24 M of the FP64 raw bound (CNN and random MLPs).
 """
 import itertools
 
@@ -481,6 +485,153 @@ def test_crown_alpha0_not_looser_than_ibp_one_hidden(seed):
     up = -O.spec_lower(net, 2, -C, bounds, lo, hi, alpha, use_slack=False)
     assert np.all(low >= ib[1][0] - 1e-12)
     assert np.all(up <= ib[1][1] + 1e-12)
+
+
+def test_adaptive_alpha_minimises_the_relaxed_area():
+    """The default lower slope (alpha = 1 if u >= -l, else 0) picks, of the two slopes in
+    {0, 1}, the one whose lower line leaves the smaller area between the two relaxation
+    lines over [l, u] (the choice plain CROWN makes when no alpha is given).  Areas are
+    integrated numerically on a dense z-grid, not taken from a closed form; at u = -l
+    both areas are equal and the rule takes 1."""
+    ls = -np.geomspace(1e-3, 10.0, 61)
+    us = np.geomspace(1e-3, 10.0, 61)
+    for l in ls:
+        for u in us:
+            z = np.linspace(l, u, 2001)
+            D_lo, D_up, b_lo, b_up, unst = O.relax(np.array([l]), np.array([u]), np.array([0.0]))
+            assert unst[0]
+            upper = D_up[0] * z + b_up[0]
+            area = [np.trapezoid(upper - a * z, z) for a in (0.0, 1.0)]
+            a = float(O.adaptive_alpha(np.array([l]), np.array([u]))[0])
+            other = 1.0 - a
+            assert area[int(a)] <= area[int(other)] + 1e-9 * abs(area[int(other)])
+    # exact tie and the two sides of it
+    assert O.adaptive_alpha(np.array([-2.0]), np.array([2.0]))[0] == 1.0
+    assert O.adaptive_alpha(np.array([-2.0]), np.array([1.999]))[0] == 0.0
+    assert O.adaptive_alpha(np.array([-1.999]), np.array([2.0]))[0] == 1.0
+
+
+# ---------------------------------------------------- FP32 rounding allowance (kappa)
+def _t32(a):
+    return torch.as_tensor(np.asarray(a, np.float32))
+
+
+def _lin_T32(layer, lam):
+    Wt = _t32(layer["W"])
+    if layer["kind"] == "linear":
+        return lam @ Wt
+    R = lam.shape[0]
+    ci, H, Wd = layer["in_shape"]
+    co, OH, OW = layer["out_shape"]
+    s, p = layer["stride"], layer["pad"]
+    k = Wt.shape[2]
+    op = H - ((OH - 1) * s - 2 * p + k)
+    return F.conv_transpose2d(lam.reshape(R, co, OH, OW), Wt, stride=s, padding=p,
+                              output_padding=op).reshape(R, -1)
+
+
+def _bias32(layer):
+    b = _t32(layer["b"])
+    if layer["kind"] == "conv":
+        b = b.repeat_interleave(layer["out_shape"][1] * layer["out_shape"][2])
+    return b
+
+
+def _bound_fp32(net, k, C, bounds, x_lo, x_hi, alpha, splits, beta):
+    """The bound of Theorem 1 + Theorem 2 with every operation in float32 (PyTorch CPU
+    products): what an FP32 implementation of the same steps returns."""
+    A = _t32(C)
+    Wt = _lin_T32(net[k - 1], A)
+    bt = A @ _bias32(net[k - 1])
+    for m in range(k - 1, 0, -1):
+        l, u = _t32(bounds[m - 1][0]).clone(), _t32(bounds[m - 1][1]).clone()
+        for (ms, j, sg) in splits:
+            if ms == m:
+                if sg > 0:
+                    l[j] = max(float(l[j]), 0.0)
+                else:
+                    u[j] = min(float(u[j]), 0.0)
+        a = _t32(alpha[m - 1]) if alpha is not None else torch.where(u >= -l, 1.0, 0.0)
+        act = l >= 0
+        ina = (~act) & (u <= 0)
+        un = ~(act | ina)
+        su = torch.where(un, u / torch.where(un, u - l, torch.ones_like(u)), torch.zeros_like(u))
+        D_lo = torch.where(act, 1.0, torch.where(ina, 0.0, a))
+        D_up = torch.where(act, 1.0, torch.where(ina, 0.0, su))
+        b_up = torch.where(un, -l * su, torch.zeros_like(u))
+        pos = Wt >= 0
+        Am = torch.where(pos, Wt * D_lo, Wt * D_up)
+        bt = bt + torch.where(pos, torch.zeros_like(Wt), Wt * b_up).sum(1)
+        for q, (ms, j, sg) in enumerate(splits):
+            if ms == m and beta is not None:
+                Am[:, j] -= _t32(beta[q]) * float(sg)
+        Wt = _lin_T32(net[m - 1], Am)
+        bt = bt + Am @ _bias32(net[m - 1])
+    xl, xh = _t32(x_lo), _t32(x_hi)
+    c, r = 0.5 * (xl + xh), 0.5 * (xh - xl)
+    return (Wt @ c - Wt.abs() @ r + bt).double().numpy()
+
+
+def _allowance_ratio(net, k, C, bounds, x_lo, x_hi, alpha, splits, beta):
+    """|FP32 bound - FP64 raw bound| in units of 2^-24 M, M the oracle's magnitude sum."""
+    cb, feasible = O.clamp_splits(bounds, splits)
+    assert feasible
+    Wt, bt, mag = O.backward(net, k, C, cb, alpha, splits, beta)
+    exact = O.concretize(Wt, bt, x_lo, x_hi)
+    allowance = O.slack(Wt, mag, x_lo, x_hi, kappa=1.0)       # 2^-24 M
+    got = _bound_fp32(net, k, C, bounds, x_lo, x_hi, alpha, splits, beta)
+    return np.abs(got - exact) / allowance
+
+
+def test_fp32_error_stays_well_inside_the_rounding_allowance():
+    """kappa = 64 is a margin, not a guess: on the 3x32x32 CNN (root 0, random splits,
+    alpha, beta) and on 20 random MLPs (random widths, depths, boxes, splits, alpha,
+    beta) the FP32 evaluation of the bound differs from the FP64 raw bound by at most
+    KAPPA / 4 units of 2^-24 M, so the outward allowance covers the FP32 arithmetic with
+    a factor of at least 4 to spare."""
+    import os
+    torch.set_num_threads(max(1, min(8, os.cpu_count() or 1)))
+    worst = 0.0
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cnn_root0.npz"))
+    w = W.cnn_cifar(1)
+    net = w.net
+    lo = g["lo"].astype(np.float32).astype(np.float64)
+    hi = g["hi"].astype(np.float32).astype(np.float64)
+    bounds = list(zip(O.per_layer(net, lo), O.per_layer(net, hi)))
+    cand = np.nonzero((lo < 0) & (hi > 0))[0]
+    rng = np.random.default_rng(0)
+    for trial in range(4):
+        sp = W.random_splits([cand], 1, 1, 12, seed=100 + trial)
+        splits = O.split_list(net, sp.neuron, sp.sign)
+        alpha = [rng.uniform(0, 1, len(l)) for (l, _) in bounds] if trial % 2 else None
+        beta = rng.uniform(0, 0.5, (len(splits), 9)) if trial > 1 else None
+        worst = max(worst, _allowance_ratio(net, len(net), w.spec[0].astype(np.float64), bounds,
+                                            w.x_lo[0], w.x_hi[0], alpha, splits, beta).max())
+    for seed in range(20):
+        dims = ([int(rng.choice([16, 64, 256, 784]))] +
+                [int(x) for x in rng.choice([32, 128, 256, 512], rng.integers(2, 6))] + [10])
+        net = W.mlp(dims, seed=200 + seed)
+        x0 = W.uniform_inputs(1, dims[0], 300 + seed)[0]
+        xl, xh = W.linf_box(x0, float(rng.choice([0.005, 0.02, 0.1])))
+        b32 = [(l.astype(np.float32).astype(np.float64), u.astype(np.float32).astype(np.float64))
+               for (l, u) in O.crown_bounds(net, xl, xh)]
+        C = W.margin_spec(W.clean_logits(net, x0[None]))[0].astype(np.float64)
+        flo = np.concatenate([b[0] for b in b32])
+        fhi = np.concatenate([b[1] for b in b32])
+        cand = np.nonzero((flo < 0) & (fhi > 0))[0]
+        splits, beta = [], None
+        if len(cand):
+            sp = W.random_splits([cand], 1, 1, 8, seed=400 + seed)
+            splits = O.split_list(net, sp.neuron, sp.sign)
+            beta = rng.uniform(0, 0.5, (len(splits), C.shape[0]))
+        alpha = [rng.uniform(0, 1, len(l)) for (l, _) in b32]
+        worst = max(worst, _allowance_ratio(net, len(net), C, b32, xl, xh, alpha, splits, beta).max())
+        # an intermediate-bound pass (identity rows on a middle layer, adaptive alpha)
+        k = len(net) // 2 + 1
+        I = np.eye(len(b32[k - 1][0]))[:64]
+        worst = max(worst, _allowance_ratio(net, k, np.concatenate([I, -I]), b32[:k - 1], xl, xh,
+                                            None, (), None).max())
+    assert worst <= O.KAPPA / 4, worst
 
 
 def test_slack_is_outward_and_small():
