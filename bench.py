@@ -6,13 +6,18 @@ Workload (the branch-and-bound batch): the 3x32x32 ReLU CNN (conv 16@3x3 s1, 32@
 inputs uniform in [0, 1] with an L-inf box of radius 2/255, 64 subdomains per root (4096)
 with 1-12 random ReLU split constraints each (drawn from the root's unstable neurons),
 9 margin rows per subdomain.  Root pre-activation bounds come from full CROWN on the GPU
-(set-up, untimed).  One step = for all 4096 subdomains: the bound pass with alpha, beta
-and the splits (SAVE_FOR_GRAD, best-so-far kept), the gradient with respect to alpha and
-beta, and one projected Adam step on each.  value = subdomains per second.
+(set-up, untimed).  An optimisation step = for all 4096 subdomains: the bound pass with
+alpha, beta and the splits (SAVE_FOR_GRAD, best-so-far kept), the gradient with respect to
+alpha and beta, and one projected Adam step on each.  The whole optimisation (10 such steps
+and a final pass) is captured as one HIP graph; a bench step is one replay of it, timed
+with HIP events (mean, median, p10, p90).  value = subdomain-steps per second (10 x 4096
+per replay).
 
-Also reported: the same work one subdomain per call ("plain"), the dominant kernel's
-roofline fraction (its average launch duration from HIP events on its own stream during
-the timed steps), and the FP64 CPU oracle timed on a bounded sample of the same units.
+Also reported: the same work one subdomain per call ("plain"), eager optimisation steps
+with per-launch HIP events (kernel breakdown; the dominant kernel's roofline fraction from
+its average launch duration), the other workloads (plain CROWN on the small MLP, full CROWN
+on the deep MLP and on the CNN, alpha-CROWN on the CNN), the planning loop, and the FP64
+CPU oracle timed on a bounded sample of the same units with all host threads and with one.
 """
 from __future__ import annotations
 
@@ -45,17 +50,36 @@ def connections(layer):
     return vy * vx * ci * co
 
 
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
+
+
+def _ev():
+    import torch
+    return torch.cuda.Event(enable_timing=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="graph replays timed (one replay = the whole alpha/beta optimisation "
+                         "of the batch)")
+    ap.add_argument("--warmup", type=int, default=3, help="untimed graph replays")
+    ap.add_argument("--eager-steps", type=int, default=5,
+                    help="optimisation steps run eagerly with per-kernel HIP events (kernel "
+                         "breakdown and the dominant kernel's roofline)")
     ap.add_argument("--roots", type=int, default=64)
     ap.add_argument("--per-root", type=int, default=64)
     ap.add_argument("--plain", type=int, default=256, help="subdomains timed one per call")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle sample budget")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="oracle sample budget per thread setting")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the kernel autotuner")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other workloads (plain CROWN MLP, deep MLP, CNN full CROWN, "
+                         "alpha-CROWN)")
     ap.add_argument("--plans", default=None,
                     help="JSON line of an earlier run: reuse its tuned kernel plans (its "
                          "'autotune' field) instead of tuning, so that profiler runs time the "
@@ -78,7 +102,7 @@ def main():
     import workloads as W
     from paper_2412_09584_amd import rocprof_summary
     from paper_2412_09584_amd import binding as B
-    from paper_2412_09584_amd import net as N
+    from paper_2412_09584_amd.batch import BetaBatch, chosen_plans
 
     dev = torch.device("cuda")
     if args.calibrate_copy:
@@ -89,90 +113,68 @@ def main():
         del src, dst
     w = W.beta_cnn(args.roots, args.per_root)
     net = w.net
-    L = len(net)
     R = w.spec.shape[1]
-    n = args.roots * args.per_root
-    bn = N.BoundNet(net, max_inst=n, max_rows=max(n * R, 36864), max_save_rows=n * R)
-
-    # ---- set-up (untimed): root bounds, splits, device state
-    lo, hi = bn.crown_bounds(w.x_lo, w.x_hi)
-    lo_np, hi_np = lo.cpu().numpy(), hi.cpu().numpy()
-    root_of = np.repeat(np.arange(args.roots), args.per_root).astype(np.int32)
-    cands = [np.nonzero((lo_np[r] < 0) & (hi_np[r] > 0))[0] for r in range(args.roots)]
-    sp = W.random_splits(cands, n, w.extra["kmin"], w.extra["kmax"], seed=W.SPLIT_SEED,
-                         root_of=root_of)
-    spd = N.splits_to_device(sp)
-    C = torch.as_tensor(w.spec[root_of], device=dev)
-    x_lo = torch.as_tensor(w.x_lo[root_of], device=dev)
-    x_hi = torch.as_tensor(w.x_hi[root_of], device=dev)
-    bof = torch.as_tensor(root_of, device=dev)
-    n_relu = bn.n_relu
-    alpha = torch.full((n, n_relu), w.extra["alpha0"], device=dev)
-    beta = torch.zeros(sp.nnz, R, device=dev)
-    ma, va = torch.zeros_like(alpha), torch.zeros_like(alpha)
-    mb, vb = torch.zeros_like(beta), torch.zeros_like(beta)
-    ga = torch.empty_like(alpha)
-    gb = torch.empty_like(beta)
-    lower = torch.empty(n, R, device=dev)
-    best = torch.full((n, R), -float("inf"), device=dev)
-    ones = torch.ones(n, R, device=dev)
-    lr = w.extra["lr"]
+    # ---- set-up (untimed): root bounds by full CROWN, splits, device state
+    bb = BetaBatch(w, args.per_root, split_seed=W.SPLIT_SEED, max_rows=36864)
+    n = bb.n
+    opt_steps = int(w.extra["steps"])
     stream = torch.cuda.current_stream()
-
-    def step(t, h=bn.handle):
-        B.bound_backward(h, n, R, L, spec=C, lo=lo, hi=hi, n_bounds=args.roots, bound_of=bof,
-                         alpha=alpha, split_off=spd["off"], split_idx=spd["idx"],
-                         split_sign=spd["sign"], nnz=sp.nnz, beta=beta, x_lo=x_lo, x_hi=x_hi,
-                         flags=B.BOUND_SAVE_FOR_GRAD, lower=lower, best=best, stream=stream)
-        B.bound_grad(h, ones, ga, gb, stream=stream)
-        B.bound_adam(alpha, ga, ma, va, t, lr, grad_scale=-1.0, clip_lo=0.0, clip_hi=1.0,
-                     stream=stream)
-        B.bound_adam(beta, gb, mb, vb, t, lr, grad_scale=-1.0, clip_lo=0.0, stream=stream)
 
     tune_log = None
     pinned = None
     if args.plans:
         with open(args.plans) as f:
             pinned = json.loads(f.read().strip().splitlines()[-1])["autotune"]
-        for key, plan in pinned.items():
-            path, cfg, cc = plan.split()[:3]
-            B.bound_set_plan(bn.handle, key[0], int(key[1:]), 1 if path == "direct" else 2,
-                             int(cfg.split("=")[1]), int(cc.split("=")[1]))
+        bb.set_plans(pinned)
     elif not args.no_tune:
-        tune_log = B.bound_autotune(bn.handle, n, R, L, grad_lower=ones, spec=C, lo=lo, hi=hi,
-                                    n_bounds=args.roots, bound_of=bof, alpha=alpha,
-                                    split_off=spd["off"], split_idx=spd["idx"],
-                                    split_sign=spd["sign"], nnz=sp.nnz, beta=beta, x_lo=x_lo,
-                                    x_hi=x_hi, flags=B.BOUND_SAVE_FOR_GRAD, lower=lower,
-                                    stream=stream)
-        best.fill_(-float("inf"))
+        tune_log = bb.autotune(stream)
         print(tune_log, file=sys.stderr)
+    plans = pinned if pinned is not None else chosen_plans(tune_log)
+
+    # ---- eager steps with per-kernel HIP events on the library's stream
+    bb.reset()
     t = 0
+    for _ in range(3):
+        t += 1
+        bb.step(t, stream)
+    torch.cuda.synchronize()
+    B.bound_profile_read(bb.bn.handle)          # discard
+    B.bound_profile(bb.bn.handle, True)
+    e0, e1 = _ev(), _ev()
+    e0.record(stream)
+    for _ in range(args.eager_steps):
+        t += 1
+        bb.step(t, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    B.bound_profile(bb.bn.handle, False)
+    prof = B.bound_profile_read(bb.bn.handle)
+    eager_ms = e0.elapsed_time(e1) / max(args.eager_steps, 1)
+
+    # ---- the headline: the whole optimisation (steps x (pass + gradient + Adam) for every
+    # subdomain, then the final pass) captured as one HIP graph and replayed
+    opt = bb.optimizer(opt_steps)
+    opt.capture()
     for _ in range(args.warmup):
-        t += 1
-        step(t)
+        opt.replay()
     torch.cuda.synchronize()
-    B.bound_profile_read(bn.handle)          # discard
-    B.bound_profile(bn.handle, True)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    evs = [_ev() for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        t += 1
-        step(t)
-    ev1.record(stream)
+    evs[0].record(stream)
+    for i in range(args.steps):
+        opt.replay()
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    B.bound_profile(bn.handle, False)
-    prof = B.bound_profile_read(bn.handle)
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    value = n / (ms_step / 1e3)
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
+    ms_replay = evs[0].elapsed_time(evs[-1]) / args.steps
+    units = n * opt_steps
+    value = units / (ms_replay / 1e3)
 
     # ---- algorithmic work
     conn = [connections(l) for l in net]
     flop_unit = 2.0 * R * (sum(conn) + sum(conn[:-1]))
-    tflops = flop_unit * n / (ms_step / 1e3) / 1e12
+    tflops = flop_unit * value / 1e12
 
     def launch_flops(label):
         if label.startswith("bwd_relax_L") or label.startswith("adj_L"):
@@ -198,55 +200,21 @@ def main():
     roofline = {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12,
                 "peak": PEAK_FP32_MFMA / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_MFMA, "traffic": traffic,
-                "avg_launch_ms": dom_ms, "flop_per_launch": dom_flops}
-    breakdown = {k: round(v[0] / args.steps, 4) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
+                "avg_launch_ms": dom_ms, "flop_per_launch": dom_flops,
+                "timed_over": f"{args.eager_steps} eager optimisation steps (HIP events per launch)"}
+    breakdown = {k: round(v[0] / max(args.eager_steps, 1), 4)
+                 for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
 
     # ---- plain path: one subdomain per call
-    plain = None
-    if args.plain > 0:
-        m = min(args.plain, n)
-        per = []
-        for i in range(m):
-            q0, q1 = int(sp.off[i]), int(sp.off[i + 1])
-            per.append(dict(
-                C=C[i:i + 1].contiguous(), x_lo=x_lo[i:i + 1].contiguous(),
-                x_hi=x_hi[i:i + 1].contiguous(), bof=bof[i:i + 1].contiguous(),
-                alpha=alpha[i:i + 1].clone(), ma=torch.zeros(1, n_relu, device=dev),
-                va=torch.zeros(1, n_relu, device=dev),
-                off=torch.tensor([0, q1 - q0], dtype=torch.int32, device=dev),
-                idx=spd["idx"][q0:q1].contiguous(), sign=spd["sign"][q0:q1].contiguous(),
-                beta=beta[q0:q1].clone(), mb=torch.zeros(q1 - q0, R, device=dev),
-                vb=torch.zeros(q1 - q0, R, device=dev), nnz=q1 - q0,
-                lower=torch.empty(1, R, device=dev), best=torch.full((1, R), -float("inf"), device=dev),
-                ga=torch.empty(1, n_relu, device=dev), gb=torch.empty(max(q1 - q0, 1), R, device=dev)))
-        ones1 = torch.ones(1, R, device=dev)
+    plain = plain_path(bb, min(args.plain, n), stream) if args.plain > 0 else None
+    if plain is not None:
+        plain["batched_speedup"] = value / plain["value"]
 
-        def plain_unit(u, tt):
-            B.bound_backward(bn.handle, 1, R, L, spec=u["C"], lo=lo, hi=hi, n_bounds=args.roots,
-                             bound_of=u["bof"], alpha=u["alpha"], split_off=u["off"],
-                             split_idx=u["idx"], split_sign=u["sign"], nnz=u["nnz"],
-                             beta=u["beta"] if u["nnz"] else None, x_lo=u["x_lo"], x_hi=u["x_hi"],
-                             flags=B.BOUND_SAVE_FOR_GRAD, lower=u["lower"], best=u["best"],
-                             stream=stream)
-            B.bound_grad(bn.handle, ones1, u["ga"], u["gb"] if u["nnz"] else None, stream=stream)
-            B.bound_adam(u["alpha"], u["ga"], u["ma"], u["va"], tt, lr, grad_scale=-1.0,
-                         clip_lo=0.0, clip_hi=1.0, stream=stream)
-            if u["nnz"]:
-                B.bound_adam(u["beta"], u["gb"], u["mb"], u["vb"], tt, lr, grad_scale=-1.0,
-                             clip_lo=0.0, stream=stream)
-
-        for u in per[:4]:
-            plain_unit(u, 1)
+    others = None
+    if not args.no_configs:
+        del opt
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for u in per:
-            plain_unit(u, 2)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        pms = e0.elapsed_time(e1)
-        plain = {"value": m / (pms / 1e3), "unit": "subdomains/s", "sample": m,
-                 "ms_per_subdomain": pms / m, "batched_speedup": value / (m / (pms / 1e3))}
+        others = other_configs(w, bb, stream)
 
     # ---- branch-and-bound planning loop (pick-out, split, search, bound, prune)
     bab = bab_loop(args.bab_iters) if args.bab_iters > 0 else None
@@ -257,18 +225,184 @@ def main():
         cpu = cpu_baseline(w, args.cpu_seconds)
 
     rec = {"metric": METRIC, "value": value, "unit": "subdomains/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_replay,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": f"beta-crown BaB batch: CNN 3x32x32 c16k3s1-c32k4s2-c32k3s1-"
                                   f"c64k4s2-fc4096-512-10, {args.roots} roots x {args.per_root} "
-                                  f"subdomains, 1-12 splits, {R} margin rows, eps 2/255",
-                      "subdomains": n, "rows": R, "split_nnz": sp.nnz, "parallelism": "none"},
-           "tflops_step": tflops, "flop_per_subdomain": flop_unit, "wall_s": wall,
+                                  f"subdomains, 1-12 splits, {R} margin rows, eps 2/255, "
+                                  f"{opt_steps} alpha/beta steps per graph replay",
+                      "subdomains": n, "rows": R, "split_nnz": bb.nnz,
+                      "units_per_step": units, "parallelism": "none"},
+           "step": "one HIP-graph replay of the whole optimisation: per subdomain "
+                   f"{opt_steps} x (bound pass + alpha/beta gradient + Adam) and a final pass",
+           "replay_ms": {"mean": ms_replay, "median": _pct(per, 50), "p10": _pct(per, 10),
+                         "p90": _pct(per, 90), "n": len(per)},
+           "eager_ms_per_opt_step": eager_ms, "eager_value": n / (eager_ms / 1e3),
+           "tflops_step": tflops, "flop_per_subdomain": flop_unit,
+           "roofline_frac_step": tflops * 1e12 / PEAK_FP32_MFMA, "wall_s": wall,
            "plain": plain, "roofline": roofline, "kernel_ms_per_step": breakdown,
-           "autotune": _tuned(tune_log) if pinned is None else pinned, "bab_loop": bab,
-           "cpu_baseline": cpu}
+           "autotune": plans, "configs": others, "bab_loop": bab, "cpu_baseline": cpu}
     print(json.dumps(rec))
+
+
+def plain_path(bb, m, stream):
+    """The same units one subdomain per call (n_inst = 1, per-layer kernels, no graph)."""
+    import torch
+
+    from paper_2412_09584_amd import binding as B
+    dev = bb.alpha.device
+    R, L, n_relu = bb.R, bb.L, bb.bn.n_relu
+    sp, spd = bb.splits, bb.spd
+    per = []
+    for i in range(m):
+        q0, q1 = int(sp.off[i]), int(sp.off[i + 1])
+        per.append(dict(
+            C=bb.C[i:i + 1].contiguous(), x_lo=bb.x_lo[i:i + 1].contiguous(),
+            x_hi=bb.x_hi[i:i + 1].contiguous(), bof=bb.bof[i:i + 1].contiguous(),
+            alpha=torch.full((1, n_relu), bb.alpha0, device=dev),
+            ma=torch.zeros(1, n_relu, device=dev), va=torch.zeros(1, n_relu, device=dev),
+            off=torch.tensor([0, q1 - q0], dtype=torch.int32, device=dev),
+            idx=spd["idx"][q0:q1].contiguous(), sign=spd["sign"][q0:q1].contiguous(),
+            beta=torch.zeros(q1 - q0, R, device=dev), mb=torch.zeros(q1 - q0, R, device=dev),
+            vb=torch.zeros(q1 - q0, R, device=dev), nnz=q1 - q0,
+            lower=torch.empty(1, R, device=dev), best=torch.full((1, R), -float("inf"), device=dev),
+            ga=torch.empty(1, n_relu, device=dev), gb=torch.empty(max(q1 - q0, 1), R, device=dev)))
+    ones1 = torch.ones(1, R, device=dev)
+
+    def unit(u, tt):
+        B.bound_backward(bb.bn.handle, 1, R, L, spec=u["C"], lo=bb.lo, hi=bb.hi,
+                         n_bounds=bb.n_roots, bound_of=u["bof"], alpha=u["alpha"],
+                         split_off=u["off"], split_idx=u["idx"], split_sign=u["sign"], nnz=u["nnz"],
+                         beta=u["beta"] if u["nnz"] else None, x_lo=u["x_lo"], x_hi=u["x_hi"],
+                         flags=B.BOUND_SAVE_FOR_GRAD, lower=u["lower"], best=u["best"],
+                         stream=stream)
+        B.bound_grad(bb.bn.handle, ones1, u["ga"], u["gb"][:u["nnz"]] if u["nnz"] else None,
+                     stream=stream)
+        B.bound_adam(u["alpha"], u["ga"], u["ma"], u["va"], tt, bb.lr, grad_scale=-1.0,
+                     clip_lo=0.0, clip_hi=1.0, stream=stream)
+        if u["nnz"]:
+            B.bound_adam(u["beta"], u["gb"][:u["nnz"]], u["mb"], u["vb"], tt, bb.lr,
+                         grad_scale=-1.0, clip_lo=0.0, stream=stream)
+
+    for u in per[:4]:
+        unit(u, 1)
+    torch.cuda.synchronize()
+    e0, e1 = _ev(), _ev()
+    e0.record(stream)
+    for u in per:
+        unit(u, 2)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    pms = e0.elapsed_time(e1)
+    return {"value": m / (pms / 1e3), "unit": "subdomains/s", "sample": m,
+            "ms_per_subdomain": pms / m,
+            "path": "n_inst = 1 per call, per-layer kernels, no graph"}
+
+
+def crown_flops(net, rows_final):
+    """Algorithmic FLOP of full CROWN on one input: every pre-activation layer k bounded
+    by a backward pass with rows [I; -I] through the products of layers k-1 .. 1 (the
+    first step A W_k with A = I is a gather, not a product), then the spec rows [C; -C]
+    through all layers; 2 FLOP per weight application, padding taps excluded."""
+    import numpy as np
+    conn = [connections(l) for l in net]
+    dims = [int(np.prod(l["out_shape"])) for l in net]
+    f = sum(2.0 * 2 * dims[k - 1] * sum(conn[:k - 1]) for k in range(2, len(net)))
+    return f + 2.0 * 2 * rows_final * sum(conn)
+
+
+def _time(fn, reps, warm=2):
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = _ev(), _ev()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def other_configs(w_cnn, bb, stream):
+    """The smaller workloads, each with its own unit: plain CROWN on the small MLP (latency,
+    eager and as one HIP graph), full CROWN on the deep MLP and on the CNN (inputs/s and
+    the fraction of the FP32 MFMA peak), alpha-CROWN on the CNN (input-steps/s)."""
+    import torch
+
+    import workloads as W
+    from paper_2412_09584_amd import net as N
+    out = {}
+    # plain CROWN, MLP 784-100-100-10, one input: lower and upper bounds of z_1, z_2 and the
+    # margins
+    w0 = W.mlp_small()
+    bn0 = N.BoundNet(w0.net, 1, 4096)
+    C0 = torch.as_tensor(w0.spec, device="cuda")
+    xl0, xh0 = torch.as_tensor(w0.x_lo, device="cuda"), torch.as_tensor(w0.x_hi, device="cuda")
+
+    def full0():
+        lo, hi = bn0.crown_bounds(xl0, xh0)
+        return bn0.spec_bounds(C0, lo, hi, xl0, xh0)
+
+    us_eager = 1e3 * _time(full0, 50, 5)
+    g0 = torch.cuda.CUDAGraph()
+    full0()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g0):
+        full0()
+    us_graph = 1e3 * _time(g0.replay, 200, 5)
+    out["plain_crown_mlp784-100-100-10_1_input"] = {
+        "us_per_full_crown_eager": us_eager, "us_per_full_crown_graph": us_graph,
+        "flop": crown_flops(w0.net, 9), "bound": "launch latency"}
+    del g0, bn0
+    # full CROWN, MLP 784-256x6-10, 256 inputs
+    w1 = W.mlp_deep(256)
+    bn1 = N.BoundNet(w1.net, 256, 256 * 512)
+    C1 = torch.as_tensor(w1.spec, device="cuda")
+    xl1, xh1 = torch.as_tensor(w1.x_lo, device="cuda"), torch.as_tensor(w1.x_hi, device="cuda")
+
+    def full1():
+        lo, hi = bn1.crown_bounds(xl1, xh1)
+        return bn1.spec_bounds(C1, lo, hi, xl1, xh1)
+
+    ms1 = _time(full1, 10, 2)
+    f1 = crown_flops(w1.net, 9)
+    out["full_crown_mlp784-256x6-10_256_inputs"] = {
+        "inputs_per_s": 256 / (ms1 / 1e3), "ms_per_batch": ms1, "flop_per_input": f1,
+        "tflops": f1 * 256 / (ms1 / 1e3) / 1e12,
+        "frac_fp32_mfma": f1 * 256 / (ms1 / 1e3) / PEAK_FP32_MFMA}
+    del bn1
+    # full CROWN, the CNN, 64 inputs (the roots of the batch above)
+    bn2 = bb.bn
+    C2 = torch.as_tensor(w_cnn.spec, device="cuda")
+    xl2, xh2 = torch.as_tensor(w_cnn.x_lo, device="cuda"), torch.as_tensor(w_cnn.x_hi, device="cuda")
+    n2 = C2.shape[0]
+
+    def full2():
+        lo, hi = bn2.crown_bounds(xl2, xh2)
+        return bn2.spec_bounds(C2, lo, hi, xl2, xh2)
+
+    ms2 = _time(full2, 3, 1)
+    f2 = crown_flops(w_cnn.net, 9)
+    out[f"full_crown_cnn_{n2}_inputs"] = {
+        "inputs_per_s": n2 / (ms2 / 1e3), "ms_per_batch": ms2, "flop_per_input": f2,
+        "tflops": f2 * n2 / (ms2 / 1e3) / 1e12,
+        "frac_fp32_mfma": f2 * n2 / (ms2 / 1e3) / PEAK_FP32_MFMA,
+        "note": "padding taps excluded from the FLOP count"}
+    # alpha-CROWN on the CNN: 64 inputs, 20 Adam steps, as one HIP graph
+    lo, hi = bn2.crown_bounds(xl2, xh2)
+    opt = N.AlphaBetaOptimizer(bn2, C2, lo, hi, xl2, xh2, steps=20, lr=0.1, alpha0=0.5,
+                               use_beta=False)
+    opt.capture()
+    ms3 = _time(opt.replay, 5, 1)
+    conn = [connections(l) for l in w_cnn.net]
+    fu = 2.0 * 9 * (sum(conn) + sum(conn[:-1]))
+    out[f"alpha_crown_cnn_{n2}_inputs_20_steps"] = {
+        "input_steps_per_s": n2 * 20 / (ms3 / 1e3), "ms_per_replay": ms3, "flop_per_unit": fu,
+        "frac_fp32_mfma": fu * n2 * 20 / (ms3 / 1e3) / PEAK_FP32_MFMA}
+    return out
 
 
 def bab_loop(iters, d=16, hidden=(256, 256, 256), n_pick=1024, samples=64):
@@ -296,31 +430,31 @@ def bab_loop(iters, d=16, hidden=(256, 256, 256), n_pick=1024, samples=64):
             "best": best, "candidates": int(P["lo"].shape[0])}
 
 
-def _tuned(log):
-    """Chosen plan per product from the autotuner's log (fastest line per product)."""
-    if not log:
-        return None
-    best = {}
-    for line in log.strip().splitlines():
-        key, path, cfg, cc, ms, _ = line.split()
-        t = float(ms)
-        if key not in best or t < best[key][0]:
-            best[key] = (t, f"{path} {cfg} {cc}")
-    return {k: f"{v[1]} {v[0]:.3f}ms" for k, v in best.items()}
+def _cpu_model():
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return None
 
 
-def cpu_baseline(w, budget_s):
-    """The FP64 oracle (as it stands) on a bounded sample of the same units: for each
-    sampled subdomain of root 0, the bound, its alpha/beta gradient and one Adam step."""
+def _oracle_units(w, budget_s):
+    """The FP64 oracle (as it stands) on subdomains of root 0 for about budget_s seconds:
+    per subdomain the bound, its alpha/beta gradient and one Adam step."""
     import numpy as np
 
     from oracle import crown as O
     import workloads as W
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        threads = os.cpu_count()
     g = np.load(os.path.join(ROOT, "tests", "golden", "cnn_root0.npz"))
     net = w.net
     lo = g["lo"].astype(np.float32).astype(np.float64)
@@ -343,10 +477,31 @@ def cpu_baseline(w, budget_s):
             O.adam_step(alpha[i], -ga[i], np.zeros_like(ga[i]), np.zeros_like(ga[i]), 1, 0.1, lo=0.0, hi=1.0)
         O.adam_step(beta, -gb, np.zeros_like(gb), np.zeros_like(gb), 1, 0.1, lo=0.0)
         done += 1
-    el = time.perf_counter() - t0
+    return done, time.perf_counter() - t0
+
+
+def cpu_baseline(w, budget_s):
+    """The oracle on a bounded sample of the same units, with every host thread as BLAS
+    threads and with one thread."""
+    threads = os.cpu_count()
+    limits = None
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [threads])
+        limits = threadpool_limits
+    except Exception:
+        pass
+    done, el = _oracle_units(w, budget_s)
+    one = None
+    if limits is not None:
+        with limits(limits=1):
+            d1, e1 = _oracle_units(w, budget_s)
+        one = {"value": d1 / e1, "unit": "subdomains/s", "cores": 1,
+               "sample": f"{d1} subdomains of root 0, {e1:.1f} s"}
     return {"value": done / el, "unit": "subdomains/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} subdomains of root 0 (bound + alpha/beta gradient + Adam step), "
-                      f"{el:.1f} s", "host_cpus": os.cpu_count()}
+                      f"{el:.1f} s", "host_cpus": os.cpu_count(), "cpu_model": _cpu_model(),
+            "one_thread": one}
 
 
 if __name__ == "__main__":

@@ -86,12 +86,16 @@ typedef struct {
  * alpha     [n_inst, n_relu] lower relaxation slopes in [0, 1] (read at unstable
  *           neurons only), or NULL for the rule alpha = 1 if u >= -l else 0.
  * split_off [n_inst + 1], split_idx [nnz], split_sign [nnz]: CSR list of split
- *           constraints sign * z_j >= 0 (j a global ReLU index: relu_off(m) + neuron);
- *           each neuron at most once per instance.  A split clamps l or u to 0; an
- *           instance whose clamped box is empty gets lower = +inf (upper = -inf).
- *           All three NULL and nnz = 0 when there are no splits; nnz < 2^24.
+ *           constraints sign * z_j >= 0 (j a global ReLU index: relu_off(m) + neuron).
+ *           A split clamps l (sign +1) or u (sign -1) to 0; an instance whose clamped
+ *           box is empty gets lower = +inf (upper = -inf).  A neuron may appear in
+ *           several entries of one instance: the clamps compose, every entry has its own
+ *           multiplier, and their terms add.  Entries whose neuron lies outside layers
+ *           1 .. target-1 are ignored.  All three NULL and nnz = 0 when there are no
+ *           splits; nnz < 2^24.
  * beta      [nnz, rows] Lagrange multipliers (>= 0) of the splits, or NULL (= 0):
- *           each adds -beta * sign to the coefficient of its split neuron.
+ *           entry q adds -beta[q, r] * sign[q] to row r's coefficient of its split
+ *           neuron (after the relaxation of Lemma 1).
  * x_lo,x_hi [n_inst, d_0] the input box.  NULL: do not concretise; the pass then
  *           writes the coefficient form (bound_out.coeff / offset / offset_mag).
  * flags     BOUND_SAVE_FOR_GRAD (requires an explicit spec, no BOTH_SIDES, and
@@ -140,7 +144,9 @@ enum { BOUND_STOP_RELU = 1, BOUND_STOP_LINEAR = 2 };
  * offset [n_inst*rows(*2)] the offsets b~(1), offset_mag [...] the sum of |terms| of
  *        b~(1) (for the rounding allowance) -- written only when x_lo == NULL;
  * best   [n_inst, ld] or NULL: updated to max(best, lower) (every alpha in [0, 1] and
- *        beta >= 0 gives a valid bound, so the best over optimisation steps is kept). */
+ *        beta >= 0 gives a valid bound, so the best over optimisation steps is kept);
+ * pass_id host pointer or NULL: a SAVE_FOR_GRAD pass writes its id (1, 2, ... per
+ *        handle), which bound_grad can be asked to check. */
 typedef struct {
     float *lower;
     float *upper;
@@ -149,6 +155,7 @@ typedef struct {
     float *offset;
     float *offset_mag;
     float *best;
+    int64_t *pass_id;
 } bound_out;
 
 /* Create a network handle.  Validates the layer chain, packs the weights for the
@@ -199,11 +206,21 @@ bound_status bound_concretize(int32_t n_inst, int32_t rows, int32_t d0, const fl
 
 /* Gradient of sum_{i,r} grad_lower[i,r] * lower_raw[i,r] of the last SAVE_FOR_GRAD
  * pass (the raw bound, i.e. without the rounding allowance; intermediate bounds held
- * fixed) with respect to alpha and beta:
+ * fixed) with respect to alpha and beta -- the reverse mode of Theorem 1's recursion and
+ * Theorem 2's concretisation:
+ * grad_lower [n_inst, rows];
  * grad_alpha [n_inst, n_relu] (overwritten; zero outside unstable, unsplit neurons of
- * layers 1 .. target-1), grad_beta [nnz, rows] (overwritten; may be NULL).
- * Infeasible instances get zero gradients. */
-bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alpha,
+ * layers 1 .. target-1), grad_beta [nnz, rows] (overwritten; may be NULL): entry q of
+ * row r gets -sign[q] * (the derivative with respect to its neuron's coefficient), so
+ * repeated entries of one neuron get the same value up to their signs.
+ * Infeasible instances get zero gradients.
+ * pass_id: 0 = the last SAVE_FOR_GRAD pass, else the id that pass wrote to
+ * bound_out.pass_id; BOUND_E_STATE when that pass is no longer the saved one (any later
+ * bound_backward or bound_sample_bounds call invalidates it).  n_inst, rows and nnz state
+ * the caller's buffer shapes; BOUND_E_SHAPE unless they are the saved pass's (nnz is
+ * checked only when grad_beta is given). */
+bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t rows,
+                        int32_t nnz, const float *grad_lower, float *grad_alpha,
                         float *grad_beta, void *stream);
 
 /* One Adam step (PyTorch's bias-corrected form) on n parameters, minimising a loss

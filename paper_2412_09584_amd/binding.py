@@ -48,7 +48,8 @@ class BoundPass(ctypes.Structure):
 
 class BoundOut(ctypes.Structure):
     _fields_ = [("lower", _p), ("upper", _p), ("ld", ctypes.c_int64), ("coeff", _p),
-                ("offset", _p), ("offset_mag", _p), ("best", _p)]
+                ("offset", _p), ("offset_mag", _p), ("best", _p),
+                ("pass_id", ctypes.POINTER(ctypes.c_int64))]
 
 
 class BoundError(RuntimeError):
@@ -75,7 +76,8 @@ def lib():
         L.bound_backward.argtypes = [_p, ctypes.POINTER(BoundPass), ctypes.POINTER(BoundOut), _p]
         L.bound_concretize.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _p, _p, _p,
                                        _p, _p, ctypes.c_int32, _p, _p]
-        L.bound_grad.argtypes = [_p, _p, _p, _p, _p]
+        L.bound_grad.argtypes = [_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_int32, _p, _p, _p, _p]
         L.bound_sample_bounds.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p, _p]
         L.bound_adam.argtypes = [ctypes.c_int64, _p, _p, _p, _p, ctypes.c_int32, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
@@ -166,7 +168,7 @@ def _pass_out(n_inst, rows, target, spec, lo, hi, n_bounds, bound_of, alpha, spl
                   int(nnz), _ptr(beta), _ptr(x_lo), _ptr(x_hi), int(flags), int(stop_layer),
                   int(stop_mode))
     O = BoundOut(_ptr(lower), _ptr(upper), int(ld), _ptr(coeff), _ptr(offset), _ptr(offset_mag),
-                 _ptr(best))
+                 _ptr(best), None)
     return P, O
 
 
@@ -197,13 +199,16 @@ def bound_backward(handle, n_inst, rows, target, *, spec=None, lo=None, hi=None,
                    nnz=0, beta=None, x_lo=None, x_hi=None, flags=0, lower=None, upper=None,
                    ld=0, coeff=None, offset=None, offset_mag=None, best=None, stop_layer=0,
                    stop_mode=0, stream=None):
+    """One bound pass; returns the pass id (a SAVE_FOR_GRAD pass's, else 0)."""
     P = BoundPass(int(n_inst), int(rows), int(target), int(n_bounds), _ptr(spec), _ptr(lo), _ptr(hi),
                   _ptr(bound_of), _ptr(alpha), _ptr(split_off), _ptr(split_idx), _ptr(split_sign),
                   int(nnz), _ptr(beta), _ptr(x_lo), _ptr(x_hi), int(flags), int(stop_layer),
                   int(stop_mode))
+    pid = ctypes.c_int64(0)
     O = BoundOut(_ptr(lower), _ptr(upper), int(ld), _ptr(coeff), _ptr(offset), _ptr(offset_mag),
-                 _ptr(best))
+                 _ptr(best), ctypes.pointer(pid))
     _check(lib().bound_backward(handle, ctypes.byref(P), ctypes.byref(O), _stream(stream)))
+    return pid.value
 
 
 def bound_concretize(n_inst, rows, d0, coeff, offset, offset_mag, x_lo, x_hi, flags, lower,
@@ -218,9 +223,12 @@ def bound_sample_bounds(handle, n_sub, per_sub, x, lo=None, hi=None, out=None, s
                                      _ptr(out), _stream(stream)))
 
 
-def bound_grad(handle, grad_lower, grad_alpha, grad_beta=None, stream=None):
-    _check(lib().bound_grad(handle, _ptr(grad_lower), _ptr(grad_alpha), _ptr(grad_beta),
-                            _stream(stream)))
+def bound_grad(handle, grad_lower, grad_alpha, grad_beta=None, pass_id=0, stream=None):
+    """Shapes are taken from the buffers: grad_lower [n_inst, rows], grad_beta [nnz, rows]."""
+    n_inst, rows = grad_lower.shape
+    nnz = 0 if grad_beta is None else grad_beta.shape[0]
+    _check(lib().bound_grad(handle, int(pass_id), int(n_inst), int(rows), int(nnz),
+                            _ptr(grad_lower), _ptr(grad_alpha), _ptr(grad_beta), _stream(stream)))
 
 
 def bound_adam(param, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8, grad_scale=1.0,

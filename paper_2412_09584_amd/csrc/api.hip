@@ -68,6 +68,8 @@ struct bound_net {
     int32_t *sp = nullptr;           // 4 x sp_cap: instance, layer, internal index, repeated entry
     int8_t *sp_sign = nullptr;
     long sp_cap = 0;
+    float *bsum = nullptr;           // [nnz][rows]: split-multiplier term per first entry
+    long bsum_cap = 0;
     int options = 0;
     // kernel plan per product (key: 'R'/'C'/'A' * 256 + layer), chosen by bound_autotune
     std::map<int, Plan> plans;
@@ -80,7 +82,8 @@ struct bound_net {
     std::vector<hipEvent_t> pool;
     // state of the last SAVE_FOR_GRAD pass
     bool saved = false;
-    int s_target = 0, s_rows = 0, s_n_inst = 0, s_nnz = 0, s_stop = 0, s_mode = 0;
+    int64_t pass_seq = 0;            // id of the last SAVE_FOR_GRAD pass (1, 2, ...)
+    int s_target = 0, s_rows = 0, s_n_inst = 0, s_nnz = 0, s_nnz_arg = 0, s_stop = 0, s_mode = 0;
     std::vector<long> s_off;         // offset of saved G_m (m = 1..k) in the save buffer
     long s_lam_off = 0;              // saved Lambda at a linear early stop
 
@@ -270,20 +273,32 @@ bound_status build_geoms(bound_net *net, hipStream_t st) {
     return BOUND_OK;
 }
 
-bound_status ensure_split_cap(bound_net *net, long nnz, hipStream_t st) {
-    if (nnz <= net->sp_cap) return BOUND_OK;
+// Scratch for the split list (nnz entries) and, with beta, its per-row multiplier terms
+// (nnz x rows).  Grows only outside stream capture; old buffers stay until bound_destroy.
+bound_status ensure_split_cap(bound_net *net, long nnz, long rows, hipStream_t st) {
+    const bool grow_sp = nnz > net->sp_cap, grow_b = nnz * rows > net->bsum_cap;
+    if (!grow_sp && !grow_b) return BOUND_OK;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
         return fail(BOUND_E_NOMEM, "split list larger than any earlier pass while the stream is "
                                    "being captured; run one pass of this size before capturing");
-    const long cap = roundup(nnz, 4096);
-    int32_t *sp;
-    int8_t *sg;
-    if (!net->alloc(&sp, 4 * cap) || !net->alloc(&sg, cap))
-        return fail(BOUND_E_NOMEM, "split scratch");
-    net->sp = sp;
-    net->sp_sign = sg;
-    net->sp_cap = cap;
+    if (grow_sp) {
+        const long cap = roundup(nnz, 4096);
+        int32_t *sp;
+        int8_t *sg;
+        if (!net->alloc(&sp, 4 * cap) || !net->alloc(&sg, cap))
+            return fail(BOUND_E_NOMEM, "split scratch");
+        net->sp = sp;
+        net->sp_sign = sg;
+        net->sp_cap = cap;
+    }
+    if (grow_b) {
+        const long cap = roundup(nnz * rows, 4096);
+        float *b;
+        if (!net->alloc(&b, cap)) return fail(BOUND_E_NOMEM, "split multiplier scratch");
+        net->bsum = b;
+        net->bsum_cap = cap;
+    }
     return BOUND_OK;
 }
 
@@ -402,7 +417,7 @@ bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max
         delete net;
         return fail(BOUND_E_NOMEM, "bound_init: workspace allocation failed");
     }
-    bound_status s = ensure_split_cap(net, (long)max_inst * 16, st);
+    bound_status s = ensure_split_cap(net, (long)max_inst * 16, 0, st);
     if (s != BOUND_OK) { delete net; return s; }
     s = build_geoms(net, st);
     if (s != BOUND_OK) { delete net; return s; }
@@ -482,8 +497,9 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
 
     // Relaxation tables (Lemma 1) for z_1 .. z_{k-1}, split clamping, box.
     const int used = k - 1;
+    const bool inject = P->beta != nullptr && used > 0;
     if (nnz > 0) {
-        bound_status s = ensure_split_cap(net, nnz, st);
+        bound_status s = ensure_split_cap(net, nnz, inject ? P->rows : 0, st);
         if (s != BOUND_OK) return s;
     }
     int32_t *sp_inst = net->sp, *sp_layer = net->sp + net->sp_cap, *sp_j = net->sp + 2 * net->sp_cap;
@@ -508,6 +524,9 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
                                   sp_inst, sp_layer, sp_j, sp_dup, P->n_bounds, sl - 1,
                                   smode == BOUND_STOP_RELU, sl > 0 ? net->stop_cen : nullptr,
                                   sl > 0 ? net->stop_rad : nullptr, st));
+        if (inject)
+            HIPCHK(launch_beta_sum(nnz, P->rows, P->split_off, P->split_idx, P->split_sign, sp_inst,
+                                   sp_layer, sp_dup, P->beta, net->bsum, st));
     } else if (sl > 0) {
         HIPCHK(launch_prep_stop_box(P->n_inst, *SL, net->n_relu, P->lo, P->hi, P->bound_of,
                                     P->n_bounds, smode == BOUND_STOP_RELU, net->stop_cen,
@@ -532,7 +551,6 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
         }
         lam_off = o;
     }
-    const bool inject = P->beta != nullptr && used > 0;
     for (long img0 = 0; img0 < total; img0 += chunk) {
         const long n_img = total - img0 < chunk ? total - img0 : chunk;
         float *cur = net->buf[0], *nxt = net->buf[1];
@@ -561,15 +579,11 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
                 ip.bias_m = (smode == BOUND_STOP_LINEAR && sl == k - 1) ? net->zeros : net->bias(k - 1);
                 ip.chan_m = net->chan(k - 1);
                 ip.out = cur;
+                ip.bsum = inject ? net->bsum : nullptr;
                 {
                     ProfScope ps(net, st, lbl("init_identity_L%d", k));
                     HIPCHK(launch_init_identity(ip, n_img, false, st));
                 }
-                if (inject)
-                    HIPCHK(launch_beta_inject(nnz, P->rows, rpi, img0, n_img, k - 2, sp_inst, sp_layer,
-                                              sp_j, P->split_sign, P->beta, cur, net->d[k - 1],
-                                              ip.bias_m, net->chan(k - 1), net->acc_s,
-                                              net->acc_mag, st));
                 m_start = k - 1;
             }
         } else {
@@ -595,6 +609,7 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             rp.img0 = img0;
             rp.rpi = rpi;
             rp.rrpi = 1.0f / (float)rpi;
+            rp.bsum = inject ? net->bsum : nullptr;   // split terms fused into the epilogue
             {
                 ProfScope ps(net, st, lbl("bwd_relax_L%d", m));
                 const GeomSet &gs = net->layers[m - 1].gT;
@@ -604,11 +619,6 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
                 });
                 if (bs != BOUND_OK) return bs;
             }
-            ProfScope pb(net, st, "beta_inject");
-            if (inject)
-                HIPCHK(launch_beta_inject(nnz, P->rows, rpi, img0, n_img, m - 2, sp_inst, sp_layer, sp_j,
-                                          P->split_sign, P->beta, nxt, net->d[m - 1], rp.bias,
-                                          net->chan(m - 1), net->acc_s, net->acc_mag, st));
             float *t = cur; cur = nxt; nxt = t;
         }
         if (smode == BOUND_STOP_LINEAR) {
@@ -643,10 +653,13 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
     }
     if (save) {
         net->saved = true;
+        ++net->pass_seq;
+        if (out->pass_id) *out->pass_id = net->pass_seq;
         net->s_target = k;
         net->s_rows = P->rows;
         net->s_n_inst = P->n_inst;
         net->s_nnz = used > 0 ? nnz : 0;
+        net->s_nnz_arg = nnz;
         net->s_off = soff;
         net->s_stop = sl;
         net->s_mode = smode;
@@ -658,10 +671,20 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
     return BOUND_OK;
 }
 
-bound_status bound_grad(bound_net *net, const float *grad_lower, float *grad_alpha,
-                        float *grad_beta, void *stream) {
+bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t rows_arg,
+                        int32_t nnz, const float *grad_lower, float *grad_alpha, float *grad_beta,
+                        void *stream) {
     if (!net || !grad_lower || !grad_alpha) return fail(BOUND_E_ARG, "bound_grad: null argument");
     if (!net->saved) return fail(BOUND_E_STATE, "bound_grad: no SAVE_FOR_GRAD pass to differentiate");
+    if (pass_id != 0 && pass_id != net->pass_seq)
+        return fail(BOUND_E_STATE, "bound_grad: pass " + std::to_string(pass_id) +
+                                       " is not the last SAVE_FOR_GRAD pass (" +
+                                       std::to_string(net->pass_seq) + ") or was invalidated");
+    if (n_inst != net->s_n_inst || rows_arg != net->s_rows || (grad_beta && nnz != net->s_nnz_arg))
+        return fail(BOUND_E_SHAPE, "bound_grad: n_inst / rows / nnz differ from the saved pass (" +
+                                       std::to_string(net->s_n_inst) + " / " +
+                                       std::to_string(net->s_rows) + " / " +
+                                       std::to_string(net->s_nnz_arg) + ")");
     hipStream_t st = (hipStream_t)stream;
     const int k = net->s_target, rows = net->s_rows;
     const long n_img = (long)net->s_n_inst * rows;
@@ -839,7 +862,8 @@ bound_status bound_autotune(bound_net *net, const bound_pass *pass, const bound_
         if (hipMalloc(&ga, sizeof(float) * (size_t)pass->n_inst * (size_t)net->n_relu) != hipSuccess)
             s = fail(BOUND_E_NOMEM, "bound_autotune: gradient scratch");
         else
-            s = bound_grad(net, grad_lower, ga, nullptr, stream);
+            s = bound_grad(net, 0, pass->n_inst, pass->rows, pass->nnz, grad_lower, ga, nullptr,
+                           stream);
     }
     net->tuning = false;
     if (s == BOUND_OK) s = bound_backward(net, pass, out, stream);   // leave valid outputs

@@ -333,10 +333,12 @@ __global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, 
         if (l > u) infeas[i] = 1;
         const long j = to_internal(jn, L.C, L.HW);
         // a split neuron's record carries w = -(q + 1), q its first entry in the
-        // instance's list: the adjoint epilogue writes that entry's beta-gradient
+        // instance's list, and that entry's sign in the sign bit of z: the adjoint
+        // epilogue writes the entry's beta-gradient -sign * Lambda_bar
         const float wq = -(float)(first + 1);
-        tab[(long)i * n_relu + L.off + j] = l >= 0.f ? make_float4(1.f, 1.f, 0.f, wq)
-                                                     : make_float4(0.f, 0.f, 0.f, wq);
+        const float zs = sign[first] < 0 ? -0.0f : 0.0f;
+        tab[(long)i * n_relu + L.off + j] = l >= 0.f ? make_float4(1.f, 1.f, zs, wq)
+                                                     : make_float4(0.f, 0.f, zs, wq);
         sp_dup[q] = first != q;   // a repeated entry: k_beta_grad computes it
         if (m == stop_m && stop_cen) {  // the early-stop node's box sees the clamp too
             const float a = stop_relu ? fmaxf(l, 0.f) : l, c = stop_relu ? fmaxf(u, 0.f) : u;
@@ -458,7 +460,9 @@ __global__ void k_init_identity(const IdentityParams p, long n_img) {
             if (p.emit) p.emit[li * p.din + (long)c * hwin + pix] = gval;
         } else {
             const Relax t = p.tab[inst * p.tab_ld + j];
-            const float lam = gval >= 0.f ? gval * t.x : gval * t.y;
+            float lam = gval >= 0.f ? gval * t.x : gval * t.y;
+            // split neuron: the multipliers' term of its first entry (rows = rpi here)
+            if (p.bsum && t.w < 0.f) lam -= p.bsum[(long)(-(int)t.w - 1) * p.rpi + rr];
             const float off = gval < 0.f ? gval * t.z : 0.f;
             const float bt = lam * p.bias_m[j % p.chan_m];
             a += bt + off;
@@ -480,23 +484,19 @@ __global__ void k_init_identity(const IdentityParams p, long n_img) {
     }
 }
 
-__global__ void k_beta_inject(int nnz, int rows, int rpi, long img0, long n_img, int layer,
-                              const int32_t *sp_inst, const int32_t *sp_layer,
-                              const int32_t *sp_j, const int8_t *sign, const float *beta,
-                              float *lam, long D, const float *bias, int chan, float *s,
-                              float *mag) {
+__global__ void k_beta_sum(int nnz, int rows, const int32_t *off, const int32_t *idx,
+                           const int8_t *sign, const int32_t *sp_inst, const int32_t *sp_layer,
+                           const int32_t *sp_dup, const float *beta, float *bsum) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (long)nnz * rows) return;
     const int q = (int)(e / rows), r = (int)(e - (long)q * rows);
-    if (sp_layer[q] != layer) return;
-    const long img = (long)sp_inst[q] * rpi + r - img0;
-    if (img < 0 || img >= n_img) return;
-    const float delta = -beta[(long)q * rows + r] * (float)sign[q];
-    const long j = sp_j[q];
-    atomicAdd(lam + img * D + j, delta);
-    const float bt = delta * bias[j % chan];
-    atomicAdd(s + img, bt);
-    atomicAdd(mag + img, fabsf(bt));
+    // entries this pass does not relax, and repeats (their term is in the first entry's)
+    if (sp_layer[q] < 0 || sp_dup[q]) return;
+    const int i = sp_inst[q], g = idx[q];
+    float s = 0.f;
+    for (int q2 = off[i]; q2 < off[i + 1]; ++q2)
+        if (idx[q2] == g) s += (float)sign[q2] * beta[(long)q2 * rows + r];
+    bsum[e] = s;
 }
 
 __global__ void k_finalize(long img0, long n_img, int rows, int rpi, const float *s,
@@ -880,15 +880,13 @@ hipError_t launch_init_identity(const IdentityParams &p, long n_img, bool conc, 
     return hipGetLastError();
 }
 
-hipError_t launch_beta_inject(int nnz, int rows, int rpi, long img0, long n_img, int layer,
-                              const int32_t *sp_inst, const int32_t *sp_layer, const int32_t *sp_j,
-                              const int8_t *sign, const float *beta, float *lam, long D,
-                              const float *bias, int chan, float *s, float *mag, hipStream_t st) {
+hipError_t launch_beta_sum(int nnz, int rows, const int32_t *off, const int32_t *idx,
+                           const int8_t *sign, const int32_t *sp_inst, const int32_t *sp_layer,
+                           const int32_t *sp_dup, const float *beta, float *bsum, hipStream_t st) {
     const long total = (long)nnz * rows;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_beta_inject, dim3(blocks_for(total)), dim3(TPB), 0, st, nnz, rows, rpi,
-                       img0, n_img, layer, sp_inst, sp_layer, sp_j, sign, beta, lam, D, bias, chan,
-                       s, mag);
+    hipLaunchKernelGGL(k_beta_sum, dim3(blocks_for(total)), dim3(TPB), 0, st, nnz, rows, off, idx,
+                       sign, sp_inst, sp_layer, sp_dup, beta, bsum);
     return hipGetLastError();
 }
 

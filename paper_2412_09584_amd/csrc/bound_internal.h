@@ -47,7 +47,9 @@ struct GeomSet {
 // x = lower slope, y = upper slope, z = upper intercept; w = 0 for a stable neuron,
 // -(q + 1) for a split neuron whose first entry in the instance's split list is q, and
 // k + 1 for an unstable one, k its slot in the compact rows of saved coefficients (alpha
-// free).  Records with w <= 0 have x = y and z = 0.
+// free).  Records with w <= 0 have x = y and z = +-0: a split record carries the sign of
+// its first entry's constraint in the sign bit of z (-0 for sign -1), which the adjoint
+// needs for that entry's beta-gradient (the slope cannot tell it when l = u = 0).
 typedef float4 Relax;
 
 // ----- epilogue parameter blocks -----------------------------------------------------
@@ -64,6 +66,8 @@ struct RelaxParams {       // G_m = Lambda_m W_m  ->  Lambda_{m-1} = relax(G_m)
     long img0;             // global img index of local img 0
     int rpi;               // imgs per instance
     float rrpi;            // fl(1 / rpi)
+    const float *bsum;     // [nnz][rpi] split-multiplier term per first split entry and
+                           // row, subtracted at the split neuron (nullable: no beta)
 };
 
 struct ConcParams {        // G_1 = Lambda_1 W_1  ->  concretise over the box
@@ -214,6 +218,7 @@ struct IdentityParams {
     const float *bias_m;
     int chan_m;
     float *out;                // Lambda_{k-1} [img][din]
+    const float *bsum;         // split-multiplier terms (see RelaxParams), nullable
     // concretise mode (k == 1)
     const float *cen, *rad;
     float *emit;
@@ -222,11 +227,11 @@ struct IdentityParams {
 };
 hipError_t launch_init_identity(const IdentityParams &p, long n_img, bool conc, hipStream_t st);
 
-hipError_t launch_beta_inject(int nnz, int rows, int rpi, long img0, long n_img, int layer,
-                              const int32_t *sp_inst, const int32_t *sp_layer,
-                              const int32_t *sp_j, const int8_t *sign, const float *beta,
-                              float *lam, long D, const float *bias, int chan, float *s,
-                              float *mag, hipStream_t st);
+// Per first split entry q and row r: sum over the instance's entries on the same neuron
+// of sign * beta (the term the relaxation epilogue subtracts at the split neuron).
+hipError_t launch_beta_sum(int nnz, int rows, const int32_t *off, const int32_t *idx,
+                           const int8_t *sign, const int32_t *sp_inst, const int32_t *sp_layer,
+                           const int32_t *sp_dup, const float *beta, float *bsum, hipStream_t st);
 hipError_t launch_finalize(long img0, long n_img, int rows, int rpi, const float *s,
                            const float *low, const float *mag, const int32_t *infeas,
                            bool slack, float *lower, float *upper, long ld, float *offset,

@@ -97,6 +97,14 @@ struct EpiRelax {
         const long o = (long)img * p.D;
         return Row{p.tab + inst * p.tab_ld, p.out + o, p.save ? p.save + o : nullptr};
     }
+    // split multipliers' term of row rc at first split entry q: the row within its
+    // instance is recovered from the row's output pointer (only on this rare path, so the
+    // common path keeps no extra register per row)
+    __device__ float split_term(const Row &rc, int q) const {
+        const long gi = p.img0 + (rc.out - p.out) / p.D;
+        const long r = gi - (gi / p.rpi) * p.rpi;
+        return p.bsum[(long)q * p.rpi + r];
+    }
     __device__ float colv(int n) const { return p.bias[n % p.chan]; }
     __device__ float *red0() const { return p.s; }
     __device__ float *red1() const { return p.mag; }
@@ -104,7 +112,13 @@ struct EpiRelax {
     __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &t, const Row &rc, int, int, int j, float bcol, float g,
                          float &r0, float &r1) const {
-        const float lam = g >= 0.f ? g * t.x : g * t.y;
+        // Lemma 1's line by the sign of G, then -sum(beta sign) of the split entries at a
+        // split neuron (first entry q = -w - 1); split neurons are a few per instance, so
+        // their term is loaded here, in a branch most waves skip, rather than carried in
+        // registers with every element's record.  The bias term takes the coefficient with
+        // the split term included.
+        float lam = g >= 0.f ? g * t.x : g * t.y;
+        if (t.w < 0.f && p.bsum) lam -= split_term(rc, -(int)t.w - 1);
         const float off = g < 0.f ? g * t.z : 0.f;
         const float bt = lam * bcol;
         r0 += bt + off;
@@ -174,8 +188,8 @@ struct EpiAdj {
         // instance's rows by k_alpha_grad)
         if (t.w > 0.f) at(rc.gc, (int)t.w - 1) = g >= 0.f ? g * v : 0.f;
         // split neuron (first entry q of the instance's list): d lower / d beta_{q,r} =
-        // -sign * Lambda_bar; the active split's record has slope 1, the inactive one 0
-        if (t.w < 0.f && rc.gb) rc.gb[(long)(-(int)t.w - 1) * p.rpi] = t.x > 0.5f ? -v : v;
+        // -sign_q * Lambda_bar, sign_q carried in the sign bit of the record's z
+        if (t.w < 0.f && rc.gb) rc.gb[(long)(-(int)t.w - 1) * p.rpi] = signbit(t.z) ? v : -v;
     }
 };
 

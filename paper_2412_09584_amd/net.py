@@ -78,10 +78,11 @@ class BoundNet:
             kw = dict(split_off=splits["off"], split_idx=splits["idx"], split_sign=splits["sign"],
                       nnz=int(splits["idx"].numel()))
         n_bounds = lo.shape[0] if lo is not None else 0
-        B.bound_backward(self.handle, n, rows, target, spec=C, lo=lo, hi=hi, n_bounds=n_bounds,
-                         bound_of=bound_of, alpha=alpha, beta=beta, x_lo=_dev(x_lo, self.device),
-                         x_hi=_dev(x_hi, self.device), flags=flags, lower=lower, upper=upper,
-                         best=best, stop_layer=stop_layer, stop_mode=stop_mode, **kw)
+        self.last_pass_id = B.bound_backward(
+            self.handle, n, rows, target, spec=C, lo=lo, hi=hi, n_bounds=n_bounds,
+            bound_of=bound_of, alpha=alpha, beta=beta, x_lo=_dev(x_lo, self.device),
+            x_hi=_dev(x_hi, self.device), flags=flags, lower=lower, upper=upper, best=best,
+            stop_layer=stop_layer, stop_mode=stop_mode, **kw)
         return lower, upper
 
     def coefficients(self, C, lo, hi, *, target=None, alpha=None, both=False):
@@ -99,12 +100,13 @@ class BoundNet:
                          offset_mag=mag)
         return coeff, offset, mag
 
-    def grad(self, grad_lower, nnz=0, rows=None):
-        """d(sum grad_lower * lower_raw)/d(alpha, beta) of the last saved pass."""
+    def grad(self, grad_lower, nnz=0, pass_id=0):
+        """d(sum grad_lower * lower_raw)/d(alpha, beta) of the last saved pass (or of the
+        pass with this id: the library refuses if another pass has run since)."""
         n = grad_lower.shape[0]
         ga = torch.empty(n, self.n_relu, device=self.device)
         gb = torch.empty(nnz, grad_lower.shape[1], device=self.device) if nnz else None
-        B.bound_grad(self.handle, grad_lower.contiguous(), ga, gb)
+        B.bound_grad(self.handle, grad_lower.contiguous(), ga, gb, pass_id=pass_id)
         return ga, gb
 
 
@@ -116,7 +118,11 @@ def splits_to_device(sp, device="cuda"):
 
 
 class CrownBound(torch.autograd.Function):
-    """lower = CROWN bound of C z_L as a function of (alpha, beta); backward = bound_grad."""
+    """lower = CROWN bound of C z_L as a function of (alpha, beta); backward = bound_grad.
+
+    The library keeps the state of one SAVE_FOR_GRAD pass per handle; backward names the
+    pass its forward made (by id), so a forward of another batch in between makes the
+    backward raise instead of returning that batch's gradient."""
 
     @staticmethod
     def forward(ctx, alpha, beta, net, C, lo, hi, x_lo, x_hi, bound_of, splits, best):
@@ -125,13 +131,14 @@ class CrownBound(torch.autograd.Function):
                                    bound_of=bound_of, splits=splits, both=False, save=True,
                                    best=best)
         ctx.net = net
+        ctx.pass_id = net.last_pass_id
         ctx.nnz = 0 if splits is None else int(splits["idx"].numel())
         ctx.has_beta = beta is not None
         return lower
 
     @staticmethod
     def backward(ctx, grad_lower):
-        ga, gb = ctx.net.grad(grad_lower, ctx.nnz)
+        ga, gb = ctx.net.grad(grad_lower, ctx.nnz if ctx.has_beta else 0, pass_id=ctx.pass_id)
         return (ga, gb if ctx.has_beta else None) + (None,) * 9
 
 

@@ -42,7 +42,7 @@ def test_error_paths_without_device(L):
     from paper_2412_09584_amd import binding as B
     assert L.bound_backward(None, None, None, None) == B.BOUND_E_ARG
     assert "null" in B.bound_last_error()
-    assert L.bound_grad(None, None, None, None, None) == B.BOUND_E_ARG
+    assert L.bound_grad(None, 0, 0, 0, 0, None, None, None, None) == B.BOUND_E_ARG
     assert L.bound_concretize(-1, 1, 1, None, None, None, None, None, 0, None, None) == B.BOUND_E_ARG
     assert L.bound_adam(10, None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, 1.0, 0.0, 1.0,
                         None) == B.BOUND_E_ARG
