@@ -339,6 +339,16 @@ bound_status bound_bab_update_best(bound_bab *bab, int32_t n, const float *f_hi,
 bound_status bound_bab_prune(bound_bab *bab, int32_t n, const float *f_lo, const float *best,
                              int32_t *keep, int32_t *n_keep, void *stream);
 
+/* The pruner of bound_bab_prune (same arguments, same output, without a bound_bab
+ * handle) for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  It allocates nothing; its
+ * scratch (per-block counts of the stable compaction) is a fixed 16 KiB array in the
+ * library that each GPU holds until the process ends.  0 <= n <= 4194304
+ * (BOUND_E_ARG otherwise).  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (different streams or threads without ordering) race. */
+bound_status bound_bab_prune_noalloc(int32_t n, const float *f_lo, const float *best,
+                                     int32_t *keep, int32_t *n_keep, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

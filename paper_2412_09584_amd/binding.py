@@ -24,8 +24,8 @@ EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "b
             "bound_adam", "bound_sample_bounds", "bound_autotune", "bound_autotune_report", "bound_set_options", "bound_set_plan",
             "bound_profile", "bound_profile_read", "bound_destroy",
             "bound_bab_init", "bound_bab_pick_out", "bound_bab_samples", "bound_bab_search_summary",
-            "bound_bab_split", "bound_bab_update_best", "bound_bab_prune", "bound_bab_destroy",
-            "bound_last_error")
+            "bound_bab_split", "bound_bab_update_best", "bound_bab_prune", "bound_bab_prune_noalloc",
+            "bound_bab_destroy", "bound_last_error")
 
 _p = ctypes.c_void_p
 
@@ -105,6 +105,7 @@ def lib():
         L.bound_bab_split.argtypes = [_p, i32, _p, _p, _p, i32, _p, _p, _p, _p]
         L.bound_bab_update_best.argtypes = [_p, i32, _p, _p, i32, _p, _p, _p]
         L.bound_bab_prune.argtypes = [_p, i32, _p, _p, _p, _p, _p]
+        L.bound_bab_prune_noalloc.argtypes = [i32, _p, _p, _p, _p, _p]
         L.bound_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[:-1]:
             if name not in ("bound_profile_read", "bound_autotune_report", "bound_destroy",
@@ -314,6 +315,11 @@ def bound_bab_update_best(handle, n, f_hi, top, k, best, u_best, stream=None):
 def bound_bab_prune(handle, n, f_lo, best, keep, n_keep, stream=None):
     _check(lib().bound_bab_prune(handle, int(n), _ptr(f_lo), _ptr(best), _ptr(keep), _ptr(n_keep),
                                  _stream(stream)))
+
+
+def bound_bab_prune_noalloc(n, f_lo, best, keep, n_keep, stream=None):
+    _check(lib().bound_bab_prune_noalloc(int(n), _ptr(f_lo), _ptr(best), _ptr(keep), _ptr(n_keep),
+                                         _stream(stream)))
 
 
 def bound_last_error():

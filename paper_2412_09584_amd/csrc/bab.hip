@@ -11,6 +11,7 @@
 
 #include <cfloat>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "bound.h"
@@ -19,6 +20,13 @@
 namespace bp {
 bound_status set_error(bound_status s, const std::string &msg);   // api.hip
 }
+
+// Scratch of the allocation-free pruner (bound_bab_prune_noalloc): the per-block counts,
+// then offsets, of up to 4096 blocks of 1024 subdomains (16 KiB).  Every GPU the library
+// runs on holds its own copy until the process ends.  Host code passes the address that
+// hipGetSymbolAddress returned for the current device, never the symbol itself (that is
+// a host-side stand-in, not a device address).
+static __device__ __align__(256) int32_t scratch[4096];
 
 struct bound_bab {
     int max_dom = 0, dim = 0, max_samples = 0;
@@ -256,6 +264,94 @@ __global__ void k_prune_flags(int n, const float *f_lo, const float *best, uint8
     if (i < n) flag[i] = canon(f_lo[i]) <= canon(*best) ? 1 : 0;
 }
 
+// ---- pruner without allocation: stable compaction through per-block counts.
+// Block b of the count and scatter kernels covers subdomains [b * PRUNE_TILE, ...);
+// the scan kernel turns the block counts into block offsets and writes the total.
+constexpr int PRUNE_TILE = 1024;                  // subdomains per block (4 per thread)
+constexpr int PRUNE_MAX_BLOCKS = 4096;
+constexpr long PRUNE_MAX_N = (long)PRUNE_TILE * PRUNE_MAX_BLOCKS;
+static_assert(PRUNE_MAX_BLOCKS == sizeof(::scratch) / sizeof(int32_t), "scratch holds the block counts");
+
+__device__ inline bool kept(const float *f_lo, int i, float b) { return canon(f_lo[i]) <= b; }
+
+__global__ __launch_bounds__(TPB) void k_prune_count(int n, const float *f_lo, const float *best,
+                                                     int32_t *counts) {
+    __shared__ int wsum[TPB / 64];
+    const float b = canon(*best);
+    const int i0 = blockIdx.x * PRUNE_TILE;
+    int c = 0;
+    for (int t = threadIdx.x; t < PRUNE_TILE; t += TPB) {
+        const int i = i0 + t;
+        c += (i < n && kept(f_lo, i, b)) ? 1 : 0;
+    }
+    for (int m = 1; m < 64; m <<= 1) c += __shfl_xor(c, m, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int w = 0; w < TPB / 64; ++w) s += wsum[w];
+        counts[blockIdx.x] = s;
+    }
+}
+
+// One block: exclusive scan of nb block counts in place, total to *n_keep.
+__global__ __launch_bounds__(TPB) void k_prune_scan(int nb, int32_t *counts, int32_t *n_keep) {
+    __shared__ int part[TPB];
+    const int per = (nb + TPB - 1) / TPB, a = threadIdx.x * per;
+    int s = 0;
+    for (int k = 0; k < per && a + k < nb; ++k) s += counts[a + k];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < TPB; ++t) {
+            const int v = part[t];
+            part[t] = run;
+            run += v;
+        }
+        *n_keep = run;
+    }
+    __syncthreads();
+    int run = part[threadIdx.x];
+    for (int k = 0; k < per && a + k < nb; ++k) {
+        const int v = counts[a + k];
+        counts[a + k] = run;
+        run += v;
+    }
+}
+
+// Block b writes its kept subdomains, in index order, from offset counts[b] on: the
+// rank of a kept subdomain inside the block is the number of kept ones before it (wave
+// ballots, then the waves' and rounds' totals through LDS).
+__global__ __launch_bounds__(TPB) void k_prune_scatter(int n, const float *f_lo, const float *best,
+                                                       const int32_t *offsets, int32_t *keep) {
+    __shared__ int wcnt[PRUNE_TILE / 64];
+    const float b = canon(*best);
+    const int i0 = blockIdx.x * PRUNE_TILE, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    bool f[PRUNE_TILE / TPB];
+    uint64_t m[PRUNE_TILE / TPB];
+#pragma unroll
+    for (int r = 0; r < PRUNE_TILE / TPB; ++r) {   // round r covers [r * TPB, (r + 1) * TPB)
+        const int i = i0 + r * TPB + threadIdx.x;
+        f[r] = i < n && kept(f_lo, i, b);
+        m[r] = __ballot(f[r]);
+        if (lane == 0) wcnt[r * (TPB / 64) + w] = __popcll(m[r]);
+    }
+    __syncthreads();
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const int base = offsets[blockIdx.x];
+#pragma unroll
+    for (int r = 0; r < PRUNE_TILE / TPB; ++r) {
+        // kept subdomains of the (round, wave) segments before this one
+        int before = base;
+        for (int s = 0; s < r * (TPB / 64) + w; ++s) before += wcnt[s];
+        if (f[r]) keep[before + __popcll(m[r] & below)] = i0 + r * TPB + threadIdx.x;
+    }
+}
+
+std::mutex g_scratch_mu;
+int32_t *g_scratch_ptr[64] = {};   // per device: the address of `scratch` on that GPU
+
 hipError_t sort_pairs(bound_bab *b, int n, hipStream_t st) {
     size_t bytes = b->tmp_bytes;
     return hipcub::DeviceRadixSort::SortPairs(b->tmp, bytes, b->keys, b->keys_out, b->vals,
@@ -393,6 +489,38 @@ bound_status bound_bab_update_best(bound_bab *b, int32_t n, const float *f_hi, c
     if (n == 0) return BOUND_OK;
     hipLaunchKernelGGL(bp::k_update_best, dim3(1), dim3(bp::TPB), 0, (hipStream_t)stream, n, f_hi,
                        top, k, b->dim, best, u_best);
+    BCHK(hipGetLastError());
+    return BOUND_OK;
+}
+
+bound_status bound_bab_prune_noalloc(int32_t n, const float *f_lo, const float *best, int32_t *keep,
+                                     int32_t *n_keep, void *stream) {
+    if (n < 0 || (long)n > bp::PRUNE_MAX_N || !best || !n_keep || (n > 0 && (!f_lo || !keep)))
+        return set_error(BOUND_E_ARG, "bound_bab_prune_noalloc: bad arguments (need 0 <= n <= " +
+                                          std::to_string(bp::PRUNE_MAX_N) + ")");
+    int dev = 0;
+    BCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return set_error(BOUND_E_ARG, "bound_bab_prune_noalloc: device id");
+    int32_t *scr;
+    {
+        std::lock_guard<std::mutex> lk(bp::g_scratch_mu);
+        if (!bp::g_scratch_ptr[dev]) {
+            void *p = nullptr;
+            BCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+            bp::g_scratch_ptr[dev] = (int32_t *)p;
+        }
+        scr = bp::g_scratch_ptr[dev];
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) {
+        hipLaunchKernelGGL(bp::k_zero_i32, dim3(1), dim3(1), 0, st, n_keep);
+        BCHK(hipGetLastError());
+        return BOUND_OK;
+    }
+    const int nb = (int)((n + bp::PRUNE_TILE - 1) / bp::PRUNE_TILE);
+    hipLaunchKernelGGL(bp::k_prune_count, dim3(nb), dim3(bp::TPB), 0, st, n, f_lo, best, scr);
+    hipLaunchKernelGGL(bp::k_prune_scan, dim3(1), dim3(bp::TPB), 0, st, nb, scr, n_keep);
+    hipLaunchKernelGGL(bp::k_prune_scatter, dim3(nb), dim3(bp::TPB), 0, st, n, f_lo, best, scr, keep);
     BCHK(hipGetLastError());
     return BOUND_OK;
 }

@@ -80,3 +80,10 @@ def test_shape_validation_without_device(L):
     assert L.bound_init(arr2, 1, 1, 16, 0, None, ctypes.byref(out)) == B.BOUND_E_SHAPE
     arr3 = (B.BoundLayer * 1)(B.BoundLayer(B.BOUND_CONV2D, 3, 8, 8, 4, 3, 3, 3, 3, 3, 0, fake, fake))
     assert L.bound_init(arr3, 1, 1, 16, 0, None, ctypes.byref(out)) == B.BOUND_E_SHAPE
+
+
+def test_noalloc_prune_rejects_sizes_without_device(L):
+    from paper_2412_09584_amd import binding as B
+    assert L.bound_bab_prune_noalloc(4194305, None, None, None, None, None) == B.BOUND_E_ARG
+    assert "4194304" in B.bound_last_error()
+    assert L.bound_bab_prune_noalloc(-1, None, None, None, None, None) == B.BOUND_E_ARG
