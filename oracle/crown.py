@@ -39,6 +39,10 @@ Readings where the text is silent or garbled (each is listed in the design notes
   * Adam with PyTorch's default moments, followed by projection of alpha to [0, 1] and
     beta to [0, inf).  Parity of optimiser trajectories is unpinned: only single steps
     at identical alpha / beta are compared.
+  * Optimised intermediate bounds (alpha_crown_bounds): every pass that bounds a
+    pre-activation layer gets its own slopes, optimised like the final pass's (one slope
+    per neuron shared by the lower- and upper-bound rows of that layer), bottom-up; each
+    bound is the best over the evaluated passes, which include the default-rule pass.
   * Propagation early stop (Appendix B.2, the early-stop algorithm): the backward
     search ends at an early-stop node and the bound is concretised against that node's
     box.  On a layer chain the node is either the ReLU of layer s (its propagation step
@@ -305,6 +309,38 @@ def crown_bounds(net, x_lo, x_hi, use_slack=True, chunk=4096):
             lo[a:b] = spec_lower(net, k, I, bounds, x_lo, x_hi, use_slack=use_slack)
             hi[a:b] = -spec_lower(net, k, -I, bounds, x_lo, x_hi, use_slack=use_slack)
         bounds.append((lo, hi))
+    return bounds
+
+
+def alpha_crown_bounds(net, x_lo, x_hi, steps=5, lr=0.1, alpha0=0.5, use_slack=True):
+    """Pre-activation bounds (l_m, u_m), m = 1..L-1, for one box, with the slopes of every
+    intermediate pass optimised (the relaxation's alpha is free for any bound, Lemma 1).
+
+    Layers are bounded bottom-up.  For z_k the rows are [I; -I] (lower bounds of z_k and
+    of -z_k).  First the pass with the default slope rule and the bounds found so far;
+    then `steps` projected Adam steps (lr, PyTorch's default moments) on the slopes of
+    layers 1..k-1, one slope per neuron shared by all rows of this target layer, starting
+    at alpha0 and maximising the sum of the rows' lower bounds; then one more pass.  Each
+    neuron keeps the best of the steps + 2 passes.  Layer 1 is exact (no ReLU below)."""
+    bounds = []
+    for k in range(1, len(net)):
+        d = out_dim(net[k - 1])
+        A = np.concatenate([np.eye(d), -np.eye(d)])
+        best = spec_lower(net, k, A, bounds, x_lo, x_hi, None, use_slack=use_slack)
+        if k > 1 and steps > 0:
+            alpha = [np.full(len(l), float(alpha0)) for (l, _) in bounds]
+            ma = [np.zeros(len(l)) for (l, _) in bounds]
+            va = [np.zeros(len(l)) for (l, _) in bounds]
+            for t in range(1, steps + 1):
+                best = np.maximum(best, spec_lower(net, k, A, bounds, x_lo, x_hi, alpha,
+                                                   use_slack=use_slack))
+                _, ga, _ = spec_lower_grad(net, k, A, bounds, x_lo, x_hi, alpha)
+                for i in range(len(alpha)):
+                    alpha[i], ma[i], va[i] = adam_step(alpha[i], -ga[i], ma[i], va[i], t, lr,
+                                                       lo=0.0, hi=1.0)
+            best = np.maximum(best, spec_lower(net, k, A, bounds, x_lo, x_hi, alpha,
+                                               use_slack=use_slack))
+        bounds.append((best[:d], -best[d:]))
     return bounds
 
 

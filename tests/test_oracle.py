@@ -794,3 +794,86 @@ def test_sample_bounds_inside_sound_bounds_and_exact_on_vertices():
     ev = O.sample_bounds(net, verts)
     np.testing.assert_allclose(ev[0][0], crown_b[0][0], rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(ev[0][1], crown_b[0][1], rtol=1e-12, atol=1e-12)
+
+
+# -------------------------------------------- unrolled dynamics and optimised bounds
+def test_unrolled_chain_equals_stepwise_rollout():
+    """The layer chain of the unrolled dynamics model (composed step boundaries, carried
+    actions) computes the same objective as stepping the dynamics MLP H times."""
+    for H in (1, 2, 3, 20):
+        uw = W.pushing_unrolled(H)
+        assert len(uw.net) == 4 * H + 2 and W.in_dim(uw.net) == 2 * H
+        rng = np.random.default_rng(H)
+        u = rng.uniform(uw.u_lo, uw.u_hi, (64, 2 * H))
+        f = O.forward(uw.net, u)[-1][:, 0]
+        ref = W.rollout_cost(u, uw)
+        assert np.max(np.abs(f - ref) / np.maximum(1.0, np.abs(ref))) < 1e-5
+    assert sum(l["W"].size + l["b"].size for l in W.pushing_mlp()) == 134152
+
+
+def test_carried_actions_are_stable_active_neurons():
+    """Carried actions stay >= the pass-through offset on the action box, so CROWN keeps
+    them exact (active neurons, no relaxation)."""
+    uw = W.pushing_unrolled(3)
+    lo, hi = W.action_subboxes(uw, 1, seed=31)
+    b = O.crown_bounds(uw.net, lo[0], hi[0])
+    for m, (l, u) in enumerate(b[:-1]):
+        width = W.out_dim(uw.net[m])
+        hidden = {0: 128, 1: 256, 2: 256, 3: 128}[m % 4]
+        assert width >= hidden
+        assert np.all(l[hidden:] >= 0.5 * W.PUSH_PASS)
+
+
+@pytest.mark.parametrize("H,seed", [(1, 41), (2, 42)])
+def test_alpha_crown_bounds_sound_and_tighter(H, seed):
+    """Optimised intermediate bounds of the unrolled model on an action sub-box: sound on
+    10^5 sampled action sequences (every pre-activation inside [l, u]), and in total
+    tighter than plain CROWN's (each layer's bound includes the default-rule pass on the
+    same lower-layer bounds, and the slopes are optimised from there)."""
+    uw = W.pushing_unrolled(H)
+    lo, hi = W.action_subboxes(uw, 1, seed=seed, width=(0.3, 0.6))
+    lo, hi = lo[0], hi[0]
+    plain = O.crown_bounds(uw.net, lo, hi)
+    opt = O.alpha_crown_bounds(uw.net, lo, hi, steps=5)
+    u = sample_box(lo, hi, 100000, seed)
+    zs = O.forward(uw.net, u)
+    for m, (l, h) in enumerate(opt):
+        assert np.all(zs[m].min(axis=0) >= l - 1e-9), m
+        assert np.all(zs[m].max(axis=0) <= h + 1e-9), m
+    w_plain = sum(float(np.sum(h - l)) for (l, h) in plain)
+    w_opt = sum(float(np.sum(h - l)) for (l, h) in opt)
+    assert w_opt < w_plain
+    # layer by layer: never looser than the default-rule pass on the same lower-layer bounds
+    for k in range(2, len(uw.net)):
+        d = W.out_dim(uw.net[k - 1])
+        A = np.concatenate([np.eye(d), -np.eye(d)])
+        ref = O.spec_lower(uw.net, k, A, opt[:k - 1], lo, hi, None)
+        assert np.all(opt[k - 1][0] >= ref[:d]) and np.all(opt[k - 1][1] <= -ref[d:])
+
+
+def test_both_sided_rows_adjoint_fd():
+    """The adjoint of a pass whose rows are [I; -I] (the optimised intermediate bounds'
+    objective) against central differences, on the unrolled model."""
+    uw = W.pushing_unrolled(2)
+    lo, hi = W.action_subboxes(uw, 1, seed=43, width=(0.3, 0.6))
+    bounds = O.crown_bounds(uw.net, lo[0], hi[0])
+    k = 6
+    d = W.out_dim(uw.net[k - 1])
+    A = np.concatenate([np.eye(d), -np.eye(d)])
+    rng = np.random.default_rng(44)
+    alpha = [rng.uniform(0.05, 0.95, len(l)) for (l, _) in bounds[:k - 1]]
+    gbar = rng.normal(size=2 * d)
+    _, ga, _ = O.spec_lower_grad(uw.net, k, A, bounds[:k - 1], lo[0], hi[0], alpha, gbar=gbar)
+    unst = [(m, j) for m, (l, u) in enumerate(bounds[:k - 1]) for j in np.nonzero((l < 0) & (u > 0))[0]]
+    assert len(unst) >= 16
+    h = 1e-6
+    for i in rng.choice(len(unst), size=16, replace=False):
+        m, j = unst[i]
+        ap = [a.copy() for a in alpha]
+        am = [a.copy() for a in alpha]
+        ap[m][j] += h
+        am[m][j] -= h
+        fp = gbar @ O.spec_lower(uw.net, k, A, bounds[:k - 1], lo[0], hi[0], ap, use_slack=False)
+        fm = gbar @ O.spec_lower(uw.net, k, A, bounds[:k - 1], lo[0], hi[0], am, use_slack=False)
+        fd = (fp - fm) / (2 * h)
+        assert ga[m][j] == pytest.approx(fd, rel=1e-5, abs=1e-7 * (1 + abs(fd)))

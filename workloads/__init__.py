@@ -266,3 +266,137 @@ def plan_uniforms(seed=PLAN_SEED):
         return rng.random(shape, dtype=np.float64).astype(np.float32)
 
     return draw
+
+
+# ----------------------------------------------------------------- unrolled dynamics model
+PUSH_DIMS = (10, 128, 256, 256, 128, 8)   # state 8 (four keypoints, 2-D) + action 2 -> state 8
+PUSH_PASS = 1.0                           # pass-through offset (see pushing_unrolled)
+
+
+@dataclass
+class Unrolled:
+    """A dynamics MLP unrolled over a planning horizon as one ReLU layer chain.
+
+    net      layer dicts of the chain (input: the H actions, 2H values)
+    mlp      layer dicts of the dynamics MLP itself
+    x0       initial state [8]; target [8]
+    u_lo, u_hi  the action box [2H] (the root domain of the planner)
+    H        horizon
+    """
+    net: list
+    mlp: list
+    x0: np.ndarray
+    target: np.ndarray
+    u_lo: np.ndarray
+    u_hi: np.ndarray
+    H: int
+
+
+def pushing_mlp(seed=WEIGHT_SEED):
+    """The Pushing-with-Obstacles dynamics model's shape: MLP 10-128-256-256-128-8 (134,152
+    parameters), He-normal weights from seed (trained weights are not available)."""
+    return mlp(list(PUSH_DIMS), seed=seed)
+
+
+def pushing_unrolled(H=20, seed=WEIGHT_SEED, state_seed=5, u_bound=1.0):
+    """f(u) = sum_j |x_H - target|_j with x_{t+1} = MLP(x_t, u_t), as a ReLU layer chain.
+
+    The objective is the L1 step cost at the horizon, written with ReLUs
+    (|y| = ReLU(y) + ReLU(-y)), so the whole objective is a chain of Linear layers with a
+    ReLU after every layer but the last:
+
+      * step t's first layer reads x_t and u_t.  For t > 0, x_t = W5 h + b5 is the
+        previous step's last (linear) layer, so that layer and this one are composed
+        into one linear layer (no ReLU lies between them);
+      * actions not yet used are carried through the ReLU layers as pass-through neurons
+        v = u - u_lo + PUSH_PASS >= PUSH_PASS > 0 (identity rows; ReLU(v) = v on the
+        box), and read back as u = v + u_lo - PUSH_PASS where they enter;
+      * after the last step, the layer [W5; -W5] h + [b5 - target; target - b5] gives the
+        16 values +-(x_H - target), a ReLU, and a final layer of ones sums them.
+
+    Layers: 4 H + 2 (4 H + 1 ReLU layers); input 2 H.  Composed weights are formed in
+    float64 and rounded to float32 once.
+    """
+    m = pushing_mlp(seed)
+    W = [l["W"].astype(np.float64) for l in m]
+    b = [l["b"].astype(np.float64) for l in m]
+    rng = np.random.default_rng(state_seed)
+    x0 = rng.uniform(-1.0, 1.0, 8)
+    target = rng.uniform(-1.0, 1.0, 8)
+    nu = 2 * H
+    u_lo = -u_bound * np.ones(nu)
+    u_hi = u_bound * np.ones(nu)
+    W1x, W1u = W[0][:, :8], W[0][:, 8:]
+    layers = []
+
+    def add(Wm, bm):
+        Wm = np.asarray(Wm)
+        layers.append({"kind": "linear", "W": Wm.astype(np.float32), "b": np.asarray(bm).astype(np.float32),
+                       "in_shape": (Wm.shape[1],), "out_shape": (Wm.shape[0],)})
+
+    def pass_rows(first_action, n_in, col_of):
+        """Identity rows carrying actions first_action .. H-1 (2 values each)."""
+        rows = []
+        for a in range(first_action, H):
+            for c in range(2):
+                r = np.zeros(n_in)
+                r[col_of(a, c)] = 1.0
+                rows.append(r)
+        return np.array(rows).reshape(-1, n_in)
+
+    # step 0, first layer: input u (2H)
+    P = 2 * (H - 1)
+    top = np.zeros((128, nu))
+    top[:, 0:2] = W1u
+    rows = pass_rows(1, nu, lambda a, c: 2 * a + c)
+    Wm = np.vstack([top, rows])
+    bm = np.concatenate([W1x @ x0 + b[0], (PUSH_PASS - u_lo[2:])])
+    add(Wm, bm)
+    for t in range(H):
+        P = 2 * (H - 1 - t)                      # actions carried after step t's first layer
+        # layers 2..4 of step t: hidden plus the carried actions
+        for k in (1, 2, 3):
+            d_in, d_out = W[k].shape[1], W[k].shape[0]
+            Wm = np.zeros((d_out + P, d_in + P))
+            Wm[:d_out, :d_in] = W[k]
+            Wm[d_out:, d_in:] = np.eye(P)
+            add(Wm, np.concatenate([b[k], np.zeros(P)]))
+        if t + 1 < H:
+            # W5 of step t composed with W1 of step t + 1; u_{t+1} from its carried values
+            Pn = P - 2
+            Wm = np.zeros((128 + Pn, 128 + P))
+            Wm[:128, :128] = W1x @ W[4]
+            Wm[:128, 128:130] = W1u
+            if Pn:
+                Wm[128:, 130:] = np.eye(Pn)
+            ua = u_lo[2 * (t + 1):2 * (t + 1) + 2]
+            bm = np.concatenate([W1x @ b[4] + b[0] + W1u @ (ua - PUSH_PASS), np.zeros(Pn)])
+            add(Wm, bm)
+    add(np.vstack([W[4], -W[4]]), np.concatenate([b[4] - target, target - b[4]]))
+    add(np.ones((1, 16)), np.zeros(1))
+    return Unrolled(layers, m, x0, target, u_lo, u_hi, H)
+
+
+def rollout_cost(u_seq, uw):
+    """The same objective by stepping the dynamics MLP in float64: u_seq [n, 2H]."""
+    u = np.asarray(u_seq, np.float64)
+    n = u.shape[0]
+    x = np.repeat(uw.x0[None], n, 0)
+    for t in range(uw.H):
+        h = np.concatenate([x, u[:, 2 * t:2 * t + 2]], axis=1)
+        for i, l in enumerate(uw.mlp):
+            h = h @ l["W"].astype(np.float64).T + l["b"].astype(np.float64)
+            if i + 1 < len(uw.mlp):
+                h = np.maximum(h, 0.0)
+        x = h
+    return np.abs(x - uw.target).sum(axis=1)
+
+
+def action_subboxes(uw, n, seed=6, width=(0.05, 0.4)):
+    """n random sub-boxes of the action box (planning subdomains): per coordinate a
+    width drawn uniformly from `width` (fractions of the box) at a uniform position."""
+    rng = np.random.default_rng(seed)
+    span = uw.u_hi - uw.u_lo
+    w = rng.uniform(width[0], width[1], (n, span.size)) * span
+    lo = uw.u_lo + rng.uniform(0.0, 1.0, (n, span.size)) * (span - w)
+    return lo.astype(np.float32), (lo + w).astype(np.float32)
