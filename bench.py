@@ -402,6 +402,77 @@ def other_configs(w_cnn, bb, stream):
     out[f"alpha_crown_cnn_{n2}_inputs_20_steps"] = {
         "input_steps_per_s": n2 * 20 / (ms3 / 1e3), "ms_per_replay": ms3, "flop_per_unit": fu,
         "frac_fp32_mfma": fu * n2 * 20 / (ms3 / 1e3) / PEAK_FP32_MFMA}
+    del opt
+    out["planning_unrolled_pushing_H20"] = planning_unrolled()
+    return out
+
+
+def planning_unrolled(n=256, n_opt=64, samples=64, steps=2, stops=(77, 65, 41)):
+    """The planning-shaped workload: the Pushing dynamics MLP unrolled over 20 steps (82
+    layers, input = 40 action values), L1 objective, bounded over n action sub-boxes.
+    Compared: full CROWN (every pre-activation layer bounded by a backward pass: 81
+    passes), optimised intermediate bounds (each pass's slopes optimised, `steps` Adam
+    steps per layer, on n_opt sub-boxes), and the paper's bounding -- pre-activation
+    bounds from `samples` search samples per sub-box, then the objective's pass stopped
+    early at a ReLU layer.  Reported per method: sub-boxes per second, the mean lower
+    bound of the objective and the fraction that is finite, beside the mean best sample
+    value (what the bound estimates from below)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2412_09584_amd import binding as B
+    from paper_2412_09584_amd import net as N
+    uw = W.pushing_unrolled(20)
+    lo_b, hi_b = W.action_subboxes(uw, n, seed=61)
+    xl, xh = torch.as_tensor(lo_b, device="cuda"), torch.as_tensor(hi_b, device="cuda")
+    C = torch.ones(n, 1, 1, device="cuda")
+    width = max(W.out_dim(l) for l in uw.net)
+    bn = N.BoundNet(uw.net, n, max(n * 2 * width, n * samples))
+
+    def stats(v):
+        v = v.detach().double().cpu().numpy().ravel()
+        fin = np.isfinite(v)
+        return {"mean_lower": float(v[fin].mean()) if fin.any() else None,
+                "finite": float(fin.mean())}
+
+    out = {"layers": len(uw.net), "relu_layers": len(uw.net) - 1, "subdomains": n}
+
+    def full():
+        lo, hi = bn.crown_bounds(xl, xh)
+        return bn.spec_bounds(C, lo, hi, xl, xh, both=False)[0]
+
+    ms = _time(full, 2, 1)
+    out["full_crown"] = {"subdomains_per_s": n / (ms / 1e3), "ms": ms, **stats(full())}
+    # the paper's bounding: search samples -> empirical pre-activation bounds -> early stop
+    rng = np.random.default_rng(62)
+    U = torch.as_tensor(rng.uniform(0, 1, (n, samples, lo_b.shape[1])), dtype=torch.float32,
+                        device="cuda")
+    x = (xl[:, None, :] + (xh - xl)[:, None, :] * U).reshape(n * samples, -1).contiguous()
+    slo = torch.empty(n, bn.n_relu, device="cuda")
+    shi = torch.empty_like(slo)
+    fval = torch.empty(n * samples, 1, device="cuda")
+    B.bound_sample_bounds(bn.handle, n, samples, x, slo, shi, fval)
+    out["best_sample_mean"] = float(fval.reshape(n, samples).min(dim=1).values.mean())
+    for s in stops:
+        def early(s=s):
+            B.bound_sample_bounds(bn.handle, n, samples, x, slo, shi)
+            return bn.spec_bounds(C, slo, shi, xl, xh, both=False, stop_layer=s,
+                                  stop_mode=B.BOUND_STOP_RELU)[0]
+        ms = _time(early, 5, 1)
+        out[f"search_bounds_early_stop_at_relu_{s}"] = {"subdomains_per_s": n / (ms / 1e3),
+                                                        "ms": ms, **stats(early())}
+    del bn
+    bo = N.BoundNet(uw.net, n_opt, n_opt * 2 * width, n_opt * 2 * width)
+
+    def opt():
+        lo, hi = bo.alpha_crown_bounds(xl[:n_opt], xh[:n_opt], steps=steps)
+        return bo.spec_bounds(C[:n_opt], lo, hi, xl[:n_opt], xh[:n_opt], both=False)[0]
+
+    ms = _time(opt, 1, 0)
+    out["optimised_intermediate"] = {"subdomains_per_s": n_opt / (ms / 1e3), "ms": ms,
+                                     "subdomains": n_opt, "adam_steps_per_layer": steps,
+                                     **stats(opt())}
     return out
 
 

@@ -98,9 +98,9 @@ typedef struct {
  *           neuron (after the relaxation of Lemma 1).
  * x_lo,x_hi [n_inst, d_0] the input box.  NULL: do not concretise; the pass then
  *           writes the coefficient form (bound_out.coeff / offset / offset_mag).
- * flags     BOUND_SAVE_FOR_GRAD (requires an explicit spec, no BOTH_SIDES, and
- *           n_inst*rows <= max_save_rows), BOUND_NO_SLACK, BOUND_BOTH_SIDES (not
- *           with beta).
+ * flags     BOUND_SAVE_FOR_GRAD (requires an explicit spec and n_inst * rows (x2 with
+ *           BOTH_SIDES) <= max_save_rows), BOUND_NO_SLACK, BOUND_BOTH_SIDES (not with
+ *           beta).
  * stop_layer, stop_mode  propagation early stop (Appendix B.2, the early-stop
  *           algorithm): 0 = propagate to the input and concretise over the input box.
  *           1 <= stop_layer < target: the backward search ends at the early-stop node
@@ -146,7 +146,8 @@ enum { BOUND_STOP_RELU = 1, BOUND_STOP_LINEAR = 2 };
  * best   [n_inst, ld] or NULL: updated to max(best, lower) (every alpha in [0, 1] and
  *        beta >= 0 gives a valid bound, so the best over optimisation steps is kept);
  * pass_id host pointer or NULL: a SAVE_FOR_GRAD pass writes its id (1, 2, ... per
- *        handle), which bound_grad can be asked to check. */
+ *        handle), which bound_grad can be asked to check;
+ * best_upper [n_inst, ld] or NULL (BOTH_SIDES): updated to min(best_upper, upper). */
 typedef struct {
     float *lower;
     float *upper;
@@ -156,10 +157,11 @@ typedef struct {
     float *offset_mag;
     float *best;
     int64_t *pass_id;
+    float *best_upper;
 } bound_out;
 
-/* Create a network handle.  Validates the layer chain, packs the weights for the
- * gfx950 kernels and allocates the workspace:
+/* Create a network handle for a chain of 1 <= n_layers <= 129 layers.  Validates the
+ * layer chain, packs the weights for the gfx950 kernels and allocates the workspace:
  *  max_inst      most instances in one pass;
  *  max_rows      most coefficient rows (instances x rows, x2 with BOTH_SIDES) held at
  *                once; larger passes without SAVE_FOR_GRAD are processed in chunks;
@@ -169,7 +171,8 @@ bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max
                         int64_t max_rows, int64_t max_save_rows, void *stream,
                         bound_net **out);
 
-/* Widths d_0 .. d_L into d (host, n_layers + 1 entries) and n_relu into *n_relu. */
+/* Widths d_0 .. d_L into d (host, n_layers + 1 entries; NULL to query n_layers first) and
+ * n_relu into *n_relu. */
 bound_status bound_dims(const bound_net *net, int32_t *n_layers, int32_t *d, int32_t *n_relu);
 
 /* Backward bound pass (Theorem 1 with Lemma 1's relaxation, the split multipliers,
@@ -208,7 +211,8 @@ bound_status bound_concretize(int32_t n_inst, int32_t rows, int32_t d0, const fl
  * pass (the raw bound, i.e. without the rounding allowance; intermediate bounds held
  * fixed) with respect to alpha and beta -- the reverse mode of Theorem 1's recursion and
  * Theorem 2's concretisation:
- * grad_lower [n_inst, rows];
+ * grad_lower [n_inst, rows] (rows = the pass's rows, twice them with BOTH_SIDES: the first
+ * half weights the lower bounds, the second the lower bounds of -spec, i.e. -upper);
  * grad_alpha [n_inst, n_relu] (overwritten; zero outside unstable, unsplit neurons of
  * layers 1 .. target-1), grad_beta [nnz, rows] (overwritten; may be NULL): entry q of
  * row r gets -sign[q] * (the derivative with respect to its neuron's coefficient), so

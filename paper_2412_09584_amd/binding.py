@@ -49,7 +49,7 @@ class BoundPass(ctypes.Structure):
 class BoundOut(ctypes.Structure):
     _fields_ = [("lower", _p), ("upper", _p), ("ld", ctypes.c_int64), ("coeff", _p),
                 ("offset", _p), ("offset_mag", _p), ("best", _p),
-                ("pass_id", ctypes.POINTER(ctypes.c_int64))]
+                ("pass_id", ctypes.POINTER(ctypes.c_int64)), ("best_upper", _p)]
 
 
 class BoundError(RuntimeError):
@@ -153,23 +153,24 @@ def bound_init(layers, max_inst, max_rows, max_save_rows=0, stream=None):
     return h
 
 
-def bound_dims(handle, n_layers_max=32):
+def bound_dims(handle):
     n = ctypes.c_int32()
-    d = (ctypes.c_int32 * (n_layers_max + 1))()
     nr = ctypes.c_int32()
+    _check(lib().bound_dims(handle, ctypes.byref(n), None, ctypes.byref(nr)))   # the layer count
+    d = (ctypes.c_int32 * (n.value + 1))()
     _check(lib().bound_dims(handle, ctypes.byref(n), d, ctypes.byref(nr)))
     return [d[i] for i in range(n.value + 1)], nr.value
 
 
 def _pass_out(n_inst, rows, target, spec, lo, hi, n_bounds, bound_of, alpha, split_off, split_idx,
               split_sign, nnz, beta, x_lo, x_hi, flags, lower, upper, ld, coeff, offset,
-              offset_mag, best, stop_layer=0, stop_mode=0):
+              offset_mag, best, stop_layer=0, stop_mode=0, best_upper=None):
     P = BoundPass(int(n_inst), int(rows), int(target), int(n_bounds), _ptr(spec), _ptr(lo), _ptr(hi),
                   _ptr(bound_of), _ptr(alpha), _ptr(split_off), _ptr(split_idx), _ptr(split_sign),
                   int(nnz), _ptr(beta), _ptr(x_lo), _ptr(x_hi), int(flags), int(stop_layer),
                   int(stop_mode))
     O = BoundOut(_ptr(lower), _ptr(upper), int(ld), _ptr(coeff), _ptr(offset), _ptr(offset_mag),
-                 _ptr(best), None)
+                 _ptr(best), None, _ptr(best_upper))
     return P, O
 
 
@@ -177,11 +178,11 @@ def bound_autotune(handle, n_inst, rows, target, *, grad_lower=None, spec=None, 
                    n_bounds=0, bound_of=None, alpha=None, split_off=None, split_idx=None,
                    split_sign=None, nnz=0, beta=None, x_lo=None, x_hi=None, flags=0, lower=None,
                    upper=None, ld=0, coeff=None, offset=None, offset_mag=None, best=None,
-                   stop_layer=0, stop_mode=0, stream=None):
+                   stop_layer=0, stop_mode=0, best_upper=None, stream=None):
     """Tune every product of this pass (and its gradient); returns the timing log."""
     P, O = _pass_out(n_inst, rows, target, spec, lo, hi, n_bounds, bound_of, alpha, split_off,
                      split_idx, split_sign, nnz, beta, x_lo, x_hi, flags, lower, upper, ld, coeff,
-                     offset, offset_mag, best, stop_layer, stop_mode)
+                     offset, offset_mag, best, stop_layer, stop_mode, best_upper)
     _check(lib().bound_autotune(handle, ctypes.byref(P), ctypes.byref(O), _ptr(grad_lower),
                                 _stream(stream)))
     return bound_autotune_report(handle)
@@ -199,7 +200,7 @@ def bound_backward(handle, n_inst, rows, target, *, spec=None, lo=None, hi=None,
                    bound_of=None, alpha=None, split_off=None, split_idx=None, split_sign=None,
                    nnz=0, beta=None, x_lo=None, x_hi=None, flags=0, lower=None, upper=None,
                    ld=0, coeff=None, offset=None, offset_mag=None, best=None, stop_layer=0,
-                   stop_mode=0, stream=None):
+                   stop_mode=0, best_upper=None, stream=None):
     """One bound pass; returns the pass id (a SAVE_FOR_GRAD pass's, else 0)."""
     P = BoundPass(int(n_inst), int(rows), int(target), int(n_bounds), _ptr(spec), _ptr(lo), _ptr(hi),
                   _ptr(bound_of), _ptr(alpha), _ptr(split_off), _ptr(split_idx), _ptr(split_sign),
@@ -207,7 +208,7 @@ def bound_backward(handle, n_inst, rows, target, *, spec=None, lo=None, hi=None,
                   int(stop_mode))
     pid = ctypes.c_int64(0)
     O = BoundOut(_ptr(lower), _ptr(upper), int(ld), _ptr(coeff), _ptr(offset), _ptr(offset_mag),
-                 _ptr(best), ctypes.pointer(pid))
+                 _ptr(best), ctypes.pointer(pid), _ptr(best_upper))
     _check(lib().bound_backward(handle, ctypes.byref(P), ctypes.byref(O), _stream(stream)))
     return pid.value
 

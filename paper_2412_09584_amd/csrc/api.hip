@@ -310,10 +310,11 @@ const char *bound_last_error(void) { return g_err.c_str(); }
 
 bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max_inst,
                         int64_t max_rows, int64_t max_save_rows, void *stream, bound_net **out) {
-    if (!layers || !out || n_layers < 1 || n_layers > 17 || max_inst < 1 || max_rows < 1 ||
-        max_save_rows < 0 || max_save_rows > max_rows)
-        return fail(BOUND_E_ARG, "bound_init: bad arguments (need 1 <= n_layers <= 17, "
-                                 "max_inst >= 1, 0 <= max_save_rows <= max_rows)");
+    if (!layers || !out || n_layers < 1 || n_layers > MAX_RELU_LAYERS + 1 || max_inst < 1 ||
+        max_rows < 1 || max_save_rows < 0 || max_save_rows > max_rows)
+        return fail(BOUND_E_ARG, "bound_init: bad arguments (need 1 <= n_layers <= " +
+                                     std::to_string(MAX_RELU_LAYERS + 1) +
+                                     ", max_inst >= 1, 0 <= max_save_rows <= max_rows)");
     *out = nullptr;
     hipStream_t st = (hipStream_t)stream;
     auto *net = new bound_net();
@@ -368,10 +369,6 @@ bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max
             }
         }
     }
-    if (n_layers - 1 > 16) {
-        delete net;
-        return fail(BOUND_E_ARG, "at most 16 ReLU layers");
-    }
     net->d.push_back(net->layers[0].din);
     for (auto &li : net->layers) net->d.push_back(li.dout);
     net->C0 = layers[0].in_c;
@@ -413,9 +410,31 @@ bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max
               net->alloc(&net->stop_cen, (long)max_inst * net->max_relu_d) &&
               net->alloc(&net->stop_rad, (long)max_inst * net->max_relu_d) &&
               net->alloc(&net->zeros, net->max_chan);
+    LayerShape *dls = nullptr;
+    int32_t *dt0 = nullptr;
+    ok = ok && net->alloc(&dls, n_layers) && net->alloc(&dt0, n_layers + 1);
     if (!ok) {
         delete net;
         return fail(BOUND_E_NOMEM, "bound_init: workspace allocation failed");
+    }
+    // the layer shapes and the relaxation-table tile prefix in device memory
+    {
+        std::vector<int32_t> t0(n_layers + 1, 0);
+        for (int t = 0; t < net->ns.n; ++t) t0[t + 1] = t0[t] + prep_tiles(net->ns.l[t]);
+        if (hipMemcpyAsync(dls, net->ns.l, sizeof(LayerShape) * (size_t)(net->ns.n > 0 ? net->ns.n : 1),
+                           hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(dt0, t0.data(), sizeof(int32_t) * t0.size(), hipMemcpyHostToDevice, st) !=
+                hipSuccess) {
+            delete net;
+            return fail(BOUND_E_HIP, "bound_init: layer table upload");
+        }
+        net->ns.dev = dls;
+        net->ns.tile0 = dt0;
+        // the host vector must outlive the asynchronous copy
+        if (hipStreamSynchronize(st) != hipSuccess) {
+            delete net;
+            return fail(BOUND_E_HIP, "bound_init: layer table upload");
+        }
     }
     bound_status s = ensure_split_cap(net, (long)max_inst * 16, 0, st);
     if (s != BOUND_OK) { delete net; return s; }
@@ -477,8 +496,8 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
     const int rpi = P->rows * (both ? 2 : 1);
     const long total = (long)P->n_inst * rpi;
     if (save) {
-        if (ident || both || !conc)
-            return fail(BOUND_E_ARG, "SAVE_FOR_GRAD needs an explicit spec, a box and no BOTH_SIDES");
+        if (ident || !conc)
+            return fail(BOUND_E_ARG, "SAVE_FOR_GRAD needs an explicit spec and a box");
         if (total > net->max_save_rows) return fail(BOUND_E_NOMEM, "n_inst*rows > max_save_rows");
     }
     const int sl = P->stop_layer, smode = sl > 0 ? P->stop_mode : 0;
@@ -649,14 +668,15 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
         HIPCHK(launch_finalize(img0, n_img, P->rows, rpi, net->acc_s, net->acc_low, net->acc_mag,
                                net->infeas, slack, conc ? out->lower : nullptr,
                                conc ? out->upper : nullptr, ld, conc ? nullptr : out->offset,
-                               conc ? nullptr : out->offset_mag, conc ? out->best : nullptr, st));
+                               conc ? nullptr : out->offset_mag, conc ? out->best : nullptr,
+                               conc && both ? out->best_upper : nullptr, st));
     }
     if (save) {
         net->saved = true;
         ++net->pass_seq;
         if (out->pass_id) *out->pass_id = net->pass_seq;
         net->s_target = k;
-        net->s_rows = P->rows;
+        net->s_rows = rpi;               // rows per instance, the negated spec rows included
         net->s_n_inst = P->n_inst;
         net->s_nnz = used > 0 ? nnz : 0;
         net->s_nnz_arg = nnz;
@@ -862,7 +882,9 @@ bound_status bound_autotune(bound_net *net, const bound_pass *pass, const bound_
         if (hipMalloc(&ga, sizeof(float) * (size_t)pass->n_inst * (size_t)net->n_relu) != hipSuccess)
             s = fail(BOUND_E_NOMEM, "bound_autotune: gradient scratch");
         else
-            s = bound_grad(net, 0, pass->n_inst, pass->rows, pass->nnz, grad_lower, ga, nullptr,
+            s = bound_grad(net, 0, pass->n_inst,
+                           pass->rows * ((pass->flags & BOUND_BOTH_SIDES) ? 2 : 1), pass->nnz,
+                           grad_lower, ga, nullptr,
                            stream);
     }
     net->tuning = false;

@@ -31,11 +31,16 @@ __device__ inline void block_sum2(float &a, float &b) {
     }
 }
 
-__device__ inline int layer_of(const NetShapes &ns, int used, long jg) {
-    int m = 0;
-    for (int t = 1; t < used; ++t)
-        if (jg >= ns.l[t].off) m = t;
-    return m;
+// ReLU layer (0-based, < used) holding global ReLU index jg: the last layer whose offset
+// is <= jg (binary search over the layers' offsets).
+__device__ inline int layer_of(const LayerShape *ls, int used, long jg) {
+    int a = 0, b = used - 1;
+    while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (ls[mid].off <= jg) a = mid;
+        else b = mid - 1;
+    }
+    return a;
 }
 
 // Row of lo/hi used by an instance; out-of-range indices are clamped so a bad index can
@@ -64,12 +69,12 @@ __device__ inline Relax relax_of(float l, float u, float a, int k) {
 // coefficient only where the neuron is unstable, so a pass saves G at these slots only.
 // Block (row r, layer m); each thread counts a contiguous segment, then the segment
 // bases come from a scan of the 256 counts.
-__global__ void k_prep_slots(const NetShapes ns, long n_relu, const float *lo, const float *hi,
+__global__ void k_prep_slots(const LayerShape *ls, long n_relu, const float *lo, const float *hi,
                              const int32_t *bound_of, int n_bounds, int per_inst, int32_t *slot,
                              int32_t *inv, int32_t *count) {
     __shared__ int cnt[256];
     const long r = blockIdx.x;
-    const LayerShape &L = ns.l[blockIdx.y];
+    const LayerShape L = ls[blockIdx.y];
     const long b = per_inst ? bound_row(bound_of, r, n_bounds) : r;
     const float *lr = lo + b * n_relu + L.off, *hr = hi + b * n_relu + L.off;
     const long seg = (L.d + 255) / 256, j0 = threadIdx.x * seg;
@@ -192,17 +197,10 @@ __global__ void k_fill4(float4 *p, long n4, float v) {
 // into the records, stored pixel-major, through LDS: both the reads and the 16-byte
 // record writes are contiguous across the block.  Layers with more channels than a tile
 // take one pixel's channels per block with direct (strided) reads.
-constexpr int PREP_TILE = 1024;
 constexpr int PREP_SH = PREP_TILE + PREP_TILE / 8;  // room for one pad per pixel when C >= 8
 
-__device__ inline int prep_tiles(const LayerShape &L) {
-    if (L.HW == 1) return (int)((L.d + PREP_TILE - 1) / PREP_TILE);
-    if (L.C > PREP_TILE) return L.HW * ((L.C + PREP_TILE - 1) / PREP_TILE);
-    const int P = PREP_TILE / L.C;
-    return (L.HW + P - 1) / P;
-}
-
-__global__ __launch_bounds__(256) void k_prep_tables(const NetShapes ns, int used, long n_relu,
+__global__ __launch_bounds__(256) void k_prep_tables(const LayerShape *ls, const int32_t *tile0,
+                                                     int used, long n_relu,
                                                      const float *lo, const float *hi,
                                                      const int32_t *bound_of, const float *alpha,
                                                      Relax *tab, int32_t *infeas, int n_bounds,
@@ -213,14 +211,16 @@ __global__ __launch_bounds__(256) void k_prep_tables(const NetShapes ns, int use
     // write one contiguous stretch of the record table (and share one bounds row)
     const long inst = blockIdx.x / (unsigned)tiles;
     const int t0 = (int)(blockIdx.x - inst * tiles);
-    int t = t0, m = 0;
-    for (; m < used; ++m) {
-        const int nt = prep_tiles(ns.l[m]);
-        if (t < nt) break;
-        t -= nt;
+    if (t0 >= tile0[used]) return;
+    // the tile's layer: the last m < used with tile0[m] <= t0
+    int m = 0, mb = used - 1;
+    while (m < mb) {
+        const int mid = (m + mb + 1) >> 1;
+        if (tile0[mid] <= t0) m = mid;
+        else mb = mid - 1;
     }
-    if (m >= used) return;
-    const LayerShape &L = ns.l[m];
+    const int t = t0 - tile0[m];
+    const LayerShape L = ls[m];
     const long b = bound_row(bound_of, inst, n_bounds);
     if (t0 == 0 && threadIdx.x == 0) {
         infeas[inst] = 0;
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) void k_prep_tables(const NetShapes ns, int use
     }
 }
 
-__global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, long n_relu,
+__global__ void k_prep_splits(const LayerShape *ls, int used, long T, int n_inst, long n_relu,
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const int32_t *off, const int32_t *idx, const int8_t *sign,
                               Relax *tab, int32_t *infeas, int32_t *sp_inst, int32_t *sp_layer,
@@ -319,8 +319,8 @@ __global__ void k_prep_splits(const NetShapes ns, int used, long T, int n_inst, 
         sp_j[q] = 0;
         sp_dup[q] = 0;
         if (g < 0 || g >= T) continue;  // not a layer this pass relaxes
-        const int m = layer_of(ns, used, g);
-        const LayerShape &L = ns.l[m];
+        const int m = layer_of(ls, used, g);
+        const LayerShape L = ls[m];
         const long jn = g - L.off;
         float l = lo[b * n_relu + g], u = hi[b * n_relu + g];
         int first = q;
@@ -502,7 +502,7 @@ __global__ void k_beta_sum(int nnz, int rows, const int32_t *off, const int32_t 
 __global__ void k_finalize(long img0, long n_img, int rows, int rpi, const float *s,
                            const float *low, const float *mag, const int32_t *infeas, int slack,
                            float *lower, float *upper, long ld, float *offset, float *offset_mag,
-                           float *best) {
+                           float *best, float *best_upper) {
     const long li = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (li >= n_img) return;
     const long gimg = img0 + li;
@@ -519,6 +519,8 @@ __global__ void k_finalize(long img0, long n_img, int rows, int rpi, const float
         if (best) best[inst * ld + rr] = fmaxf(best[inst * ld + rr], v);
     } else if (upper) {
         upper[inst * ld + rr - rows] = -v;
+        if (best_upper)
+            best_upper[inst * ld + rr - rows] = fminf(best_upper[inst * ld + rr - rows], -v);
     }
 }
 
@@ -806,19 +808,14 @@ hipError_t launch_prep_tables(const NetShapes &ns, int used, int n_inst, long n_
     // slots per bound row when the rows fit the slot table, else per instance
     const bool per_inst = bound_of == nullptr || n_bounds > max_rows;
     const int rows = per_inst ? n_inst : n_bounds;
-    hipLaunchKernelGGL(k_prep_slots, dim3((unsigned)rows, (unsigned)used), dim3(256), 0, st, ns,
+    hipLaunchKernelGGL(k_prep_slots, dim3((unsigned)rows, (unsigned)used), dim3(256), 0, st, ns.dev,
                        n_relu, lo, hi, bound_of, n_bounds, per_inst ? 1 : 0, slot, slot_inv,
                        slot_count);
     long tiles = 0;
-    for (int m = 0; m < used; ++m) {
-        const LayerShape &L = ns.l[m];
-        tiles += L.HW == 1 ? (L.d + PREP_TILE - 1) / PREP_TILE
-                 : L.C > PREP_TILE ? (long)L.HW * ((L.C + PREP_TILE - 1) / PREP_TILE)
-                                   : (L.HW + PREP_TILE / L.C - 1) / (PREP_TILE / L.C);
-    }
+    for (int m = 0; m < used; ++m) tiles += prep_tiles(ns.l[m]);
     if (tiles * n_inst > 0x7fffffffL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_prep_tables, dim3((unsigned)(tiles * n_inst)), dim3(256), 0, st, ns,
-                       used, n_relu, lo, hi, bound_of, alpha, tab, infeas, n_bounds, slot,
+    hipLaunchKernelGGL(k_prep_tables, dim3((unsigned)(tiles * n_inst)), dim3(256), 0, st, ns.dev,
+                       ns.tile0, used, n_relu, lo, hi, bound_of, alpha, tab, infeas, n_bounds, slot,
                        per_inst ? 1 : 0, srow, (int)tiles);
     return hipGetLastError();
 }
@@ -844,7 +841,7 @@ hipError_t launch_prep_splits(const NetShapes &ns, int used, int n_inst, long n_
                               int32_t *sp_j, int32_t *sp_dup, int n_bounds, int stop_m,
                               int stop_relu, float *stop_cen, float *stop_rad, hipStream_t st) {
     const long T = used > 0 ? ns.l[used - 1].off + ns.l[used - 1].d : 0;
-    hipLaunchKernelGGL(k_prep_splits, dim3(blocks_for(n_inst, 64)), dim3(64), 0, st, ns, used, T,
+    hipLaunchKernelGGL(k_prep_splits, dim3(blocks_for(n_inst, 64)), dim3(64), 0, st, ns.dev, used, T,
                        n_inst, n_relu, lo, hi, bound_of, off, idx, sign, tab, infeas, sp_inst,
                        sp_layer, sp_j, sp_dup, n_bounds, stop_m, stop_relu, stop_cen, stop_rad);
     return hipGetLastError();
@@ -893,10 +890,10 @@ hipError_t launch_beta_sum(int nnz, int rows, const int32_t *off, const int32_t 
 hipError_t launch_finalize(long img0, long n_img, int rows, int rpi, const float *s,
                            const float *low, const float *mag, const int32_t *infeas, bool slack,
                            float *lower, float *upper, long ld, float *offset, float *offset_mag,
-                           float *best, hipStream_t st) {
+                           float *best, float *best_upper, hipStream_t st) {
     hipLaunchKernelGGL(k_finalize, dim3(blocks_for(n_img)), dim3(TPB), 0, st, img0, n_img, rows,
                        rpi, s, low, mag, infeas, slack ? 1 : 0, lower, upper, ld, offset,
-                       offset_mag, best);
+                       offset_mag, best, best_upper);
     return hipGetLastError();
 }
 

@@ -156,10 +156,24 @@ struct LayerShape {        // output shape of a ReLU layer (for index maps)
     long d;
 };
 
+constexpr int MAX_RELU_LAYERS = 128;
+
+// The ReLU layers' shapes on the host (l) and in device memory (dev), with the device
+// prefix sums of the relaxation-table tiles per layer (tile0[m] = tiles of layers < m).
 struct NetShapes {
     int n;                 // number of ReLU layers described
-    LayerShape l[16];
+    LayerShape l[MAX_RELU_LAYERS];
+    const LayerShape *dev;
+    const int32_t *tile0;
 };
+// Tiles of the relaxation-table kernel for one ReLU layer (host and device).
+constexpr int PREP_TILE = 1024;
+__host__ __device__ inline int prep_tiles(const LayerShape &L) {
+    if (L.HW == 1) return (int)((L.d + PREP_TILE - 1) / PREP_TILE);
+    if (L.C > PREP_TILE) return L.HW * ((L.C + PREP_TILE - 1) / PREP_TILE);
+    const int P = PREP_TILE / L.C;
+    return (L.HW + P - 1) / P;
+}
 
 hipError_t launch_fill(float *p, long n, float v, hipStream_t st);
 hipError_t launch_prep_tables(const NetShapes &ns, int n_layers_used, int n_inst,
@@ -174,7 +188,6 @@ hipError_t launch_alpha_grad(int n_inst, int rows, long D, const LayerShape &L, 
                              const int32_t *slot_inv, const float *gc, float *galpha, long ga_ld,
                              long ga_off, int nnz, const int32_t *sp_inst, const int32_t *sp_layer,
                              const int32_t *sp_j, hipStream_t st);
-constexpr int MAX_RELU_LAYERS = 16;
 hipError_t launch_prep_splits(const NetShapes &ns, int n_layers_used, int n_inst, long n_relu,
                               const float *lo, const float *hi, const int32_t *bound_of,
                               const int32_t *off, const int32_t *idx, const int8_t *sign,
@@ -235,7 +248,7 @@ hipError_t launch_beta_sum(int nnz, int rows, const int32_t *off, const int32_t 
 hipError_t launch_finalize(long img0, long n_img, int rows, int rpi, const float *s,
                            const float *low, const float *mag, const int32_t *infeas,
                            bool slack, float *lower, float *upper, long ld, float *offset,
-                           float *offset_mag, float *best, hipStream_t st);
+                           float *offset_mag, float *best, float *best_upper, hipStream_t st);
 hipError_t launch_adj_init(long n_img, int rows, long d0, const float *gl, const float *g1,
                            const float *cen, const float *rad, const int32_t *infeas,
                            float *gbar, float *sbar, hipStream_t st);

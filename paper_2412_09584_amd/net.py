@@ -62,6 +62,46 @@ class BoundNet:
                              ld=self.n_relu)
         return lo, hi
 
+    def alpha_crown_bounds(self, x_lo, x_hi, steps=5, lr=0.1, alpha0=0.5, slack=True):
+        """Pre-activation bounds of z_1 .. z_{L-1} with every intermediate pass's slopes
+        optimised: bottom-up, for z_k the default-rule pass (rows [I; -I]), then `steps`
+        projected Adam steps on the slopes of layers < k (one per neuron and instance,
+        shared by the layer's lower- and upper-bound rows, starting at alpha0) maximising
+        the rows' summed lower bounds, then one more pass; the library keeps the best
+        lower / upper bound of every neuron over these passes (best / best_upper).
+        Needs max_save_rows >= n * 2 * max width.  Returns (lo, hi) [n, n_relu]."""
+        x_lo = _dev(x_lo, self.device)
+        x_hi = _dev(x_hi, self.device)
+        n = x_lo.shape[0]
+        nr = max(self.n_relu, 1)
+        lo = torch.zeros(n, nr, device=self.device)
+        hi = torch.zeros_like(lo)
+        tlo, thi = torch.empty_like(lo), torch.empty_like(lo)
+        flags = B.BOUND_BOTH_SIDES | (0 if slack else B.BOUND_NO_SLACK)
+        alpha = torch.empty(n, nr, device=self.device)
+        ma, va, ga = torch.empty_like(alpha), torch.empty_like(alpha), torch.empty_like(alpha)
+        for k in range(1, self.L):
+            off, d = self.relu_off[k - 1], self.d[k]
+            # the default slope rule on the bounds found so far: the starting best bounds
+            B.bound_backward(self.handle, n, d, k, lo=lo, hi=hi, n_bounds=n, x_lo=x_lo, x_hi=x_hi,
+                             flags=flags, lower=lo[:, off:], upper=hi[:, off:], ld=self.n_relu)
+            if k == 1 or steps <= 0:
+                continue
+            spec = torch.eye(d, device=self.device).expand(n, d, d).contiguous()
+            ones = torch.ones(n, 2 * d, device=self.device)
+            alpha.fill_(float(alpha0))
+            ma.zero_()
+            va.zero_()
+            kw = dict(spec=spec, lo=lo, hi=hi, n_bounds=n, alpha=alpha, x_lo=x_lo, x_hi=x_hi,
+                      lower=tlo[:, off:], upper=thi[:, off:], ld=self.n_relu,
+                      best=lo[:, off:], best_upper=hi[:, off:])
+            for t in range(1, steps + 1):
+                B.bound_backward(self.handle, n, d, k, flags=flags | B.BOUND_SAVE_FOR_GRAD, **kw)
+                B.bound_grad(self.handle, ones, ga)
+                B.bound_adam(alpha, ga, ma, va, t, lr, grad_scale=-1.0, clip_lo=0.0, clip_hi=1.0)
+            B.bound_backward(self.handle, n, d, k, flags=flags, **kw)
+        return lo, hi
+
     def spec_bounds(self, C, lo, hi, x_lo, x_hi, *, target=None, alpha=None, bound_of=None,
                     splits=None, beta=None, both=True, slack=True, save=False, best=None,
                     stop_layer=0, stop_mode=0):
