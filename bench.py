@@ -210,6 +210,8 @@ def main():
     if plain is not None:
         plain["batched_speedup"] = value / plain["value"]
 
+    recompute = recompute_compare(bb, stream)
+
     others = None
     if not args.no_configs:
         del opt
@@ -242,8 +244,58 @@ def main():
            "tflops_step": tflops, "flop_per_subdomain": flop_unit,
            "roofline_frac_step": tflops * 1e12 / PEAK_FP32_MFMA, "wall_s": wall,
            "plain": plain, "roofline": roofline, "kernel_ms_per_step": breakdown,
-           "autotune": plans, "configs": others, "bab_loop": bab, "cpu_baseline": cpu}
+           "autotune": plans, "checkpointed_recompute": recompute, "configs": others,
+           "bab_loop": bab, "cpu_baseline": cpu}
     print(json.dumps(rec))
+
+
+def _saved_floats_per_row(net, lo, hi, recompute):
+    """Floats the gradient's saved state takes per coefficient row: the concretised layer's
+    coefficients (dense), plus either every relaxed layer's pre-relaxation coefficients at
+    its unstable neurons (mean over the bound rows lo / hi) or, checkpointed, the
+    coefficient rows at every c-th product (c = ceil(sqrt(L - 1))) and the largest
+    segment's layers."""
+    import numpy as np
+    L = len(net)
+    d = [int(np.prod(net[0]["in_shape"]))] + [int(np.prod(l["out_shape"])) for l in net]
+    if not recompute:
+        unst = ((lo < 0) & (hi > 0)).sum(axis=1).mean()
+        return float(d[0] + unst)
+    c = 1
+    while c * c < L - 1:
+        c += 1
+    f, seg = d[0], 0
+    for t in range(L, 1, -c):
+        f += d[t]
+        seg = max(seg, sum(d[p - 1] for p in range(t, max(t - c, 1), -1)))
+    return float(f + seg)
+
+
+def recompute_compare(bb, stream, steps=5):
+    """One optimisation step (pass + gradient + Adam) of the batch with the saved
+    coefficients kept for every layer, and with checkpointed recomputation: time and the
+    saved bytes per subdomain."""
+    import torch
+    lo, hi = bb.lo.double().cpu().numpy(), bb.hi.double().cpu().numpy()
+    out = {}
+    for mode in (False, True):
+        bb.recompute = mode
+        bb.reset()
+        bb.step(1, stream)
+        torch.cuda.synchronize()
+        e0, e1 = _ev(), _ev()
+        e0.record(stream)
+        for t in range(2, steps + 2):
+            bb.step(t, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out["checkpointed" if mode else "stored"] = {
+            "ms_per_step": ms, "subdomains_per_s": bb.n / (ms / 1e3),
+            "saved_bytes_per_subdomain": 4.0 * bb.R * _saved_floats_per_row(bb.w.net, lo, hi, mode)}
+    bb.recompute = False
+    bb.reset()
+    return out
 
 
 def plain_path(bb, m, stream):
@@ -428,7 +480,7 @@ def planning_unrolled(n=256, n_opt=64, samples=64, steps=2, stops=(77, 65, 41)):
     xl, xh = torch.as_tensor(lo_b, device="cuda"), torch.as_tensor(hi_b, device="cuda")
     C = torch.ones(n, 1, 1, device="cuda")
     width = max(W.out_dim(l) for l in uw.net)
-    bn = N.BoundNet(uw.net, n, max(n * 2 * width, n * samples))
+    bn = N.BoundNet(uw.net, n, max(n * 2 * width, n * samples), n)
 
     def stats(v):
         v = v.detach().double().cpu().numpy().ravel()
@@ -444,6 +496,24 @@ def planning_unrolled(n=256, n_opt=64, samples=64, steps=2, stops=(77, 65, 41)):
 
     ms = _time(full, 2, 1)
     out["full_crown"] = {"subdomains_per_s": n / (ms / 1e3), "ms": ms, **stats(full())}
+    # the objective's pass with its gradient (random slopes) on these bounds: every layer's
+    # coefficients kept vs checkpointed recomputation
+    lo, hi = bn.crown_bounds(xl, xh)
+    alpha = torch.rand(n, bn.n_relu, device="cuda", generator=torch.Generator("cuda").manual_seed(63))
+    low = torch.empty(n, 1, device="cuda")
+    ones = torch.ones(n, 1, device="cuda")
+    ga = torch.empty(n, bn.n_relu, device="cuda")
+    lo_np, hi_np = lo.double().cpu().numpy(), hi.double().cpu().numpy()
+    for mode in (0, B.BOUND_RECOMPUTE):
+        def pg(mode=mode):
+            B.bound_backward(bn.handle, n, 1, len(uw.net), spec=C, lo=lo, hi=hi, n_bounds=n,
+                             alpha=alpha, x_lo=xl, x_hi=xh, flags=B.BOUND_SAVE_FOR_GRAD | mode,
+                             lower=low)
+            B.bound_grad(bn.handle, ones, ga)
+        ms = _time(pg, 3, 1)
+        out["pass_and_gradient_" + ("checkpointed" if mode else "stored")] = {
+            "subdomains_per_s": n / (ms / 1e3), "ms": ms,
+            "saved_bytes_per_subdomain": 4.0 * _saved_floats_per_row(uw.net, lo_np, hi_np, bool(mode))}
     # the paper's bounding: search samples -> empirical pre-activation bounds -> early stop
     rng = np.random.default_rng(62)
     U = torch.as_tensor(rng.uniform(0, 1, (n, samples, lo_b.shape[1])), dtype=torch.float32,

@@ -49,7 +49,8 @@ enum { BOUND_LINEAR = 0, BOUND_CONV2D = 1 };
 enum {
     BOUND_SAVE_FOR_GRAD = 1, /* keep the pre-relaxation coefficients for bound_grad */
     BOUND_NO_SLACK = 2,      /* report the raw bound without the FP32 rounding allowance */
-    BOUND_BOTH_SIDES = 4     /* also upper bounds: rows [spec; -spec], upper = -lower(-spec) */
+    BOUND_BOTH_SIDES = 4,    /* also upper bounds: rows [spec; -spec], upper = -lower(-spec) */
+    BOUND_RECOMPUTE = 8      /* with SAVE_FOR_GRAD: checkpointed layer recomputation (below) */
 };
 
 typedef struct bound_net bound_net; /* opaque, owned by the library */
@@ -100,7 +101,14 @@ typedef struct {
  *           writes the coefficient form (bound_out.coeff / offset / offset_mag).
  * flags     BOUND_SAVE_FOR_GRAD (requires an explicit spec and n_inst * rows (x2 with
  *           BOTH_SIDES) <= max_save_rows), BOUND_NO_SLACK, BOUND_BOTH_SIDES (not with
- *           beta).
+ *           beta), BOUND_RECOMPUTE (with SAVE_FOR_GRAD, no early stop): instead of the
+ *           pre-relaxation coefficients of every layer (kept at the unstable neurons),
+ *           the pass keeps the coefficient rows Lambda_t entering every c-th product
+ *           from the top (c = ceil(sqrt(target - 1))); bound_grad recomputes each
+ *           segment's products from its checkpoint before the reverse pass crosses it
+ *           (about one more backward pass of work; memory c dense rows + checkpoints
+ *           instead of every layer's unstable coefficients -- the smaller footprint for
+ *           deep chains).  The gradient is the same.
  * stop_layer, stop_mode  propagation early stop (Appendix B.2, the early-stop
  *           algorithm): 0 = propagate to the input and concretise over the input box.
  *           1 <= stop_layer < target: the backward search ends at the early-stop node

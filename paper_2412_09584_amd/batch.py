@@ -57,6 +57,7 @@ class BetaBatch:
         self.ones = torch.ones(n, R, device=dev)
         self.alpha0 = float(workload.extra.get("alpha0", 0.5))
         self.lr = float(workload.extra.get("lr", 0.1))
+        self.recompute = False       # checkpointed layer recomputation for the gradient
         self.reset()
 
     def reset(self):
@@ -71,7 +72,8 @@ class BetaBatch:
         return dict(spec=self.C, lo=self.lo, hi=self.hi, n_bounds=self.n_roots, bound_of=self.bof,
                     alpha=self.alpha, split_off=self.spd["off"], split_idx=self.spd["idx"],
                     split_sign=self.spd["sign"], nnz=self.nnz, beta=self.beta, x_lo=self.x_lo,
-                    x_hi=self.x_hi, flags=B.BOUND_SAVE_FOR_GRAD)
+                    x_hi=self.x_hi,
+                    flags=B.BOUND_SAVE_FOR_GRAD | (B.BOUND_RECOMPUTE if self.recompute else 0))
 
     def bound_and_grad(self, stream=None):
         """The bound pass (SAVE_FOR_GRAD, best kept) and its alpha / beta gradient."""

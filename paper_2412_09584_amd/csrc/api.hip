@@ -86,6 +86,15 @@ struct bound_net {
     int s_target = 0, s_rows = 0, s_n_inst = 0, s_nnz = 0, s_nnz_arg = 0, s_stop = 0, s_mode = 0;
     std::vector<long> s_off;         // offset of saved G_m (m = 1..k) in the save buffer
     long s_lam_off = 0;              // saved Lambda at a linear early stop
+    // checkpointed mode: Lambda_t kept at checkpoint products t (offsets), every c-th
+    // product from the top; the adjoint recomputes a segment's G from its checkpoint
+    // into the segment area (c layers, each total x max_relu_d)
+    bool s_recompute = false, s_inject = false;
+    int s_c = 1;
+    std::vector<long> s_ck;          // offset of Lambda_t, or -1 if t is not a checkpoint
+    long s_seg_off = 0;
+    float *rbuf = nullptr;           // ping-pong scratch of the recomputation
+    long rbuf_cap = 0;
 
     ~bound_net() {
         for (auto &r : recs) { pool.push_back(r.a); pool.push_back(r.b); }
@@ -500,6 +509,10 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             return fail(BOUND_E_ARG, "SAVE_FOR_GRAD needs an explicit spec and a box");
         if (total > net->max_save_rows) return fail(BOUND_E_NOMEM, "n_inst*rows > max_save_rows");
     }
+    const bool recompute = (P->flags & BOUND_RECOMPUTE) != 0;
+    if (recompute && !save) return fail(BOUND_E_ARG, "BOUND_RECOMPUTE needs BOUND_SAVE_FOR_GRAD");
+    if (recompute && P->stop_layer > 0)
+        return fail(BOUND_E_ARG, "BOUND_RECOMPUTE is not combined with an early stop");
     const int sl = P->stop_layer, smode = sl > 0 ? P->stop_mode : 0;
     if (sl < 0 || (sl > 0 && (sl >= k || (smode != BOUND_STOP_RELU && smode != BOUND_STOP_LINEAR))))
         return fail(BOUND_E_ARG, "stop_layer must be 0 or in 1..target-1 with a stop_mode");
@@ -562,13 +575,47 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
     const long chunk = save ? total : net->max_rows;
     std::vector<long> soff(k + 2, 0);  // offset of saved G_m for m = 1..k
     long lam_off = 0;                  // saved Lambda on z_sl at a linear stop
-    if (save) {
+    std::vector<long> ck(k + 2, -1);   // checkpointed mode: offset of Lambda_t
+    int ck_c = 1;
+    long seg_off = 0;
+    if (save && !recompute) {
         long o = 0;
         for (int m = 1; m <= k; ++m) {
             soff[m] = o;
             o += total * net->d[m - 1];
         }
         lam_off = o;
+    } else if (recompute) {
+        // G_1 (dense, the concretised layer), then Lambda_t at the checkpoints t = k,
+        // k - c, ... >= 2 with c = ceil(sqrt(k - 1)), then the segment area: the largest
+        // segment's G (products t .. t - c + 1 keep G on layers t - 1 .. t - c)
+        long o = total * net->d[0];
+        soff[1] = 0;
+        ck_c = 1;
+        while ((long)ck_c * ck_c < k - 1) ++ck_c;
+        long seg = 0;
+        for (int t = k; t >= 2; t -= ck_c) {
+            ck[t] = o;
+            o += total * net->d[t];
+            long s = 0;
+            for (int p = t; p >= 2 && p > t - ck_c; --p) s += net->d[p - 1];
+            seg = s > seg ? s : seg;
+        }
+        seg_off = o;
+        o += total * seg;
+        if (o > net->max_save_rows * (net->d[0] + net->n_relu + net->max_relu_d))
+            return fail(BOUND_E_NOMEM, "checkpointed layout exceeds the save workspace");
+        const long need = total * net->max_d;
+        if (need > net->rbuf_cap) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+                return fail(BOUND_E_NOMEM, "recomputation scratch larger than any earlier pass while "
+                                           "the stream is being captured");
+            float *r;
+            if (!net->alloc(&r, need)) return fail(BOUND_E_NOMEM, "recomputation scratch");
+            net->rbuf = r;
+            net->rbuf_cap = need;
+        }
     }
     for (long img0 = 0; img0 < total; img0 += chunk) {
         const long n_img = total - img0 < chunk ? total - img0 : chunk;
@@ -614,9 +661,12 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             m_start = k;
         }
         for (int m = m_start; m >= relax_low; --m) {
+            if (recompute && ck[m] >= 0)       // checkpoint: keep Lambda_m for the adjoint
+                HIPCHK(hipMemcpyAsync(net->save + ck[m], cur, sizeof(float) * (size_t)(n_img * net->d[m]),
+                                      hipMemcpyDeviceToDevice, st));
             RelaxParams rp{};
             rp.out = nxt;
-            rp.save = save ? net->save + soff[m] : nullptr;
+            rp.save = save && !recompute ? net->save + soff[m] : nullptr;
             rp.tab = net->tab + net->relu_off(m - 1);
             rp.tab_ld = net->n_relu;
             // at a linear stop the box is on z_sl itself, so its bias is not added
@@ -684,6 +734,11 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
         net->s_stop = sl;
         net->s_mode = smode;
         net->s_lam_off = lam_off;
+        net->s_recompute = recompute;
+        net->s_inject = inject;
+        net->s_c = ck_c;
+        net->s_ck = ck;
+        net->s_seg_off = seg_off;
         if (net->s_nnz > 0) {
             HIPCHK(hipMemcpyAsync(net->sp_sign, P->split_sign, (size_t)nnz, hipMemcpyDeviceToDevice, st));
         }
@@ -749,14 +804,53 @@ bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t
         m0 = cm;
     }
     (void)d0;
+    // checkpointed mode: G of the products of one segment, recomputed from its checkpoint
+    std::vector<const float *> gseg(k + 2, nullptr);
     for (int m = m0; m <= k - 1; ++m) {
         const LayerInfo &li = net->layers[m - 1];
+        if (net->s_recompute && gseg[m + 1] == nullptr) {
+            // the segment holding product m + 1: checkpoint t >= m + 1, products t .. bot
+            int t = m + 1;
+            while (t <= k && net->s_ck[t] < 0) ++t;
+            const int bot = t - net->s_c + 1 > 2 ? t - net->s_c + 1 : 2;
+            const float *A = net->save + net->s_ck[t];
+            float *outs[2] = {net->rbuf, nxt};
+            long so = net->s_seg_off;       // G of product p: n_img x d_{p-1}, stacked from t down
+            for (int p = t; p >= bot; --p) {
+                RelaxParams rp{};
+                rp.out = outs[(t - p) & 1];
+                rp.save = net->save + so;
+                so += n_img * net->d[p - 1];
+                rp.tab = net->tab + net->relu_off(p - 1);
+                rp.tab_ld = net->n_relu;
+                rp.bias = net->bias(p - 1);
+                rp.chan = net->chan(p - 1);
+                rp.D = net->d[p - 1];
+                rp.s = net->acc_s;              // scratch here: the pass's sums are final
+                rp.mag = net->acc_mag;
+                rp.img0 = 0;
+                rp.rpi = rows;
+                rp.rrpi = 1.0f / (float)rows;
+                rp.bsum = net->s_inject ? net->bsum : nullptr;
+                {
+                    ProfScope ps(net, st, lbl("recompute_L%d", p));
+                    const GeomSet &gs = net->layers[p - 1].gT;
+                    const float *Ap = A;
+                    bound_status bs = run_product(net, st, pkey('R', p), gs, [&](const Plan &pl) {
+                        return gemm_relax(gs, Ap, n_img, rp, st, pl);
+                    });
+                    if (bs != BOUND_OK) return bs;
+                }
+                gseg[p] = rp.save;
+                A = rp.out;
+            }
+        }
         AdjParams ap{};
         ap.sbar = net->sbar;
         ap.bias = li.L.bias;
         ap.chan = li.L.out_c;
         ap.D = net->d[m];
-        ap.gsave = net->save + net->s_off[m + 1];
+        ap.gsave = net->s_recompute ? gseg[m + 1] : net->save + net->s_off[m + 1];
         ap.tab = net->tab + net->relu_off(m);
         ap.tab_ld = net->n_relu;
         ap.gout = m + 1 < k ? nxt : nullptr;
