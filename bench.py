@@ -219,7 +219,10 @@ def main():
         others = other_configs(w, bb, stream)
 
     # ---- branch-and-bound planning loop (pick-out, split, search, bound, prune)
-    bab = bab_loop(args.bab_iters) if args.bab_iters > 0 else None
+    bab = None
+    if args.bab_iters > 0:
+        bab = {"crown": bab_loop(args.bab_iters),
+               "early_stop": bab_loop(args.bab_iters, bounding="early_stop")}
 
     # ---- CPU oracle on a bounded sample (rank 0, N=1)
     cpu = None
@@ -546,16 +549,17 @@ def planning_unrolled(n=256, n_opt=64, samples=64, steps=2, stops=(77, 65, 41)):
     return out
 
 
-def bab_loop(iters, d=16, hidden=(256, 256, 256), n_pick=1024, samples=64):
+def bab_loop(iters, d=16, hidden=(256, 256, 256), n_pick=1024, samples=64, bounding="crown"):
     """Throughput of the planning loop (Algorithm 2) on a seeded scalar ReLU objective over
     [-1, 1]^d: each iteration picks n_pick subdomains, splits them, searches the 2 n_pick
-    children (samples each) and bounds them with full CROWN, then prunes."""
+    children (samples each) and bounds them -- with full CROWN, or with the paper's
+    search-integrated bounds and an early stop at the last ReLU layer -- then prunes."""
     import torch
 
     import workloads as W
     from paper_2412_09584_amd.bab import BaBPlanner
     net, lo, hi = W.plan_objective(d=d, hidden=hidden)
-    pl = BaBPlanner(net, lo, hi, n_pick=n_pick, samples=samples)
+    pl = BaBPlanner(net, lo, hi, n_pick=n_pick, samples=samples, bounding=bounding)
     uni = W.plan_uniforms()
     pl.run(2, uni)                                   # warm-up
     torch.cuda.synchronize()
@@ -564,7 +568,7 @@ def bab_loop(iters, d=16, hidden=(256, 256, 256), n_pick=1024, samples=64):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     bounded = sum(2 * len(e["picked"]) for e in log)          # children searched and bounded
-    return {"objective": f"MLP {d}-{'-'.join(map(str, hidden))}-1 over [-1,1]^{d}",
+    return {"objective": f"MLP {d}-{'-'.join(map(str, hidden))}-1 over [-1,1]^{d}", "bounding": bounding,
             "n_pick": n_pick, "samples": samples, "iters": len(log),
             "ms_per_iter": 1e3 * dt / max(len(log), 1),
             "subdomains_bounded_per_s": bounded / dt if log else None,

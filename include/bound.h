@@ -40,7 +40,8 @@ typedef enum {
     BOUND_E_SHAPE = -2,  /* layer chain or tensor shapes do not fit together */
     BOUND_E_NOMEM = -3,  /* request exceeds the workspace sized at bound_init */
     BOUND_E_HIP = -4,    /* a HIP runtime call failed */
-    BOUND_E_STATE = -5   /* call order violated (e.g. bound_grad with no saved pass) */
+    BOUND_E_STATE = -5,  /* call order violated (e.g. bound_grad with no saved pass) */
+    BOUND_E_NUMERIC = -6 /* BOUND_OPT_CHECK found NaN / Inf in a product's output */
 } bound_status;
 
 enum { BOUND_LINEAR = 0, BOUND_CONV2D = 1 };
@@ -250,8 +251,12 @@ bound_status bound_adam(int64_t n, float *param, const float *grad, float *m, fl
  * them).  BOUND_OPT_DIRECT_DMA makes the direct-convolution kernels of products that
  * bound_autotune has not planned stage their tiles by LDS DMA instead of through
  * registers.  All variants compute the same bound; the options exist to test and
- * compare them. */
-enum { BOUND_OPT_GEMM_ONLY = 1, BOUND_OPT_DIRECT_DMA = 2 };
+ * compare them.  BOUND_OPT_CHECK (debugging): after every product of bound_backward and
+ * bound_grad the library counts NaN and Inf values in the product's output (and in the
+ * gradient it returns), waits for the count, and returns BOUND_E_NUMERIC naming the
+ * product if there are any; the calls become synchronous.  Not applied while the stream
+ * is being captured.  The environment variable BOUND_DEBUG=1 sets it at bound_init. */
+enum { BOUND_OPT_GEMM_ONLY = 1, BOUND_OPT_DIRECT_DMA = 2, BOUND_OPT_CHECK = 4 };
 bound_status bound_set_options(bound_net *net, int32_t options);
 
 /* Kernel autotuning: runs the given pass (and, if grad_lower is not NULL and the pass

@@ -27,6 +27,9 @@ Readings where the text leaves a choice (each is listed in the design notes):
     (the paper uses CEM; its refits are a plug not built here); f_hi = the smallest
     objective among them and u~ its sample (ties: lower index).
   * Pruner: a subdomain is kept iff f_lo <= f_hi_best (pruned iff f_lo > f_hi_best).
+  * Bounding: any lower-bound function of a box; with search-integrated bounding it also
+    receives the box's search samples (the paper's bounding takes pre-activation bounds
+    from them and stops the backward propagation early).
   * Loop: Algorithm 2's order (search, then bound, on the new subdomains); the best
     (f_hi, u~) is updated from the children; the pruner tests only the children, which
     join the rest of P.  It stops after a given number of iterations or when P is empty.
@@ -114,11 +117,14 @@ def prune(f_lo, best):
     return np.nonzero(f_lo <= best)[0]
 
 
-def bab_plan(objective, bound, lo0, hi0, n_pick, M, iters, eta, T, w, uniforms):
+def bab_plan(objective, bound, lo0, hi0, n_pick, M, iters, eta, T, w, uniforms,
+             bound_uses_samples=False):
     """Algorithm 2 with the heuristics above.  objective(u [m, d]) -> [m] values;
-    bound(lo [b, d], hi [b, d]) -> [b] lower bounds of the objective over each box;
-    uniforms(tag, shape) -> the supplied random numbers (tag 'search0', ('search', t),
-    ('pick', t)).  Returns the best value, its sample and the per-iteration trace."""
+    bound(lo [b, d], hi [b, d]) -> [b] lower bounds of the objective over each box, or
+    with bound_uses_samples bound(lo, hi, S [b, M, d]) taking each box's search samples
+    too (search-integrated bounding, Section 3.2); uniforms(tag, shape) -> the supplied
+    random numbers (tag 'search0', ('search', t), ('pick', t)).  Returns the best value,
+    its sample and the per-iteration trace."""
     lo0 = np.asarray(lo0, F32)[None]
     hi0 = np.asarray(hi0, F32)[None]
     d = lo0.shape[1]
@@ -128,10 +134,13 @@ def bab_plan(objective, bound, lo0, hi0, n_pick, M, iters, eta, T, w, uniforms):
         U = np.asarray(uniforms(tag, (lo.shape[0], M, d)), F32)
         S = lo[:, None, :] + (hi - lo)[:, None, :] * U
         vals = np.asarray(objective(S.reshape(-1, d)), np.float64).reshape(lo.shape[0], M)
-        return search_summary(vals, S, k)
+        return search_summary(vals, S, k) + (S,)
 
-    f_hi, top = search(lo0, hi0, "search0")
-    f_lo = np.asarray(bound(lo0, hi0), np.float64)
+    def bound_of(lo, hi, S):
+        return np.asarray(bound(lo, hi, S) if bound_uses_samples else bound(lo, hi), np.float64)
+
+    f_hi, top, S0 = search(lo0, hi0, "search0")
+    f_lo = bound_of(lo0, hi0, S0)
     best, ubest = float(f_hi[0]), top[0, 0]
     P = dict(lo=lo0, hi=hi0, f_lo=f_lo, f_hi=f_hi, top=top)
     trace = []
@@ -141,8 +150,8 @@ def bab_plan(objective, bound, lo0, hi0, n_pick, M, iters, eta, T, w, uniforms):
             break
         picked, rest = pick_out(P["f_lo"], P["f_hi"], uniforms(("pick", t), (N,)), n_pick, eta, T)
         clo, chi, dims = split(P["lo"][picked], P["hi"][picked], P["top"][picked])
-        c_fhi, c_top = search(clo, chi, ("search", t))
-        c_flo = np.asarray(bound(clo, chi), np.float64)
+        c_fhi, c_top, cS = search(clo, chi, ("search", t))
+        c_flo = bound_of(clo, chi, cS)
         j = int(np.argmin(c_fhi))
         if c_fhi[j] < best:
             best, ubest = float(c_fhi[j]), c_top[j, 0]

@@ -22,8 +22,15 @@ from .net import BoundNet
 
 
 class BaBPlanner:
+    """bounding: "crown" -- each box's lower bound by full CROWN (sound); "early_stop" --
+    the paper's bounding for planning (Section 3.2): pre-activation bounds are the min /
+    max of the box's search samples (search-integrated), and the objective's backward
+    pass stops at the ReLU of layer stop_layer, concretised over that node's empirical box
+    (a tight estimate, not a sound bound)."""
+
     def __init__(self, layers, box_lo, box_hi, *, n_pick=64, samples=64, eta=0.75,
-                 temperature=0.05, w=1.0, max_dom=1 << 16, device="cuda"):
+                 temperature=0.05, w=1.0, max_dom=1 << 16, bounding="crown", stop_layer=None,
+                 device="cuda"):
         self.device = torch.device(device)
         self.lo0 = torch.as_tensor(np.asarray(box_lo, np.float32), device=self.device)[None]
         self.hi0 = torch.as_tensor(np.asarray(box_hi, np.float32), device=self.device)[None]
@@ -39,6 +46,13 @@ class BaBPlanner:
         if self.net.d[-1] != 1:
             raise ValueError("the objective network must have a scalar output")
         self.bab = B.bound_bab_init(self.max_dom, self.d, self.M)
+        if bounding not in ("crown", "early_stop"):
+            raise ValueError("bounding must be 'crown' or 'early_stop'")
+        self.bounding = bounding
+        self.stop = int(stop_layer) if stop_layer is not None else len(layers) - 1
+        if bounding == "early_stop" and not 1 <= self.stop < len(layers):
+            raise ValueError("stop_layer must be in 1 .. n_layers - 1")
+        self._sb = None        # empirical pre-activation bounds of the last searched boxes
 
     def __del__(self):
         h = getattr(self, "bab", None)
@@ -48,10 +62,17 @@ class BaBPlanner:
 
     # ------------------------------------------------------------------ steps
     def bound(self, lo, hi):
-        """CROWN lower bound of the objective over each box [n]."""
+        """Lower bound (or, with early stop, its estimate) of the objective over each box
+        [n]; the early-stop bound uses the empirical bounds of the last search() of
+        these boxes."""
         n = lo.shape[0]
-        blo, bhi = self.net.crown_bounds(lo, hi)
         C = torch.ones(n, 1, 1, device=self.device)
+        if self.bounding == "early_stop":
+            slo, shi = self._sb
+            lower, _ = self.net.spec_bounds(C, slo, shi, lo, hi, both=False, stop_layer=self.stop,
+                                            stop_mode=B.BOUND_STOP_RELU)
+            return lower[:, 0].contiguous()
+        blo, bhi = self.net.crown_bounds(lo, hi)
         lower, _ = self.net.spec_bounds(C, blo, bhi, lo, hi, both=False)
         return lower[:, 0].contiguous()
 
@@ -61,7 +82,15 @@ class BaBPlanner:
         S = torch.empty(n, self.M, self.d, device=self.device)
         B.bound_bab_samples(self.bab, n, self.M, lo, hi, U, S)
         vals = torch.empty(n * self.M, 1, device=self.device)
-        B.bound_sample_bounds(self.net.handle, n, self.M, S.view(n * self.M, self.d), out=vals)
+        if self.bounding == "early_stop":
+            # the same forward pass gives the empirical pre-activation bounds
+            slo = torch.empty(n, self.net.n_relu, device=self.device)
+            shi = torch.empty_like(slo)
+            B.bound_sample_bounds(self.net.handle, n, self.M, S.view(n * self.M, self.d), slo, shi,
+                                  out=vals)
+            self._sb = (slo, shi)
+        else:
+            B.bound_sample_bounds(self.net.handle, n, self.M, S.view(n * self.M, self.d), out=vals)
         f_hi = torch.empty(n, device=self.device)
         top = torch.empty(n, self.k, self.d, device=self.device)
         B.bound_bab_search_summary(self.bab, n, self.M, vals, S, self.k, f_hi, top)

@@ -14,10 +14,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbound.so")
 
 BOUND_OK, BOUND_E_ARG, BOUND_E_SHAPE, BOUND_E_NOMEM, BOUND_E_HIP, BOUND_E_STATE = 0, -1, -2, -3, -4, -5
+BOUND_E_NUMERIC = -6
 BOUND_LINEAR, BOUND_CONV2D = 0, 1
 BOUND_SAVE_FOR_GRAD, BOUND_NO_SLACK, BOUND_BOTH_SIDES, BOUND_RECOMPUTE = 1, 2, 4, 8
 BOUND_OPT_GEMM_ONLY = 1
 BOUND_OPT_DIRECT_DMA = 2
+BOUND_OPT_CHECK = 4
 BOUND_STOP_RELU, BOUND_STOP_LINEAR = 1, 2
 
 EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "bound_grad",

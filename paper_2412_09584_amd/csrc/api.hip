@@ -6,6 +6,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -70,6 +71,7 @@ struct bound_net {
     long sp_cap = 0;
     float *bsum = nullptr;           // [nnz][rows]: split-multiplier term per first entry
     long bsum_cap = 0;
+    int32_t *dbg = nullptr;          // [2] NaN / Inf counts of the debug checks
     int options = 0;
     // kernel plan per product (key: 'R'/'C'/'A' * 256 + layer), chosen by bound_autotune
     std::map<int, Plan> plans;
@@ -195,6 +197,24 @@ bound_status run_product(bound_net *net, hipStream_t st, int key, const GeomSet 
 }
 
 inline int pkey(char c, int m) { return ((int)c << 8) | m; }
+
+// BOUND_OPT_CHECK: count the NaN / Inf values of n floats at p (a product's output) and
+// fail with BOUND_E_NUMERIC naming `what` if there are any.  Synchronises the stream;
+// skipped while the stream is being captured.
+bound_status debug_check(bound_net *net, hipStream_t st, const float *p, long n, const std::string &what) {
+    if (!(net->options & BOUND_OPT_CHECK) || !p || n <= 0) return BOUND_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return BOUND_OK;
+    int32_t h[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(net->dbg, h, sizeof h, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_count_nonfinite(p, n, net->dbg, st));
+    HIPCHK(hipMemcpyAsync(h, net->dbg, sizeof h, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h[0] || h[1])
+        return fail(BOUND_E_NUMERIC, what + ": " + std::to_string(h[0]) + " NaN and " +
+                                         std::to_string(h[1]) + " Inf values");
+    return BOUND_OK;
+}
 
 std::string lbl(const char *f, int m) {
     char buf[48];
@@ -421,7 +441,12 @@ bound_status bound_init(const bound_layer *layers, int32_t n_layers, int32_t max
               net->alloc(&net->zeros, net->max_chan);
     LayerShape *dls = nullptr;
     int32_t *dt0 = nullptr;
-    ok = ok && net->alloc(&dls, n_layers) && net->alloc(&dt0, n_layers + 1);
+    ok = ok && net->alloc(&dls, n_layers) && net->alloc(&dt0, n_layers + 1) &&
+         net->alloc(&net->dbg, 2);
+    {
+        const char *e = std::getenv("BOUND_DEBUG");
+        if (e && e[0] && e[0] != '0') net->options |= BOUND_OPT_CHECK;
+    }
     if (!ok) {
         delete net;
         return fail(BOUND_E_NOMEM, "bound_init: workspace allocation failed");
@@ -688,6 +713,10 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
                 });
                 if (bs != BOUND_OK) return bs;
             }
+            {
+                bound_status bs = debug_check(net, st, nxt, n_img * net->d[m - 1], lbl("bwd_relax_L%d", m));
+                if (bs != BOUND_OK) return bs;
+            }
             float *t = cur; cur = nxt; nxt = t;
         }
         if (smode == BOUND_STOP_LINEAR) {
@@ -712,6 +741,8 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             bound_status bs = run_product(net, st, pkey('C', conc_m), gs, [&](const Plan &pl) {
                 return gemm_conc(gs, A, n_img, cp, st, pl);
             });
+            if (bs != BOUND_OK) return bs;
+            bs = debug_check(net, st, net->acc_low, n_img, lbl("bwd_conc_L%d", conc_m));
             if (bs != BOUND_OK) return bs;
         }
         ProfScope pf(net, st, "finalize");
@@ -866,6 +897,8 @@ bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t
                 return gemm_adj(li.gF, A, n_img, ap, st, pl);
             });
             if (bs != BOUND_OK) return bs;
+            if (ap.gout) bs = debug_check(net, st, ap.gout, n_img * net->d[m], lbl("adj_L%d", m));
+            if (bs != BOUND_OK) return bs;
         }
         {
             ProfScope ps(net, st, "alpha_grad");
@@ -887,7 +920,10 @@ bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t
         }
         float *t = cur; cur = nxt; nxt = t;
     }
-    return BOUND_OK;
+    bound_status bs = debug_check(net, st, grad_alpha, (long)net->s_n_inst * net->n_relu, "grad_alpha");
+    if (bs == BOUND_OK && grad_beta)
+        bs = debug_check(net, st, grad_beta, (long)net->s_nnz * rows, "grad_beta");
+    return bs;
 }
 
 bound_status bound_sample_bounds(bound_net *net, int32_t n_sub, int32_t per_sub, const float *x,
@@ -1002,7 +1038,7 @@ int32_t bound_autotune_report(const bound_net *net, char *buf, int32_t cap) {
 }
 
 bound_status bound_set_options(bound_net *net, int32_t options) {
-    if (!net || (options & ~(BOUND_OPT_GEMM_ONLY | BOUND_OPT_DIRECT_DMA)))
+    if (!net || (options & ~(BOUND_OPT_GEMM_ONLY | BOUND_OPT_DIRECT_DMA | BOUND_OPT_CHECK)))
         return fail(BOUND_E_ARG, "bound_set_options: bad arguments");
     net->options = options;
     return BOUND_OK;

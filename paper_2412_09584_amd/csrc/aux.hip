@@ -180,6 +180,17 @@ __global__ void k_alpha_split_zero(int nnz, int layer, const LayerShape L, const
     galpha[(long)sp_inst[q] * ga_ld + ga_off + (long)c * L.HW + p] = 0.f;
 }
 
+__global__ void k_count_nonfinite(const float *p, long n, int32_t *cnt) {
+    int a = 0, b = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const float v = p[i];
+        a += v != v;
+        b += isinf(v);
+    }
+    if (a) atomicAdd(cnt, a);
+    if (b) atomicAdd(cnt + 1, b);
+}
+
 __global__ void k_fill(float *p, long n, float v) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -788,6 +799,13 @@ __global__ void k_pack_F(const float *W, int kind, int ci, int hwin, int kh, int
 }
 
 }  // namespace
+
+hipError_t launch_count_nonfinite(const float *p, long n, int32_t *cnt, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const long nb = blocks_for(n) < 4096 ? blocks_for(n) : 4096;
+    hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)nb), dim3(TPB), 0, st, p, n, cnt);
+    return hipGetLastError();
+}
 
 hipError_t launch_fill(float *p, long n, float v, hipStream_t st) {
     if (n <= 0) return hipSuccess;

@@ -176,6 +176,8 @@ __host__ __device__ inline int prep_tiles(const LayerShape &L) {
 }
 
 hipError_t launch_fill(float *p, long n, float v, hipStream_t st);
+// cnt[0] += NaN count, cnt[1] += Inf count of p[0 .. n) (debug checks)
+hipError_t launch_count_nonfinite(const float *p, long n, int32_t *cnt, hipStream_t st);
 hipError_t launch_prep_tables(const NetShapes &ns, int n_layers_used, int n_inst,
                               long n_relu, const float *lo, const float *hi,
                               const int32_t *bound_of, const float *alpha, Relax *tab,

@@ -57,35 +57,80 @@ __device__ inline void stage_input(float *In, const ConvTile &ct, const Geom &g,
             *(float4 *)(In + ((gi * ct.IH + iy) * ct.IW + ix) * ct.CS + 4 * c4) = v;
         }
     } else {  // C < 4: one chunk, channels padded with zeros up to CS = 4
+        // The first SP pixels of every thread are loaded together before any LDS store
+        // (one memory latency for the tile instead of one per pixel); larger tiles
+        // continue one pixel at a time.
+        constexpr int SP = 4;
         const int total = ct.G * ct.IH * ct.IW;
-        for (int e = tid; e < total; e += 256) {
+        auto src_of = [&](int e, int &dst) -> const float * {
             const int t2 = qdiv(e, ct.rIW), ix = e - t2 * ct.IW;
             const int gi = qdiv(t2, ct.rIH), iy = t2 - gi * ct.IH;
             const long img = img0 + gi;
             const int y = iy0 + iy, x = ix0 + ix;
-            float v[4] = {0.f, 0.f, 0.f, 0.f};
-            if (img < n_img && (unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W) {
-                const float *src = X + ((img * g.H + y) * (long)g.W + x) * g.C;
-                for (int c = 0; c < g.C; ++c) v[c] = src[c];
+            dst = ((gi * ct.IH + iy) * ct.IW + ix) * ct.CS;
+            return img < n_img && (unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W
+                       ? X + ((img * g.H + y) * (long)g.W + x) * g.C
+                       : nullptr;
+        };
+        float v[SP][4];
+        int dst[SP];
+#pragma unroll
+        for (int i = 0; i < SP; ++i) {
+            const int e = tid + i * 256;
+            dst[i] = -1;
+            v[i][0] = v[i][1] = v[i][2] = v[i][3] = 0.f;
+            if (e < total) {
+                const float *src = src_of(e, dst[i]);
+                if (src) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        if (c < g.C) v[i][c] = src[c];
+                }
             }
-            *(float4 *)(In + ((gi * ct.IH + iy) * ct.IW + ix) * ct.CS) = make_float4(v[0], v[1], v[2], v[3]);
+        }
+#pragma unroll
+        for (int i = 0; i < SP; ++i)
+            if (dst[i] >= 0) *(float4 *)(In + dst[i]) = make_float4(v[i][0], v[i][1], v[i][2], v[i][3]);
+        for (int e = tid + SP * 256; e < total; e += 256) {
+            int d;
+            const float *src = src_of(e, d);
+            float w[4] = {0.f, 0.f, 0.f, 0.f};
+            if (src)
+                for (int c = 0; c < g.C; ++c) w[c] = src[c];
+            *(float4 *)(In + d) = make_float4(w[0], w[1], w[2], w[3]);
         }
     }
 }
 
 // Stage weights of output channels [n0, n0+BN) for channels [c0, c0+CC), all taps:
 // Wl[n][t*CC + c] = Bt[n0+n][t*C + c0 + c]; zero for k >= T*CC (padding to KB).
+// The first SW elements of every thread are loaded together before any LDS store.
 __device__ inline void stage_weights(float *Wl, const ConvTile &ct, const Geom &g, int BN, int n0, int c0) {
+    constexpr int SW = 4;
     const int total = BN * ct.KB;
     const int TC = ct.T * ct.CC;
-    for (int e = threadIdx.x; e < total; e += 256) {
+    auto one = [&](int e, int &dst) -> float {
         const int n = qdiv(e, ct.rKB), k = e - n * ct.KB;
-        float v = 0.f;
-        if (k < TC) {
-            const int t = qdiv(k, ct.rCC), c = k - t * ct.CC;
-            v = g.Bt[(long)(n0 + n) * g.Kp + t * g.C + c0 + c];
-        }
-        Wl[n * ct.WS + k] = v;
+        dst = n * ct.WS + k;
+        if (k >= TC) return 0.f;
+        const int t = qdiv(k, ct.rCC), c = k - t * ct.CC;
+        return g.Bt[(long)(n0 + n) * g.Kp + t * g.C + c0 + c];
+    };
+    float v[SW];
+    int dst[SW];
+#pragma unroll
+    for (int i = 0; i < SW; ++i) {
+        const int e = threadIdx.x + i * 256;
+        dst[i] = -1;
+        v[i] = e < total ? one(e, dst[i]) : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < SW; ++i)
+        if (dst[i] >= 0) Wl[dst[i]] = v[i];
+    for (int e = threadIdx.x + SW * 256; e < total; e += 256) {
+        int d;
+        const float w = one(e, d);
+        Wl[d] = w;
     }
 }
 

@@ -5,6 +5,12 @@ Two reports, each printed as Markdown that records the command which produced th
 ``trace``   per-kernel totals from a ``--kernel-trace`` CSV, plus the average duration of
             one kernel (name + grid size) over its last N dispatches -- the launches of
             the timed steps when the traced command ends with them.
+``counters`` per-kernel SQ counters of the last dispatch of each kernel and grid from
+            ``--pmc`` runs (instruction counts, MFMA busy cycles, wave wait / activity
+            cycles): MFMA busy % = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / XCDs x
+            SIMDs), the GRBM count being the sum over the XCDs.
+``gaps``    the idle time between consecutive kernels inside each replay of the captured
+            optimisation (a replay opens with the torch fills that reset its state).
 ``traffic`` HBM bytes of that kernel's last dispatch from a ``--pmc FETCH_SIZE`` run and
             a ``--pmc WRITE_SIZE`` run (KiB per dispatch), each scaled by what the same
             counter reads for a plain copy of known size in the same run (the largest
@@ -141,6 +147,74 @@ def report_traffic(a) -> str:
     return "\n".join(lines) + "\n"
 
 
+def _counter_rows(paths):
+    """{(short name, grid): {counter: value of the last dispatch}} over several CSVs."""
+    agg = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                key = (_short(r["Kernel_Name"]), int(r.get("Grid_Size") or 0))
+                agg[key][r["Counter_Name"]].append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    return {k: {c: sorted(v)[-1][1] for c, v in cs.items()} for k, cs in agg.items()}
+
+
+def report_counters(a) -> str:
+    rows = _counter_rows(a.csv)
+    lines = [f"# {a.title}", "", "Commands (TMPDIR=/tmp; <repo> is the repository root):", ""]
+    lines += [f"    {c}" for c in a.cmd]
+    lines += ["", f"Last dispatch of each kernel and grid; MFMA busy % = SQ_VALU_MFMA_BUSY_CYCLES / "
+              f"(GRBM_GUI_ACTIVE / {a.xcds} XCDs x {a.simds} SIMDs); wave-cycle shares are of "
+              "SQ_WAVE_CYCLES.", "",
+              "| kernel | grid | GUI cycles / XCD | VALU insts | MFMA insts | VALU / MFMA | MFMA busy % "
+              "| wait % | wait-issue % | VALU active % |",
+              "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    order = sorted(rows.items(), key=lambda kv: -kv[1].get("GRBM_GUI_ACTIVE", 0))[: a.top]
+    for (name, grid), c in order:
+        gui = c.get("GRBM_GUI_ACTIVE", 0) / a.xcds
+        valu, mfma = c.get("SQ_INSTS_VALU"), c.get("SQ_INSTS_MFMA")
+        busy = c.get("SQ_VALU_MFMA_BUSY_CYCLES")
+        wc = c.get("SQ_WAVE_CYCLES")
+        f = lambda v: "" if v is None else f"{v:.0f}"
+        pct = lambda k: "" if not wc or k not in c else f"{100 * c[k] / wc:.1f}"
+        util = "" if busy is None or not gui else f"{100 * busy / (gui * a.simds):.1f}"
+        ratio = "" if not valu or not mfma else f"{valu / mfma:.2f}"
+        lines.append(f"| `{name[:70]}` | {grid} | {gui:.0f} | {f(valu)} | {f(mfma)} | {ratio} | {util} | "
+                     f"{pct('SQ_WAIT_ANY')} | {pct('SQ_WAIT_INST_ANY')} | {pct('SQ_ACTIVE_INST_VALU')} |")
+    return "\n".join(lines) + "\n"
+
+
+def report_gaps(a) -> str:
+    with open(a.csv) as f:
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
+    st = [int(r["Start_Timestamp"]) for r in rows]
+    en = [int(r["End_Timestamp"]) for r in rows]
+    fill = ["FillFunctor" in r["Kernel_Name"] for r in rows]
+    starts, i = [], 0
+    while i < len(rows):          # a run of >= a.reset torch fills opens a replay
+        j = i
+        while j < len(rows) and fill[j]:
+            j += 1
+        if j - i >= a.reset:
+            starts.append(i)
+        i = max(j, i + 1)
+    starts.append(len(rows))
+    lines = [f"# {a.title}", "", "Command (TMPDIR=/tmp; <repo> is the repository root):", "",
+             f"    {a.cmd}", "", "Windows that open with the optimiser's reset and hold at least "
+             f"{a.min_kernels} kernels (the graph replays; warm-up and eager windows hold fewer "
+             "or carry host gaps):", "",
+             "| kernels | span ms | kernel busy ms | gaps ms | gaps % |", "|---:|---:|---:|---:|---:|"]
+    for s, e in zip(starts[:-1], starts[1:]):
+        e -= 1
+        if e - s + 1 < a.min_kernels:
+            continue
+        span = en[e] - st[s]
+        busy = sum(en[k] - st[k] for k in range(s, e + 1))
+        gaps = sum(max(0, st[k + 1] - en[k]) for k in range(s, e))
+        lines.append(f"| {e - s + 1} | {span / 1e6:.3f} | {busy / 1e6:.3f} | {gaps / 1e6:.3f} | "
+                     f"{100 * gaps / max(span, 1):.2f} |")
+    return "\n".join(lines) + "\n"
+
+
 def read_traffic(path: str, label: str):
     """The traffic record of a summary, or None if missing, for another kernel, or taken
     from kernel sources other than the current ones."""
@@ -184,8 +258,23 @@ def main(argv=None):
     r.add_argument("--copy-bytes", type=float, default=float(2**30))
     r.add_argument("--title", required=True)
     r.add_argument("--cmd", action="append", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--csv", action="append", required=True)
+    c.add_argument("--xcds", type=int, default=8)
+    c.add_argument("--simds", type=int, default=1024)
+    c.add_argument("--top", type=int, default=16)
+    c.add_argument("--title", required=True)
+    c.add_argument("--cmd", action="append", required=True)
+    g = sub.add_parser("gaps")
+    g.add_argument("--csv", required=True)
+    g.add_argument("--reset", type=int, default=7, help="torch fills that open a replay")
+    g.add_argument("--min-kernels", type=int, default=300)
+    g.add_argument("--title", required=True)
+    g.add_argument("--cmd", required=True)
     a = ap.parse_args(argv)
-    print(report_trace(a) if a.what == "trace" else report_traffic(a), end="")
+    rep = {"trace": report_trace, "traffic": report_traffic, "counters": report_counters,
+           "gaps": report_gaps}[a.what]
+    print(rep(a), end="")
 
 
 if __name__ == "__main__":

@@ -165,3 +165,31 @@ def test_planning_loop_larger_objective(B):
     x = lo_b + (hi_b - lo_b) * rng.random(lo_b.shape)
     fx = O.forward(net, x.astype(np.float64))[-1][:, 0]
     assert np.all(P["f_lo"].cpu().numpy() <= fx + 1e-4)
+
+
+def test_planning_loop_with_early_stop_bounding(B):
+    """The loop with the paper's bounding (each box's pre-activation bounds from its own
+    search samples, the objective's pass stopped at the last ReLU layer) on the GPU
+    against the oracle's loop with the same bounding on the same random numbers."""
+    from paper_2412_09584_amd.bab import BaBPlanner
+    net, lo, hi = W.plan_objective(d=2, hidden=(16, 16))
+    g = np.linspace(-1.0, 1.0, 401)
+    G = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    true_min = O.forward(net, G)[-1][:, 0].min()
+    pl = BaBPlanner(net, lo, hi, n_pick=8, samples=64, eta=0.75, temperature=0.05, w=5.0,
+                    bounding="early_stop", stop_layer=2)
+    best, ub, P, log = pl.run(12, W.plan_uniforms(), trace=True)
+    assert best <= true_min + 2e-3 * max(1.0, abs(true_min))
+    f_lo, f_hi = P["f_lo"].cpu().numpy(), P["f_hi"].cpu().numpy()
+    assert np.all(f_lo <= f_hi + 1e-4 * np.maximum(1.0, np.abs(f_hi)))
+
+    def bound(a, b, S):
+        out = []
+        for i in range(a.shape[0]):
+            sb = O.sample_bounds(net, S[i].astype(np.float64))
+            out.append(O.spec_lower_early_stop(net, len(net), np.ones((1, 1)), sb, 2, "relu")[0])
+        return np.array(out)
+
+    ob, _, _, _ = OB.bab_plan(lambda U: O.forward(net, U)[-1][:, 0], bound, lo, hi, 8, 64, 12,
+                              0.75, 0.05, 5.0, W.plan_uniforms(), bound_uses_samples=True)
+    assert abs(best - ob) <= 2e-3 * max(1.0, abs(ob))

@@ -121,3 +121,28 @@ def test_recompute_rejects_early_stop_and_needs_save(mod):
                          x_lo=torch.as_tensor(x_lo, device="cuda"), x_hi=torch.as_tensor(x_hi, device="cuda"),
                          flags=B.BOUND_RECOMPUTE | B.BOUND_SAVE_FOR_GRAD, lower=low, stop_layer=1,
                          stop_mode=B.BOUND_STOP_RELU)
+
+
+def test_debug_check_reports_non_finite(mod):
+    """BOUND_OPT_CHECK: a clean pass and gradient pass the checks; a NaN in the input box
+    reaches the concretising product's sums and is reported as BOUND_E_NUMERIC."""
+    N, B = mod
+    net = W.mlp([10, 12, 12, 3], seed=182)
+    x0 = W.uniform_inputs(1, 10, 183)
+    x_lo, x_hi = W.linf_box(x0, 0.1)
+    bn = N.BoundNet(net, 1, 256, 256)
+    lo, hi = bn.crown_bounds(x_lo, x_hi)
+    B.bound_set_options(bn.handle, B.BOUND_OPT_CHECK)
+    C = torch.eye(3, device="cuda")[None]
+    low = torch.empty(1, 3, device="cuda")
+    xl, xh = torch.as_tensor(x_lo, device="cuda"), torch.as_tensor(x_hi, device="cuda")
+    B.bound_backward(bn.handle, 1, 3, 3, spec=C, lo=lo, hi=hi, n_bounds=1, x_lo=xl, x_hi=xh,
+                     flags=B.BOUND_SAVE_FOR_GRAD, lower=low)
+    ga = torch.empty(1, bn.n_relu, device="cuda")
+    B.bound_grad(bn.handle, torch.ones(1, 3, device="cuda"), ga)
+    xl_bad = xl.clone()
+    xl_bad[0, 3] = float("nan")
+    with pytest.raises(B.BoundError) as e:
+        B.bound_backward(bn.handle, 1, 3, 3, spec=C, lo=lo, hi=hi, n_bounds=1, x_lo=xl_bad, x_hi=xh,
+                         lower=low)
+    assert e.value.status == B.BOUND_E_NUMERIC and "NaN" in str(e.value)

@@ -156,3 +156,30 @@ def test_bab_loop_reaches_the_brute_force_minimum():
     assert P["f_lo"].min() <= true_min + 1e-9
     # the loop shrinks the search space: boxes are smaller than the root
     assert trace[-1]["size"] > 0 and np.all(P["hi"] - P["lo"] <= 2.0)
+
+
+def _early_stop_bound(net, stop):
+    """The paper's bounding of a box from its search samples: empirical pre-activation
+    bounds, then the objective's pass stopped at the ReLU of layer `stop`."""
+    def bound(lo, hi, S):
+        out = []
+        for b in range(lo.shape[0]):
+            sb = O.sample_bounds(net, S[b].astype(np.float64))
+            out.append(O.spec_lower_early_stop(net, len(net), np.ones((1, 1)), sb, stop, "relu")[0])
+        return np.array(out)
+    return bound
+
+
+def test_bab_loop_with_search_integrated_early_stop_bounding():
+    """The loop with the paper's bounding (empirical bounds from each box's own search
+    samples, early stop at the last ReLU layer) still reaches the brute-force minimum of
+    a small 2-D objective, and its estimates sit at or below the box's best sample."""
+    net, lo, hi = W.plan_objective(d=2, hidden=(16, 16))
+    g = np.linspace(-1.0, 1.0, 401)
+    G = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    true_min = O.forward(net, G)[-1][:, 0].min()
+    best, ub, trace, P = OB.bab_plan(lambda U: O.forward(net, U)[-1][:, 0], _early_stop_bound(net, 2),
+                                     lo, hi, 8, 64, 12, 0.75, 0.05, 5.0, W.plan_uniforms(),
+                                     bound_uses_samples=True)
+    assert best <= true_min + 2e-3 * max(1.0, abs(true_min))
+    assert np.all(P["f_lo"] <= P["f_hi"] + 1e-9)
