@@ -35,6 +35,10 @@ struct ConvTile {
     int in_floats; // G * IH * IW * CS
     // fl(1 / d) of the divisors the kernels split indices by (qdiv), set on the host
     float rTY, rCC, rKW, rTP, rIH, rIW, rPin, rPw, rC4, rTK, rKB, rSPP, rSPR;
+    // DMA staging: a thread's slots are tid, tid + 256, ...; these are the mixed-radix
+    // digits of a 256-slot step of the input tile (channel quad, pixel column, row, image)
+    // and of the weight tile (k quad, output row), each below its radix but the last
+    int dC4, dIX, dIY, dGI, dK4, dN;
 };
 
 // Stage the input tile (channels [c0, c0+CC)) of images img0.. into LDS, zero outside.
@@ -250,16 +254,24 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     const float *Bb = g.Bt + (long)n0 * g.Kp;
     int gin[NIN], lin[NIN], gw[NW], lw[NW];
     if (VEC && DMA) {
+        // slot sl = ((gi * IH + iy) * IW + ix) * spp + c4: the first slot is decomposed
+        // with quotients, the later ones step its digits by 256 slots (host-computed)
         const int spp = ct.CS >> 2, S_in = ct.in_floats >> 2;
+        int c4, ix, iy, gi;
+        {
+            const int pix = qdiv(tid, ct.rSPP);
+            c4 = tid - pix * spp;
+            const int row = qdiv(pix, ct.rIW);
+            ix = pix - row * ct.IW;
+            gi = qdiv(row, ct.rIH);
+            iy = row - gi * ct.IH;
+        }
 #pragma unroll
         for (int i = 0; i < NIN; ++i) {
             const int sl = i * 256 + tid;
             int o = -2;
             if (sl < S_in) {
                 o = -1;
-                const int pix = qdiv(sl, ct.rSPP), c4 = sl - pix * spp;
-                const int row = qdiv(pix, ct.rIW), ix = pix - row * ct.IW;
-                const int gi = qdiv(row, ct.rIH), iy = row - gi * ct.IH;
                 const int y = iy0 + iy, x = ix0 + ix;
                 if (c4 < (ct.CC >> 2) && (unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W)
                     o = (((gi * g.H + y) * g.W + x) * g.C + 4 * c4) * 4;
@@ -268,19 +280,35 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
             }
             gin[i] = o;
             if (o == -1) *(float4 *)(In + 4 * sl) = make_float4(0.f, 0.f, 0.f, 0.f);
+            c4 += ct.dC4;
+            const int cc = c4 >= spp;
+            c4 -= cc ? spp : 0;
+            ix += ct.dIX + cc;
+            const int cx = ix >= ct.IW;
+            ix -= cx ? ct.IW : 0;
+            iy += ct.dIY + cx;
+            const int cy = iy >= ct.IH;
+            iy -= cy ? ct.IH : 0;
+            gi += ct.dGI + cy;
         }
+        // weight slot sl = n * spr + k4, stepped the same way
         const int spr = ct.WS >> 2, S_w = BN * spr;
+        int n = qdiv(tid, ct.rSPR), k4 = tid - n * spr;
 #pragma unroll
         for (int i = 0; i < NW; ++i) {
             const int sl = i * 256 + tid;
             int o = -2;
             if (sl < S_w) {
-                const int n = qdiv(sl, ct.rSPR), k4 = sl - n * spr, k = 4 * k4;
+                const int k = 4 * k4;
                 if (k4 < (ct.KB >> 2))
                     o = k < TC ? (n * g.Kp + (k >> ct.lcc) * g.C + (k & (ct.CC - 1))) * 4 : -1;
             }
             gw[i] = o;
             if (o == -1) *(float4 *)(Wl + 4 * sl) = make_float4(0.f, 0.f, 0.f, 0.f);
+            k4 += ct.dK4;
+            const int ck = k4 >= spr;
+            k4 -= ck ? spr : 0;
+            n += ct.dN + ck;
         }
     } else if (VEC) {
         Walk w(Pin, ct.rPin);
@@ -451,13 +479,20 @@ __device__ inline void dma_input_tile(float *In, const ConvTile &ct, const Geom 
                                       int xbytes, int iy0, int ix0) {
     const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int spp = ct.CS >> 2, S_in = ct.in_floats >> 2, c4n = ct.CC >> 2;
+    // slot digits stepped by 256 slots as in k_conv's DMA staging
+    int c4, ix, iy, gi;
+    {
+        const int pix = qdiv(tid, ct.rSPP);
+        c4 = tid - pix * spp;
+        const int row = qdiv(pix, ct.rIW);
+        ix = pix - row * ct.IW;
+        gi = qdiv(row, ct.rIH);
+        iy = row - gi * ct.IH;
+    }
 #pragma unroll
     for (int i = 0; i < NIN; ++i) {
         const int sl = i * 256 + tid;
         if (sl < S_in) {
-            const int pix = qdiv(sl, ct.rSPP), c4 = sl - pix * spp;
-            const int row = qdiv(pix, ct.rIW), ix = pix - row * ct.IW;
-            const int gi = qdiv(row, ct.rIH), iy = row - gi * ct.IH;
             const int y = iy0 + iy, x = ix0 + ix;
             if (c4 < c4n) {
                 if ((unsigned)y < (unsigned)g.H && (unsigned)x < (unsigned)g.W)
@@ -467,6 +502,16 @@ __device__ inline void dma_input_tile(float *In, const ConvTile &ct, const Geom 
                     *(float4 *)(In + 4 * sl) = make_float4(0.f, 0.f, 0.f, 0.f);
             }
         }
+        c4 += ct.dC4;
+        const int cc = c4 >= spp;
+        c4 -= cc ? spp : 0;
+        ix += ct.dIX + cc;
+        const int cx = ix >= ct.IW;
+        ix -= cx ? ct.IW : 0;
+        iy += ct.dIY + cx;
+        const int cy = iy >= ct.IH;
+        iy -= cy ? ct.IH : 0;
+        gi += ct.dGI + cy;
     }
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 }
@@ -621,6 +666,14 @@ void set_tile_recips(const Geom &g, ConvTile &ct) {
     ct.rKB = recip(ct.KB);
     ct.rSPP = recip(ct.CS >> 2);
     ct.rSPR = recip(ct.WS >> 2);
+    const int spp = ct.CS >= 4 ? ct.CS >> 2 : 1, dp = 256 / spp, spr = ct.WS >> 2;
+    const int drow = dp / (ct.IW > 0 ? ct.IW : 1), ih = ct.IH > 0 ? ct.IH : 1;
+    ct.dC4 = 256 - dp * spp;
+    ct.dIX = dp - drow * ct.IW;
+    ct.dIY = drow % ih;
+    ct.dGI = drow / ih;
+    ct.dK4 = spr > 0 ? 256 % spr : 0;
+    ct.dN = spr > 0 ? 256 / spr : 0;
 }
 
 bool same_shape(const GeomSet &gs) {
