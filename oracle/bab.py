@@ -23,9 +23,19 @@ Readings where the text leaves a choice (each is listed in the design notes):
     with the smallest objective (ties: lower index); a sample counts on the lower side
     of dimension j iff u_j <= mid_j.  score_j = (hi_j - lo_j) * |n_lo_j - n_up_j| in
     FP32; j* = argmax (ties: lower j); if every score is 0, the widest dimension.
-  * batch_search: M samples per box, u = lo + (hi - lo) * U with supplied uniforms U
-    (the paper uses CEM; its refits are a plug not built here); f_hi = the smallest
-    objective among them and u~ its sample (ties: lower index).
+  * batch_search, uniform: M samples per box, u = lo + (hi - lo) * U with supplied
+    uniforms U; f_hi = the smallest objective among them and u~ its sample (ties: lower
+    index).
+  * batch_search, CEM (the paper's choice of sampler; it gives no details, so this is
+    the textbook cross-entropy method per box): a Gaussian with per-coordinate mean mu
+    and deviation sigma, started at mu = the parent's best sample u~ for the child that
+    contains it (the paper: the recorded u~ initialises the search of a split
+    subdomain), else the box centre, and sigma = half the box width; each of R rounds
+    draws M samples u = min(max(mu + sigma * Z, lo), hi) from supplied standard normals
+    Z (product and sum rounded to FP32), evaluates them and refits mu and sigma to the
+    n_elite samples of smallest objective (ties: lower index; NaN as +inf): their mean
+    and their deviation about it (divided by n_elite) plus a jitter.  All R * M samples
+    are the box's search samples (summary, top samples, search-integrated bounds).
   * Pruner: a subdomain is kept iff f_lo <= f_hi_best (pruned iff f_lo > f_hi_best).
   * Bounding: any lower-bound function of a box; with search-integrated bounding it also
     receives the box's search samples (the paper's bounding takes pre-activation bounds
@@ -83,6 +93,67 @@ def search_summary(values, samples, k):
     return f_hi, top
 
 
+def cem_start(lo, hi, u=None, u_div=1):
+    """Start of each box's search distribution: mu = u[i // u_div] when that point lies
+    in box i (lo <= u <= hi in every coordinate), else the box centre (lo + hi) * 0.5;
+    sigma = (hi - lo) * 0.5.  FP32, as the boxes."""
+    lo = np.asarray(lo, F32)
+    hi = np.asarray(hi, F32)
+    mu = (lo + hi) * F32(0.5)
+    if u is not None:
+        for i in range(lo.shape[0]):
+            p = np.asarray(u[i // u_div], F32)
+            if np.all((p >= lo[i]) & (p <= hi[i])):
+                mu[i] = p
+    return mu, (hi - lo) * F32(0.5)
+
+
+def cem_samples(lo, hi, mu, sigma, Z):
+    """One round's samples u = min(max(mu + sigma * Z, lo), hi) of each box; Z [n, M, d]
+    standard normals; the product and the sum are each rounded to FP32."""
+    lo, hi = np.asarray(lo, F32), np.asarray(hi, F32)
+    mu, sigma = np.asarray(mu, F32), np.asarray(sigma, F32)
+    step = sigma[:, None, :] * np.asarray(Z, F32)
+    u = mu[:, None, :] + step
+    return np.minimum(np.maximum(u, lo[:, None, :]), hi[:, None, :])
+
+
+def cem_elites(values, n_elite):
+    """Indices of the n_elite smallest values of each row (ascending; ties: lower index;
+    NaN counts as +inf)."""
+    v = np.asarray(values, np.float64)
+    v = np.where(np.isnan(v), np.inf, v)
+    return np.argsort(v, axis=1, kind="stable")[:, :n_elite]
+
+
+def cem_refit(values, samples, n_elite, jitter):
+    """Mean and deviation (about that mean, divided by n_elite) of each box's elites, the
+    deviation plus jitter (FP64).  values [n, M], samples [n, M, d]."""
+    idx = cem_elites(values, n_elite)
+    E = np.stack([np.asarray(samples[i], np.float64)[idx[i]] for i in range(idx.shape[0])])
+    mu = E.mean(axis=1)
+    sigma = np.sqrt(((E - mu[:, None, :]) ** 2).mean(axis=1)) + float(jitter)
+    return mu, sigma
+
+
+def cem_search(objective, lo, hi, normals, rounds, M, n_elite, jitter, u=None, u_div=1):
+    """R = rounds of CEM on each box; normals(r, shape) gives round r's Z.  Returns all
+    samples [n, R * M, d] (round by round per box), their values [n, R * M] and the final
+    mu, sigma."""
+    lo, hi = np.asarray(lo, F32), np.asarray(hi, F32)
+    n, d = lo.shape
+    mu, sigma = cem_start(lo, hi, u, u_div)
+    S_all, V_all = [], []
+    for r in range(rounds):
+        S = cem_samples(lo, hi, mu, sigma, normals(r, (n, M, d)))
+        V = np.asarray(objective(S.reshape(-1, d)), np.float64).reshape(n, M)
+        m64, s64 = cem_refit(V, S, n_elite, jitter)
+        mu, sigma = m64.astype(F32), s64.astype(F32)
+        S_all.append(S)
+        V_all.append(V)
+    return np.concatenate(S_all, axis=1), np.concatenate(V_all, axis=1), mu, sigma
+
+
 def n_top(w, M):
     return max(1, min(M, int(math.ceil(float(w) / 100.0 * M))))
 
@@ -118,19 +189,27 @@ def prune(f_lo, best):
 
 
 def bab_plan(objective, bound, lo0, hi0, n_pick, M, iters, eta, T, w, uniforms,
-             bound_uses_samples=False):
+             bound_uses_samples=False, cem=None, normals=None):
     """Algorithm 2 with the heuristics above.  objective(u [m, d]) -> [m] values;
     bound(lo [b, d], hi [b, d]) -> [b] lower bounds of the objective over each box, or
-    with bound_uses_samples bound(lo, hi, S [b, M, d]) taking each box's search samples
-    too (search-integrated bounding, Section 3.2); uniforms(tag, shape) -> the supplied
-    random numbers (tag 'search0', ('search', t), ('pick', t)).  Returns the best value,
-    its sample and the per-iteration trace."""
+    with bound_uses_samples bound(lo, hi, S [b, R * M, d]) taking each box's search
+    samples too (search-integrated bounding, Section 3.2); uniforms(tag, shape) -> the
+    supplied random numbers (tag 'search0', ('search', t), ('pick', t)).  With cem =
+    dict(rounds, n_elite, jitter) the search is CEM (normals(tag, shape), tags ('cem0',
+    r) and ('cem', t, r)) started from the parents' best samples; else M uniform
+    samples.  Returns the best value, its sample and the per-iteration trace."""
     lo0 = np.asarray(lo0, F32)[None]
     hi0 = np.asarray(hi0, F32)[None]
     d = lo0.shape[1]
-    k = n_top(w, M)
+    R = int(cem["rounds"]) if cem else 1
+    k = n_top(w, R * M)
 
-    def search(lo, hi, tag):
+    def search(lo, hi, tag, u_par=None):
+        if cem:
+            ztag = (lambda r: ("cem0", r)) if tag == "search0" else (lambda r: ("cem", tag[1], r))
+            S, vals, _, _ = cem_search(objective, lo, hi, lambda r, shape: normals(ztag(r), shape),
+                                       R, M, cem["n_elite"], cem["jitter"], u_par, 2)
+            return search_summary(vals, S, k) + (S,)
         U = np.asarray(uniforms(tag, (lo.shape[0], M, d)), F32)
         S = lo[:, None, :] + (hi - lo)[:, None, :] * U
         vals = np.asarray(objective(S.reshape(-1, d)), np.float64).reshape(lo.shape[0], M)
@@ -150,7 +229,7 @@ def bab_plan(objective, bound, lo0, hi0, n_pick, M, iters, eta, T, w, uniforms,
             break
         picked, rest = pick_out(P["f_lo"], P["f_hi"], uniforms(("pick", t), (N,)), n_pick, eta, T)
         clo, chi, dims = split(P["lo"][picked], P["hi"][picked], P["top"][picked])
-        c_fhi, c_top, cS = search(clo, chi, ("search", t))
+        c_fhi, c_top, cS = search(clo, chi, ("search", t), P["top"][picked][:, 0])
         c_flo = bound_of(clo, chi, cS)
         j = int(np.argmin(c_fhi))
         if c_fhi[j] < best:

@@ -183,3 +183,97 @@ def test_bab_loop_with_search_integrated_early_stop_bounding():
                                      bound_uses_samples=True)
     assert best <= true_min + 2e-3 * max(1.0, abs(true_min))
     assert np.all(P["f_lo"] <= P["f_hi"] + 1e-9)
+
+
+# ------------------------------------------------------------------ CEM search (Section 3.3)
+def test_cem_start_uses_the_parent_sample_only_inside_the_child():
+    lo = np.array([[0.0, 0.0], [0.5, 0.0]], np.float32)
+    hi = np.array([[0.5, 1.0], [1.0, 1.0]], np.float32)
+    u = np.array([[0.25, 0.75]], np.float32)          # lies in child 0, not in child 1
+    mu, sigma = OB.cem_start(lo, hi, u, 2)
+    assert np.array_equal(mu[0], u[0])
+    assert np.array_equal(mu[1], np.array([0.75, 0.5], np.float32))
+    assert np.array_equal(sigma, np.array([[0.25, 0.5], [0.25, 0.5]], np.float32))
+    mu0, _ = OB.cem_start(lo, hi)
+    assert np.array_equal(mu0, (lo + hi) / 2)
+
+
+def test_cem_samples_follow_the_clipped_normal_law():
+    """Mean and deviation of unclipped samples match mu and sigma; in a tight box the
+    mass at each face is the normal tail beyond it, Phi((lo - mu) / sigma)."""
+    from scipy.stats import norm
+    rng = np.random.default_rng(3)
+    n, M, d = 1, 200000, 2
+    Z = rng.standard_normal((n, M, d)).astype(np.float32)
+    mu = np.array([[0.3, -0.2]], np.float32)
+    sg = np.array([[0.05, 0.1]], np.float32)
+    S = OB.cem_samples(np.full((1, d), -10, np.float32), np.full((1, d), 10, np.float32), mu, sg, Z)
+    assert np.all(np.abs(S[0].mean(0) - mu[0]) < 4 * sg[0] / np.sqrt(M))
+    assert np.all(np.abs(S[0].std(0) / sg[0] - 1) < 0.01)
+    lo, hi = np.array([[0.25, -0.3]], np.float32), np.array([[0.4, -0.05]], np.float32)
+    S = OB.cem_samples(lo, hi, mu, sg, Z)
+    assert np.all((S >= lo[:, None]) & (S <= hi[:, None]))
+    p_lo = norm.cdf((lo[0] - mu[0]) / sg[0])
+    p_hi = norm.sf((hi[0] - mu[0]) / sg[0])
+    assert np.all(np.abs((S[0] == lo[0]).mean(0) - p_lo) < 5 * np.sqrt(p_lo * (1 - p_lo) / M) + 1e-4)
+    assert np.all(np.abs((S[0] == hi[0]).mean(0) - p_hi) < 5 * np.sqrt(p_hi * (1 - p_hi) / M) + 1e-4)
+
+
+def test_cem_refit_with_every_sample_an_elite_is_the_sample_mean_and_std():
+    rng = np.random.default_rng(4)
+    S = rng.normal(size=(3, 50, 4)).astype(np.float32)
+    V = rng.normal(size=(3, 50))
+    mu, sigma = OB.cem_refit(V, S, 50, 0.0)
+    assert np.allclose(mu, S.astype(np.float64).mean(1), rtol=0, atol=1e-12)
+    assert np.allclose(sigma, S.astype(np.float64).std(1), rtol=0, atol=1e-12)
+    mu, sigma = OB.cem_refit(V, S, 50, 0.25)
+    assert np.allclose(sigma, S.astype(np.float64).std(1) + 0.25, rtol=0, atol=1e-12)
+
+
+def test_cem_refit_single_elite_ties_and_nan():
+    S = np.arange(10, dtype=np.float32).reshape(1, 5, 2)
+    V = np.array([[2.0, 1.0, np.nan, 1.0, np.inf]])
+    mu, sigma = OB.cem_refit(V, S, 1, 0.001)
+    assert np.array_equal(mu[0], S[0, 1]) and np.all(sigma == 0.001)   # tie: lower index
+    assert list(OB.cem_elites(V, 5)[0]) == [1, 3, 0, 2, 4]              # NaN as +inf, by index
+
+
+def test_cem_elites_by_brute_force():
+    rng = np.random.default_rng(5)
+    for trial in range(50):
+        M = int(rng.integers(1, 12))
+        E = int(rng.integers(1, M + 1))
+        V = rng.integers(0, 4, size=(1, M)).astype(np.float64)     # many ties
+        best = min(itertools.combinations(range(M), E), key=lambda c: (sorted(V[0, list(c)]), c))
+        assert set(OB.cem_elites(V, E)[0]) == set(best)
+
+
+def test_cem_concentrates_on_the_minimiser_of_a_convex_quadratic():
+    """On f(u) = |u - c|^2 the refitted mean approaches c, and the best of R rounds beats
+    R * M uniform samples."""
+    c = np.array([0.31, -0.52, 0.77], np.float32)
+    lo, hi = -np.ones((1, 3), np.float32), np.ones((1, 3), np.float32)
+    f = lambda U: np.sum((np.asarray(U, np.float64) - c) ** 2, axis=1)
+    rng = np.random.default_rng(6)
+    S, V, mu, sigma = OB.cem_search(f, lo, hi, lambda r, shape: rng.standard_normal(shape).astype(np.float32),
+                                    10, 200, 20, 1e-4)
+    assert np.max(np.abs(mu[0] - c)) < 5e-3
+    assert np.max(sigma) < 5e-3
+    U = np.random.default_rng(7).uniform(-1, 1, (2000, 3))
+    assert V.min() < f(U).min()
+    assert S.shape == (1, 2000, 3) and V.shape == (1, 2000)
+
+
+def test_bab_loop_with_cem_search_reaches_the_brute_force_minimum():
+    net, lo, hi = W.plan_objective(d=2, hidden=(16, 16))
+    objective, bound = _objective_and_bound(net)
+    g = np.linspace(-1.0, 1.0, 401)
+    G = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    true_min = objective(G).min()
+    best, ubest, trace, P = OB.bab_plan(objective, bound, lo, hi, n_pick=8, M=32, iters=12,
+                                        eta=0.75, T=0.05, w=5.0, uniforms=W.plan_uniforms(),
+                                        cem=dict(rounds=3, n_elite=4, jitter=1e-3),
+                                        normals=W.plan_normals())
+    assert abs(objective(ubest[None])[0] - best) < 1e-9
+    assert best <= true_min + 2e-3 * max(1.0, abs(true_min))
+    assert P["f_lo"].min() <= true_min + 1e-9

@@ -268,6 +268,23 @@ def plan_uniforms(seed=PLAN_SEED):
     return draw
 
 
+def plan_normals(seed=PLAN_SEED):
+    """normals(tag, shape): float32 standard normals for the CEM rounds of the planning
+    loop's search, one independent stream per tag (('cem0', r) for the root's round r,
+    ('cem', t, r) for round r of iteration t's children)."""
+    def code(tag):
+        if tag[0] == "cem0":
+            return (1 << 20) + int(tag[1])
+        _, t, r = tag
+        return (2 << 20) + (int(t) << 8) + int(r)
+
+    def draw(tag, shape):
+        rng = np.random.default_rng([seed, code(tag)])
+        return rng.standard_normal(shape, dtype=np.float64).astype(np.float32)
+
+    return draw
+
+
 # ----------------------------------------------------------------- unrolled dynamics model
 PUSH_DIMS = (10, 128, 256, 256, 128, 8)   # state 8 (four keypoints, 2-D) + action 2 -> state 8
 PUSH_PASS = 1.0                           # pass-through offset (see pushing_unrolled)
