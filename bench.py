@@ -222,7 +222,8 @@ def main():
     bab = None
     if args.bab_iters > 0:
         bab = {"crown": bab_loop(args.bab_iters),
-               "early_stop": bab_loop(args.bab_iters, bounding="early_stop")}
+               "early_stop": bab_loop(args.bab_iters, bounding="early_stop"),
+               "cem_early_stop": bab_loop(args.bab_iters, bounding="early_stop", search="cem")}
 
     # ---- CPU oracle on a bounded sample (rank 0, N=1)
     cpu = None
@@ -549,26 +550,33 @@ def planning_unrolled(n=256, n_opt=64, samples=64, steps=2, stops=(77, 65, 41)):
     return out
 
 
-def bab_loop(iters, d=16, hidden=(256, 256, 256), n_pick=1024, samples=64, bounding="crown"):
+def bab_loop(iters, d=16, hidden=(256, 256, 256), n_pick=1024, samples=64, bounding="crown",
+             search="uniform", rounds=3, n_elite=8):
     """Throughput of the planning loop (Algorithm 2) on a seeded scalar ReLU objective over
     [-1, 1]^d: each iteration picks n_pick subdomains, splits them, searches the 2 n_pick
-    children (samples each) and bounds them -- with full CROWN, or with the paper's
-    search-integrated bounds and an early stop at the last ReLU layer -- then prunes."""
+    children (uniform: `samples` each; CEM: `rounds` rounds of `samples`) and bounds them
+    -- with full CROWN, or with the paper's search-integrated bounds and an early stop at
+    the last ReLU layer -- then prunes.  The random numbers are drawn on the device."""
     import torch
 
     import workloads as W
     from paper_2412_09584_amd.bab import BaBPlanner
     net, lo, hi = W.plan_objective(d=d, hidden=hidden)
-    pl = BaBPlanner(net, lo, hi, n_pick=n_pick, samples=samples, bounding=bounding)
-    uni = W.plan_uniforms()
-    pl.run(2, uni)                                   # warm-up
+    pl = BaBPlanner(net, lo, hi, n_pick=n_pick, samples=samples, bounding=bounding, search=search,
+                    cem_rounds=rounds, n_elite=n_elite)
+    gu = torch.Generator(device="cuda").manual_seed(W.PLAN_SEED)
+    gn = torch.Generator(device="cuda").manual_seed(W.PLAN_SEED + 1)
+    uni = lambda tag, shape: torch.rand(shape, device="cuda", generator=gu)
+    nrm = lambda tag, shape: torch.randn(shape, device="cuda", generator=gn)
+    pl.run(2, uni, normals=nrm)                      # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    best, _, P, log = pl.run(iters, uni, trace=True)
+    best, _, P, log = pl.run(iters, uni, trace=True, normals=nrm)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     bounded = sum(2 * len(e["picked"]) for e in log)          # children searched and bounded
     return {"objective": f"MLP {d}-{'-'.join(map(str, hidden))}-1 over [-1,1]^{d}", "bounding": bounding,
+            "search": search if search == "uniform" else f"cem {rounds} rounds, {n_elite} elites",
             "n_pick": n_pick, "samples": samples, "iters": len(log),
             "ms_per_iter": 1e3 * dt / max(len(log), 1),
             "subdomains_bounded_per_s": bounded / dt if log else None,

@@ -204,6 +204,13 @@ bound_status bound_backward(bound_net *net, const bound_pass *pass, const bound_
 bound_status bound_sample_bounds(bound_net *net, int32_t n_sub, int32_t per_sub, const float *x,
                                  float *lo, float *hi, float *out, void *stream);
 
+/* bound_sample_bounds over more samples of the same subdomains (the later rounds of a
+ * search): lo and hi must hold bounds already and take lo = min(lo, samples' min),
+ * hi = max(hi, samples' max).  Arguments and errors as bound_sample_bounds. */
+bound_status bound_sample_bounds_merge(bound_net *net, int32_t n_sub, int32_t per_sub,
+                                       const float *x, float *lo, float *hi, float *out,
+                                       void *stream);
+
 /* Standalone concretisation (Theorem 2 for a box) of coefficient rows:
  * lower[i*rows + r] = coeff[i,r,:] . c - |coeff[i,r,:]| . rad + offset[i,r]
  *                     - (unless BOUND_NO_SLACK) 64 * 2^-24 * (|coeff| . (|c| + rad)
@@ -332,6 +339,41 @@ bound_status bound_bab_samples(bound_bab *bab, int32_t n, int32_t M, const float
 bound_status bound_bab_search_summary(bound_bab *bab, int32_t n, int32_t M, const float *values,
                                       const float *samples, int32_t k, float *f_hi, float *top,
                                       void *stream);
+
+/* batch_search by CEM (Section 3.3: the paper's search is CEM; it gives no details, so
+ * this is the textbook cross-entropy method, one Gaussian per box with per-coordinate
+ * mean mu and deviation sigma).  Each round: bound_bab_cem_samples, the objective at
+ * the samples (bound_sample_bounds), bound_bab_cem_refit; the rounds' samples and
+ * values gathered in archives go to bound_bab_search_summary.
+ *
+ * Start: mu[i] = u[i / u_div] when lo[i] <= that point <= hi[i] in every coordinate
+ * (the best sample of a split box starts the search of the child that holds it), else
+ * (lo[i] + hi[i]) * 0.5; sigma[i] = (hi[i] - lo[i]) * 0.5; FP32.  lo, hi, mu, sigma
+ * [n, dim]; u [*, dim] or NULL (every mu the centre); u_div >= 1. */
+bound_status bound_bab_cem_start(bound_bab *bab, int32_t n, const float *lo, const float *hi,
+                                 const float *u, int32_t u_div, float *mu, float *sigma,
+                                 void *stream);
+
+/* Round samples: samples[i, m, :] = min(max(mu[i] + sigma[i] * Z[i, m, :], lo[i]), hi[i])
+ * with the product and the sum each rounded in FP32 (finite inputs).  Z [n, M, dim]
+ * standard normals supplied by the caller; samples [n, M, dim].  With archive != NULL
+ * the samples are also written to archive[i, a0 + m, :] of an [n, ld, dim] buffer
+ * (0 <= a0, a0 + M <= ld). */
+bound_status bound_bab_cem_samples(bound_bab *bab, int32_t n, int32_t M, const float *lo,
+                                   const float *hi, const float *mu, const float *sigma,
+                                   const float *Z, float *samples, float *archive, int32_t ld,
+                                   int32_t a0, void *stream);
+
+/* Round refit: the n_elite samples of each box with the smallest values (ascending; ties
+ * toward the lower index; NaN as +inf) give, per coordinate, mu[i] = their mean and
+ * sigma[i] = sqrt(mean of (x - mu[i])^2) + jitter, the sums taken in that order in
+ * FP32.  values [n, M]; samples [n, M, dim]; 1 <= n_elite <= M <= max_samples;
+ * jitter >= 0.  With archive_values != NULL values[i, m] are also copied to
+ * archive_values[i * ld + a0 + m] (0 <= a0, a0 + M <= ld). */
+bound_status bound_bab_cem_refit(bound_bab *bab, int32_t n, int32_t M, const float *values,
+                                 const float *samples, int32_t n_elite, float jitter, float *mu,
+                                 float *sigma, float *archive_values, int32_t ld, int32_t a0,
+                                 void *stream);
 
 /* batch_split (Section 3.1): for each subdomain i the dimension j* maximising
  * (hi_j - lo_j) * |n_lo_j - n_up_j| over its k top samples (a sample is on the lower side

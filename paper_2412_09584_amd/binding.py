@@ -27,7 +27,8 @@ EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "b
             "bound_profile", "bound_profile_read", "bound_destroy",
             "bound_bab_init", "bound_bab_pick_out", "bound_bab_samples", "bound_bab_search_summary",
             "bound_bab_split", "bound_bab_update_best", "bound_bab_prune", "bound_bab_prune_noalloc",
-            "bound_bab_destroy", "bound_last_error")
+            "bound_sample_bounds_merge", "bound_bab_cem_start", "bound_bab_cem_samples",
+            "bound_bab_cem_refit", "bound_bab_destroy", "bound_last_error")
 
 _p = ctypes.c_void_p
 
@@ -81,6 +82,7 @@ def lib():
         L.bound_grad.argtypes = [_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_int32, _p, _p, _p, _p]
         L.bound_sample_bounds.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p, _p]
+        L.bound_sample_bounds_merge.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p, _p]
         L.bound_adam.argtypes = [ctypes.c_int64, _p, _p, _p, _p, ctypes.c_int32, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                  ctypes.c_float, ctypes.c_float, _p]
@@ -108,6 +110,9 @@ def lib():
         L.bound_bab_update_best.argtypes = [_p, i32, _p, _p, i32, _p, _p, _p]
         L.bound_bab_prune.argtypes = [_p, i32, _p, _p, _p, _p, _p]
         L.bound_bab_prune_noalloc.argtypes = [i32, _p, _p, _p, _p, _p]
+        L.bound_bab_cem_start.argtypes = [_p, i32, _p, _p, _p, i32, _p, _p, _p]
+        L.bound_bab_cem_samples.argtypes = [_p, i32, i32, _p, _p, _p, _p, _p, _p, _p, i32, i32, _p]
+        L.bound_bab_cem_refit.argtypes = [_p, i32, i32, _p, _p, i32, f32, _p, _p, _p, i32, i32, _p]
         L.bound_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[:-1]:
             if name not in ("bound_profile_read", "bound_autotune_report", "bound_destroy",
@@ -227,6 +232,11 @@ def bound_sample_bounds(handle, n_sub, per_sub, x, lo=None, hi=None, out=None, s
                                      _ptr(out), _stream(stream)))
 
 
+def bound_sample_bounds_merge(handle, n_sub, per_sub, x, lo, hi, out=None, stream=None):
+    _check(lib().bound_sample_bounds_merge(handle, int(n_sub), int(per_sub), _ptr(x), _ptr(lo),
+                                           _ptr(hi), _ptr(out), _stream(stream)))
+
+
 def bound_grad(handle, grad_lower, grad_alpha, grad_beta=None, pass_id=0, stream=None):
     """Shapes are taken from the buffers: grad_lower [n_inst, rows], grad_beta [nnz, rows]."""
     n_inst, rows = grad_lower.shape
@@ -298,6 +308,25 @@ def bound_bab_pick_out(handle, n_dom, f_lo, f_hi, u, n_pick, eta, temperature, p
 def bound_bab_samples(handle, n, M, lo, hi, U, samples, stream=None):
     _check(lib().bound_bab_samples(handle, int(n), int(M), _ptr(lo), _ptr(hi), _ptr(U),
                                    _ptr(samples), _stream(stream)))
+
+
+def bound_bab_cem_start(handle, n, lo, hi, u, u_div, mu, sigma, stream=None):
+    _check(lib().bound_bab_cem_start(handle, int(n), _ptr(lo), _ptr(hi), _ptr(u), int(u_div),
+                                     _ptr(mu), _ptr(sigma), _stream(stream)))
+
+
+def bound_bab_cem_samples(handle, n, M, lo, hi, mu, sigma, Z, samples, archive=None, ld=0, a0=0,
+                          stream=None):
+    _check(lib().bound_bab_cem_samples(handle, int(n), int(M), _ptr(lo), _ptr(hi), _ptr(mu),
+                                       _ptr(sigma), _ptr(Z), _ptr(samples), _ptr(archive), int(ld),
+                                       int(a0), _stream(stream)))
+
+
+def bound_bab_cem_refit(handle, n, M, values, samples, n_elite, jitter, mu, sigma,
+                        archive_values=None, ld=0, a0=0, stream=None):
+    _check(lib().bound_bab_cem_refit(handle, int(n), int(M), _ptr(values), _ptr(samples),
+                                     int(n_elite), float(jitter), _ptr(mu), _ptr(sigma),
+                                     _ptr(archive_values), int(ld), int(a0), _stream(stream)))
 
 
 def bound_bab_search_summary(handle, n, M, values, samples, k, f_hi, top, stream=None):

@@ -926,12 +926,14 @@ bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t
     return bs;
 }
 
-bound_status bound_sample_bounds(bound_net *net, int32_t n_sub, int32_t per_sub, const float *x,
-                                 float *lo, float *hi, float *out, void *stream) {
+namespace {
+bound_status sample_bounds(bound_net *net, int32_t n_sub, int32_t per_sub, const float *x, float *lo,
+                           float *hi, float *out, bool merge, void *stream) {
+    const char *fn = merge ? "bound_sample_bounds_merge" : "bound_sample_bounds";
     if (!net || n_sub < 1 || per_sub < 1 || !x || (!lo) != (!hi) || (!lo && !out))
-        return fail(BOUND_E_ARG, "bound_sample_bounds: bad arguments");
+        return fail(BOUND_E_ARG, std::string(fn) + ": bad arguments");
     if ((long)per_sub > net->max_rows)
-        return fail(BOUND_E_NOMEM, "bound_sample_bounds: per_sub > max_rows");
+        return fail(BOUND_E_NOMEM, std::string(fn) + ": per_sub > max_rows");
     hipStream_t st = (hipStream_t)stream;
     net->saved = false;
     const int L = net->n_layers;
@@ -965,15 +967,26 @@ bound_status bound_sample_bounds(bound_net *net, int32_t n_sub, int32_t per_sub,
                 HIPCHK(launch_sample_minmax(ns, per_sub, net->d[m], C, HW, nxt,
                                             lo ? lo + s0 * net->n_relu + net->relu_off(m) : nullptr,
                                             hi ? hi + s0 * net->n_relu + net->relu_off(m) : nullptr,
-                                            net->n_relu, true, nullptr, st));
+                                            net->n_relu, true, nullptr, merge, st));
             } else if (out) {
                 HIPCHK(launch_sample_minmax(ns, per_sub, net->d[m], C, HW, nxt, nullptr, nullptr, 0,
-                                            false, out + s0 * per_sub * net->d[L], st));
+                                            false, out + s0 * per_sub * net->d[L], false, st));
             }
             float *t = cur; cur = nxt; nxt = t;
         }
     }
     return BOUND_OK;
+}
+}  // namespace
+
+bound_status bound_sample_bounds(bound_net *net, int32_t n_sub, int32_t per_sub, const float *x,
+                                 float *lo, float *hi, float *out, void *stream) {
+    return sample_bounds(net, n_sub, per_sub, x, lo, hi, out, false, stream);
+}
+
+bound_status bound_sample_bounds_merge(bound_net *net, int32_t n_sub, int32_t per_sub, const float *x,
+                                       float *lo, float *hi, float *out, void *stream) {
+    return sample_bounds(net, n_sub, per_sub, x, lo, hi, out, true, stream);
 }
 
 bound_status bound_concretize(int32_t n_inst, int32_t rows, int32_t d0, const float *coeff,

@@ -694,10 +694,10 @@ __global__ void k_to_internal(long total, long D, int C, int HW, const float *x,
 }
 
 // Per subdomain and neuron: min / max of z over its per_sub sample rows (written C-major
-// at lo/hi[sub*ld + j]); then z <- ReLU(z) in place for the next layer, or a copy of the
-// last layer's output to `out` (C-major).
+// at lo/hi[sub*ld + j], merged with the values there when `merge`); then z <- ReLU(z) in
+// place for the next layer, or a copy of the last layer's output to `out` (C-major).
 __global__ void k_sample_minmax(long n_sub, int per_sub, long D, int C, int HW, float *z, float *lo,
-                                float *hi, long ld, int relu, float *out) {
+                                float *hi, long ld, int relu, float *out, int merge) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_sub * D) return;
     const long sub = e / D, j = e - sub * D;
@@ -711,8 +711,9 @@ __global__ void k_sample_minmax(long n_sub, int per_sub, long D, int C, int HW, 
         if (out) out[(sub * per_sub + s) * D + to_cmajor(j, C, HW)] = v;
     }
     if (lo) {
-        lo[sub * ld + to_cmajor(j, C, HW)] = mn;
-        hi[sub * ld + to_cmajor(j, C, HW)] = mx;
+        const long o = sub * ld + to_cmajor(j, C, HW);
+        lo[o] = merge ? fminf(lo[o], mn) : mn;
+        hi[o] = merge ? fmaxf(hi[o], mx) : mx;
     }
 }
 
@@ -986,11 +987,11 @@ hipError_t launch_to_internal(long n_img, int C, int HW, const float *x, float *
 }
 
 hipError_t launch_sample_minmax(long n_sub, int per_sub, long D, int C, int HW, float *z, float *lo,
-                                float *hi, long ld, bool relu, float *out, hipStream_t st) {
+                                float *hi, long ld, bool relu, float *out, bool merge, hipStream_t st) {
     const long total = n_sub * D;
     if (total == 0) return hipSuccess;
     hipLaunchKernelGGL(k_sample_minmax, dim3(blocks_for(total)), dim3(TPB), 0, st, n_sub, per_sub, D,
-                       C, HW, z, lo, hi, ld, relu ? 1 : 0, out);
+                       C, HW, z, lo, hi, ld, relu ? 1 : 0, out, merge ? 1 : 0);
     return hipGetLastError();
 }
 

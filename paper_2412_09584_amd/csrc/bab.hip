@@ -138,15 +138,12 @@ __global__ void k_samples(long total, int M, int d, const float *lo, const float
     S[e] = a + (b - a) * U[e];
 }
 
-// One block per subdomain: bitonic sort of (value, index) over its M samples in LDS,
-// then f_hi and the k best samples.
-__global__ void k_search_summary(int M, int P2, int d, const float *values, const float *S, int k,
-                                 float *f_hi, float *top) {
-    __shared__ float sv[MAX_SAMPLES];
-    __shared__ int si[MAX_SAMPLES];
-    const long b = blockIdx.x;
+// Bitonic sort, by the whole block, of the (canonical value, index) pairs of v[0 .. M)
+// in LDS (P2 = M rounded up to a power of two; the padding sorts last): ascending
+// value, equal values by index.
+__device__ void block_sort(const float *v, int M, int P2, float *sv, int *si) {
     for (int t = threadIdx.x; t < P2; t += TPB) {
-        sv[t] = t < M ? canon(values[b * M + t]) : INFINITY;
+        sv[t] = t < M ? canon(v[t]) : INFINITY;
         si[t] = t;
     }
     __syncthreads();
@@ -168,11 +165,81 @@ __global__ void k_search_summary(int M, int P2, int d, const float *values, cons
             __syncthreads();
         }
     }
+}
+
+// One block per subdomain: its M samples sorted by value, then f_hi and the k best
+// samples.
+__global__ void k_search_summary(int M, int P2, int d, const float *values, const float *S, int k,
+                                 float *f_hi, float *top) {
+    __shared__ float sv[MAX_SAMPLES];
+    __shared__ int si[MAX_SAMPLES];
+    const long b = blockIdx.x;
+    block_sort(values + b * M, M, P2, sv, si);
     if (threadIdx.x == 0) f_hi[b] = values[b * M + si[0]];
     for (long e = threadIdx.x; e < (long)k * d; e += TPB) {
         const int t = (int)(e / d), j = (int)(e - (long)t * d);
         top[(b * k + t) * d + j] = S[(b * M + si[t]) * d + j];
     }
+}
+
+// CEM start of box i: mu = u[i / u_div] if it lies in the box, else the centre;
+// sigma = half the width.  One thread per box.
+__global__ void k_cem_start(int n, int d, const float *lo, const float *hi, const float *u,
+                            int u_div, float *mu, float *sigma) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float *p = u ? u + (long)(i / u_div) * d : nullptr;
+    bool in = p != nullptr;
+    for (int j = 0; j < d && in; ++j) in = p[j] >= lo[(long)i * d + j] && p[j] <= hi[(long)i * d + j];
+    for (int j = 0; j < d; ++j) {
+        const float a = lo[(long)i * d + j], c = hi[(long)i * d + j];
+        mu[(long)i * d + j] = in ? p[j] : (a + c) * 0.5f;
+        sigma[(long)i * d + j] = (c - a) * 0.5f;
+    }
+}
+
+// One CEM round's samples (and their copy into the round's slice of the archive).
+__global__ void k_cem_samples(long total, int M, int d, const float *lo, const float *hi,
+                              const float *mu, const float *sigma, const float *Z, float *S,
+                              float *arch, int ld, int a0) {
+#pragma clang fp contract(off)   // the product and the sum rounded separately (plain
+                                 // operators: the header's __fmul_rn / __fadd_rn may fuse)
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const long i = e / ((long)M * d);
+    const int r = (int)(e - i * M * d), m = r / d, j = r - m * d;
+    const long o = i * d + j;
+    const float u = mu[o] + sigma[o] * Z[e];
+    const float v = fminf(fmaxf(u, lo[o]), hi[o]);
+    S[e] = v;
+    if (arch) arch[((i * ld) + a0 + m) * d + j] = v;
+}
+
+// One block per box: the round's values sorted, then mean and deviation of the n_elite
+// best samples per coordinate, summed in elite order.
+__global__ void k_cem_refit(int M, int P2, int d, const float *values, const float *S, int E,
+                            float jitter, float *mu, float *sigma, float *arch_v, int ld, int a0) {
+#pragma clang fp contract(off)
+    __shared__ float sv[MAX_SAMPLES];
+    __shared__ int si[MAX_SAMPLES];
+    const long b = blockIdx.x;
+    block_sort(values + b * M, M, P2, sv, si);
+    const float rE = (float)E;
+    for (int j = threadIdx.x; j < d; j += TPB) {
+        float s = 0.f;
+        for (int r = 0; r < E; ++r) s += S[(b * M + si[r]) * d + j];
+        const float m = s / rE;
+        float q = 0.f;
+        for (int r = 0; r < E; ++r) {
+            const float dv = S[(b * M + si[r]) * d + j] - m;
+            q += dv * dv;
+        }
+        mu[b * d + j] = m;
+        sigma[b * d + j] = sqrtf(q / rE) + jitter;
+    }
+    if (arch_v)
+        for (int t = threadIdx.x; t < M; t += TPB) arch_v[b * ld + a0 + t] = values[b * M + t];
 }
 
 // One block per subdomain: split dimension and the two children.
@@ -478,6 +545,48 @@ bound_status bound_bab_split(bound_bab *b, int32_t n, const float *lo, const flo
     if (n == 0) return BOUND_OK;
     hipLaunchKernelGGL(bp::k_split, dim3(n), dim3(bp::TPB), 0, (hipStream_t)stream, b->dim, lo, hi,
                        top, k, child_lo, child_hi, split_dim);
+    BCHK(hipGetLastError());
+    return BOUND_OK;
+}
+
+bound_status bound_bab_cem_start(bound_bab *b, int32_t n, const float *lo, const float *hi,
+                                 const float *u, int32_t u_div, float *mu, float *sigma, void *stream) {
+    if (!b || n < 0 || u_div < 1 || (n > 0 && (!lo || !hi || !mu || !sigma)))
+        return set_error(BOUND_E_ARG, "bound_bab_cem_start: bad arguments");
+    if (n == 0) return BOUND_OK;
+    hipLaunchKernelGGL(bp::k_cem_start, dim3(bp::blocks(n)), dim3(bp::TPB), 0, (hipStream_t)stream,
+                       n, b->dim, lo, hi, u, u_div, mu, sigma);
+    BCHK(hipGetLastError());
+    return BOUND_OK;
+}
+
+bound_status bound_bab_cem_samples(bound_bab *b, int32_t n, int32_t M, const float *lo, const float *hi,
+                                   const float *mu, const float *sigma, const float *Z, float *samples,
+                                   float *archive, int32_t ld, int32_t a0, void *stream) {
+    if (!b || n < 0 || M < 1 || (archive && (a0 < 0 || (long)a0 + M > ld)) ||
+        (n > 0 && (!lo || !hi || !mu || !sigma || !Z || !samples)))
+        return set_error(BOUND_E_ARG, "bound_bab_cem_samples: bad arguments");
+    const long total = (long)n * M * b->dim;
+    if (total == 0) return BOUND_OK;
+    hipLaunchKernelGGL(bp::k_cem_samples, dim3(bp::blocks(total)), dim3(bp::TPB), 0, (hipStream_t)stream,
+                       total, M, b->dim, lo, hi, mu, sigma, Z, samples, archive, ld, a0);
+    BCHK(hipGetLastError());
+    return BOUND_OK;
+}
+
+bound_status bound_bab_cem_refit(bound_bab *b, int32_t n, int32_t M, const float *values,
+                                 const float *samples, int32_t n_elite, float jitter, float *mu,
+                                 float *sigma, float *archive_values, int32_t ld, int32_t a0,
+                                 void *stream) {
+    if (!b || n < 0 || M < 1 || M > b->max_samples || n_elite < 1 || n_elite > M ||
+        !(jitter >= 0.f) || (archive_values && (a0 < 0 || (long)a0 + M > ld)) ||
+        (n > 0 && (!values || !samples || !mu || !sigma)))
+        return set_error(BOUND_E_ARG, "bound_bab_cem_refit: bad arguments");
+    if (n == 0) return BOUND_OK;
+    int P2 = 1;
+    while (P2 < M) P2 <<= 1;
+    hipLaunchKernelGGL(bp::k_cem_refit, dim3(n), dim3(bp::TPB), 0, (hipStream_t)stream, M, P2, b->dim,
+                       values, samples, n_elite, jitter, mu, sigma, archive_values, ld, a0);
     BCHK(hipGetLastError());
     return BOUND_OK;
 }

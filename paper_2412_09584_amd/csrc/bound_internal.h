@@ -269,7 +269,8 @@ hipError_t launch_beta_grad(int nnz, int rows, int layer, const BetaGradLayer &L
                             float *gbeta, hipStream_t st);
 hipError_t launch_to_internal(long n_img, int C, int HW, const float *x, float *y, hipStream_t st);
 hipError_t launch_sample_minmax(long n_sub, int per_sub, long D, int C, int HW, float *z,
-                                float *lo, float *hi, long ld, bool relu, float *out, hipStream_t st);
+                                float *lo, float *hi, long ld, bool relu, float *out, bool merge,
+                                hipStream_t st);
 hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int step,
                        float lr, float b1, float b2, float eps, float gs, float lo, float hi,
                        hipStream_t st);

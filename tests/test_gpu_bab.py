@@ -1,5 +1,6 @@
 """GPU parity of the branch-and-bound steps (libbound.so, through the C ABI) against the
-oracle (oracle/bab.py), and the planning loop on the GPU against brute force."""
+oracle (oracle/bab.py) -- pick-out, uniform and CEM search, summary, split, best, pruner
+-- and the planning loop on the GPU against brute force and the oracle's loop."""
 import os
 import sys
 
@@ -192,4 +193,104 @@ def test_planning_loop_with_early_stop_bounding(B):
 
     ob, _, _, _ = OB.bab_plan(lambda U: O.forward(net, U)[-1][:, 0], bound, lo, hi, 8, 64, 12,
                               0.75, 0.05, 5.0, W.plan_uniforms(), bound_uses_samples=True)
+    assert abs(best - ob) <= 2e-3 * max(1.0, abs(ob))
+
+
+def test_cem_steps_match_oracle(B):
+    """CEM start and round samples bit-exact (FP32 steps), the refit's elites exact (one
+    elite: the argmin sample itself, ties to the lower index) and its moments within FP32
+    summation error of the FP64 oracle; the archives hold the round's slice."""
+    rng = np.random.default_rng(11)
+    n, M, d, R = 64, 48, 5, 3
+    lo = rng.uniform(-2, 0, size=(n, d)).astype(np.float32)
+    hi = (lo + rng.uniform(0.01, 2, size=(n, d))).astype(np.float32)
+    par = (lo[0::2] + (hi[0::2] - lo[0::2]) * rng.random((n // 2, d))).astype(np.float32)
+    par[3] = hi[7] + 1.0                                   # outside both children: centres
+    bab = B.bound_bab_init(4 * n, d, R * M)
+    mu, sg = torch.empty(n, d, device="cuda"), torch.empty(n, d, device="cuda")
+    B.bound_bab_cem_start(bab, n, dev(lo), dev(hi), dev(par), 2, mu, sg)
+    omu, osg = OB.cem_start(lo, hi, par, 2)
+    assert np.array_equal(mu.cpu().numpy(), omu) and np.array_equal(sg.cpu().numpy(), osg)
+    B.bound_bab_cem_start(bab, n, dev(lo), dev(hi), None, 1, mu, sg)
+    assert np.array_equal(mu.cpu().numpy(), OB.cem_start(lo, hi)[0])
+    Z = (3.0 * rng.standard_normal((n, M, d))).astype(np.float32)   # many clipped samples
+    S = torch.empty(n, M, d, device="cuda")
+    S_all = torch.full((n, R * M, d), float("nan"), device="cuda")
+    B.bound_bab_cem_samples(bab, n, M, dev(lo), dev(hi), dev(omu), dev(osg), dev(Z), S, S_all, R * M, M)
+    oS = OB.cem_samples(lo, hi, omu, osg, Z)
+    assert np.array_equal(S.cpu().numpy(), oS)
+    assert np.array_equal(S_all[:, M:2 * M].cpu().numpy(), oS)
+    assert torch.isnan(S_all[:, :M]).all() and torch.isnan(S_all[:, 2 * M:]).all()
+    vals = rng.integers(0, 6, size=(n, M)).astype(np.float32)       # many ties
+    vals[5, 0] = np.nan
+    V_all = torch.full((n, R * M), float("nan"), device="cuda")
+    for E, jit in ((1, 0.0), (7, 1e-3), (M, 0.0)):
+        B.bound_bab_cem_refit(bab, n, M, dev(vals), S, E, jit, mu, sg, V_all, R * M, 2 * M)
+        rmu, rsg = OB.cem_refit(vals, oS, E, jit)
+        gmu, gsg = mu.cpu().numpy(), sg.cpu().numpy()
+        if E == 1:
+            idx = OB.cem_elites(vals, 1)[:, 0]
+            assert np.array_equal(gmu, oS[np.arange(n), idx]) and np.all(gsg == 0.0)
+        scale = np.maximum(np.abs(lo), np.abs(hi))
+        assert np.all(np.abs(gmu - rmu) <= 4 * E * 2.0 ** -24 * scale), f"mu, {E} elites"
+        assert np.all(np.abs(gsg - rsg) <= 1e-5 * scale), f"sigma, {E} elites"
+    assert np.array_equal(V_all[:, 2 * M:].cpu().numpy(), vals, equal_nan=True)
+    assert torch.isnan(V_all[:, :2 * M]).all()
+    with pytest.raises(B.BoundError):
+        B.bound_bab_cem_refit(bab, n, M, dev(vals), S, M + 1, 0.0, mu, sg)   # n_elite > M
+    with pytest.raises(B.BoundError):
+        B.bound_bab_cem_samples(bab, n, M, dev(lo), dev(hi), mu, sg, dev(Z), S, S_all, R * M, 2 * M + 1)
+    B.bound_bab_destroy(bab)
+
+
+def test_sample_bounds_merge_equals_one_pass_over_all_samples(B):
+    from paper_2412_09584_amd.net import BoundNet
+    net, lo, hi = W.plan_objective(d=4, hidden=(32, 32))
+    bn = BoundNet(net, 8, 8 * 64)
+    rng = np.random.default_rng(12)
+    n, M = 6, 40
+    X = rng.uniform(-1, 1, (n, 2 * M, 4)).astype(np.float32)
+    a_lo = torch.empty(n, bn.n_relu, device="cuda")
+    a_hi = torch.empty_like(a_lo)
+    B.bound_sample_bounds(bn.handle, n, 2 * M, dev(X.reshape(-1, 4)), a_lo, a_hi)
+    m_lo, m_hi = torch.empty_like(a_lo), torch.empty_like(a_lo)
+    B.bound_sample_bounds(bn.handle, n, M, dev(X[:, :M].reshape(-1, 4)), m_lo, m_hi)
+    out = torch.empty(n * M, 1, device="cuda")
+    B.bound_sample_bounds_merge(bn.handle, n, M, dev(X[:, M:].reshape(-1, 4)), m_lo, m_hi, out=out)
+    assert torch.equal(m_lo, a_lo) and torch.equal(m_hi, a_hi)
+    ref = O.forward(net, X[:, M:].reshape(-1, 4).astype(np.float64))[-1]
+    assert np.allclose(out.cpu().numpy(), ref, rtol=1e-4, atol=1e-5)
+
+
+@pytest.mark.parametrize("bounding", ["crown", "early_stop"])
+def test_planning_loop_with_cem_search(B, bounding):
+    """The loop with the CEM search (3 rounds of 32 samples, 4 elites) reaches the
+    brute-force minimum and agrees with the oracle's loop on the same random numbers."""
+    from paper_2412_09584_amd.bab import BaBPlanner
+    net, lo, hi = W.plan_objective(d=2, hidden=(16, 16))
+    g = np.linspace(-1.0, 1.0, 401)
+    G = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
+    true_min = O.forward(net, G)[-1][:, 0].min()
+    cem = dict(rounds=3, n_elite=4, jitter=1e-3)
+    pl = BaBPlanner(net, lo, hi, n_pick=8, samples=32, eta=0.75, temperature=0.05, w=5.0,
+                    bounding=bounding, stop_layer=2, search="cem", cem_rounds=3, n_elite=4,
+                    jitter=1e-3)
+    best, ub, P, log = pl.run(12, W.plan_uniforms(), trace=True, normals=W.plan_normals())
+    fu = O.forward(net, ub.cpu().numpy()[None].astype(np.float64))[-1][0, 0]
+    assert abs(fu - best) <= 1e-5 * max(1.0, abs(best))
+    assert best <= true_min + 2e-3 * max(1.0, abs(true_min))
+    if bounding == "crown":
+        assert float(P["f_lo"].min()) <= true_min + 1e-5
+        bound = (lambda a, b: np.array([O.crown(net, np.ones((1, 1)), a[i].astype(np.float64),
+                                                b[i].astype(np.float64))[1][0]
+                                        for i in range(a.shape[0])]))
+    else:
+        def bound(a, b, S):
+            return np.array([O.spec_lower_early_stop(net, len(net), np.ones((1, 1)),
+                                                     O.sample_bounds(net, S[i].astype(np.float64)),
+                                                     2, "relu")[0] for i in range(a.shape[0])])
+    ob, _, _, _ = OB.bab_plan(lambda U: O.forward(net, U)[-1][:, 0], bound, lo, hi, 8, 32, 12,
+                              0.75, 0.05, 5.0, W.plan_uniforms(),
+                              bound_uses_samples=bounding == "early_stop", cem=cem,
+                              normals=W.plan_normals())
     assert abs(best - ob) <= 2e-3 * max(1.0, abs(ob))
