@@ -5,8 +5,8 @@ the search summary (Section 3.3) and the pruner (Section 3).
 TEST INFRASTRUCTURE. Only tests/, the smoke check of the package entry file and the
 cpu_baseline leg of the bench may import this module.  The HIP library never calls it,
 and it shares no code with the HIP library: only the seeded input generators in
-``workloads`` serve both.  Random numbers the method draws (Gumbel uniforms for the
-pick-out, uniforms for the search samples) are inputs.
+``workloads`` serve both.  Random numbers the method draws (Gumbel variates for the
+pick-out, uniforms or normals for the search samples) are inputs.
 
 Readings where the text leaves a choice (each is listed in the design notes):
   * batch_pick_out: n = min(n, |P|) and n1 = floor(eta * n) (in double precision).
@@ -14,10 +14,11 @@ Readings where the text leaves a choice (each is listed in the design notes):
     lower index).  The other n - n1 are drawn without replacement from the rest with
     p_i proportional to exp(-s_i / T), s_i = (f_lo_i - min) / (max - min) over the rest
     (min-max scaling; s = 0 when max = min).  Drawing without replacement uses the
-    Gumbel-top-k construction -- the n - n1 largest of -s_i / T + G_i, G_i = -log(-log
-    U_i) with U_i the supplied uniforms (ties: lower index) -- which yields the ordered
-    sample of successive softmax draws.  A subdomain with a non-finite f_lo comes after
-    every finite one.
+    Gumbel-top-k construction -- the n - n1 largest of -s_i / T + G_i with G_i supplied
+    standard Gumbel variates (ties: lower index) -- which yields the ordered sample of
+    successive softmax draws.  The keys decide integers, so they are formed in the
+    kernel's precision (FP32, each operation rounded: s_i * fl(1 / T) - G_i, smallest
+    first).  A subdomain with a non-finite f_lo comes after every finite one.
   * batch_split: the box coordinates are FP32 and so is the midpoint (lo + hi) * 0.5.
     The top samples are the k = max(1, ceil(w / 100 * M)) samples of the box's search
     with the smallest objective (ties: lower index); a sample counts on the lower side
@@ -53,10 +54,15 @@ import numpy as np
 F32 = np.float32
 
 
-def pick_out(f_lo, f_hi, u, n, eta, T):
-    """Indices picked (in pick order) and the rest (in original order)."""
-    f_lo = np.asarray(f_lo, np.float64)
-    f_hi = np.asarray(f_hi, np.float64)
+def pick_out(f_lo, f_hi, g, n, eta, T):
+    """Indices picked (in pick order) and the rest (in original order).  g: the supplied
+    standard Gumbel variates.  The draw's keys decide integers, so they are formed in the
+    kernel's precision: FP32 throughout, each operation rounded (s = (f_lo - min) /
+    (max - min), key = s * fl(1 / T) - g, ascending; -0 equals +0, NaN counts as +inf)."""
+    f_lo = np.asarray(f_lo, F32)
+    f_hi = np.asarray(f_hi, F32)
+    f_hi = np.where(np.isnan(f_hi), F32(np.inf), f_hi)
+    g = np.asarray(g, F32)
     N = f_lo.size
     n = min(int(n), N)
     n1 = int(math.floor(float(eta) * n))
@@ -67,14 +73,13 @@ def pick_out(f_lo, f_hi, u, n, eta, T):
     fin = rest[np.isfinite(f_lo[rest])]
     picks = []
     if n - n1 > 0 and rest.size:
-        lo = f_lo[fin].min() if fin.size else 0.0
-        hi = f_lo[fin].max() if fin.size else 0.0
-        score = np.full(N, -np.inf)
-        for i in fin:
-            s = (f_lo[i] - lo) / (hi - lo) if hi > lo else 0.0
-            uu = min(max(float(u[i]), 1e-30), 1.0 - 2.0 ** -24)
-            score[i] = -s / T - math.log(-math.log(uu))
-        order = sorted(rest, key=lambda i: (-score[i] if np.isfinite(f_lo[i]) else math.inf, i))
+        lo = f_lo[fin].min() if fin.size else F32(0)
+        hi = f_lo[fin].max() if fin.size else F32(0)
+        inv_t = F32(1) / F32(T)
+        s = (f_lo[fin] - lo) / (hi - lo) if hi > lo else np.zeros(fin.size, F32)
+        key = np.full(N, np.inf, F32)
+        key[fin] = s * inv_t - g[fin]
+        order = sorted(rest, key=lambda i: (0, float(key[i]), i) if np.isfinite(f_lo[i]) else (1, 0.0, i))
         picks = list(order[: n - n1])
     picked = [int(i) for i in first] + [int(i) for i in picks]
     mark = np.zeros(N, bool)
@@ -188,13 +193,14 @@ def prune(f_lo, best):
     return np.nonzero(f_lo <= best)[0]
 
 
-def bab_plan(objective, bound, lo0, hi0, n_pick, M, iters, eta, T, w, uniforms,
+def bab_plan(objective, bound, lo0, hi0, n_pick, M, iters, eta, T, w, uniforms, gumbels,
              bound_uses_samples=False, cem=None, normals=None):
     """Algorithm 2 with the heuristics above.  objective(u [m, d]) -> [m] values;
     bound(lo [b, d], hi [b, d]) -> [b] lower bounds of the objective over each box, or
     with bound_uses_samples bound(lo, hi, S [b, R * M, d]) taking each box's search
     samples too (search-integrated bounding, Section 3.2); uniforms(tag, shape) -> the
-    supplied random numbers (tag 'search0', ('search', t), ('pick', t)).  With cem =
+    supplied uniforms of the search (tag 'search0', ('search', t)); gumbels(tag, shape) ->
+    the supplied Gumbel variates of the pick-out (tag ('pick', t)).  With cem =
     dict(rounds, n_elite, jitter) the search is CEM (normals(tag, shape), tags ('cem0',
     r) and ('cem', t, r)) started from the parents' best samples; else M uniform
     samples.  Returns the best value, its sample and the per-iteration trace."""
@@ -227,7 +233,7 @@ def bab_plan(objective, bound, lo0, hi0, n_pick, M, iters, eta, T, w, uniforms,
         N = P["lo"].shape[0]
         if N == 0:
             break
-        picked, rest = pick_out(P["f_lo"], P["f_hi"], uniforms(("pick", t), (N,)), n_pick, eta, T)
+        picked, rest = pick_out(P["f_lo"], P["f_hi"], gumbels(("pick", t), (N,)), n_pick, eta, T)
         clo, chi, dims = split(P["lo"][picked], P["hi"][picked], P["top"][picked])
         c_fhi, c_top, cS = search(clo, chi, ("search", t), P["top"][picked][:, 0])
         c_flo = bound_of(clo, chi, cS)

@@ -24,11 +24,16 @@ def test_prune_paper_example():
     assert list(OB.prune(f_lo, 3.0)) == [1, 2]        # C1 pruned, equality kept
 
 
+def _gumbel(u):
+    """Standard Gumbel variates from uniforms (float64, then float32)."""
+    return (-np.log(-np.log(np.asarray(u, np.float64)))).astype(np.float32)
+
+
 def test_pick_eta_one_is_the_sort_by_upper_bound():
     rng = np.random.default_rng(0)
     f_hi = rng.normal(size=50)
     f_hi[7] = f_hi[3]                                   # a tie: lower index first
-    picked, rest = OB.pick_out(rng.normal(size=50), f_hi, rng.random(50), 10, 1.0, 0.05)
+    picked, rest = OB.pick_out(rng.normal(size=50), f_hi, _gumbel(rng.random(50)), 10, 1.0, 0.05)
     ref = sorted(range(50), key=lambda i: (f_hi[i], i))[:10]
     assert list(picked) == ref
     assert list(rest) == [i for i in range(50) if i not in ref]
@@ -49,7 +54,7 @@ def test_pick_single_draw_follows_the_softmax():
     cnt = np.zeros(5)
     f_hi = np.zeros(5)
     for _ in range(n_draw):
-        picked, _ = OB.pick_out(f_lo, f_hi, rng.random(5), 1, 0.0, T)
+        picked, _ = OB.pick_out(f_lo, f_hi, _gumbel(rng.random(5)), 1, 0.0, T)
         cnt[picked[0]] += 1
     sd = np.sqrt(n_draw * p * (1 - p))
     assert np.all(np.abs(cnt - n_draw * p) <= 4.5 * sd), (cnt / n_draw, p)
@@ -66,7 +71,7 @@ def test_pick_two_draws_without_replacement():
     n_draw = 30000
     cnt = {k: 0 for k in law}
     for _ in range(n_draw):
-        picked, _ = OB.pick_out(f_lo, np.zeros(4), rng.random(4), 2, 0.0, T)
+        picked, _ = OB.pick_out(f_lo, np.zeros(4), _gumbel(rng.random(4)), 2, 0.0, T)
         assert picked[0] != picked[1]
         cnt[frozenset(picked)] += 1
     for k, q in law.items():
@@ -79,7 +84,7 @@ def test_pick_low_temperature_takes_the_smallest_lower_bounds():
     f_lo = rng.permutation(40).astype(float)            # distinct, spaced by 1
     f_hi = rng.normal(size=40)
     n, eta = 12, 0.5
-    picked, _ = OB.pick_out(f_lo, f_hi, rng.random(40), n, eta, 1e-4)
+    picked, _ = OB.pick_out(f_lo, f_hi, _gumbel(rng.random(40)), n, eta, 1e-4)
     first = sorted(range(40), key=lambda i: (f_hi[i], i))[:6]
     assert list(picked[:6]) == first
     rest = [i for i in range(40) if i not in first]
@@ -88,7 +93,7 @@ def test_pick_low_temperature_takes_the_smallest_lower_bounds():
 
 def test_pick_is_invariant_to_affine_rescaling_of_lower_bounds():
     rng = np.random.default_rng(4)
-    f_lo, f_hi, u = rng.normal(size=30), rng.normal(size=30), rng.random(30)
+    f_lo, f_hi, u = rng.normal(size=30), rng.normal(size=30), _gumbel(rng.random(30))
     a, _ = OB.pick_out(f_lo, f_hi, u, 10, 0.3, 0.05)
     b, _ = OB.pick_out(3.0 * f_lo + 7.0, f_hi, u, 10, 0.3, 0.05)
     assert list(a) == list(b)
@@ -96,7 +101,7 @@ def test_pick_is_invariant_to_affine_rescaling_of_lower_bounds():
 
 def test_pick_puts_nonfinite_lower_bounds_last():
     f_lo = np.array([np.inf, 0.2, np.inf, 0.1, 0.3])
-    picked, rest = OB.pick_out(f_lo, np.zeros(5), np.full(5, 0.5), 4, 0.0, 0.05)
+    picked, rest = OB.pick_out(f_lo, np.zeros(5), np.zeros(5, np.float32), 4, 0.0, 0.05)
     assert set(picked[:3]) == {1, 3, 4} and picked[3] == 0 and list(rest) == [2]
 
 
@@ -149,7 +154,8 @@ def test_bab_loop_reaches_the_brute_force_minimum():
     G = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
     true_min = objective(G).min()
     best, ubest, trace, P = OB.bab_plan(objective, bound, lo, hi, n_pick=8, M=64, iters=12,
-                                        eta=0.75, T=0.05, w=5.0, uniforms=W.plan_uniforms())
+                                        eta=0.75, T=0.05, w=5.0, uniforms=W.plan_uniforms(),
+                                        gumbels=W.plan_gumbels())
     assert abs(objective(ubest[None])[0] - best) < 1e-9        # the best value is attained
     assert best <= true_min + 2e-3 * max(1.0, abs(true_min))
     # sound pruning: the surviving boxes still bound the minimum from below
@@ -179,7 +185,7 @@ def test_bab_loop_with_search_integrated_early_stop_bounding():
     G = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
     true_min = O.forward(net, G)[-1][:, 0].min()
     best, ub, trace, P = OB.bab_plan(lambda U: O.forward(net, U)[-1][:, 0], _early_stop_bound(net, 2),
-                                     lo, hi, 8, 64, 12, 0.75, 0.05, 5.0, W.plan_uniforms(),
+                                     lo, hi, 8, 64, 12, 0.75, 0.05, 5.0, W.plan_uniforms(), W.plan_gumbels(),
                                      bound_uses_samples=True)
     assert best <= true_min + 2e-3 * max(1.0, abs(true_min))
     assert np.all(P["f_lo"] <= P["f_hi"] + 1e-9)
@@ -272,8 +278,25 @@ def test_bab_loop_with_cem_search_reaches_the_brute_force_minimum():
     true_min = objective(G).min()
     best, ubest, trace, P = OB.bab_plan(objective, bound, lo, hi, n_pick=8, M=32, iters=12,
                                         eta=0.75, T=0.05, w=5.0, uniforms=W.plan_uniforms(),
-                                        cem=dict(rounds=3, n_elite=4, jitter=1e-3),
+                                        gumbels=W.plan_gumbels(), cem=dict(rounds=3, n_elite=4, jitter=1e-3),
                                         normals=W.plan_normals())
     assert abs(objective(ubest[None])[0] - best) < 1e-9
     assert best <= true_min + 2e-3 * max(1.0, abs(true_min))
     assert P["f_lo"].min() <= true_min + 1e-9
+
+
+def test_pick_fp32_keys_agree_with_fp64_softmax_draws_up_to_rounding():
+    """The FP32 keys of the pick-out give a valid Gumbel-top-k under keys formed in FP64:
+    every pick's FP64 score is within rounding of the best score left out."""
+    rng = np.random.default_rng(9)
+    N, n = 3000, 500
+    f_lo = rng.normal(size=N).astype(np.float32)
+    g = _gumbel(rng.random(N))
+    T = 0.05
+    picked, _ = OB.pick_out(f_lo, np.zeros(N, np.float32), g, n, 0.0, T)
+    f = f_lo.astype(np.float64)
+    score = -(f - f.min()) / (f.max() - f.min()) / T + g.astype(np.float64)
+    out = np.setdiff1d(np.arange(N), picked)
+    tol = 1e-5 * (1.0 + np.abs(score).max())
+    assert score[picked].min() >= score[out].max() - tol
+    assert np.all(np.diff(score[picked]) <= tol)          # in descending order of score

@@ -268,6 +268,21 @@ def plan_uniforms(seed=PLAN_SEED):
     return draw
 
 
+def plan_gumbels(seed=PLAN_SEED):
+    """gumbels(tag, shape): float32 standard Gumbel variates -log(-log U) for the
+    planning loop's pick-out, from the uniform streams of plan_uniforms (tag ('pick', t)),
+    formed in float64 before the cast."""
+    def draw(tag, shape):
+        kind, t = tag
+        if kind != "pick":
+            raise ValueError("Gumbel variates are drawn for the pick-out only")
+        rng = np.random.default_rng([seed, 1 + 2 * int(t) + 1])
+        u = np.clip(rng.random(shape, dtype=np.float64), 1e-300, 1.0)
+        return (-np.log(-np.log(u))).astype(np.float32)
+
+    return draw
+
+
 def plan_normals(seed=PLAN_SEED):
     """normals(tag, shape): float32 standard normals for the CEM rounds of the planning
     loop's search, one independent stream per tag (('cem0', r) for the root's round r,
