@@ -87,6 +87,9 @@ def main():
     ap.add_argument("--bab-iters", type=int, default=10,
                     help="iterations of the branch-and-bound planning loop timed after the "
                          "main measurement (0: skip)")
+    ap.add_argument("--no-recompute", action="store_true",
+                    help="skip the stored vs checkpointed comparison (profiling runs: the "
+                         "timed replays are then the last launches of every kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (a known-size kernel "
                          "for scaling the HBM traffic counters)")
@@ -210,7 +213,7 @@ def main():
     if plain is not None:
         plain["batched_speedup"] = value / plain["value"]
 
-    recompute = recompute_compare(bb, stream)
+    recompute = None if args.no_recompute else recompute_compare(bb, stream)
 
     others = None
     if not args.no_configs:
@@ -568,10 +571,12 @@ def bab_loop(iters, d=16, hidden=(256, 256, 256), n_pick=1024, samples=64, bound
     gn = torch.Generator(device="cuda").manual_seed(W.PLAN_SEED + 1)
     uni = lambda tag, shape: torch.rand(shape, device="cuda", generator=gu)
     nrm = lambda tag, shape: torch.randn(shape, device="cuda", generator=gn)
-    pl.run(2, uni, normals=nrm)                      # warm-up
+    # standard Gumbel variates: -log of a standard exponential
+    gum = lambda tag, shape: torch.empty(shape, device="cuda").exponential_(generator=gu).log_().neg_()
+    pl.run(2, uni, normals=nrm, gumbels=gum)         # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    best, _, P, log = pl.run(iters, uni, trace=True, normals=nrm)
+    best, _, P, log = pl.run(iters, uni, trace=True, normals=nrm, gumbels=gum)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     bounded = sum(2 * len(e["picked"]) for e in log)          # children searched and bounded

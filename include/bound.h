@@ -319,12 +319,14 @@ void bound_bab_destroy(bound_bab *bab);
  * n1 = floor(eta * n) (host double precision), picked[0 .. n1) are the n1 subdomains
  * with the smallest f_hi; picked[n1 .. n) are drawn without replacement from the
  * others with probability proportional to exp(-s_i / temperature), s_i = f_lo min-max
- * scaled over those others (0 if all equal), by the Gumbel-top-k rule: the n - n1
- * largest -s_i / T - log(-log u_i) (u clamped to [1e-30, 1 - 2^-24]); subdomains with
- * non-finite f_lo come last.  rest [n_dom - n] lists the others in ascending order.
- * f_lo, f_hi, u [n_dom]; temperature > 0; 0 <= eta <= 1; n_dom <= max_dom. */
+ * scaled over those others (0 if all equal), by the Gumbel-top-k rule on the supplied
+ * standard Gumbel variates g_i (-log(-log U) of uniforms U): in ascending order of the
+ * key s_i * fl(1 / temperature) - g_i, every operation rounded in FP32 (finite g;
+ * ties toward the lower index); subdomains with non-finite f_lo come last.  rest
+ * [n_dom - n] lists the others in ascending order.  f_lo, f_hi, g [n_dom];
+ * temperature > 0; 0 <= eta <= 1; n_dom <= max_dom. */
 bound_status bound_bab_pick_out(bound_bab *bab, int32_t n_dom, const float *f_lo,
-                                const float *f_hi, const float *u, int32_t n_pick, float eta,
+                                const float *f_hi, const float *g, int32_t n_pick, float eta,
                                 float temperature, int32_t *picked, int32_t *rest, void *stream);
 
 /* batch_search, sampling: samples[i, m, :] = lo[i] + (hi[i] - lo[i]) * U[i, m, :], each

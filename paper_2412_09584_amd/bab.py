@@ -7,9 +7,10 @@ split, sampling, search summary, best update and pruner run in libbound.so's ker
 rows by the index lists the kernels return.
 
 The objective is the scalar output of a ReLU network over an action box.  Random
-numbers are drawn by the caller's ``uniforms(tag, shape)`` (the same stream layout as
-the test oracle: 'search0', ('search', t), ('pick', t)) and, for the CEM search,
-``normals(tag, shape)`` (('cem0', r), ('cem', t, r)).
+numbers are supplied by the caller: ``uniforms(tag, shape)`` for the uniform search
+('search0', ('search', t)), ``gumbels(tag, shape)`` (standard Gumbel variates) for the
+pick-out (('pick', t)) and ``normals(tag, shape)`` for the CEM search (('cem0', r),
+('cem', t, r)) -- the stream layout of the test oracle.
 """
 from __future__ import annotations
 
@@ -162,7 +163,7 @@ class BaBPlanner:
         return torch.as_tensor(np.asarray(x, np.float32), device=self.device)
 
     # ------------------------------------------------------------------ the loop
-    def run(self, iters, uniforms, trace=False, normals=None):
+    def run(self, iters, uniforms, trace=False, normals=None, gumbels=None):
         """Returns (best value, its sample [d], candidate set dict, per-iteration trace)."""
         dev = self.device
         f_hi, top = self.search(self.lo0, self.hi0, self._rand(uniforms, normals, "search0", 1))
@@ -181,7 +182,9 @@ class BaBPlanner:
             n = min(self.n_pick, N)
             picked = torch.empty(n, dtype=torch.int32, device=dev)
             rest = torch.empty(max(N - n, 1), dtype=torch.int32, device=dev)
-            B.bound_bab_pick_out(self.bab, N, P["f_lo"], P["f_hi"], self._u(uniforms, ("pick", t), (N,)),
+            if gumbels is None:
+                raise ValueError("the pick-out needs gumbels(tag, shape)")
+            B.bound_bab_pick_out(self.bab, N, P["f_lo"], P["f_hi"], self._u(gumbels, ("pick", t), (N,)),
                                  self.n_pick, self.eta, self.T, picked, rest)
             rest = rest[: N - n]
             pl = P["lo"].index_select(0, picked).contiguous()

@@ -104,10 +104,12 @@ __global__ void k_minmax(int n, const float *f_lo, const uint8_t *avail, float *
     }
 }
 
-// Sort key of the softmax draw (ascending = pick first): -( -s/T + G(u) ) for available
-// subdomains with finite f_lo, FLT_MAX for non-finite f_lo, +inf for taken ones.
-__global__ void k_gumbel_keys(int n, const float *f_lo, const float *u, const uint8_t *avail,
+// Sort key of the softmax draw (ascending = pick first): s * fl(1/T) - g, each operation
+// rounded in FP32, for available subdomains with finite f_lo; FLT_MAX for non-finite
+// f_lo, +inf for taken ones.
+__global__ void k_gumbel_keys(int n, const float *f_lo, const float *gum, const uint8_t *avail,
                               const float *mm, float inv_t, float *keys, int32_t *vals) {
+#pragma clang fp contract(off)   // s * inv_t and the subtraction rounded separately
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     vals[i] = i;
@@ -122,9 +124,7 @@ __global__ void k_gumbel_keys(int n, const float *f_lo, const float *u, const ui
     }
     const float lo = mm[0], hi = mm[1];
     const float s = hi > lo ? (v - lo) / (hi - lo) : 0.f;
-    const float uc = fminf(fmaxf(u[i], 1e-30f), 1.0f - 5.9604645e-8f);
-    const float g = -logf(-logf(uc));
-    keys[i] = canon(s * inv_t - g);
+    keys[i] = canon(s * inv_t - gum[i]);
 }
 
 __global__ void k_samples(long total, int M, int d, const float *lo, const float *hi,
@@ -478,11 +478,11 @@ bound_status bound_bab_init(int32_t max_dom, int32_t dim, int32_t max_samples, b
 void bound_bab_destroy(bound_bab *b) { delete b; }
 
 bound_status bound_bab_pick_out(bound_bab *b, int32_t n_dom, const float *f_lo, const float *f_hi,
-                                const float *u, int32_t n_pick, float eta, float temperature,
+                                const float *g, int32_t n_pick, float eta, float temperature,
                                 int32_t *picked, int32_t *rest, void *stream) {
     if (!b || n_dom < 0 || n_dom > b->max_dom || n_pick < 0 || !(eta >= 0.f && eta <= 1.f) ||
         !(temperature > 0.f) || !(1.0f / temperature < FLT_MAX) ||
-        (n_dom > 0 && (!f_lo || !f_hi || !u || !picked || !rest)))
+        (n_dom > 0 && (!f_lo || !f_hi || !g || !picked || !rest)))
         return set_error(BOUND_E_ARG, "bound_bab_pick_out: bad arguments");
     if (n_dom == 0) return BOUND_OK;
     hipStream_t st = (hipStream_t)stream;
@@ -500,7 +500,7 @@ bound_status bound_bab_pick_out(bound_bab *b, int32_t n_dom, const float *f_lo, 
     if (n - n1 > 0) {
         hipLaunchKernelGGL(bp::k_minmax, dim3(1), dim3(bp::TPB), 0, st, n_dom, f_lo, b->flag, b->mm);
         hipLaunchKernelGGL(bp::k_gumbel_keys, dim3(bp::blocks(n_dom)), dim3(bp::TPB), 0, st, n_dom,
-                           f_lo, u, b->flag, b->mm, 1.0f / temperature, b->keys, b->vals);
+                           f_lo, g, b->flag, b->mm, 1.0f / temperature, b->keys, b->vals);
         BCHK(bp::sort_pairs(b, n_dom, st));
         hipLaunchKernelGGL(bp::k_take, dim3(bp::blocks(n - n1)), dim3(bp::TPB), 0, st, n - n1,
                            b->vals_out, picked, n1, b->flag);

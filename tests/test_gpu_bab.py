@@ -30,49 +30,32 @@ def dev(a, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
 
 
-def _scores(f_lo, u, avail, T):
-    """Oracle softmax-draw scores (float64) of the available subdomains."""
-    fin = avail & np.isfinite(f_lo)
-    lo, hi = f_lo[fin].min(), f_lo[fin].max()
-    s = (f_lo - lo) / (hi - lo) if hi > lo else np.zeros_like(f_lo)
-    uu = np.clip(u.astype(np.float64), 1e-30, 1 - 2.0 ** -24)
-    return np.where(fin, -s / T - np.log(-np.log(uu)), -np.inf)
-
-
 @pytest.mark.parametrize("N,n,eta,T", [(1, 4, 0.75, 0.05), (37, 10, 0.75, 0.05), (300, 64, 0.5, 0.05),
                                        (5000, 1024, 0.75, 0.05), (200, 200, 0.0, 1.0),
                                        (2000, 100, 1.0, 0.05)])
 def test_pick_out_matches_oracle(B, N, n, eta, T):
+    """Picked and rest index lists identical to the oracle's: both sides form the draw's
+    keys from the same Gumbel variates with the same FP32 operations."""
     rng = np.random.default_rng(N + n)
     f_lo = rng.normal(size=N).astype(np.float32)
     f_hi = rng.normal(size=N).astype(np.float32)
     if N > 10:
         f_hi[5] = f_hi[2]                      # a tie in the upper bounds
         f_lo[7] = np.inf                       # an infeasible subdomain
-    u = rng.random(N).astype(np.float32)
+        f_lo[9] = f_lo[8]                      # equal lower bounds ...
+    g = (-np.log(-np.log(rng.random(N)))).astype(np.float32)
+    if N > 10:
+        g[9] = g[8]                            # ... and equal variates: a key tie
     bab = B.bound_bab_init(max(N, 1), 2, 8)
     m = min(n, N)
     picked = torch.empty(m, dtype=torch.int32, device="cuda")
     rest = torch.empty(max(N - m, 1), dtype=torch.int32, device="cuda")
-    B.bound_bab_pick_out(bab, N, dev(f_lo), dev(f_hi), dev(u), n, eta, T, picked, rest)
+    B.bound_bab_pick_out(bab, N, dev(f_lo), dev(f_hi), dev(g), n, eta, T, picked, rest)
     torch.cuda.synchronize()
     gp, gr = picked.cpu().numpy(), rest.cpu().numpy()[: N - m]
-    op, orr = OB.pick_out(f_lo, f_hi, u, n, eta, T)
-    n1 = int(np.floor(eta * m))
-    assert list(gp[:n1]) == list(op[:n1])             # the sort by upper bound: exact
-    assert len(set(gp)) == m
-    # the softmax draws: the GPU's picks are the top scores up to FP32 rounding of the keys
-    avail = np.ones(N, bool)
-    avail[gp[:n1]] = False
-    sc = _scores(f_lo.astype(np.float64), u, avail, T)
-    fin_sel = [i for i in gp[n1:] if np.isfinite(f_lo[i])]
-    others = [i for i in range(N) if avail[i] and i not in set(gp[n1:])]
-    if fin_sel and others:
-        tol = 1e-5 * (1.0 + np.max(np.abs(sc[np.isfinite(sc)])))
-        assert min(sc[fin_sel]) >= max(sc[others]) - tol
-    agree = np.mean([a == b for a, b in zip(gp[n1:], op[n1:])]) if m > n1 else 1.0
-    assert agree >= 0.98, agree
-    assert sorted(gr) == sorted(set(range(N)) - set(gp)) and list(gr) == sorted(gr)
+    op, orr = OB.pick_out(f_lo, f_hi, g, n, eta, T)
+    assert list(gp) == list(op)
+    assert list(gr) == list(orr)
     B.bound_bab_destroy(bab)
 
 
@@ -138,7 +121,7 @@ def test_planning_loop_on_gpu_reaches_the_brute_force_minimum(B):
     G = np.stack(np.meshgrid(g, g, indexing="ij"), -1).reshape(-1, 2)
     true_min = O.forward(net, G)[-1][:, 0].min()
     pl = BaBPlanner(net, lo, hi, n_pick=8, samples=64, eta=0.75, temperature=0.05, w=5.0)
-    best, ub, P, log = pl.run(12, W.plan_uniforms(), trace=True)
+    best, ub, P, log = pl.run(12, W.plan_uniforms(), trace=True, gumbels=W.plan_gumbels())
     fu = O.forward(net, ub.cpu().numpy()[None].astype(np.float64))[-1][0, 0]
     assert abs(fu - best) <= 1e-5 * max(1.0, abs(best))          # the best value is attained
     assert best <= true_min + 2e-3 * max(1.0, abs(true_min))
@@ -148,7 +131,7 @@ def test_planning_loop_on_gpu_reaches_the_brute_force_minimum(B):
                               lambda a, b: np.array([O.crown(net, np.ones((1, 1)), a[i].astype(np.float64),
                                                              b[i].astype(np.float64))[1][0]
                                                      for i in range(a.shape[0])]),
-                              lo, hi, 8, 64, 12, 0.75, 0.05, 5.0, W.plan_uniforms())
+                              lo, hi, 8, 64, 12, 0.75, 0.05, 5.0, W.plan_uniforms(), W.plan_gumbels())
     assert abs(best - ob) <= 2e-3 * max(1.0, abs(ob))
 
 
@@ -156,8 +139,8 @@ def test_planning_loop_larger_objective(B):
     from paper_2412_09584_amd.bab import BaBPlanner
     net, lo, hi = W.plan_objective(d=8, hidden=(64, 64))
     pl = BaBPlanner(net, lo, hi, n_pick=64, samples=64)
-    best0, _, P0, _ = pl.run(0, W.plan_uniforms())
-    best, ub, P, log = pl.run(8, W.plan_uniforms(), trace=True)
+    best0, _, P0, _ = pl.run(0, W.plan_uniforms(), gumbels=W.plan_gumbels())
+    best, ub, P, log = pl.run(8, W.plan_uniforms(), trace=True, gumbels=W.plan_gumbels())
     assert best <= best0
     assert all(a["best"] >= b["best"] for a, b in zip(log, log[1:]))  # monotone
     # every kept box's lower bound is below the value of a random point inside it
@@ -179,7 +162,7 @@ def test_planning_loop_with_early_stop_bounding(B):
     true_min = O.forward(net, G)[-1][:, 0].min()
     pl = BaBPlanner(net, lo, hi, n_pick=8, samples=64, eta=0.75, temperature=0.05, w=5.0,
                     bounding="early_stop", stop_layer=2)
-    best, ub, P, log = pl.run(12, W.plan_uniforms(), trace=True)
+    best, ub, P, log = pl.run(12, W.plan_uniforms(), trace=True, gumbels=W.plan_gumbels())
     assert best <= true_min + 2e-3 * max(1.0, abs(true_min))
     f_lo, f_hi = P["f_lo"].cpu().numpy(), P["f_hi"].cpu().numpy()
     assert np.all(f_lo <= f_hi + 1e-4 * np.maximum(1.0, np.abs(f_hi)))
@@ -192,7 +175,8 @@ def test_planning_loop_with_early_stop_bounding(B):
         return np.array(out)
 
     ob, _, _, _ = OB.bab_plan(lambda U: O.forward(net, U)[-1][:, 0], bound, lo, hi, 8, 64, 12,
-                              0.75, 0.05, 5.0, W.plan_uniforms(), bound_uses_samples=True)
+                              0.75, 0.05, 5.0, W.plan_uniforms(), W.plan_gumbels(),
+                              bound_uses_samples=True)
     assert abs(best - ob) <= 2e-3 * max(1.0, abs(ob))
 
 
@@ -275,7 +259,8 @@ def test_planning_loop_with_cem_search(B, bounding):
     pl = BaBPlanner(net, lo, hi, n_pick=8, samples=32, eta=0.75, temperature=0.05, w=5.0,
                     bounding=bounding, stop_layer=2, search="cem", cem_rounds=3, n_elite=4,
                     jitter=1e-3)
-    best, ub, P, log = pl.run(12, W.plan_uniforms(), trace=True, normals=W.plan_normals())
+    best, ub, P, log = pl.run(12, W.plan_uniforms(), trace=True, normals=W.plan_normals(),
+                                  gumbels=W.plan_gumbels())
     fu = O.forward(net, ub.cpu().numpy()[None].astype(np.float64))[-1][0, 0]
     assert abs(fu - best) <= 1e-5 * max(1.0, abs(best))
     assert best <= true_min + 2e-3 * max(1.0, abs(true_min))
@@ -290,7 +275,7 @@ def test_planning_loop_with_cem_search(B, bounding):
                                                      O.sample_bounds(net, S[i].astype(np.float64)),
                                                      2, "relu")[0] for i in range(a.shape[0])])
     ob, _, _, _ = OB.bab_plan(lambda U: O.forward(net, U)[-1][:, 0], bound, lo, hi, 8, 32, 12,
-                              0.75, 0.05, 5.0, W.plan_uniforms(),
+                              0.75, 0.05, 5.0, W.plan_uniforms(), W.plan_gumbels(),
                               bound_uses_samples=bounding == "early_stop", cem=cem,
                               normals=W.plan_normals())
     assert abs(best - ob) <= 2e-3 * max(1.0, abs(ob))
