@@ -88,8 +88,9 @@ def main():
                     help="iterations of the branch-and-bound planning loop timed after the "
                          "main measurement (0: skip)")
     ap.add_argument("--no-recompute", action="store_true",
-                    help="skip the stored vs checkpointed comparison (profiling runs: the "
-                         "timed replays are then the last launches of every kernel)")
+                    help="skip the stored vs checkpointed and the atomic vs deterministic "
+                         "comparisons (profiling runs: the timed replays are then the last "
+                         "launches of every kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one plain 1 GiB device-to-device copy (a known-size kernel "
                          "for scaling the HBM traffic counters)")
@@ -214,6 +215,7 @@ def main():
         plain["batched_speedup"] = value / plain["value"]
 
     recompute = None if args.no_recompute else recompute_compare(bb, stream)
+    determinism = None if args.no_recompute else deterministic_compare(bb, stream)
 
     others = None
     if not args.no_configs:
@@ -251,6 +253,7 @@ def main():
            "tflops_step": tflops, "flop_per_subdomain": flop_unit,
            "roofline_frac_step": tflops * 1e12 / PEAK_FP32_MFMA, "wall_s": wall,
            "plain": plain, "roofline": roofline, "kernel_ms_per_step": breakdown,
+           "determinism": determinism,
            "autotune": plans, "checkpointed_recompute": recompute, "configs": others,
            "bab_loop": bab, "cpu_baseline": cpu}
     print(json.dumps(rec))
@@ -301,6 +304,41 @@ def recompute_compare(bb, stream, steps=5):
             "ms_per_step": ms, "subdomains_per_s": bb.n / (ms / 1e3),
             "saved_bytes_per_subdomain": 4.0 * bb.R * _saved_floats_per_row(bb.w.net, lo, hi, mode)}
     bb.recompute = False
+    bb.reset()
+    return out
+
+
+def deterministic_compare(bb, stream, steps=5):
+    """One optimisation step of the batch with the row sums formed without float atomics
+    (BOUND_OPT_DETERMINISTIC): time per step, and whether two passes from the same state
+    give bitwise the same bounds (with and without the mode)."""
+    import torch
+
+    from paper_2412_09584_amd import binding as B
+    out = {}
+    for det in (False, True):
+        B.bound_set_options(bb.bn.handle, B.BOUND_OPT_DETERMINISTIC if det else 0)
+        lows = []
+        for _ in range(2):
+            bb.reset()
+            bb.bound_and_grad(stream)
+            torch.cuda.synchronize()
+            lows.append(bb.lower.clone())
+        bb.reset()
+        bb.step(1, stream)
+        torch.cuda.synchronize()
+        e0, e1 = _ev(), _ev()
+        e0.record(stream)
+        for t in range(2, steps + 2):
+            bb.step(t, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out["deterministic" if det else "atomic"] = {
+            "ms_per_step": ms, "bitwise_repeat": bool(torch.equal(lows[0], lows[1])),
+            "max_rel_diff_between_repeats": float(((lows[0] - lows[1]).abs() /
+                                                    lows[1].abs().clamp_min(1.0)).max())}
+    B.bound_set_options(bb.bn.handle, 0)
     bb.reset()
     return out
 

@@ -263,7 +263,16 @@ bound_status bound_adam(int64_t n, float *param, const float *grad, float *m, fl
  * gradient it returns), waits for the count, and returns BOUND_E_NUMERIC naming the
  * product if there are any; the calls become synchronous.  Not applied while the stream
  * is being captured.  The environment variable BOUND_DEBUG=1 sets it at bound_init. */
-enum { BOUND_OPT_GEMM_ONLY = 1, BOUND_OPT_DIRECT_DMA = 2, BOUND_OPT_CHECK = 4 };
+/* BOUND_OPT_DETERMINISTIC: the row sums of the products (the bias and intercept terms
+ * of Theorem 1, the concretised bound of Theorem 2 and the rounding-allowance
+ * magnitudes) are formed without float atomics: every tile stores its partial sums in
+ * a slot of its own and the slots are added in a fixed order, so bound_backward's
+ * results are bitwise reproducible run to run (the gradient already is); slower.  The
+ * slots take max_rows x (output pixels x ceil(channels / 16), at most over the layers)
+ * x 8 bytes of device memory, allocated here on first use (BOUND_E_NOMEM if that
+ * fails). */
+enum { BOUND_OPT_GEMM_ONLY = 1, BOUND_OPT_DIRECT_DMA = 2, BOUND_OPT_CHECK = 4,
+       BOUND_OPT_DETERMINISTIC = 8 };
 bound_status bound_set_options(bound_net *net, int32_t options);
 
 /* Kernel autotuning: runs the given pass (and, if grad_lower is not NULL and the pass

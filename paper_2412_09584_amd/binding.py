@@ -20,6 +20,7 @@ BOUND_SAVE_FOR_GRAD, BOUND_NO_SLACK, BOUND_BOTH_SIDES, BOUND_RECOMPUTE = 1, 2, 4
 BOUND_OPT_GEMM_ONLY = 1
 BOUND_OPT_DIRECT_DMA = 2
 BOUND_OPT_CHECK = 4
+BOUND_OPT_DETERMINISTIC = 8
 BOUND_STOP_RELU, BOUND_STOP_LINEAR = 1, 2
 
 EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "bound_grad",

@@ -4,6 +4,7 @@
 #include "../../include/bound.h"
 #include "bound_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -72,6 +73,8 @@ struct bound_net {
     float *bsum = nullptr;           // [nnz][rows]: split-multiplier term per first entry
     long bsum_cap = 0;
     int32_t *dbg = nullptr;          // [2] NaN / Inf counts of the debug checks
+    float *det_part = nullptr;       // deterministic row-sum slots (BOUND_OPT_DETERMINISTIC)
+    long det_cap = 0;                // slots per img it holds
     int options = 0;
     // kernel plan per product (key: 'R'/'C'/'A' * 256 + layer), chosen by bound_autotune
     std::map<int, Plan> plans;
@@ -197,6 +200,29 @@ bound_status run_product(bound_net *net, hipStream_t st, int key, const GeomSet 
 }
 
 inline int pkey(char c, int m) { return ((int)c << 8) | m; }
+
+// Row-sum slots per img of the relaxation / concretisation product of layer m: its
+// output pixels (width / N) times ceil(N / 16) column groups, N the product's columns.
+long det_slots(const bound_net *net, int m) {
+    const int N = net->layers[m - 1].gT.g[0].N;
+    const long D = net->d[m - 1];
+    return N > 0 ? (D / N) * ((N + 15) / 16) : 1;
+}
+
+// With BOUND_OPT_DETERMINISTIC: the zeroed slots of the product of layer m for n_img imgs
+// (det.part stays null otherwise: float atomics).
+bound_status det_begin(bound_net *net, hipStream_t st, int m, long n_img, DetSums &det) {
+    det = DetSums{};
+    if (!(net->options & BOUND_OPT_DETERMINISTIC)) return BOUND_OK;
+    det.nslot = det_slots(net, m);
+    const int N = net->layers[m - 1].gT.g[0].N;
+    det.ncu = (N + 15) / 16;
+    if (!net->det_part || det.nslot > net->det_cap)
+        return fail(BOUND_E_STATE, "deterministic row sums: slots not allocated");
+    det.part = net->det_part;
+    HIPCHK(launch_fill(det.part, n_img * det.nslot * 2, 0.f, st));
+    return BOUND_OK;
+}
 
 // BOUND_OPT_CHECK: count the NaN / Inf values of n floats at p (a product's output) and
 // fail with BOUND_E_NUMERIC naming `what` if there are any.  Synchronises the stream;
@@ -705,13 +731,23 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             rp.rrpi = 1.0f / (float)rpi;
             rp.bsum = inject ? net->bsum : nullptr;   // split terms fused into the epilogue
             {
+                bound_status bs = det_begin(net, st, m, n_img, rp.det);
+                if (bs != BOUND_OK) return bs;
+            }
+            {
                 ProfScope ps(net, st, lbl("bwd_relax_L%d", m));
                 const GeomSet &gs = net->layers[m - 1].gT;
                 const float *A = cur;
                 bound_status bs = run_product(net, st, pkey('R', m), gs, [&](const Plan &pl) {
+                    if (rp.det.part) {   // a tuning re-run starts from zeroed slots too
+                        const hipError_t e = launch_fill(rp.det.part, n_img * rp.det.nslot * 2, 0.f, st);
+                        if (e != hipSuccess) return e;
+                    }
                     return gemm_relax(gs, A, n_img, rp, st, pl);
                 });
                 if (bs != BOUND_OK) return bs;
+                if (rp.det.part)
+                    HIPCHK(launch_det_reduce(n_img, rp.det.nslot, rp.det.part, rp.s, rp.mag, st));
             }
             {
                 bound_status bs = debug_check(net, st, nxt, n_img * net->d[m - 1], lbl("bwd_relax_L%d", m));
@@ -735,13 +771,23 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
             cp.chan = sl > 0 ? SL->C : net->C0;
             cp.hw = sl > 0 ? SL->HW : net->HW0;
             cp.img0 = img0; cp.rpi = rpi; cp.rrpi = 1.0f / (float)rpi;
-            ProfScope ps(net, st, lbl("bwd_conc_L%d", conc_m));
-            const GeomSet &gs = net->layers[conc_m - 1].gT;
-            const float *A = cur;
-            bound_status bs = run_product(net, st, pkey('C', conc_m), gs, [&](const Plan &pl) {
-                return gemm_conc(gs, A, n_img, cp, st, pl);
-            });
+            bound_status bs = det_begin(net, st, conc_m, n_img, cp.det);
             if (bs != BOUND_OK) return bs;
+            {
+                ProfScope ps(net, st, lbl("bwd_conc_L%d", conc_m));
+                const GeomSet &gs = net->layers[conc_m - 1].gT;
+                const float *A = cur;
+                bs = run_product(net, st, pkey('C', conc_m), gs, [&](const Plan &pl) {
+                    if (cp.det.part) {
+                        const hipError_t e = launch_fill(cp.det.part, n_img * cp.det.nslot * 2, 0.f, st);
+                        if (e != hipSuccess) return e;
+                    }
+                    return gemm_conc(gs, A, n_img, cp, st, pl);
+                });
+                if (bs != BOUND_OK) return bs;
+                if (cp.det.part)
+                    HIPCHK(launch_det_reduce(n_img, cp.det.nslot, cp.det.part, cp.low, cp.mag, st));
+            }
             bs = debug_check(net, st, net->acc_low, n_img, lbl("bwd_conc_L%d", conc_m));
             if (bs != BOUND_OK) return bs;
         }
@@ -1051,8 +1097,19 @@ int32_t bound_autotune_report(const bound_net *net, char *buf, int32_t cap) {
 }
 
 bound_status bound_set_options(bound_net *net, int32_t options) {
-    if (!net || (options & ~(BOUND_OPT_GEMM_ONLY | BOUND_OPT_DIRECT_DMA | BOUND_OPT_CHECK)))
+    if (!net || (options & ~(BOUND_OPT_GEMM_ONLY | BOUND_OPT_DIRECT_DMA | BOUND_OPT_CHECK |
+                             BOUND_OPT_DETERMINISTIC)))
         return fail(BOUND_E_ARG, "bound_set_options: bad arguments");
+    if ((options & BOUND_OPT_DETERMINISTIC) && !net->det_part) {
+        long cap = 1;
+        for (int m = 1; m <= net->n_layers; ++m)
+            cap = std::max(cap, det_slots(net, m));
+        float *p = nullptr;
+        if (!net->alloc(&p, net->max_rows * cap * 2))
+            return fail(BOUND_E_NOMEM, "bound_set_options: deterministic row-sum slots");
+        net->det_part = p;
+        net->det_cap = cap;
+    }
     net->options = options;
     return BOUND_OK;
 }

@@ -808,6 +808,36 @@ hipError_t launch_count_nonfinite(const float *p, long n, int32_t *cnt, hipStrea
     return hipGetLastError();
 }
 
+// One wave per img: lane l sums slots l, l + 64, ... in order, then a fixed xor tree.
+__global__ void k_det_reduce(long n_img, long nslot, const float *part, float *s, float *mag) {
+    const long img = (long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (img >= n_img) return;
+    const float *p = part + img * nslot * 2;
+    float a = 0.f, b = 0.f;
+    for (long k = lane; k < nslot; k += 64) {
+        a += p[2 * k];
+        b += p[2 * k + 1];
+    }
+#pragma unroll
+    for (int mk = 32; mk > 0; mk >>= 1) {
+        a += __shfl_xor(a, mk, 64);
+        b += __shfl_xor(b, mk, 64);
+    }
+    if (lane == 0) {
+        s[img] += a;
+        mag[img] += b;
+    }
+}
+
+hipError_t launch_det_reduce(long n_img, long nslot, const float *part, float *s, float *mag,
+                             hipStream_t st) {
+    if (n_img <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_det_reduce, dim3((unsigned)((n_img + 3) / 4)), dim3(256), 0, st, n_img,
+                       nslot, part, s, mag);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(float *p, long n, float v, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (n % 4 == 0 && ((uintptr_t)p & 15) == 0)

@@ -53,6 +53,16 @@ struct GeomSet {
 typedef float4 Relax;
 
 // ----- epilogue parameter blocks -----------------------------------------------------
+// Deterministic row sums: each tile's partial sums of a row go to their own slot
+// part[(img * nslot + dp * ncu + n0 / 16) * 2 + {0, 1}] (dp the destination pixel of the
+// tile's first row, n0 its first column, ncu = ceil(N / 16)) of a zeroed workspace, and
+// launch_det_reduce adds the slots to the accumulators in slot order.
+struct DetSums {
+    float *part;
+    long nslot;
+    int ncu;
+};
+
 struct RelaxParams {       // G_m = Lambda_m W_m  ->  Lambda_{m-1} = relax(G_m)
     float *out;            // Lambda_{m-1}  [img][D]
     float *save;           // G_m kept for the gradient (nullable): per img, the unstable
@@ -68,6 +78,7 @@ struct RelaxParams {       // G_m = Lambda_m W_m  ->  Lambda_{m-1} = relax(G_m)
     float rrpi;            // fl(1 / rpi)
     const float *bsum;     // [nnz][rpi] split-multiplier term per first split entry and
                            // row, subtracted at the split neuron (nullable: no beta)
+    DetSums det;           // deterministic row sums (det.part null: float atomics)
 };
 
 struct ConcParams {        // G_1 = Lambda_1 W_1  ->  concretise over the box
@@ -80,6 +91,7 @@ struct ConcParams {        // G_1 = Lambda_1 W_1  ->  concretise over the box
     long img0;
     int rpi;
     float rrpi;
+    DetSums det;
 };
 
 struct AdjParams {         // Lambda_bar_m = G_bar_m W_m^T + s_bar b_m  -> G_bar_{m+1}
@@ -176,6 +188,10 @@ __host__ __device__ inline int prep_tiles(const LayerShape &L) {
 }
 
 hipError_t launch_fill(float *p, long n, float v, hipStream_t st);
+// deterministic row sums: s[img] += the slots' first values, mag[img] += their second
+// values, each summed in slot order (one wave per img, a fixed shuffle tree)
+hipError_t launch_det_reduce(long n_img, long nslot, const float *part, float *s, float *mag,
+                             hipStream_t st);
 // cnt[0] += NaN count, cnt[1] += Inf count of p[0 .. n) (debug checks)
 hipError_t launch_count_nonfinite(const float *p, long n, int32_t *cnt, hipStream_t st);
 hipError_t launch_prep_tables(const NetShapes &ns, int n_layers_used, int n_inst,

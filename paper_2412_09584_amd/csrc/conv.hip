@@ -594,8 +594,8 @@ __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvT
     }
     const long img = img0 + gi;
     float r0 = 0.f, r1 = 0.f;
+    const int dpix = ((oyb + py) * g.ostr + g.oy0) * g.DW + (px * g.ostr + g.ox0);
     if (img < n_img) {
-        const int dpix = ((oyb + py) * g.ostr + g.oy0) * g.DW + (px * g.ostr + g.ox0);
         const auto rc = epi.row((int)img);
         typename Epi::Pre pre[NMAX];
 #pragma unroll
@@ -614,12 +614,9 @@ __global__ __launch_bounds__(256) void k_conv_valu(const GeomSet gs, const ConvT
         const int wave = tid >> 6;
         const int gf = qdiv(wave * 64, ct.rTP), gl = qdiv(wave * 64 + 63, ct.rTP);
         if (gf == gl) {
-            if (img0 + gf < n_img) reduce_wave_atomic(r0, r1, img0 + gf, lane, epi.red0(), epi.red1());
+            if (img0 + gf < n_img) reduce_wave(epi, r0, r1, img0 + gf, dpix, 0, lane);
         } else {
-            if (img < n_img) {
-                atomicAdd(epi.red0() + img, r0);
-                atomicAdd(epi.red1() + img, r1);
-            }
+            if (img < n_img) put_row_sums(epi, img, dpix, 0, r0, r1);
         }
     }
 }

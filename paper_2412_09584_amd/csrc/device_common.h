@@ -108,6 +108,7 @@ struct EpiRelax {
     __device__ float colv(int n) const { return p.bias[n % p.chan]; }
     __device__ float *red0() const { return p.s; }
     __device__ float *red1() const { return p.mag; }
+    __device__ const DetSums *det() const { return &p.det; }
     __device__ Pre pre(const Row &rc, int j) const { return at(rc.tb, j); }
     __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &t, const Row &rc, int, int, int j, float bcol, float g,
@@ -145,6 +146,7 @@ struct EpiConc {
     __device__ float colv(int) const { return 0.f; }
     __device__ float *red0() const { return p.low; }
     __device__ float *red1() const { return p.mag; }
+    __device__ const DetSums *det() const { return &p.det; }
     __device__ Pre pre(const Row &rc, int j) const { return make_float2(at(rc.cen, j), at(rc.rad, j)); }
     __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &cr, const Row &rc, int dpix, int n, int j, float, float g,
@@ -171,6 +173,7 @@ struct EpiAdj {
     __device__ float colv(int n) const { return p.bias[n]; }
     __device__ float *red0() const { return nullptr; }
     __device__ float *red1() const { return nullptr; }
+    __device__ const DetSums *det() const { return nullptr; }
     // G is saved at the unstable neurons only (slot w - 1), a load that depends on the
     // record: pre() fetches the record, pre2() the saved coefficient.  Elsewhere x = y
     // and z = 0, so the sign of G does not matter.
@@ -203,6 +206,7 @@ struct EpiFwd {
     __device__ float colv(int n) const { return p.bias[n]; }
     __device__ float *red0() const { return nullptr; }
     __device__ float *red1() const { return nullptr; }
+    __device__ const DetSums *det() const { return nullptr; }
     __device__ Pre pre(const Row &, int) const { return Pre{}; }
     __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &, const Row &rc, int, int, int j, float bcol, float acc,
@@ -211,33 +215,46 @@ struct EpiFwd {
     }
 };
 
+// One row sum pair of a tile: a float atomic per accumulator, or with deterministic sums
+// a store to the tile's own slot (dp: destination pixel of the tile's first row, n0: its
+// first column).
+template <class Epi>
+__device__ inline void put_row_sums(const Epi &epi, long img, int dp, int n0, float r0, float r1) {
+    const DetSums *d = epi.det();
+    if (d && d->part) {
+        float *q = d->part + (img * d->nslot + (long)dp * d->ncu + (n0 >> 4)) * 2;
+        q[0] = r0;
+        q[1] = r1;
+    } else {
+        atomicAdd(epi.red0() + img, r0);
+        atomicAdd(epi.red1() + img, r1);
+    }
+}
+
 // Sum of r0 / r1 over the lanes that hold the same output row (they differ only in the
-// column bits of the lane id), then one atomic per row from the column-0 lane.
-template <int MF>
-__device__ inline void reduce_row_atomic(float r0, float r1, int img, int lane, float *red0,
-                                         float *red1) {
+// column bits of the lane id), then one sum pair per row from the column-0 lane.
+template <int MF, class Epi>
+__device__ inline void reduce_row(const Epi &epi, float r0, float r1, int img, int dp, int n0,
+                                  int lane) {
 #pragma unroll
     for (int mk = 1; mk < MF; mk <<= 1) {
         r0 += __shfl_xor(r0, mk, 64);
         r1 += __shfl_xor(r1, mk, 64);
     }
-    if ((lane & (MF - 1)) == 0 && img >= 0) {
-        atomicAdd(red0 + img, r0);
-        atomicAdd(red1 + img, r1);
-    }
+    if ((lane & (MF - 1)) == 0 && img >= 0) put_row_sums(epi, img, dp, n0, r0, r1);
 }
 
-__device__ inline void reduce_wave_atomic(float u0, float u1, long img, int lane, float *red0,
-                                          float *red1) {
+// The sums of a whole wave (one img), then one pair from lane 0 (which holds the wave's
+// first row and its tile's first column).
+template <class Epi>
+__device__ inline void reduce_wave(const Epi &epi, float u0, float u1, long img, int dp, int n0,
+                                   int lane) {
 #pragma unroll
     for (int mk = 1; mk < 64; mk <<= 1) {
         u0 += __shfl_xor(u0, mk, 64);
         u1 += __shfl_xor(u1, mk, 64);
     }
-    if (lane == 0) {
-        atomicAdd(red0 + img, u0);
-        atomicAdd(red1 + img, u1);
-    }
+    if (lane == 0) put_row_sums(epi, img, dp, n0, u0, u1);
 }
 
 // Epilogue of one wave's accumulator tile.  The accumulator rows of a lane come in
@@ -293,6 +310,7 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
         PreG preA, preB;
         load1(0, dpA, preA);
         load2(preA);
+        const int dp0 = dpA[0];           // lane 0: the wave's first row
         if (DEPTH == 2 && NG > 1) load1(1, dpB, preB);
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
@@ -319,7 +337,7 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
             if (g + 1 < NG) copy(dpA, preA, dpB, preB);
             if (DEPTH == 2 && g + 2 < NG) copy(dpB, preB, dpC, preC);
         }
-        if (NR > 0) reduce_wave_atomic(u0, u1, uimg, lane, epi.red0(), epi.red1());
+        if (NR > 0) reduce_wave(epi, u0, u1, uimg, dp0, ncol[0], lane);
         return;
     }
     if (LEAN) {
@@ -345,7 +363,7 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
                                          acc[i][j][vg * 4 + q], r0, r1);
                             }
                     }
-                    if (NR > 0) reduce_row_atomic<MF>(r0, r1, img[q], lane, epi.red0(), epi.red1());
+                    if (NR > 0) reduce_row<MF>(epi, r0, r1, img[q], dp[q], ncol[0], lane);
                 }
             }
         }
@@ -392,11 +410,10 @@ __device__ inline void tile_epilogue_impl(const Epi &epi, Acc (&acc)[FM][FN], co
             if (NR > 0 && !FAST) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
-                    reduce_row_atomic<MF>(r0[q], r1[q], img[q], lane, epi.red0(), epi.red1());
+                    reduce_row<MF>(epi, r0[q], r1[q], img[q], dp[q], ncol[0], lane);
             }
         }
     }
-    if (NR > 0 && FAST) reduce_wave_atomic(u0, u1, uimg, lane, epi.red0(), epi.red1());
 }
 
 // fast: see tile_epilogue_impl (wave-uniform).
