@@ -299,9 +299,10 @@ def bound_bab_destroy(handle):
         lib().bound_bab_destroy(handle)
 
 
-def bound_bab_pick_out(handle, n_dom, f_lo, f_hi, u, n_pick, eta, temperature, picked, rest,
+def bound_bab_pick_out(handle, n_dom, f_lo, f_hi, g, n_pick, eta, temperature, picked, rest,
                        stream=None):
-    _check(lib().bound_bab_pick_out(handle, int(n_dom), _ptr(f_lo), _ptr(f_hi), _ptr(u),
+    """g: standard Gumbel variates [n_dom] (the draw's random input)."""
+    _check(lib().bound_bab_pick_out(handle, int(n_dom), _ptr(f_lo), _ptr(f_hi), _ptr(g),
                                     int(n_pick), float(eta), float(temperature), _ptr(picked),
                                     _ptr(rest), _stream(stream)))
 
