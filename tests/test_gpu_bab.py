@@ -180,16 +180,18 @@ def test_planning_loop_with_early_stop_bounding(B):
     assert abs(best - ob) <= 2e-3 * max(1.0, abs(ob))
 
 
-def test_cem_steps_match_oracle(B):
+@pytest.mark.parametrize("n,M,d,R", [(64, 48, 5, 3), (512, 640, 16, 3), (6, 2048, 2, 1)])
+def test_cem_steps_match_oracle(B, n, M, d, R):
     """CEM start and round samples bit-exact (FP32 steps), the refit's elites exact (one
     elite: the argmin sample itself, ties to the lower index) and its moments within FP32
-    summation error of the FP64 oracle; the archives hold the round's slice."""
-    rng = np.random.default_rng(11)
-    n, M, d, R = 64, 48, 5, 3
+    summation error of the FP64 oracle; the archives hold the round's slice.  Sizes up to
+    the largest per-box sort (2048 samples)."""
+    rng = np.random.default_rng(11 + n)
     lo = rng.uniform(-2, 0, size=(n, d)).astype(np.float32)
     hi = (lo + rng.uniform(0.01, 2, size=(n, d))).astype(np.float32)
     par = (lo[0::2] + (hi[0::2] - lo[0::2]) * rng.random((n // 2, d))).astype(np.float32)
-    par[3] = hi[7] + 1.0                                   # outside both children: centres
+    if n // 2 > 3:
+        par[3] = hi[7] + 1.0                               # outside both children: centres
     bab = B.bound_bab_init(4 * n, d, R * M)
     mu, sg = torch.empty(n, d, device="cuda"), torch.empty(n, d, device="cuda")
     B.bound_bab_cem_start(bab, n, dev(lo), dev(hi), dev(par), 2, mu, sg)
@@ -200,16 +202,18 @@ def test_cem_steps_match_oracle(B):
     Z = (3.0 * rng.standard_normal((n, M, d))).astype(np.float32)   # many clipped samples
     S = torch.empty(n, M, d, device="cuda")
     S_all = torch.full((n, R * M, d), float("nan"), device="cuda")
-    B.bound_bab_cem_samples(bab, n, M, dev(lo), dev(hi), dev(omu), dev(osg), dev(Z), S, S_all, R * M, M)
+    sA, sV = min(1, R - 1), R - 1              # archive slices written by the calls below
+    B.bound_bab_cem_samples(bab, n, M, dev(lo), dev(hi), dev(omu), dev(osg), dev(Z), S, S_all,
+                            R * M, sA * M)
     oS = OB.cem_samples(lo, hi, omu, osg, Z)
     assert np.array_equal(S.cpu().numpy(), oS)
-    assert np.array_equal(S_all[:, M:2 * M].cpu().numpy(), oS)
-    assert torch.isnan(S_all[:, :M]).all() and torch.isnan(S_all[:, 2 * M:]).all()
+    assert np.array_equal(S_all[:, sA * M:(sA + 1) * M].cpu().numpy(), oS)
+    assert torch.isnan(S_all[:, :sA * M]).all() and torch.isnan(S_all[:, (sA + 1) * M:]).all()
     vals = rng.integers(0, 6, size=(n, M)).astype(np.float32)       # many ties
-    vals[5, 0] = np.nan
+    vals[n - 1, 0] = np.nan
     V_all = torch.full((n, R * M), float("nan"), device="cuda")
-    for E, jit in ((1, 0.0), (7, 1e-3), (M, 0.0)):
-        B.bound_bab_cem_refit(bab, n, M, dev(vals), S, E, jit, mu, sg, V_all, R * M, 2 * M)
+    for E, jit in ((1, 0.0), (min(7, M), 1e-3), (M, 0.0)):
+        B.bound_bab_cem_refit(bab, n, M, dev(vals), S, E, jit, mu, sg, V_all, R * M, sV * M)
         rmu, rsg = OB.cem_refit(vals, oS, E, jit)
         gmu, gsg = mu.cpu().numpy(), sg.cpu().numpy()
         if E == 1:
@@ -218,12 +222,13 @@ def test_cem_steps_match_oracle(B):
         scale = np.maximum(np.abs(lo), np.abs(hi))
         assert np.all(np.abs(gmu - rmu) <= 4 * E * 2.0 ** -24 * scale), f"mu, {E} elites"
         assert np.all(np.abs(gsg - rsg) <= 1e-5 * scale), f"sigma, {E} elites"
-    assert np.array_equal(V_all[:, 2 * M:].cpu().numpy(), vals, equal_nan=True)
-    assert torch.isnan(V_all[:, :2 * M]).all()
+    assert np.array_equal(V_all[:, sV * M:].cpu().numpy(), vals, equal_nan=True)
+    assert torch.isnan(V_all[:, :sV * M]).all()
     with pytest.raises(B.BoundError):
         B.bound_bab_cem_refit(bab, n, M, dev(vals), S, M + 1, 0.0, mu, sg)   # n_elite > M
     with pytest.raises(B.BoundError):
-        B.bound_bab_cem_samples(bab, n, M, dev(lo), dev(hi), mu, sg, dev(Z), S, S_all, R * M, 2 * M + 1)
+        B.bound_bab_cem_samples(bab, n, M, dev(lo), dev(hi), mu, sg, dev(Z), S, S_all, R * M,
+                                (R - 1) * M + 1)
     B.bound_bab_destroy(bab)
 
 

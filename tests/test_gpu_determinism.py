@@ -9,6 +9,8 @@ float atomics.
     stage-wise (1e-4 relative); the gradient equals the atomic mode's.
   * On a 512-subdomain slice of the bench's batch with autotuned plans: two bound and
     gradient steps give bitwise the same lower bounds and gradients.
+  * Under HIP-graph capture: every replay of the whole optimisation equals the eager run
+    bit for bit.
 """
 import numpy as np
 import pytest
@@ -125,3 +127,36 @@ def test_deterministic_bench_slice_repeats_bitwise(mod):
     bb.reset()
     bb.bound_and_grad()
     close(np_(out[0][0]), np_(bb.lower), 1e-5, "lower: deterministic vs atomic")
+
+
+def test_deterministic_graph_replays_equal_the_eager_run_bitwise(mod):
+    """The whole alpha / beta optimisation captured as one HIP graph with deterministic
+    row sums: every replay's best bounds and final alpha / beta equal the eager run's
+    bit for bit (with float atomics only the bounds' rounding could differ)."""
+    N, B = mod
+    net = NETS["cnn_direct"]()
+    n_roots, per_root = 2, 6
+    n = n_roots * per_root
+    x0 = W.uniform_inputs(n_roots, W.in_dim(net), 181)
+    x_lo, x_hi = W.linf_box(x0, 0.05)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    root_of = np.repeat(np.arange(n_roots), per_root).astype(np.int32)
+    bn = N.BoundNet(net, n, 4096, 4096)
+    B.bound_set_options(bn.handle, B.BOUND_OPT_DETERMINISTIC)
+    lo, hi = bn.crown_bounds(x_lo, x_hi)
+    lo_np, hi_np = np_(lo), np_(hi)
+    cands = [np.nonzero((lo_np[r] < 0) & (hi_np[r] > 0))[0] for r in range(n_roots)]
+    sp = W.random_splits(cands, n, 1, 6, seed=182, root_of=root_of)
+    opt = N.AlphaBetaOptimizer(bn, C[root_of], lo, hi, x_lo[root_of], x_hi[root_of],
+                               bound_of=dev(root_of, torch.int32), splits=N.splits_to_device(sp),
+                               steps=5)
+    best_e = opt.run().clone()
+    alpha_e, beta_e = opt.alpha.clone(), opt.beta.clone()
+    opt.capture()
+    for rep in range(2):
+        torch.randn(256, 256, device="cuda").sum()          # eager work between replays
+        torch.cuda.synchronize()
+        best_g = opt.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(best_g, best_e), f"replay {rep}: best"
+        assert torch.equal(opt.alpha, alpha_e) and torch.equal(opt.beta, beta_e), f"replay {rep}"
