@@ -588,7 +588,40 @@ def planning_unrolled(n=256, n_opt=64, samples=64, steps=2, stops=(77, 65, 41)):
     out["optimised_intermediate"] = {"subdomains_per_s": n_opt / (ms / 1e3), "ms": ms,
                                      "subdomains": n_opt, "adam_steps_per_layer": steps,
                                      **stats(opt())}
+    del bo
+    out["planning_loop"] = bab_loop_unrolled(uw)
     return out
+
+
+def bab_loop_unrolled(uw, iters=10, n_pick=256, samples=64, rounds=3, n_elite=8, stop=77):
+    """The paper's planning method on the unrolled chain: branch and bound over the action
+    box with the CEM search, search-integrated bounds and the objective's pass stopped at
+    ReLU layer `stop`; random numbers drawn on the device."""
+    import torch
+
+    import workloads as W
+    from paper_2412_09584_amd.bab import BaBPlanner
+    pl = BaBPlanner(uw.net, uw.u_lo, uw.u_hi, n_pick=n_pick, samples=samples,
+                    bounding="early_stop", stop_layer=stop, search="cem", cem_rounds=rounds,
+                    n_elite=n_elite)
+    gu = torch.Generator(device="cuda").manual_seed(W.PLAN_SEED)
+    gn = torch.Generator(device="cuda").manual_seed(W.PLAN_SEED + 1)
+    uni = lambda tag, shape: torch.rand(shape, device="cuda", generator=gu)
+    nrm = lambda tag, shape: torch.randn(shape, device="cuda", generator=gn)
+    gum = lambda tag, shape: torch.empty(shape, device="cuda").exponential_(generator=gu).log_().neg_()
+    root_best, _, _, _ = pl.run(0, uni, normals=nrm, gumbels=gum)
+    pl.run(1, uni, normals=nrm, gumbels=gum)        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best, _, P, log = pl.run(iters, uni, trace=True, normals=nrm, gumbels=gum)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    bounded = sum(2 * len(e["picked"]) for e in log)
+    return {"search": f"cem {rounds} rounds x {samples} samples, {n_elite} elites",
+            "bounding": f"search-integrated bounds, early stop at ReLU {stop}",
+            "n_pick": n_pick, "iters": len(log), "ms_per_iter": 1e3 * dt / max(len(log), 1),
+            "subdomains_bounded_per_s": bounded / dt if log else None,
+            "root_search_best": root_best, "best": best, "candidates": int(P["lo"].shape[0])}
 
 
 def bab_loop(iters, d=16, hidden=(256, 256, 256), n_pick=1024, samples=64, bounding="crown",
