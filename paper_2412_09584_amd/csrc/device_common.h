@@ -74,10 +74,25 @@ __device__ inline long ldiv64(long n, double rd) { return (long)(((double)n + 0.
 
 // Element i of one img's row segment starting at base.  Every epilogue offset stays inside
 // such a segment (i * sizeof(T) < 2^32, layer widths are validated on the host), so the
-// byte offset is formed in 32 bits; with a wave-uniform base the load or store then
-// takes the scalar-base address form and needs no 64-bit address arithmetic per element.
-template <class T> __device__ inline T &at(T *base, int i) {
-    return *(T *)((const char *)base + (unsigned)i * (unsigned)sizeof(T));
+// byte offset is formed in 32 bits; the access goes through a global-address-space
+// pointer, so that with a wave-uniform base it takes the scalar-base global form (a
+// generic pointer that the compiler cannot place would give a flat access with 64-bit
+// address arithmetic per element).
+template <class T> __device__ inline T ld(const T *base, int i) {
+    using G = const __attribute__((address_space(1))) T;
+    return *(G *)((const char *)base + (unsigned)i * (unsigned)sizeof(T));
+}
+// float4 records through the compiler's native vector type (HIP's float4 class has no
+// copy from another address space)
+__device__ inline float4 ld(const float4 *base, int i) {
+    using V = float __attribute__((ext_vector_type(4)));
+    using G = const __attribute__((address_space(1))) V;
+    const V v = *(G *)((const char *)base + (unsigned)i * 16u);
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+template <class T> __device__ inline void st(T *base, int i, T v) {
+    using G = __attribute__((address_space(1))) T;
+    *(G *)((char *)base + (unsigned)i * (unsigned)sizeof(T)) = v;
 }
 
 // ---------------------------------------------------------------------- epilogues
@@ -109,7 +124,7 @@ struct EpiRelax {
     __device__ float *red0() const { return p.s; }
     __device__ float *red1() const { return p.mag; }
     __device__ const DetSums *det() const { return &p.det; }
-    __device__ Pre pre(const Row &rc, int j) const { return at(rc.tb, j); }
+    __device__ Pre pre(const Row &rc, int j) const { return ld(rc.tb, j); }
     __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &t, const Row &rc, int, int, int j, float bcol, float g,
                          float &r0, float &r1) const {
@@ -127,8 +142,8 @@ struct EpiRelax {
         // the sums are formed in order; without this the compiler defers them past the
         // tile's stores and keeps every lam and offset of the tile live in registers
         asm volatile("" : "+v"(r0), "+v"(r1));
-        at(rc.out, j) = lam;
-        if (rc.save && t.w > 0.f) at(rc.save, (int)t.w - 1) = g;    // unstable: compact slot
+        st(rc.out, j, lam);
+        if (rc.save && t.w > 0.f) st(rc.save, (int)t.w - 1, g);    // unstable: compact slot
     }
 };
 
@@ -147,15 +162,15 @@ struct EpiConc {
     __device__ float *red0() const { return p.low; }
     __device__ float *red1() const { return p.mag; }
     __device__ const DetSums *det() const { return &p.det; }
-    __device__ Pre pre(const Row &rc, int j) const { return make_float2(at(rc.cen, j), at(rc.rad, j)); }
+    __device__ Pre pre(const Row &rc, int j) const { return make_float2(ld(rc.cen, j), ld(rc.rad, j)); }
     __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &cr, const Row &rc, int dpix, int n, int j, float, float g,
                          float &r0, float &r1) const {
         r0 += g * cr.x - fabsf(g) * cr.y;
         r1 += fabsf(g) * (fabsf(cr.x) + cr.y);
         asm volatile("" : "+v"(r0), "+v"(r1));   // in order, as in EpiRelax
-        if (rc.save) at(rc.save, j) = g;
-        if (rc.emit) at(rc.emit, n * p.hw + dpix) = g;
+        if (rc.save) st(rc.save, j, g);
+        if (rc.emit) st(rc.emit, n * p.hw + dpix, g);
     }
 };
 
@@ -177,19 +192,19 @@ struct EpiAdj {
     // G is saved at the unstable neurons only (slot w - 1), a load that depends on the
     // record: pre() fetches the record, pre2() the saved coefficient.  Elsewhere x = y
     // and z = 0, so the sign of G does not matter.
-    __device__ Pre pre(const Row &rc, int j) const { return Pre{at(rc.tb, j), 0.f}; }
+    __device__ Pre pre(const Row &rc, int j) const { return Pre{ld(rc.tb, j), 0.f}; }
     __device__ void pre2(const Row &rc, Pre &q) const {
-        if (q.t.w > 0.f) q.g = at(rc.gs, (int)q.t.w - 1);
+        if (q.t.w > 0.f) q.g = ld(rc.gs, (int)q.t.w - 1);
     }
     __device__ void post(const Pre &q, const Row &rc, int dpix, int n, int j, float bcol, float acc,
                          float &, float &) const {
         const float v = acc + rc.sb * bcol;           // Lambda_bar_m[img, j]
         const float g = q.g;                          // G_{m+1}[img, j]
         const Relax &t = q.t;
-        if (rc.go) at(rc.go, j) = v * (g >= 0.f ? t.x : t.y) + (g < 0.f ? rc.sb * t.z : 0.f);
+        if (rc.go) st(rc.go, j, v * (g >= 0.f ? t.x : t.y) + (g < 0.f ? rc.sb * t.z : 0.f));
         // alpha-gradient contribution of this row at the neuron's slot (summed over the
         // instance's rows by k_alpha_grad)
-        if (t.w > 0.f) at(rc.gc, (int)t.w - 1) = g >= 0.f ? g * v : 0.f;
+        if (t.w > 0.f) st(rc.gc, (int)t.w - 1, g >= 0.f ? g * v : 0.f);
         // split neuron (first entry q of the instance's list): d lower / d beta_{q,r} =
         // -sign_q * Lambda_bar, sign_q carried in the sign bit of the record's z
         if (t.w < 0.f && rc.gb) rc.gb[(long)(-(int)t.w - 1) * p.rpi] = signbit(t.z) ? v : -v;
@@ -211,7 +226,7 @@ struct EpiFwd {
     __device__ void pre2(const Row &, Pre &) const {}
     __device__ void post(const Pre &, const Row &rc, int, int, int j, float bcol, float acc,
                          float &, float &) const {
-        at(rc.out, j) = acc + bcol;
+        st(rc.out, j, acc + bcol);
     }
 };
 
