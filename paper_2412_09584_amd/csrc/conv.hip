@@ -39,6 +39,7 @@ struct ConvTile {
     // digits of a 256-slot step of the input tile (channel quad, pixel column, row, image)
     // and of the weight tile (k quad, output row), each below its radix but the last
     int dC4, dIX, dIY, dGI, dK4, dN;
+    int rowdma;    // DMA staging of the input tile by rows (else by 256-slot steps)
 };
 
 // Stage the input tile (channels [c0, c0+CC)) of images img0.. into LDS, zero outside.
@@ -247,13 +248,34 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     // past the chunk) are written once, padding columns never, and slots past the last
     // image of a partial group read out of range of the buffer (no access) and feed only
     // rows the epilogue drops.
+    //
+    // With ct.rowdma (LDS rows of 64 slots or more) the input tile goes by rows instead:
+    // LDS row r = gi * IH + iy (the IW * spp slots of input row iy0 + iy of image gi) is
+    // fetched as 64-slot segments, one DMA instruction each.  A lane's source offset
+    // inside a row is then the same for every row, image and chunk and the row's offset
+    // is wave-uniform, so the per-slot index arithmetic of the set-up goes away; the tile
+    // is zeroed once, and rows of spatial padding or of images past the batch are never
+    // fetched.
     const int c4s = VEC ? ct.lcc - 2 : 0;             // log2(CC / 4)
     const int Pin = ct.IW << c4s, Rin = ct.G * ct.IH;  // input grid [G*IH][IW*CC/4]
     const int Pw = ct.KB >> 2;                         // weight grid [BN][KB/4]
     const float *Xb = X + img0 * (long)g.H * g.W * g.C;
     const float *Bb = g.Bt + (long)n0 * g.Kp;
     int gin[NIN], lin[NIN], gw[NW], lw[NW];
-    if (VEC && DMA) {
+    if (VEC && DMA && ct.rowdma) {
+        // segment q of a row: slot q * 64 + lane -> pixel column ix, channel quad c4
+        // (spp = CS / 4 slots per pixel, a power of two); -1: nothing to fetch
+        const int lsp = ct.lcc - 2, rs = ct.IW << lsp;
+#pragma unroll
+        for (int q = 0; q < NIN / 4; ++q) {
+            const int sl = q * 64 + lane;
+            const int x = ix0 + (sl >> lsp), c4 = sl & ((1 << lsp) - 1);
+            gin[q] = sl < rs && (unsigned)x < (unsigned)g.W ? (x * g.C + 4 * c4) * 4 : -1;
+        }
+        for (int e = tid; e < (ct.in_floats >> 2); e += 256)
+            *(float4 *)(In + 4 * e) = make_float4(0.f, 0.f, 0.f, 0.f);
+        __syncthreads();   // the zeros land before any DMA write to the same slots
+    } else if (VEC && DMA) {
         // slot sl = ((gi * IH + iy) * IW + ix) * spp + c4: the first slot is decomposed
         // with quotients, the later ones step its digits by 256 slots (host-computed)
         const int spp = ct.CS >> 2, S_in = ct.in_floats >> 2;
@@ -291,11 +313,18 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
             iy -= cy ? ct.IH : 0;
             gi += ct.dGI + cy;
         }
-        // weight slot sl = n * spr + k4, stepped the same way
+    }
+    if (VEC && DMA) {
+        // weight slot sl = n * spr + k4: the first one decomposed with a quotient, the
+        // later ones step its digits by 256 slots (host-computed); steps past the tile
+        // (a wave-uniform test) are skipped
         const int spr = ct.WS >> 2, S_w = BN * spr;
         int n = qdiv(tid, ct.rSPR), k4 = tid - n * spr;
 #pragma unroll
+        for (int i = 0; i < NW; ++i) gw[i] = -2;
+#pragma unroll
         for (int i = 0; i < NW; ++i) {
+            if (i * 256 >= S_w) break;
             const int sl = i * 256 + tid;
             int o = -2;
             if (sl < S_w) {
@@ -364,9 +393,28 @@ __global__ __launch_bounds__(256) void k_conv(const GeomSet gs, const ConvTile c
     const int xbytes = (int)(nvg * g.H * g.W * g.C * 4), wbytes = BN * g.Kp * 4;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     auto dma_chunk = [&](int c0) {
+        if (ct.rowdma) {
+            // rows wv, wv + 4, ... of the tile, (gi, iy) stepped by 4 rows (wave-uniform)
+            const int rs = ct.IW << (ct.lcc - 2), nrow = ct.G * ct.IH;
+            int gi = 0, iy = wv;
+            while (iy >= ct.IH) { iy -= ct.IH; ++gi; }
+            for (int r = wv; r < nrow; r += 4) {
+                const int y = iy0 + iy;
+                if ((unsigned)y < (unsigned)g.H && img0 + gi < n_img) {
+                    const int ro = (((gi * g.H + y) * g.W) * g.C + c0) * 4;
+                    float *dst = In + r * rs * 4;
 #pragma unroll
-        for (int i = 0; i < NIN; ++i)
-            if (gin[i] >= 0) lds_dma16(Xb, xbytes, In + (i * 256 + wv * 64) * 4, gin[i] + 4 * c0);
+                    for (int q = 0; q < NIN / 4; ++q)
+                        if (q * 64 < rs && gin[q] >= 0) lds_dma16(Xb, xbytes, dst + q * 256, gin[q] + ro);
+                }
+                iy += 4;
+                while (iy >= ct.IH) { iy -= ct.IH; ++gi; }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NIN; ++i)
+                if (gin[i] >= 0) lds_dma16(Xb, xbytes, In + (i * 256 + wv * 64) * 4, gin[i] + 4 * c0);
+        }
 #pragma unroll
         for (int i = 0; i < NW; ++i)
             if (gw[i] >= 0) lds_dma16(Bb, wbytes, Wl + (i * 256 + wv * 64) * 4, gw[i] + 4 * c0);
@@ -696,7 +744,7 @@ size_t plan_chunk(const Geom &g, int BN, int KPL, ConvTile &ct, int want = 0, bo
             const int cs = dma ? cc : cc + 4;   // DMA tiles unpadded (more blocks per CU)
             const size_t in = (size_t)ct.G * ct.IH * ct.IW * cs;
             const int kb = ((ct.T * cc + 15) / 16) * 16;
-            const size_t w = (size_t)BN * (kb + 4);
+            const size_t w = (size_t)BN * (dma ? kb : kb + 4);
             const bool regs =
                 dma ? in / 4 <= 256 * DMA_IN4 && w / 4 <= 256 * DMA_W4 &&
                           (size_t)ct.G * g.H * g.W * g.C * 4 < 0x7fffffffUL
@@ -711,7 +759,9 @@ size_t plan_chunk(const Geom &g, int BN, int KPL, ConvTile &ct, int want = 0, bo
         ct.nchunk = g.C / best;
     }
     ct.KB = ((ct.T * ct.CC + 15) / 16) * 16;
-    ct.WS = ct.KB + 4;
+    // weight rows padded by 4 floats against LDS bank conflicts of the B reads; DMA
+    // tiles unpadded, which keeps their LDS footprint (and so the blocks per CU) down
+    ct.WS = dma ? ct.KB : ct.KB + 4;
     ct.in_floats = ct.G * ct.IH * ct.IW * ct.CS;
     const size_t bytes = ((size_t)ct.in_floats + (size_t)BN * ct.WS + ct.KB) * 4;
     return bytes <= LDS_BUDGET ? bytes : 0;
@@ -750,17 +800,23 @@ hipError_t launch_mfma(const GeomSet &gs, const ConvTile &ct, size_t lds, const 
     if (dma) {   // planned only with C % 4 == 0
         const bool dsmall = ct.in_floats / 4 <= 256 * DMA_SMALL_IN4 &&
                             BN * ct.WS / 4 <= 256 * DMA_SMALL_W4;
+        // staging by rows where a row fills at least one 64-slot segment (narrower rows
+        // would leave most lanes of each DMA instruction idle) and fits the offset
+        // registers (NIN / 4 segments)
+        ConvTile c2 = ct;
+        const int rs = ct.IW * (ct.CS / 4);
+        c2.rowdma = rs >= 64 && rs <= 64 * ((dsmall ? DMA_SMALL_IN4 : DMA_IN4) / 4);
         if (dsmall) {
             static const hipError_t ok =
                 allow_lds(k_conv<Epi, MF, BN, true, DMA_SMALL_IN4, DMA_SMALL_W4, true>);
             if (ok != hipSuccess) return ok;
             hipLaunchKernelGGL((k_conv<Epi, MF, BN, true, DMA_SMALL_IN4, DMA_SMALL_W4, true>), grid,
-                               dim3(256), lds, st, gs, ct, X, n_img, epi);
+                               dim3(256), lds, st, gs, c2, X, n_img, epi);
         } else {
             static const hipError_t ok = allow_lds(k_conv<Epi, MF, BN, true, DMA_IN4, DMA_W4, true>);
             if (ok != hipSuccess) return ok;
             hipLaunchKernelGGL((k_conv<Epi, MF, BN, true, DMA_IN4, DMA_W4, true>), grid, dim3(256),
-                               lds, st, gs, ct, X, n_img, epi);
+                               lds, st, gs, c2, X, n_img, epi);
         }
         return hipGetLastError();
     }
