@@ -243,6 +243,32 @@ bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t
                         int32_t nnz, const float *grad_lower, float *grad_alpha,
                         float *grad_beta, void *stream);
 
+/* One projected Adam step on alpha (the form of bound_adam below) fused with
+ * bound_grad's alpha-gradient (the alpha-CROWN optimisation of the relaxation slopes):
+ * bound_grad's arguments and checks, grad_beta as there, but instead of writing a dense
+ * gradient the library steps alpha itself at the entries the bound depends on -- the
+ * unstable, unsplit neurons of layers 1 .. target-1 of each instance -- as soon as each
+ * layer's gradient is formed, so the gradient never goes to memory and the other
+ * entries are not touched.
+ * alpha [n_inst, n_relu] (bound_pass.alpha's layout), updated in place.
+ * m, v  [n_inst, n_relu] Adam moments in slot order: entry (i, off_l + s) belongs to the
+ *       s-th unstable neuron (internal order: channel fastest, then pixel) of ReLU layer l
+ *       under instance i's intermediate bounds, off_l the layer's offset in n_relu.  The
+ *       order depends only on those bounds, so the moments stay valid across the steps of
+ *       an optimisation with fixed intermediate bounds and splits; zero them when those
+ *       change.
+ * With the moments zero at the start, alpha after each step equals that of bound_grad
+ * followed by bound_adam on the dense gradient, for alpha within [clip_lo, clip_hi]. */
+typedef struct {
+    float *alpha;
+    float *m, *v;
+    int32_t step;   /* 1-based */
+    float lr, b1, b2, eps, grad_scale, clip_lo, clip_hi;
+} bound_adam_step;
+bound_status bound_grad_adam(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t rows,
+                             int32_t nnz, const float *grad_lower,
+                             const bound_adam_step *alpha_step, float *grad_beta, void *stream);
+
 /* One Adam step (PyTorch's bias-corrected form) on n parameters, minimising a loss
  * whose gradient is grad_scale * grad, then clipping to [clip_lo, clip_hi]:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;

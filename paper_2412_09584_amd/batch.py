@@ -58,6 +58,7 @@ class BetaBatch:
         self.alpha0 = float(workload.extra.get("alpha0", 0.5))
         self.lr = float(workload.extra.get("lr", 0.1))
         self.recompute = False       # checkpointed layer recomputation for the gradient
+        self.fused = True            # step(): alpha-gradient fused into its Adam step
         self.reset()
 
     def reset(self):
@@ -88,8 +89,20 @@ class BetaBatch:
                      clip_lo=0.0, stream=stream)
 
     def step(self, t, stream=None):
-        self.bound_and_grad(stream)
-        self.adam(t, stream)
+        """One optimisation step: bound pass, gradient, Adam on alpha and beta (with
+        `fused`, the alpha-gradient goes straight into alpha's Adam step inside the
+        library, the moments ma / va then in slot order)."""
+        if not self.fused:
+            self.bound_and_grad(stream)
+            self.adam(t, stream)
+            return
+        B.bound_backward(self.bn.handle, self.n, self.R, self.L, lower=self.lower, best=self.best,
+                         stream=stream, **self.pass_args())
+        B.bound_grad_adam(self.bn.handle, self.ones, self.alpha, self.ma, self.va, t, self.lr,
+                          grad_scale=-1.0, clip_lo=0.0, clip_hi=1.0, grad_beta=self.gb,
+                          stream=stream)
+        B.bound_adam(self.beta, self.gb, self.mb, self.vb, t, self.lr, grad_scale=-1.0,
+                     clip_lo=0.0, stream=stream)
 
     def autotune(self, stream=None):
         """Time every kernel variant of every product of one step on the live data and keep
@@ -111,7 +124,7 @@ class BetaBatch:
         steps = int(self.w.extra.get("steps", 10)) if steps is None else int(steps)
         return N.AlphaBetaOptimizer(self.bn, self.C, self.lo, self.hi, self.x_lo, self.x_hi,
                                     bound_of=self.bof, splits=self.spd, steps=steps, lr=self.lr,
-                                    alpha0=self.alpha0, use_beta=True)
+                                    alpha0=self.alpha0, use_beta=True, fused=self.fused)
 
 
 def chosen_plans(log):

@@ -29,7 +29,7 @@ EXPORTED = ("bound_init", "bound_dims", "bound_backward", "bound_concretize", "b
             "bound_bab_init", "bound_bab_pick_out", "bound_bab_samples", "bound_bab_search_summary",
             "bound_bab_split", "bound_bab_update_best", "bound_bab_prune", "bound_bab_prune_noalloc",
             "bound_sample_bounds_merge", "bound_bab_cem_start", "bound_bab_cem_samples",
-            "bound_bab_cem_refit", "bound_bab_destroy", "bound_last_error")
+            "bound_bab_cem_refit", "bound_grad_adam", "bound_bab_destroy", "bound_last_error")
 
 _p = ctypes.c_void_p
 
@@ -54,6 +54,12 @@ class BoundOut(ctypes.Structure):
     _fields_ = [("lower", _p), ("upper", _p), ("ld", ctypes.c_int64), ("coeff", _p),
                 ("offset", _p), ("offset_mag", _p), ("best", _p),
                 ("pass_id", ctypes.POINTER(ctypes.c_int64)), ("best_upper", _p)]
+
+
+class BoundAdamStep(ctypes.Structure):
+    _fields_ = [("alpha", _p), ("m", _p), ("v", _p), ("step", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("b1", ctypes.c_float), ("b2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("grad_scale", ctypes.c_float), ("clip_lo", ctypes.c_float), ("clip_hi", ctypes.c_float)]
 
 
 class BoundError(RuntimeError):
@@ -82,6 +88,8 @@ def lib():
                                        _p, _p, ctypes.c_int32, _p, _p]
         L.bound_grad.argtypes = [_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_int32, _p, _p, _p, _p]
+        L.bound_grad_adam.argtypes = [_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_int32, _p, ctypes.POINTER(BoundAdamStep), _p, _p]
         L.bound_sample_bounds.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p, _p]
         L.bound_sample_bounds_merge.argtypes = [_p, ctypes.c_int32, ctypes.c_int32, _p, _p, _p, _p, _p]
         L.bound_adam.argtypes = [ctypes.c_int64, _p, _p, _p, _p, ctypes.c_int32, ctypes.c_float,
@@ -244,6 +252,19 @@ def bound_grad(handle, grad_lower, grad_alpha, grad_beta=None, pass_id=0, stream
     nnz = 0 if grad_beta is None else grad_beta.shape[0]
     _check(lib().bound_grad(handle, int(pass_id), int(n_inst), int(rows), int(nnz),
                             _ptr(grad_lower), _ptr(grad_alpha), _ptr(grad_beta), _stream(stream)))
+
+
+def bound_grad_adam(handle, grad_lower, alpha, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8,
+                    grad_scale=1.0, clip_lo=-float("inf"), clip_hi=float("inf"), grad_beta=None,
+                    pass_id=0, stream=None):
+    """bound_grad with the alpha-gradient fused into an Adam step on alpha (m, v: moments in
+    slot order, shaped like alpha); grad_beta [nnz, rows] or None as in bound_grad."""
+    n_inst, rows = grad_lower.shape
+    nnz = 0 if grad_beta is None else grad_beta.shape[0]
+    a = BoundAdamStep(_ptr(alpha), _ptr(m), _ptr(v), int(step), float(lr), float(b1), float(b2),
+                      float(eps), float(grad_scale), float(clip_lo), float(clip_hi))
+    _check(lib().bound_grad_adam(handle, int(pass_id), int(n_inst), int(rows), int(nnz),
+                                 _ptr(grad_lower), ctypes.byref(a), _ptr(grad_beta), _stream(stream)))
 
 
 def bound_adam(param, grad, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8, grad_scale=1.0,

@@ -823,17 +823,23 @@ bound_status bound_backward(bound_net *net, const bound_pass *P, const bound_out
     return BOUND_OK;
 }
 
-bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t rows_arg,
-                        int32_t nnz, const float *grad_lower, float *grad_alpha, float *grad_beta,
-                        void *stream) {
-    if (!net || !grad_lower || !grad_alpha) return fail(BOUND_E_ARG, "bound_grad: null argument");
-    if (!net->saved) return fail(BOUND_E_STATE, "bound_grad: no SAVE_FOR_GRAD pass to differentiate");
+namespace {
+// The reverse pass of bound_grad; with as != null the alpha-gradient of each ReLU layer
+// goes straight into an Adam step on alpha (bound_grad_adam) instead of grad_alpha.
+bound_status grad_impl(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t rows_arg,
+                       int32_t nnz, const float *grad_lower, float *grad_alpha,
+                       const bound_adam_step *as, float *grad_beta, void *stream, const char *fn) {
+    const std::string f(fn);
+    if (!net || !grad_lower || (!grad_alpha && !as)) return fail(BOUND_E_ARG, f + ": null argument");
+    if (as && (!as->alpha || !as->m || !as->v || as->step < 1))
+        return fail(BOUND_E_ARG, f + ": bad alpha step (null buffer or step < 1)");
+    if (!net->saved) return fail(BOUND_E_STATE, f + ": no SAVE_FOR_GRAD pass to differentiate");
     if (pass_id != 0 && pass_id != net->pass_seq)
-        return fail(BOUND_E_STATE, "bound_grad: pass " + std::to_string(pass_id) +
+        return fail(BOUND_E_STATE, f + ": pass " + std::to_string(pass_id) +
                                        " is not the last SAVE_FOR_GRAD pass (" +
                                        std::to_string(net->pass_seq) + ") or was invalidated");
     if (n_inst != net->s_n_inst || rows_arg != net->s_rows || (grad_beta && nnz != net->s_nnz_arg))
-        return fail(BOUND_E_SHAPE, "bound_grad: n_inst / rows / nnz differ from the saved pass (" +
+        return fail(BOUND_E_SHAPE, f + ": n_inst / rows / nnz differ from the saved pass (" +
                                        std::to_string(net->s_n_inst) + " / " +
                                        std::to_string(net->s_rows) + " / " +
                                        std::to_string(net->s_nnz_arg) + ")");
@@ -841,11 +847,25 @@ bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t
     const int k = net->s_target, rows = net->s_rows;
     const long n_img = (long)net->s_n_inst * rows;
     const long d0 = net->d[0];
+    AdamArgs aa{};
+    if (as) aa = adam_args(as->step, as->lr, as->b1, as->b2, as->eps, as->grad_scale, as->clip_lo, as->clip_hi);
     {
         ProfScope pz(net, st, "grad_zero");
-        HIPCHK(launch_fill(grad_alpha, (long)net->s_n_inst * net->n_relu, 0.f, st));
+        if (grad_alpha) HIPCHK(launch_fill(grad_alpha, (long)net->s_n_inst * net->n_relu, 0.f, st));
         if (grad_beta && net->s_nnz > 0) HIPCHK(launch_fill(grad_beta, (long)net->s_nnz * rows, 0.f, st));
     }
+    // alpha part of ReLU layer `layer` (0-based) from the row contributions in gcbuf
+    auto alpha_part = [&](long D, const LayerShape &S, int layer, long aoff) -> hipError_t {
+        if (as)
+            return launch_alpha_adam(net->s_n_inst, rows, D, S, layer, net->n_relu, net->srow,
+                                     net->slot_count, net->slot_inv, net->slot, net->gcbuf, as->alpha,
+                                     as->m, as->v, net->n_relu, aoff, (int)net->s_nnz, net->sp,
+                                     net->sp + net->sp_cap, net->sp + 2 * net->sp_cap, aa, st);
+        return launch_alpha_grad(net->s_n_inst, rows, D, S, layer, net->n_relu, net->srow,
+                                 net->slot_count, net->slot_inv, net->gcbuf, grad_alpha, net->n_relu,
+                                 aoff, (int)net->s_nnz, net->sp, net->sp + net->sp_cap,
+                                 net->sp + 2 * net->sp_cap, st);
+    };
     float *cur = net->buf[0], *nxt = net->buf[1];
     int32_t *sp_inst = net->sp, *sp_layer = net->sp + net->sp_cap, *sp_j = net->sp + 2 * net->sp_cap;
     int32_t *sp_dup = net->sp + 3 * net->sp_cap;
@@ -861,10 +881,7 @@ bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t
                                       grad_lower, net->infeas, net->sbar,
                                       net->tab + net->relu_off(sl), net->n_relu,
                                       sl + 1 < k ? cur : nullptr, net->gcbuf, S.C, S.HW, st));
-        HIPCHK(launch_alpha_grad(net->s_n_inst, rows, Ds, S, sl - 1, net->n_relu, net->srow,
-                                 net->slot_count, net->slot_inv, net->gcbuf, grad_alpha,
-                                 net->n_relu, net->relu_off(sl), (int)net->s_nnz, sp_inst, sp_layer,
-                                 sp_j, st));
+        HIPCHK(alpha_part(Ds, S, sl - 1, net->relu_off(sl)));
         if (grad_beta && net->s_nnz > 0)
             HIPCHK(launch_beta_grad_stop(net->s_nnz, rows, sl - 1, Ds, sp_inst, sp_layer, sp_j,
                                          net->sp_sign, net->save + net->s_lam_off, net->stop_cen,
@@ -947,11 +964,8 @@ bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t
             if (bs != BOUND_OK) return bs;
         }
         {
-            ProfScope ps(net, st, "alpha_grad");
-            HIPCHK(launch_alpha_grad(net->s_n_inst, rows, net->d[m], net->ns.l[m - 1], m - 1,
-                                     net->n_relu, net->srow, net->slot_count, net->slot_inv,
-                                     net->gcbuf, grad_alpha, net->n_relu, net->relu_off(m),
-                                     (int)net->s_nnz, sp_inst, sp_layer, sp_j, st));
+            ProfScope ps(net, st, as ? "alpha_adam" : "alpha_grad");
+            HIPCHK(alpha_part(net->d[m], net->ns.l[m - 1], m - 1, net->relu_off(m)));
         }
         if (grad_beta && net->s_nnz > 0) {
             BetaGradLayer bl{};
@@ -966,10 +980,28 @@ bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t
         }
         float *t = cur; cur = nxt; nxt = t;
     }
-    bound_status bs = debug_check(net, st, grad_alpha, (long)net->s_n_inst * net->n_relu, "grad_alpha");
+    bound_status bs = as ? debug_check(net, st, as->alpha, (long)net->s_n_inst * net->n_relu, "alpha")
+                         : debug_check(net, st, grad_alpha, (long)net->s_n_inst * net->n_relu, "grad_alpha");
     if (bs == BOUND_OK && grad_beta)
         bs = debug_check(net, st, grad_beta, (long)net->s_nnz * rows, "grad_beta");
     return bs;
+}
+}  // namespace
+
+bound_status bound_grad(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t rows_arg,
+                        int32_t nnz, const float *grad_lower, float *grad_alpha, float *grad_beta,
+                        void *stream) {
+    if (!grad_alpha) return fail(BOUND_E_ARG, "bound_grad: null argument");
+    return grad_impl(net, pass_id, n_inst, rows_arg, nnz, grad_lower, grad_alpha, nullptr, grad_beta,
+                     stream, "bound_grad");
+}
+
+bound_status bound_grad_adam(bound_net *net, int64_t pass_id, int32_t n_inst, int32_t rows_arg,
+                             int32_t nnz, const float *grad_lower, const bound_adam_step *alpha_step,
+                             float *grad_beta, void *stream) {
+    if (!alpha_step) return fail(BOUND_E_ARG, "bound_grad_adam: null argument");
+    return grad_impl(net, pass_id, n_inst, rows_arg, nnz, grad_lower, nullptr, alpha_step, grad_beta,
+                     stream, "bound_grad_adam");
 }
 
 namespace {

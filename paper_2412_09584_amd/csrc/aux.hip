@@ -717,19 +717,77 @@ __global__ void k_sample_minmax(long n_sub, int per_sub, long D, int C, int HW, 
     }
 }
 
-__global__ void k_adam(long n, float *p, const float *g, float *m, float *v, float b1, float b2,
-                       float bc1, float bc2s, float lr, float eps, float gs, float lo, float hi) {
+// One projected Adam step of one parameter p with gradient g (moments m, v updated in
+// place); shared by the dense step and the fused alpha step, so both round alike.
+__device__ inline float adam_elem(float p, float g, float &m, float &v, const AdamArgs &a) {
+    const float gr = a.gs * g;
+    m = a.b1 * m + (1.f - a.b1) * gr;
+    v = a.b2 * v + (1.f - a.b2) * gr * gr;
+    const float x = p - (a.lr / a.bc1) * m / (sqrtf(v) / a.bc2s + a.eps);
+    return fminf(fmaxf(x, a.lo), a.hi);
+}
+
+__global__ void k_adam(long n, float *p, const float *g, float *m, float *v, const AdamArgs a) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float pi = p[i];   // loaded with the others, ahead of the moment stores
-    const float gr = gs * g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gr;
-    const float vi = b2 * v[i] + (1.f - b2) * gr * gr;
+    float mi = m[i], vi = v[i];
+    const float x = adam_elem(pi, g[i], mi, vi, a);
     m[i] = mi;
     v[i] = vi;
-    float x = pi - (lr / bc1) * mi / (sqrtf(vi) / bc2s + eps);
-    x = fminf(fmaxf(x, lo), hi);
     p[i] = x;
+}
+
+// Split neurons keep the slot they have as unstable neurons but take no alpha: their
+// slots' row contributions are cleared, so the fused step below sees a zero gradient
+// there, as the dense gradient has.  One thread per (split entry, row).
+__global__ void k_split_gc_zero(int nnz, int rows, int layer, long D, long n_relu, long off,
+                                const int32_t *sp_inst, const int32_t *sp_layer,
+                                const int32_t *sp_j, const int32_t *srow, const int32_t *slot,
+                                float *gc) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long)nnz * rows) return;
+    const int q = (int)(t / rows), r = (int)(t - (long)q * rows);
+    if (sp_layer[q] != layer) return;
+    const long inst = sp_inst[q];
+    const int s = slot[(long)srow[inst] * n_relu + off + sp_j[q]];
+    if (s >= 0) gc[(inst * rows + r) * D + s] = 0.f;
+}
+
+// alpha-gradient of ReLU layer L fused with the Adam step on alpha: as k_alpha_grad, the
+// block of an instance sums its rows' contributions at each slot (in the same order),
+// then steps the neuron's alpha (C-major index) with moments kept at the slot's index.
+__global__ void k_alpha_adam(int rows, long D, const LayerShape L, int layer, long n_relu,
+                             const int32_t *srow, const int32_t *count, const int32_t *inv,
+                             const float *gc, float *alpha, float *m, float *v, long ld, long aoff,
+                             const AdamArgs a) {
+    const long inst = blockIdx.x;
+    const long r = srow[inst];
+    const int cnt = count[r * MAX_RELU_LAYERS + layer];
+    const int32_t *iv = inv + r * n_relu + L.off;
+    const float *g = gc + inst * rows * D;
+    float *al = alpha + inst * ld + aoff, *mm = m + inst * ld + aoff, *vv = v + inst * ld + aoff;
+    for (int k = threadIdx.x; k < cnt; k += TPB) {
+        const int j = iv[k];
+        const int c = j % L.C, p = j / L.C;
+        const long ai = (long)c * L.HW + p;
+        const float pi = al[ai];        // issued ahead of the row loads
+        float mi = mm[k], vi = vv[k];
+        float acc = 0.f;
+        int q = 0;
+        for (; q + 8 <= rows; q += 8) {
+            float t8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t8[u] = g[(q + u) * D + k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += t8[u];
+        }
+        for (; q < rows; ++q) acc += g[q * D + k];
+        const float x = adam_elem(pi, acc, mi, vi, a);
+        mm[k] = mi;
+        vv[k] = vi;
+        al[ai] = x;
+    }
 }
 
 // One block per (instance, row): reads the row once, coalesced.
@@ -1025,13 +1083,42 @@ hipError_t launch_sample_minmax(long n_sub, int per_sub, long D, int C, int HW, 
     return hipGetLastError();
 }
 
+AdamArgs adam_args(int step, float lr, float b1, float b2, float eps, float gs, float lo, float hi) {
+    AdamArgs a;
+    a.b1 = b1;
+    a.b2 = b2;
+    a.bc1 = 1.f - powf(b1, (float)step);
+    a.bc2s = sqrtf(1.f - powf(b2, (float)step));
+    a.lr = lr;
+    a.eps = eps;
+    a.gs = gs;
+    a.lo = lo;
+    a.hi = hi;
+    return a;
+}
+
 hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int step, float lr,
                        float b1, float b2, float eps, float gs, float lo, float hi, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    const float bc1 = 1.f - powf(b1, (float)step);
-    const float bc2s = sqrtf(1.f - powf(b2, (float)step));
-    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(TPB), 0, st, n, p, g, m, v, b1, b2, bc1,
-                       bc2s, lr, eps, gs, lo, hi);
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(TPB), 0, st, n, p, g, m, v,
+                       adam_args(step, lr, b1, b2, eps, gs, lo, hi));
+    return hipGetLastError();
+}
+
+hipError_t launch_alpha_adam(int n_inst, int rows, long D, const LayerShape &L, int layer,
+                             long n_relu, const int32_t *srow, const int32_t *slot_count,
+                             const int32_t *slot_inv, const int32_t *slot, float *gc, float *alpha,
+                             float *m, float *v, long ld, long aoff, int nnz,
+                             const int32_t *sp_inst, const int32_t *sp_layer, const int32_t *sp_j,
+                             const AdamArgs &a, hipStream_t st) {
+    if (n_inst <= 0 || D <= 0) return hipSuccess;
+    if (nnz > 0) {
+        const long nt = (long)nnz * rows;
+        hipLaunchKernelGGL(k_split_gc_zero, dim3(blocks_for(nt)), dim3(TPB), 0, st, nnz, rows, layer,
+                           D, n_relu, (long)L.off, sp_inst, sp_layer, sp_j, srow, slot, gc);
+    }
+    hipLaunchKernelGGL(k_alpha_adam, dim3((unsigned)n_inst), dim3(TPB), 0, st, rows, D, L, layer,
+                       n_relu, srow, slot_count, slot_inv, gc, alpha, m, v, ld, aoff, a);
     return hipGetLastError();
 }
 

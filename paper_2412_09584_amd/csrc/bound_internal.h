@@ -290,6 +290,19 @@ hipError_t launch_sample_minmax(long n_sub, int per_sub, long D, int C, int HW, 
 hipError_t launch_adam(long n, float *p, const float *g, float *m, float *v, int step,
                        float lr, float b1, float b2, float eps, float gs, float lo, float hi,
                        hipStream_t st);
+// Adam constants of one step (bias corrections folded in on the host)
+struct AdamArgs {
+    float b1, b2, bc1, bc2s, lr, eps, gs, lo, hi;
+};
+AdamArgs adam_args(int step, float lr, float b1, float b2, float eps, float gs, float lo, float hi);
+// alpha-gradient of one ReLU layer fused with the Adam step on alpha (moments in slot
+// order); clears split neurons' slots of gc first
+hipError_t launch_alpha_adam(int n_inst, int rows, long D, const LayerShape &L, int layer,
+                             long n_relu, const int32_t *srow, const int32_t *slot_count,
+                             const int32_t *slot_inv, const int32_t *slot, float *gc, float *alpha,
+                             float *m, float *v, long ld, long aoff, int nnz,
+                             const int32_t *sp_inst, const int32_t *sp_layer, const int32_t *sp_j,
+                             const AdamArgs &a, hipStream_t st);
 hipError_t launch_concretize(int n_inst, int rows, long d0, const float *coeff,
                              const float *offset, const float *offset_mag, const float *x_lo,
                              const float *x_hi, bool slack, float *lower, hipStream_t st);

@@ -225,11 +225,13 @@ class AlphaBetaOptimizer:
     into a HIP graph (through torch.cuda.CUDAGraph on a capture stream) after one eager
     warm-up run, so a whole optimisation is one graph launch; replay() launches it.
     The library allocates nothing inside a pass, and clears memory with kernels only, so
-    the captured sequence is the eager one.
+    the captured sequence is the eager one.  With `fused` (the default) the alpha-gradient
+    goes straight into alpha's Adam step (bound_grad_adam; ma / va in slot order),
+    otherwise through a dense gradient and bound_adam; alpha comes out the same.
     """
 
     def __init__(self, net, C, lo, hi, x_lo, x_hi, *, bound_of=None, splits=None, steps=10,
-                 lr=0.1, alpha0=0.5, use_beta=True):
+                 lr=0.1, alpha0=0.5, use_beta=True, fused=True):
         dev = net.device
         self.net, self.steps, self.lr, self.alpha0 = net, int(steps), float(lr), float(alpha0)
         self.C = _dev(C, dev)
@@ -240,7 +242,8 @@ class AlphaBetaOptimizer:
         self.nnz = 0 if splits is None else int(splits["idx"].numel())
         self.alpha = torch.empty(self.n, net.n_relu, device=dev)
         self.ma, self.va = torch.empty_like(self.alpha), torch.empty_like(self.alpha)
-        self.ga = torch.empty_like(self.alpha)
+        self.fused = bool(fused)
+        self.ga = None if self.fused else torch.empty_like(self.alpha)
         self.use_beta = bool(use_beta and self.nnz)
         if self.use_beta:
             self.beta = torch.empty(self.nnz, self.rows, device=dev)
@@ -275,9 +278,14 @@ class AlphaBetaOptimizer:
         self.best.fill_(-float("inf"))
         for t in range(1, self.steps + 1):
             self._pass(True)
-            B.bound_grad(self.net.handle, self.ones, self.ga, self.gb)
-            B.bound_adam(self.alpha, self.ga, self.ma, self.va, t, self.lr, grad_scale=-1.0,
-                         clip_lo=0.0, clip_hi=1.0)
+            if self.fused:
+                B.bound_grad_adam(self.net.handle, self.ones, self.alpha, self.ma, self.va, t,
+                                  self.lr, grad_scale=-1.0, clip_lo=0.0, clip_hi=1.0,
+                                  grad_beta=self.gb)
+            else:
+                B.bound_grad(self.net.handle, self.ones, self.ga, self.gb)
+                B.bound_adam(self.alpha, self.ga, self.ma, self.va, t, self.lr, grad_scale=-1.0,
+                             clip_lo=0.0, clip_hi=1.0)
             if self.use_beta:
                 B.bound_adam(self.beta, self.gb, self.mb, self.vb, t, self.lr, grad_scale=-1.0,
                              clip_lo=0.0)

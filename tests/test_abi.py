@@ -43,6 +43,9 @@ def test_error_paths_without_device(L):
     assert L.bound_backward(None, None, None, None) == B.BOUND_E_ARG
     assert "null" in B.bound_last_error()
     assert L.bound_grad(None, 0, 0, 0, 0, None, None, None, None) == B.BOUND_E_ARG
+    assert L.bound_grad_adam(None, 0, 0, 0, 0, None, None, None, None) == B.BOUND_E_ARG
+    st = B.BoundAdamStep(None, None, None, 0, 0.1, 0.9, 0.999, 1e-8, -1.0, 0.0, 1.0)
+    assert L.bound_grad_adam(None, 0, 0, 0, 0, None, ctypes.byref(st), None, None) == B.BOUND_E_ARG
     assert L.bound_concretize(-1, 1, 1, None, None, None, None, None, 0, None, None) == B.BOUND_E_ARG
     assert L.bound_adam(10, None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, 1.0, 0.0, 1.0,
                         None) == B.BOUND_E_ARG
