@@ -501,7 +501,35 @@ def other_configs(w_cnn, bb, stream):
         "frac_fp32_mfma": fu * n2 * 20 / (ms3 / 1e3) / PEAK_FP32_MFMA}
     del opt
     out["planning_unrolled_pushing_H20"] = planning_unrolled()
+    out["standalone_concretize"] = standalone_concretize(stream)
     return out
+
+
+def standalone_concretize(stream, n=4096, rows=9, d0=3072, reps=20):
+    """Theorem 2 on its own (bound_concretize): coefficient rows G_1 [n, rows, d0] of the
+    CNN's input width against per-instance boxes; HBM-bound, reported as GB/s of the
+    algorithmic bytes (G_1, the boxes, offsets and bounds, each once) and as a fraction of
+    the 8 TB/s HBM peak."""
+    import torch
+
+    from paper_2412_09584_amd import binding as B
+    g = torch.Generator(device="cuda")
+    g.manual_seed(17)
+    coeff = torch.randn(n, rows, d0, device="cuda", generator=g)
+    offset = torch.randn(n, rows, device="cuda", generator=g)
+    mag = torch.rand(n, rows, device="cuda", generator=g)
+    x = torch.rand(n, d0, device="cuda", generator=g)
+    x_lo, x_hi = x - 0.01, x + 0.01
+    lower = torch.empty(n, rows, device="cuda")
+
+    def run():
+        B.bound_concretize(n, rows, d0, coeff, offset, mag, x_lo, x_hi, 0, lower, stream=stream)
+
+    ms = _time(run, reps, 3)
+    nbytes = 4.0 * (n * rows * d0 + 2 * n * d0 + 3 * n * rows)
+    gbs = nbytes / (ms / 1e3) / 1e9
+    return {"shape": f"G_1 [{n}, {rows}, {d0}] + boxes [{n}, {d0}]", "ms": ms,
+            "algorithmic_bytes": nbytes, "gb_per_s": gbs, "frac_hbm": gbs * 1e9 / PEAK_HBM}
 
 
 def planning_unrolled(n=256, n_opt=64, samples=64, steps=2, stops=(77, 65, 41)):

@@ -791,25 +791,60 @@ __global__ void k_alpha_adam(int rows, long D, const LayerShape L, int layer, lo
 }
 
 // One block per (instance, row): reads the row once, coalesced.
-__global__ void k_concretize(int n_inst, int rows, long d0, const float *coeff,
-                             const float *offset, const float *offset_mag, const float *x_lo,
-                             const float *x_hi, int slack, float *lower) {
-    const long row = blockIdx.x;
-    const long inst = row / rows;
-    const float *cr = coeff + row * d0;
+// One block per instance: the box (centre, radius) of each of the thread's input
+// elements is formed once and serves all the instance's rows, CROWS rows at a time, whose
+// coefficient loads are all in flight together; the rows' two sums are then reduced over
+// the block.
+constexpr int CROWS = 12;
+__global__ __launch_bounds__(256) void k_concretize(int rows, long d0, const float *coeff,
+                                                   const float *offset, const float *offset_mag,
+                                                   const float *x_lo, const float *x_hi, int slack,
+                                                   float *lower) {
+    __shared__ float red[4][2 * CROWS];
+    const long inst = blockIdx.x;
     const float *lo = x_lo + inst * d0, *hi = x_hi + inst * d0;
-    float a = 0.f, b = 0.f;
-    for (long j = threadIdx.x; j < d0; j += blockDim.x) {
-        const float c = 0.5f * (lo[j] + hi[j]), r = 0.5f * (hi[j] - lo[j]);
-        const float w = cr[j];
-        a += w * c - fabsf(w) * r;
-        b += fabsf(w) * (fabsf(c) + r);
-    }
-    block_sum2(a, b);
-    if (threadIdx.x == 0) {
-        float v = a + offset[row];
-        if (slack) v -= KAPPA_U * (b + (offset_mag ? offset_mag[row] : 0.f));
-        lower[row] = v;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int r0 = 0; r0 < rows; r0 += CROWS) {
+        const int nr = rows - r0 < CROWS ? rows - r0 : CROWS;
+        const float *cr = coeff + (inst * rows + r0) * d0;
+        float a[CROWS], b[CROWS];
+#pragma unroll
+        for (int q = 0; q < CROWS; ++q) a[q] = b[q] = 0.f;
+        for (long j = threadIdx.x; j < d0; j += TPB) {
+            const float l = lo[j], h = hi[j];
+            float w[CROWS];
+#pragma unroll
+            for (int q = 0; q < CROWS; ++q) w[q] = q < nr ? cr[q * d0 + j] : 0.f;
+            const float c = 0.5f * (l + h), r = 0.5f * (h - l), m = fabsf(c) + r;
+#pragma unroll
+            for (int q = 0; q < CROWS; ++q) {
+                a[q] += w[q] * c - fabsf(w[q]) * r;
+                b[q] += fabsf(w[q]) * m;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < CROWS; ++q) {
+            a[q] = wave_sum(a[q]);
+            b[q] = wave_sum(b[q]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < CROWS; ++q) {
+                red[wave][q] = a[q];
+                red[wave][CROWS + q] = b[q];
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < nr) {
+            const int q = threadIdx.x;
+            const float A = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+            const float M = red[0][CROWS + q] + red[1][CROWS + q] + red[2][CROWS + q] + red[3][CROWS + q];
+            const long row = inst * rows + r0 + q;
+            float v = A + offset[row];
+            if (slack) v -= KAPPA_U * (M + (offset_mag ? offset_mag[row] : 0.f));
+            lower[row] = v;
+        }
+        __syncthreads();
     }
 }
 
@@ -1127,8 +1162,8 @@ hipError_t launch_concretize(int n_inst, int rows, long d0, const float *coeff,
                              const float *x_hi, bool slack, float *lower, hipStream_t st) {
     const long nrow = (long)n_inst * rows;
     if (nrow == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_concretize, dim3((unsigned)nrow), dim3(TPB), 0, st, n_inst, rows, d0,
-                       coeff, offset, offset_mag, x_lo, x_hi, slack ? 1 : 0, lower);
+    hipLaunchKernelGGL(k_concretize, dim3((unsigned)n_inst), dim3(TPB), 0, st, rows, d0, coeff,
+                       offset, offset_mag, x_lo, x_hi, slack ? 1 : 0, lower);
     return hipGetLastError();
 }
 

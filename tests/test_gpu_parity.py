@@ -228,6 +228,36 @@ def test_coefficients_and_standalone_concretize(mod):
     close(np_(lower)[0], ol, what="standalone vs oracle")
 
 
+@pytest.mark.parametrize("d0,rows,shift", [(3072, 9, 0), (1001, 13, 0), (1000, 24, 1), (7, 3, 0)])
+def test_standalone_concretize_row_groups_and_widths(mod, d0, rows, shift):
+    """bound_concretize (one block per instance, rows in groups of twelve) against Theorem 2
+    and the allowance in FP64, per row: widths below, at and above the block width, row
+    counts with and without a partial last group, buffers shifted by one float."""
+    N, B = mod
+    rng = np.random.default_rng(301 + d0 + shift)
+    n = 3
+    G = rng.standard_normal((n, rows, d0)).astype(np.float32)
+    off = rng.standard_normal((n, rows)).astype(np.float32)
+    mag = rng.random((n, rows)).astype(np.float32)
+    x = rng.random((n, d0)).astype(np.float32)
+    xl, xh = (x - np.float32(0.02)).astype(np.float32), (x + np.float32(0.02)).astype(np.float32)
+
+    def placed(a):   # the array's data starting `shift` floats into a device buffer
+        flat_ = torch.zeros(a.size + shift, device="cuda")
+        flat_[shift:] = torch.as_tensor(a.ravel(), device="cuda")
+        return flat_[shift:]
+
+    lower = torch.empty(n, rows, device="cuda")
+    B.bound_concretize(n, rows, d0, placed(G), dev(off), dev(mag), placed(xl), placed(xh), 0, lower)
+    got = np_(lower)
+    for i in range(n):
+        for r in range(rows):
+            g64 = G[i, r].astype(np.float64)
+            ref = O.concretize(g64, float(off[i, r]), xl[i], xh[i]) - \
+                O.slack(g64, float(mag[i, r]), xl[i], xh[i])
+            close(got[i, r], ref, rel=1e-5, what=f"row {i},{r}")
+
+
 def test_eps_zero_and_first_layer(mod):
     N, B = mod
     net = tiny_cnn(seed=41)
