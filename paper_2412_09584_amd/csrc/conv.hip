@@ -146,8 +146,9 @@ constexpr int MAX_IN4 = 8, MAX_W4 = 6;
 constexpr int DMA_IN4 = 12, DMA_W4 = 6;
 // ... and a smaller set for tiles that need no more (fewer set-up instructions)
 constexpr int DMA_SMALL_IN4 = 8, DMA_SMALL_W4 = 4;
-// input slots of the narrow-output VALU kernel's DMA staging
-constexpr int VALU_DMA_IN4 = 8;
+// input slots of the narrow-output VALU kernel's DMA staging, and its row segments when
+// it stages by rows
+constexpr int VALU_DMA_IN4 = 8, DMA_ROW_SEG = 4;
 // dword 3 of a raw buffer resource (32-bit data format; no swizzle, no index stride)
 constexpr int BUF_FLAGS = 0x00020000;
 
@@ -527,6 +528,38 @@ __device__ inline void dma_input_tile(float *In, const ConvTile &ct, const Geom 
                                       int xbytes, int iy0, int ix0) {
     const int tid = threadIdx.x, wv = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int spp = ct.CS >> 2, S_in = ct.in_floats >> 2, c4n = ct.CC >> 2;
+    if (ct.rowdma) {
+        // by rows, as in k_conv (spp a power of two, rows of 64 .. 64 * DMA_ROW_SEG slots):
+        // the tile is zeroed, then each wave fetches rows wv, wv + 4, ... segment by
+        // segment; images past the batch read out of the buffer's range (their rows are
+        // dropped)
+        for (int e = tid; e < S_in; e += 256) *(float4 *)(In + 4 * e) = make_float4(0.f, 0.f, 0.f, 0.f);
+        __syncthreads();
+        const int lsp = __builtin_ctz(spp), rs = ct.IW << lsp, nrow = ct.G * ct.IH;
+        int so[DMA_ROW_SEG];
+#pragma unroll
+        for (int q = 0; q < DMA_ROW_SEG; ++q) {
+            const int sl = q * 64 + (tid & 63);
+            const int x = ix0 + (sl >> lsp), c4 = sl & (spp - 1);
+            so[q] = sl < rs && c4 < c4n && (unsigned)x < (unsigned)g.W ? (x * g.C + 4 * c4) * 4 : -1;
+        }
+        int gi = 0, iy = wv;
+        while (iy >= ct.IH) { iy -= ct.IH; ++gi; }
+        for (int r = wv; r < nrow; r += 4) {
+            const int y = iy0 + iy;
+            if ((unsigned)y < (unsigned)g.H) {
+                const int ro = ((gi * g.H + y) * g.W) * g.C * 4;
+                float *dst = In + r * rs * 4;
+#pragma unroll
+                for (int q = 0; q < DMA_ROW_SEG; ++q)
+                    if (q * 64 < rs && so[q] >= 0) lds_dma16(Xb, xbytes, dst + q * 256, so[q] + ro);
+            }
+            iy += 4;
+            while (iy >= ct.IH) { iy -= ct.IH; ++gi; }
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        return;
+    }
     // slot digits stepped by 256 slots as in k_conv's DMA staging
     int c4, ix, iy, gi;
     {
@@ -856,6 +889,10 @@ hipError_t try_direct(const GeomSet &gs, const float *X, long n_img, const Epi &
         // DMA staging when asked for and the tile fits its slots (int offsets inside a group)
         const bool dma = (mode == 1 || mode == 3) && ct.in_floats / 4 <= 256 * VALU_DMA_IN4 &&
                          (size_t)ct.G * g.H * g.W * g.C * 4 < 0x7fffffffUL;
+        // by rows where the slots per pixel are a power of two and a row fills 64 .. 256
+        // slots
+        const int spp = ct.CS / 4, rs = ct.IW * spp;
+        ct.rowdma = dma && (spp & (spp - 1)) == 0 && rs >= 64 && rs <= 64 * DMA_ROW_SEG;
         if (g.N == 3 && dma) {   // RGB input layers: no idle fourth output
             static const hipError_t ok = allow_lds(k_conv_valu<Epi, 3, true>);
             if (ok != hipSuccess) return ok;
