@@ -5,8 +5,8 @@ followed by bound_adam on the dense gradient (whose parity with the oracle the o
 tests pin), the same beta gradient, and so the same bounds -- bitwise, since the row sums
 of the gradient are added in the same order and both Adam kernels share one update
 routine.  Covered: splits (with repeated entries), full propagation, early stop at a
-linear node, checkpointed recomputation, and the bench's subdomain batch through
-AlphaBetaOptimizer.
+linear node, checkpointed recomputation, both bound sides, one bounds row per instance,
+and the bench's subdomain batch through AlphaBetaOptimizer.
 """
 import numpy as np
 import pytest
@@ -30,7 +30,7 @@ def dev(x, dtype=torch.float32):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
 
 
-@pytest.mark.parametrize("case", ["full", "stop_linear", "recompute"])
+@pytest.mark.parametrize("case", ["full", "stop_linear", "recompute", "both_sides", "per_instance"])
 def test_fused_alpha_step_equals_gradient_then_adam(mod, case):
     N, B = mod
     net = W.cnn(seed=191, in_shape=(3, 8, 8), spec=[(16, 3, 1), (16, 4, 2), (32, 3, 1)], fc=(16, 5))
@@ -55,32 +55,45 @@ def test_fused_alpha_step_equals_gradient_then_adam(mod, case):
     spd = {"off": dev(off, torch.int32), "idx": dev(neu, torch.int32), "sign": dev(sgn, torch.int8)}
     nnz, rows, L = len(neu), C.shape[1], len(net)
     Cd, xl, xh, bof = dev(C[root_of]), dev(x_lo[root_of]), dev(x_hi[root_of]), dev(root_of, torch.int32)
-    flags = B.BOUND_SAVE_FOR_GRAD | (B.BOUND_RECOMPUTE if case == "recompute" else 0)
+    flags = B.BOUND_SAVE_FOR_GRAD | (B.BOUND_RECOMPUTE if case == "recompute" else 0) | \
+        (B.BOUND_BOTH_SIDES if case == "both_sides" else 0)
     stop = dict(stop_layer=L - 1, stop_mode=B.BOUND_STOP_LINEAR) if case == "stop_linear" else {}
-    ones = torch.ones(n, rows, device="cuda")
+    nb = n_roots
+    if case == "per_instance":        # one bounds row per instance instead of per root
+        ridx = dev(root_of, torch.long)
+        lo, hi, nb, bof = lo[ridx].contiguous(), hi[ridx].contiguous(), n, None
+    # with both sides the gradient weights the lower bounds and the negated upper bounds
+    wrows = 2 * rows if case == "both_sides" else rows
+    ones = torch.ones(n, wrows, device="cuda")
+
+    use_beta = case != "both_sides"     # both sides: splits clamp, no multipliers
 
     def run(fused, steps=4):
         alpha = torch.full((n, bn.n_relu), 0.5, device="cuda")
         beta = torch.zeros(nnz, rows, device="cuda")
         ma, va = torch.zeros_like(alpha), torch.zeros_like(alpha)
         mb, vb = torch.zeros_like(beta), torch.zeros_like(beta)
-        ga, gb = torch.empty_like(alpha), torch.empty_like(beta)
+        ga, gb = torch.empty_like(alpha), torch.zeros_like(beta)
         lower = torch.empty(n, rows, device="cuda")
+        upper = torch.empty(n, rows, device="cuda") if case == "both_sides" else None
         out = []
         for t in range(1, steps + 1):
-            B.bound_backward(bn.handle, n, rows, L, spec=Cd, lo=lo, hi=hi, n_bounds=n_roots,
+            B.bound_backward(bn.handle, n, rows, L, spec=Cd, lo=lo, hi=hi, n_bounds=nb,
                              bound_of=bof, alpha=alpha, split_off=spd["off"], split_idx=spd["idx"],
-                             split_sign=spd["sign"], nnz=nnz, beta=beta, x_lo=xl, x_hi=xh,
-                             flags=flags, lower=lower, **stop)
+                             split_sign=spd["sign"], nnz=nnz, beta=beta if use_beta else None,
+                             x_lo=xl, x_hi=xh, flags=flags, lower=lower, upper=upper, **stop)
+            g_b = gb if use_beta else None
             if fused:
                 B.bound_grad_adam(bn.handle, ones, alpha, ma, va, t, 0.1, grad_scale=-1.0,
-                                  clip_lo=0.0, clip_hi=1.0, grad_beta=gb)
+                                  clip_lo=0.0, clip_hi=1.0, grad_beta=g_b)
             else:
-                B.bound_grad(bn.handle, ones, ga, gb)
+                B.bound_grad(bn.handle, ones, ga, g_b)
                 B.bound_adam(alpha, ga, ma, va, t, 0.1, grad_scale=-1.0, clip_lo=0.0, clip_hi=1.0)
-            B.bound_adam(beta, gb, mb, vb, t, 0.1, grad_scale=-1.0, clip_lo=0.0)
+            if use_beta:
+                B.bound_adam(beta, gb, mb, vb, t, 0.1, grad_scale=-1.0, clip_lo=0.0)
             torch.cuda.synchronize()
-            out.append((lower.clone(), alpha.clone(), beta.clone(), gb.clone()))
+            out.append((torch.cat([lower] + ([upper] if upper is not None else []), 1).clone(),
+                        alpha.clone(), beta.clone(), gb.clone()))
         return out
 
     ref, got = run(False), run(True)
@@ -94,7 +107,7 @@ def test_fused_alpha_step_equals_gradient_then_adam(mod, case):
     assert moved, "alpha never moved: the test exercises nothing"
     # a later pass without SAVE_FOR_GRAD leaves nothing to differentiate
     lower = torch.empty(n, rows, device="cuda")
-    B.bound_backward(bn.handle, n, rows, L, spec=Cd, lo=lo, hi=hi, n_bounds=n_roots, bound_of=bof,
+    B.bound_backward(bn.handle, n, rows, L, spec=Cd, lo=lo, hi=hi, n_bounds=nb, bound_of=bof,
                      alpha=torch.full((n, bn.n_relu), 0.5, device="cuda"), x_lo=xl, x_hi=xh,
                      flags=0, lower=lower)
     z = [torch.zeros(n, bn.n_relu, device="cuda") for _ in range(3)]
