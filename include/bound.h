@@ -318,7 +318,7 @@ int32_t bound_autotune_report(const bound_net *net, char *buf, int32_t cap);
  * 'A' (adjoint step) or 'F' (forward step of sample rows); layer is 1-based; path 1 =
  * direct convolution (cfg: -1 staging through registers, 1 by LDS DMA, 2 / 3 the same
  * with 16x16 MFMA tiles for 32 output channels; cc: channel chunk, 0 = largest that
- * fits), path 2 = implicit GEMM (cfg: tile shape 0..8), path 0 = automatic.  A plan the layer cannot run falls back to the implicit GEMM at launch.
+ * fits), path 2 = implicit GEMM (cfg: tile shape 0..10; 9 and 10 stage dense products by LDS DMA), path 0 = automatic.  A plan the layer cannot run falls back to the implicit GEMM at launch.
  * Lets a run reuse the plans of an earlier tuned run (the timing log's chosen lines). */
 bound_status bound_set_plan(bound_net *net, char product, int32_t layer, int32_t path,
                             int32_t cfg, int32_t cc);

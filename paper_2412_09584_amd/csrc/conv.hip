@@ -149,17 +149,6 @@ constexpr int DMA_SMALL_IN4 = 8, DMA_SMALL_W4 = 4;
 // input slots of the narrow-output VALU kernel's DMA staging, and its row segments when
 // it stages by rows
 constexpr int VALU_DMA_IN4 = 8, DMA_ROW_SEG = 4;
-// dword 3 of a raw buffer resource (32-bit data format; no swizzle, no index stride)
-constexpr int BUF_FLAGS = 0x00020000;
-
-// 16 bytes per lane from base + voff (bytes) into LDS at lds + 16 * lane (lds uniform
-// across the wave); offsets at or past nbytes read nothing.
-__device__ inline void lds_dma16(const float *base, int nbytes, float *lds, int voff) {
-    const __amdgpu_buffer_rsrc_t r =
-        __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nbytes, BUF_FLAGS);
-    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void *)lds, 16,
-                                             voff, 0, 0, 0);
-}
 
 // Element walk over a [rows][P] float4 grid: thread tid visits e = tid, tid + 256, ...;
 // the row / column of each visit advance incrementally (one division per thread).

@@ -95,6 +95,19 @@ template <class T> __device__ inline void st(T *base, int i, T v) {
     *(G *)((char *)base + (unsigned)i * (unsigned)sizeof(T)) = v;
 }
 
+// ---------------------------------------------------------------------- LDS DMA
+// dword 3 of a raw buffer resource (32-bit data format; no swizzle, no index stride)
+constexpr int BUF_FLAGS = 0x00020000;
+
+// 16 bytes per lane from base + voff (bytes) into LDS at lds + 16 * lane (lds uniform
+// across the wave); offsets at or past nbytes read nothing.
+__device__ inline void lds_dma16(const float *base, int nbytes, float *lds, int voff) {
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, nbytes, BUF_FLAGS);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void *)lds, 16,
+                                             voff, 0, 0, 0);
+}
+
 // ---------------------------------------------------------------------- epilogues
 // Each epilogue splits its per-element work into pre() -- the global loads it needs
 // (relaxation record, box) --, pre2() -- loads whose address depends on pre()'s result

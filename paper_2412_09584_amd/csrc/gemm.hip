@@ -33,9 +33,15 @@ using namespace dev;
 // .x = offset of (ky, kx, c) from the row's top-left source element, .y = ky << 16 | kx.
 constexpr int KDEC_MAX = 1024;
 
-template <class Epi, int MF, int BM, int BN, int WGM, int WGN, bool DENSE, bool VEC>
+// DMAG (dense products, K a multiple of 16): the k chunks go from global memory straight
+// into LDS by DMA, two buffers deep -- chunk k + 1 is in flight while chunk k's MFMAs
+// run, one barrier per chunk, no staging registers.  LDS rows are unpadded (16 floats)
+// with the four 16-byte k quads of row r stored in the order kq ^ ((r >> 1) & 3), so the
+// operand reads of consecutive rows fall in different banks.
+template <class Epi, int MF, int BM, int BN, int WGM, int WGN, bool DENSE, bool VEC, bool DMAG = false>
 __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__restrict__ A,
                                               const long n_img, const Epi epi) {
+    static_assert(!DMAG || (DENSE && VEC), "DMA chunks for dense products");
     using MM = Mma<MF>;
     using acc_t = typename MM::acc_t;
     constexpr int TM = BM / WGM, TN = BN / WGN, FM = TM / MF, FN = TN / MF;
@@ -44,8 +50,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
     constexpr int KPL = MM::KPL;
     constexpr int AF4 = BM * BK / 4, BF4 = BN * BK / 4;
     constexpr int APT = (AF4 + 255) / 256, BPT = (BF4 + 255) / 256;
-    __shared__ __attribute__((aligned(16))) float As[BM * LDSW];
-    __shared__ __attribute__((aligned(16))) float Bs[BN * LDSW];
+    __shared__ __attribute__((aligned(16))) float As[DMAG ? 2 * BM * BK : BM * LDSW];
+    __shared__ __attribute__((aligned(16))) float Bs[DMAG ? 2 * BN * BK : BN * LDSW];
     __shared__ int2 kdec[DENSE ? 1 : KDEC_MAX];
 
     const TileIdx ti = xcd_tile((gs.g[0].N + BN - 1) / BN, gs.n);
@@ -163,6 +169,73 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
 #pragma unroll
             for (int v = 0; v < MM::NACC; ++v) acc[i][j][v] = 0.f;
 
+    if constexpr (DMAG) {
+        constexpr int ASL = BM * BK / 4, BSL = BN * BK / 4;    // float4 slots per buffer
+        constexpr int AI = (ASL + 255) / 256, BI = (BSL + 255) / 256;
+        auto swz = [](int r, int kq) { return r * 4 + (kq ^ ((r >> 1) & 3)); };
+        // slot s = i * 256 + tid of a buffer holds row s / 4, k quad (s & 3) ^ ((r >> 1) & 3)
+        int aoff[AI], boff[BI];
+#pragma unroll
+        for (int i = 0; i < AI; ++i) {
+            const int s = i * 256 + tid, r = s >> 2, kq = (s & 3) ^ ((r >> 1) & 3);
+            aoff[i] = s < ASL && m0 + r < M ? (r * K + 4 * kq) * 4 : -1;
+        }
+#pragma unroll
+        for (int i = 0; i < BI; ++i) {
+            const int s = i * 256 + tid, r = s >> 2, kq = (s & 3) ^ ((r >> 1) & 3);
+            boff[i] = s < BSL ? (r * g.Kp + 4 * kq) * 4 : -1;
+        }
+        const float *Ab = A + m0 * K, *Bb = g.Bt + (long)n0 * g.Kp;
+        const int abytes = (int)((M - m0 < BM ? M - m0 : BM) * K * 4), bbytes = BN * g.Kp * 4;
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
+        auto dma = [&](int k0, int b) {
+#pragma unroll
+            for (int i = 0; i < AI; ++i)
+                if (aoff[i] >= 0) lds_dma16(Ab, abytes, As + b * BM * BK + (i * 256 + wv * 64) * 4, aoff[i] + k0 * 4);
+#pragma unroll
+            for (int i = 0; i < BI; ++i)
+                if (boff[i] >= 0) lds_dma16(Bb, bbytes, Bs + b * BN * BK + (i * 256 + wv * 64) * 4, boff[i] + k0 * 4);
+        };
+        const int nk = K / BK;
+        dma(0, 0);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        for (int kc = 0; kc < nk; ++kc) {
+            const int cur = kc & 1;
+            if (kc + 1 < nk) dma((kc + 1) * BK, cur ^ 1);
+            const float *Ac = As + cur * BM * BK, *Bc = Bs + cur * BN * BK;
+            float af[FM][KPL], bf[FN][KPL];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const int r = wm * TM + i * MF + MM::idx(lane);
+#pragma unroll
+                for (int q = 0; q < KPL; q += 4) {
+                    const int kq = (MM::grp(lane) * KPL + q) >> 2;
+                    const f32x4v t = *(const f32x4v *)(Ac + swz(r, kq) * 4);
+                    af[i][q] = t[0]; af[i][q + 1] = t[1]; af[i][q + 2] = t[2]; af[i][q + 3] = t[3];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int r = wn * TN + j * MF + MM::idx(lane);
+#pragma unroll
+                for (int q = 0; q < KPL; q += 4) {
+                    const int kq = (MM::grp(lane) * KPL + q) >> 2;
+                    const f32x4v t = *(const f32x4v *)(Bc + swz(r, kq) * 4);
+                    bf[j][q] = t[0]; bf[j][q + 1] = t[1]; bf[j][q + 2] = t[2]; bf[j][q + 3] = t[3];
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < KPL; ++s)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) acc[i][j] = MM::mma(af[i][s], bf[j][s], acc[i][j]);
+            // the next chunk has landed, and every wave is done with this one
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+        }
+    } else {
     if (!DENSE) __syncthreads();   // decode table complete
     loadA(0);
     loadB(0);
@@ -204,6 +277,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
             for (int i = 0; i < FM; ++i)
 #pragma unroll
                 for (int j = 0; j < FN; ++j) acc[i][j] = MM::mma(af[i][s], bf[j][s], acc[i][j]);
+    }
     }
 
     // ------------------------------------------------------------------ epilogue
@@ -266,7 +340,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GeomSet gs, const float *__r
 }
 
 // ---------------------------------------------------------------------- dispatch
-template <class Epi, int MF, int BM, int BN, int WGM, int WGN>
+template <class Epi, int MF, int BM, int BN, int WGM, int WGN, bool DMAG = false>
 hipError_t launch_cfg(const GeomSet &gs, const float *A, long n_img, const Epi &epi,
                       hipStream_t st) {
     const Geom &g0 = gs.g[0];
@@ -285,7 +359,11 @@ hipError_t launch_cfg(const GeomSet &gs, const float *A, long n_img, const Epi &
         if (!dense && gs.g[i].K > KDEC_MAX) return hipErrorInvalidValue;  // layer too wide
         if ((long)gs.g[i].OH * gs.g[i].OW > (1L << 20)) return hipErrorInvalidValue;  // qdiv range
     }
-    if (dense && vec)
+    bool k16 = true;
+    for (int i = 0; i < gs.n; ++i) k16 = k16 && gs.g[i].K % BK == 0;
+    if (DMAG && dense && vec && k16)
+        hipLaunchKernelGGL((k_gemm<Epi, MF, BM, BN, WGM, WGN, true, true, DMAG>), grid, dim3(256), 0, st, gs, A, n_img, epi);
+    else if (dense && vec)
         hipLaunchKernelGGL((k_gemm<Epi, MF, BM, BN, WGM, WGN, true, true>), grid, dim3(256), 0, st, gs, A, n_img, epi);
     else if (dense)
         hipLaunchKernelGGL((k_gemm<Epi, MF, BM, BN, WGM, WGN, true, false>), grid, dim3(256), 0, st, gs, A, n_img, epi);
@@ -301,8 +379,9 @@ hipError_t launch_cfg(const GeomSet &gs, const float *A, long n_img, const Epi &
 //   3: 16x16 MFMA, 256x16, 4x1    4: 32, 256x64, 4x1    5: 32, 256x128, 4x1
 //   6: 32, 128x32, 4x1 (one 32x32 tile per wave: fewest registers)
 //   7: 16x16 MFMA, 128x32, 2x2    8: 32, 128x64, 4x1
-constexpr int kGemmCfgs = 9;
-const int kCfgBN[kGemmCfgs] = {128, 64, 32, 16, 64, 128, 32, 32, 64};
+//   9, 10: 8 and 1 with the k chunks by LDS DMA (dense products with K % 16 == 0)
+constexpr int kGemmCfgs = 11;
+const int kCfgBN[kGemmCfgs] = {128, 64, 32, 16, 64, 128, 32, 32, 64, 64, 64};
 
 int default_cfg(int N) {
     if (N >= 128) return 0;
@@ -324,6 +403,8 @@ hipError_t dispatch(const GeomSet &gs, const float *A, long n_img, const Epi &ep
     case 6: return launch_cfg<Epi, 32, 128, 32, 4, 1>(gs, A, n_img, epi, st);
     case 7: return launch_cfg<Epi, 16, 128, 32, 2, 2>(gs, A, n_img, epi, st);
     case 8: return launch_cfg<Epi, 32, 128, 64, 4, 1>(gs, A, n_img, epi, st);
+    case 9: return launch_cfg<Epi, 32, 128, 64, 4, 1, true>(gs, A, n_img, epi, st);
+    case 10: return launch_cfg<Epi, 32, 128, 64, 2, 2, true>(gs, A, n_img, epi, st);
     default: return launch_cfg<Epi, 32, 256, 128, 4, 1>(gs, A, n_img, epi, st);
     }
 }
@@ -334,8 +415,13 @@ int gemm_candidates(const GeomSet &gs, int *cfgs, int cap) {
     // a tile wider than the padded N only repeats zero columns
     const int N = gs.g[0].N;
     int n = 0;
-    for (int c = 0; c < kGemmCfgs && n < cap; ++c)
+    const Geom &g = gs.g[0];
+    const bool dma = g.H == 1 && g.W == 1 && g.kh == 1 && g.kw == 1 && g.C % 4 == 0 &&
+                     g.K % BK == 0;
+    for (int c = 0; c < kGemmCfgs && n < cap; ++c) {
+        if (c >= 9 && !dma) continue;
         if (kCfgBN[c] <= 16 * ((N + 15) / 16) || c == default_cfg(N)) cfgs[n++] = c;
+    }
     return n;
 }
 

@@ -874,6 +874,53 @@ def test_sample_bounds_and_early_stop_over_them(mod, kind):
             close(np_(gl)[i], O.spec_lower_early_stop(net, L, C[i], b, L - 1, mode), what=f"{mode} {i}")
 
 
+@pytest.mark.parametrize("cfg", [9, 10])
+@pytest.mark.parametrize("kind", ["mlp", "cnn"])
+def test_gemm_dma_chunks_keep_the_bound(mod, cfg, kind):
+    """The dense GEMM with its k chunks by LDS DMA (tile configurations 9 and 10) pinned on
+    every product gives the bound and gradient of the default plans; a width that is not
+    a multiple of 16 (the MLP's 30 inputs, 5 outputs) takes the staged path."""
+    N, B = mod
+    net = (W.mlp([30, 64, 48, 32, 5], seed=211) if kind == "mlp" else
+           W.cnn(seed=212, in_shape=(3, 8, 8), spec=[(16, 3, 1), (16, 4, 2)], fc=(64, 32, 5)))
+    n_roots, per_root = 2, 6
+    x0 = W.uniform_inputs(n_roots, W.in_dim(net), 213)
+    x_lo, x_hi = W.linf_box(x0, 0.05)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    n = n_roots * per_root
+    root_of = np.repeat(np.arange(n_roots), per_root).astype(np.int32)
+    L = len(net)
+
+    def run(pin, fixed=None):
+        bn = N.BoundNet(net, n, 4096, 4096)
+        if pin is not None:
+            for m in range(1, L + 1):
+                for prod in "RCA":
+                    B.bound_set_plan(bn.handle, prod, m, 2, pin, 0)
+        glo, ghi = bn.crown_bounds(x_lo[root_of], x_hi[root_of])
+        out = [np_(glo)]
+        if fixed is None:
+            lo_np, hi_np = np_(glo), np_(ghi)
+            sp = _random_splits(net, lo_np.astype(np.float64), hi_np.astype(np.float64), n, 214,
+                                np.arange(n, dtype=np.int32))
+            fixed = (glo, ghi, sp, dev(W.random_alpha(n, lo_np.shape[1], 215)),
+                     dev(W.random_beta(sp.nnz, C.shape[1], 216)))
+        flo, fhi, sp, alpha, beta = fixed
+        gl, _ = bn.spec_bounds(C[root_of], flo, fhi, x_lo[root_of], x_hi[root_of], alpha=alpha,
+                               splits=N.splits_to_device(sp), beta=beta, both=False, save=True)
+        ga, gb = bn.grad(torch.ones(n, C.shape[1], device="cuda"), sp.nnz)
+        return out + [np_(gl), np_(ga), np_(gb)], fixed
+
+    ref, fixed = run(None)
+    got, _ = run(cfg, fixed)
+    close(got[0], ref[0], rel=1e-5, what="intermediate bounds")
+    close(got[1], ref[1], rel=1e-5, what="lower")
+    sa = np.max(np.abs(ref[2]), axis=1, keepdims=True) + 1e-30
+    assert np.max(np.abs(got[2] - ref[2]) / sa) <= 1e-3, "grad alpha"
+    sb = np.max(np.abs(ref[3])) + 1e-30
+    assert np.max(np.abs(got[3] - ref[3])) <= 1e-3 * sb, "grad beta"
+
+
 # the first two small geometries, and 32x32 images whose tiles are bands of rows
 VARIANT_GEOMS = [CNN_GEOMS[0], CNN_GEOMS[1],
                  dict(H=32, convs=((16, 3, 1), (32, 4, 2), (16, 3, 1)), fc=(10,), cin=3)]
