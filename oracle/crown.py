@@ -37,8 +37,9 @@ Readings where the text is silent or garbled (each is listed in the design notes
   * Gradient (adjoint) of the raw lower bound w.r.t. alpha and beta: reverse mode of
     backward() + concretize(), with intermediate bounds held fixed.
   * Adam with PyTorch's default moments, followed by projection of alpha to [0, 1] and
-    beta to [0, inf).  Parity of optimiser trajectories is unpinned: only single steps
-    at identical alpha / beta are compared.
+    beta to [0, inf).  Optimiser trajectories are compared over three steps on small
+    networks (the best bound); longer runs one step at a time at identical alpha / beta,
+    since an entry whose gradient is zero up to rounding may step either way.
   * Optimised intermediate bounds (alpha_crown_bounds): every pass that bounds a
     pre-activation layer gets its own slopes, optimised like the final pass's (one slope
     per neuron shared by the lower- and upper-bound rows of that layer), bottom-up; each

@@ -464,6 +464,41 @@ def test_optimisation_loop_improves_and_first_step_matches(mod):
         assert np_(beta).min() >= 0
 
 
+@pytest.mark.parametrize("dims,seed", [([12, 32, 32, 4], 221), ([8, 24, 24, 24, 3], 223)])
+def test_optimiser_trajectory_three_steps_matches_oracle(mod, dims, seed):
+    """Three projected-Adam steps on alpha and beta (GPU: bound pass, gradient, Adam) from
+    the same start and the same intermediate bounds as the oracle's optimisation: the
+    best bound after the steps agrees to 1e-4.  (Entries whose gradient is zero up to
+    rounding may step in different directions on the two sides, which moves the bound by
+    no more than that gradient; the bound is what is compared.)"""
+    N, B = mod
+    net = W.mlp(dims, seed=seed)
+    n_roots, per_root = 2, 3
+    x0 = W.uniform_inputs(n_roots, W.in_dim(net), seed + 1)
+    x_lo, x_hi = W.linf_box(x0, 0.1)
+    C = W.margin_spec(W.clean_logits(net, x0))
+    ob = oracle_bounds(net, x_lo, x_hi)
+    lo, hi = flat(ob)
+    lo, hi = f32(lo).astype(np.float64), f32(hi).astype(np.float64)
+    n = n_roots * per_root
+    root_of = np.repeat(np.arange(n_roots), per_root).astype(np.int32)
+    sp = _random_splits(net, lo, hi, n, seed + 2, root_of)
+    bn = N.BoundNet(net, n, 4096, 4096)
+    best, _, _ = N.optimize_alpha_beta(bn, C[root_of], dev(f32(lo)), dev(f32(hi)), x_lo[root_of],
+                                       x_hi[root_of], steps=3, lr=0.1,
+                                       bound_of=dev(root_of, torch.int32),
+                                       splits=N.splits_to_device(sp))
+    got = np_(best)
+    for i in range(n):
+        r = root_of[i]
+        q0, q1 = sp.off[i], sp.off[i + 1]
+        bounds = list(zip(O.per_layer(net, lo[r]), O.per_layer(net, hi[r])))
+        splits = O.split_list(net, sp.neuron[q0:q1], sp.sign[q0:q1])
+        ref, _, _ = O.optimize_alpha_beta(net, C[r], bounds, x_lo[r], x_hi[r], splits, steps=3,
+                                          lr=0.1)
+        close(got[i], ref, rel=1e-4, what=f"best bound after 3 steps, subdomain {i}")
+
+
 # -------------------------------------------------------------------------- soundness
 @pytest.mark.parametrize("dims,seed", [([2, 8, 8, 3], 91), ([2, 16, 16, 16, 2], 92), ([2, 12, 3], 93)])
 def test_soundness_tiny_2d(mod, dims, seed):
